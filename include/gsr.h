@@ -1,0 +1,236 @@
+/*
+ * gsr.h - C ABI of an MI355X (gfx950) differentiable 3D Gaussian-splatting
+ * rasterizer: Gaussians plus cameras in; colour, depth and alpha images out;
+ * gradients back.
+ *
+ * What it computes.  MAGS-SLAM optimises each agent's Gaussian submap by
+ * gradient descent on an L1 photometric plus depth loss over a window of
+ * keyframes (Sec. III-A, Eq. (map_loss)) and refines the fused map on the
+ * differentiably rendered RGB and depth with per-keyframe pose deltas
+ * (Sec. III-C, Eq. (refine_loss)); both call a 3D Gaussian-splatting
+ * rasterizer (cited in Sec. I and II-A) on every iteration.  A Gaussian has a
+ * mean, a scale vector, a rotation, an opacity and a colour (Sec. III-C,
+ * Eq. (gauss_update)); a keyframe has a world-to-camera pose (Sec. III-B)
+ * and pinhole intrinsics (Appendix A).  This library implements:
+ *
+ *   forward : EWA projection of every (view, Gaussian) pair, opacity-aware
+ *             tile binning, a (tile, depth)-key radix sort, and per-pixel
+ *             front-to-back alpha compositing of colour, depth and opacity
+ *             (alpha = min(0.99, sigma*G); entries with alpha < 1/255 are
+ *             skipped; compositing stops before transmittance would drop
+ *             below 1e-4).
+ *   backward: the exact gradient of a loss with respect to the Gaussian
+ *             parameters and each view's SE(3) pose, by reverse compositing
+ *             with transmittance recomputed by division.
+ *
+ * Conventions.  Camera space is x right, y down, z forward.  Pixel (i, j) is
+ * sampled at (i + 0.5, j + 0.5).  A view matrix is the row-major 3x4
+ * world-to-camera [R | t].  Quaternions are (w, x, y, z) and need not be
+ * unit length (they are normalised inside).  Scales are given as natural
+ * logarithms, opacities as logits (opacity = sigmoid(logit)).  Colours are
+ * raw RGB for sh_degree 0, or real spherical-harmonic coefficients
+ * (Condon-Shortley phase, index l*l + l + m) evaluated as
+ * max(0, 0.5 + sum Y_lm(d) k_lm) along the unit direction d from the camera
+ * centre to the mean for sh_degree 1..3.  Depth is the unnormalised sum of
+ * z * alpha * T; alpha is 1 - final transmittance; colour includes
+ * T_final * bg.  The pose gradient is with respect to a left perturbation
+ * [R|t] <- Exp(xi) [R|t] at xi = 0, xi = (rho, phi), translation first.
+ *
+ * Memory.  Every float pointer in gsr_scene, gsr_views, gsr_images,
+ * gsr_grads and the state buffer is DEVICE memory of the context's GPU,
+ * caller-owned, FP32, C-contiguous.  set_offsets and view_set (structure,
+ * not values) are HOST arrays read during the call.  The context owns its
+ * workspace (allocated by gsr_plan).  Each forward writes its saved state
+ * into a caller-owned device buffer of gsr_state_bytes() bytes, which the
+ * matching backward reads; several forwards may be alive at once.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ * stream).  gsr_forward and gsr_backward only enqueue work: they do not
+ * allocate, free, synchronise or copy to the host, so they may be captured
+ * in a HIP graph.  Work-dependent sizes (visible pairs, tile instances) stay
+ * on the device.
+ *
+ * Errors.  Every call returns a gsr_status and never aborts; the context's
+ * last error message gives details.  One context is used by one host
+ * thread at a time.  A forward whose tile instances exceed the planned
+ * capacity sets a device flag, renders nothing useful, and gsr_poll then
+ * reports GSR_E_OVERFLOW with the needed capacity.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_MAX_VIEWS 64 /* views per forward/backward call */
+#define GSR_MAX_SETS 64  /* Gaussian sets (submaps) per call */
+
+typedef enum gsr_status {
+  GSR_OK = 0,
+  GSR_E_INVALID_ARG = 1,   /* null pointer, bad size, unsupported option */
+  GSR_E_NOT_PLANNED = 2,   /* forward/backward before gsr_plan */
+  GSR_E_CAPACITY = 3,      /* a host-known size exceeds the plan */
+  GSR_E_OVERFLOW = 4,      /* a device-side count exceeded the plan (gsr_poll) */
+  GSR_E_DEVICE = 5,        /* HIP error or no usable gfx950 device */
+  GSR_E_OOM = 6,           /* device allocation failed */
+  GSR_E_UNIMPLEMENTED = 7
+} gsr_status;
+
+typedef struct gsr_ctx gsr_ctx;
+
+/* Capacities.  All workspace is sized from these at gsr_plan time. */
+typedef struct gsr_plan_desc {
+  int64_t max_pairs;     /* >= sum over views of the size of the view's set */
+  int64_t max_instances; /* >= (Gaussian, tile) copies per forward call */
+  int32_t max_views;     /* 1..GSR_MAX_VIEWS */
+  int32_t width;         /* image size every call of this plan uses */
+  int32_t height;
+  int32_t tile_w;        /* tile shape: 8, 16 or 32 each, tile_w*tile_h in [64, 512] */
+  int32_t tile_h;
+  int32_t chunk;         /* depth-sorted pairs per binning chunk (0 = automatic) */
+} gsr_plan_desc;
+
+/* Gaussians, concatenated over sets; set s owns [set_offsets[s], set_offsets[s+1]). */
+typedef struct gsr_scene {
+  const float* means;          /* device [N,3] */
+  const float* log_scales;     /* device [N,3] */
+  const float* quats;          /* device [N,4] (w,x,y,z) */
+  const float* opacity_logits; /* device [N] */
+  const float* colors;         /* device [N,3] (sh_degree 0) or [N,sh_stride,3] */
+  const int64_t* set_offsets;  /* HOST [n_sets+1], non-decreasing, set_offsets[0] == 0 */
+  int32_t n_sets;              /* 1..GSR_MAX_SETS */
+  int32_t sh_degree;           /* 0 (raw RGB) or 1..3 */
+  int32_t sh_stride;           /* coefficient rows per Gaussian (>= (D+1)^2; ignored for D=0) */
+  int32_t reserved;
+} gsr_scene;
+
+typedef struct gsr_views {
+  const float* viewmats;     /* device [V,3,4] world->camera */
+  const float* intrinsics;   /* device [V,4] fx, fy, cx, cy (pixels) */
+  const int32_t* view_set;   /* HOST [V] set rendered by each view */
+  const uint8_t* needs_grad; /* HOST [V] or NULL (all 1): backward skips views with 0 */
+  int32_t n_views;           /* 1..max_views */
+  int32_t width;             /* must equal the plan's */
+  int32_t height;
+  int32_t reserved;
+} gsr_views;
+
+typedef struct gsr_settings {
+  float z_near; /* Gaussians with camera depth <= z_near are culled (default 0.2) */
+  float bg[3];  /* background colour composited with the final transmittance */
+} gsr_settings;
+
+typedef struct gsr_images {
+  float* color;      /* device [V,3,H,W] */
+  float* depth;      /* device [V,H,W] */
+  float* alpha;      /* device [V,H,W] */
+  int32_t* n_eval;   /* device [V,H,W] list entries examined per pixel, or NULL */
+} gsr_images;
+
+typedef struct gsr_grad_images {
+  const float* color; /* device [V,3,H,W] dL/dcolor, or NULL (= 0) */
+  const float* depth; /* device [V,H,W] dL/ddepth, or NULL */
+  const float* alpha; /* device [V,H,W] dL/dalpha, or NULL */
+} gsr_grad_images;
+
+/* Gradients are overwritten (not accumulated).  Gaussians of sets that no
+ * grad-needing view renders get zeros.  d_pose rows of views with
+ * needs_grad == 0 get zeros. */
+typedef struct gsr_grads {
+  float* d_means;          /* device [N,3] */
+  float* d_log_scales;     /* device [N,3] */
+  float* d_quats;          /* device [N,4] */
+  float* d_opacity_logits; /* device [N] */
+  float* d_colors;         /* device, same shape as colors */
+  float* d_pose;           /* device [V,6] (rho, phi) */
+} gsr_grads;
+
+typedef struct gsr_counts {
+  int64_t visible_pairs; /* pairs that survived culling, summed over views */
+  int64_t instances;     /* (Gaussian, tile) copies of the last forward */
+  int64_t capacity;      /* max_instances of the plan */
+  int32_t overflow;      /* 1 if instances > capacity */
+  int32_t n_views;
+} gsr_counts;
+
+/* Create a context on HIP device `device`.  GSR_E_DEVICE (with *out = NULL)
+ * when no such device exists or it is not gfx950. */
+gsr_status gsr_create(gsr_ctx** out, int device);
+void gsr_destroy(gsr_ctx* ctx);
+
+/* Allocate the context's workspace for the given capacities (replacing any
+ * previous plan).  Must not be called while work of this context is queued
+ * on a stream that has not finished. */
+gsr_status gsr_plan(gsr_ctx* ctx, const gsr_plan_desc* plan);
+
+/* Bytes of the per-forward saved-state buffer for this plan (host only;
+ * needs no device).  The buffer must be 256-byte aligned. */
+gsr_status gsr_state_bytes(const gsr_plan_desc* plan, size_t* out_bytes);
+
+/* Forward render of every view (Sec. III-A Eq. (map_loss) and Sec. III-C
+ * Eq. (refine_loss) consume its colour and depth).  Writes `out` and the
+ * saved state into `state`. */
+gsr_status gsr_forward(gsr_ctx* ctx, const gsr_scene* scene, const gsr_views* views,
+                       const gsr_settings* settings, void* state, const gsr_images* out,
+                       void* stream);
+
+/* Backward of the forward that wrote `state` (same scene, views, settings,
+ * unchanged device contents). */
+gsr_status gsr_backward(gsr_ctx* ctx, const gsr_scene* scene, const gsr_views* views,
+                        const gsr_settings* settings, const void* state,
+                        const gsr_grad_images* grad_in, const gsr_grads* out, void* stream);
+
+/* Synchronise `stream` and read the device counters of the forward that
+ * wrote `state`.  Returns GSR_E_OVERFLOW if its instances exceeded the plan. */
+gsr_status gsr_poll(gsr_ctx* ctx, const void* state, gsr_counts* out, void* stream);
+
+/* Test/debug export of a forward's binning (synchronises `stream`).  Host
+ * buffers, each may be NULL:
+ *   zkeys   uint32 [P]  FP32 bits of camera depth per pair, 0xFFFFFFFF = culled
+ *   rects   uint16 [P,4] tile rect x0,y0,x1,y1 (zeros when culled)
+ *   order   uint32 [P]  pair ids of each view's visible pairs in (depth, id)
+ *                       order, views concatenated
+ *   vis_off int64 [V+1] offsets of each view's part of `order`
+ *   inst    uint32 [I]  pair id of every tile instance, tile-major, depth order
+ *   ranges  uint32 [V*TX*TY,2] [first, last+1) per tile, (0,0) when empty
+ *   t_final float [V,H,W], last uint32 [V,H,W] (last blended list position + 1)
+ * P is the call's pair count (sum of set sizes over views); I from gsr_poll. */
+typedef struct gsr_debug {
+  uint32_t* zkeys;
+  uint16_t* rects;
+  uint32_t* order;
+  int64_t* vis_off;
+  uint32_t* inst;
+  uint32_t* ranges;
+  float* t_final;
+  uint32_t* last;
+  int64_t n_pairs;     /* in: capacity of zkeys/rects/order (elements) */
+  int64_t n_inst;      /* in: capacity of inst (elements) */
+} gsr_debug;
+gsr_status gsr_debug_export(gsr_ctx* ctx, const void* state, int32_t n_views,
+                            gsr_debug* dbg, void* stream);
+
+/* viewmats_out[v] = Exp(delta[v]) * viewmats_in[v] for v < n_views (the
+ * per-keyframe pose delta of Sec. III-C); in-place allowed.  Device arrays
+ * [V,3,4], [V,6], [V,3,4]. */
+gsr_status gsr_apply_pose_delta(const float* viewmats_in, const float* delta,
+                                float* viewmats_out, int32_t n_views, void* stream);
+
+/* Time forward+backward of the given call for each candidate tile shape and
+ * report the fastest (tile_w, tile_h) in `best` (other fields copied from
+ * `base`).  Synchronises; allocates its own temporary context. */
+gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* scene,
+                        const gsr_views* views, const gsr_settings* settings,
+                        gsr_plan_desc* best, float* best_ms, void* stream);
+
+const char* gsr_status_string(gsr_status s);
+const char* gsr_last_error(const gsr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSR_H */

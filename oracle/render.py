@@ -64,9 +64,11 @@ def bin_view(setup, k, st: Settings, width, height):
 
 
 def render_view(scene, views, k, st: Settings = Settings(), mode="tiled",
-                keep=False):
+                keep=False, tiles=None):
     """Render view k.  mode 'tiled' walks per-tile sorted lists; 'brute'
-    walks all kept Gaussians in (depth bits, index) order per pixel."""
+    walks all kept Gaussians in (depth bits, index) order per pixel.
+    `tiles` (tiled mode) restricts compositing to those tile indices; the
+    other pixels are left at colour 0, alpha 0, T 1."""
     W, H = views.width, views.height
     su = setup_view(scene, views, k, st)
     rec, bg = su["rec"], np.asarray(st.bg, float)
@@ -83,7 +85,7 @@ def render_view(scene, views, k, st: Settings = Settings(), mode="tiled",
         keys, vals, rng = bin_view(su, k, st, W, H)
         out.update(keys=keys, vals=vals, ranges=rng)
         TX, TY = su["kp"]["TX"], su["kp"]["TY"]
-        for t in range(TX * TY):
+        for t in (range(TX * TY) if tiles is None else tiles):
             tx, ty = t % TX, t // TX
             x0, y0 = tx * st.tile_w, ty * st.tile_h
             xx, yy, sx, sy = pixel_grid(x0, y0, min(x0 + st.tile_w, W),
@@ -196,7 +198,13 @@ def render_backward(scene, views, grad_color, grad_depth, grad_alpha,
         gC = np.zeros((3, H, W)) if grad_color is None else np.asarray(grad_color[k], float)
         gD = np.zeros((H, W)) if grad_depth is None else np.asarray(grad_depth[k], float)
         gA = np.zeros((H, W)) if grad_alpha is None else np.asarray(grad_alpha[k], float)
-        rv = render_view(scene, views, k, st, mode="tiled", keep=True)
+        # tiles whose pixels all have zero upstream gradient contribute nothing
+        live = np.abs(gC).sum(0) + np.abs(gD) + np.abs(gA) > 0
+        TX, TY = -(-W // st.tile_w), -(-H // st.tile_h)
+        tiles = [t for t in range(TX * TY)
+                 if live[(t // TX) * st.tile_h:(t // TX + 1) * st.tile_h,
+                         (t % TX) * st.tile_w:(t % TX + 1) * st.tile_w].any()]
+        rv = render_view(scene, views, k, st, mode="tiled", keep=True, tiles=tiles)
         su = rv["setup"]
         nv = su["vis"].shape[0]
         acc = dict(u=np.zeros(nv), v=np.zeros(nv), A=np.zeros(nv), B=np.zeros(nv),

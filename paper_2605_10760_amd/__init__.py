@@ -1,0 +1,8 @@
+"""MI355X (gfx950) differentiable 3D Gaussian-splatting rasterizer.
+
+The hot path is HIP kernels behind the C ABI in include/gsr.h (libgsr.so);
+this package only marshals PyTorch tensors into those calls.
+"""
+from ._lib import GsrError, load  # noqa: F401
+from .rasterizer import (Rasterizer, SceneTensors, ViewTensors, apply_pose_delta,  # noqa: F401
+                         pairs_of, rasterize)

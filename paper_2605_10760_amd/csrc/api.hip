@@ -1,0 +1,511 @@
+// The C ABI: context, planning, argument checking and the launch sequences
+// of the forward and backward passes.
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace gsr;
+
+struct gsr_ctx {
+  int device = 0;
+  std::string err;
+  bool planned = false;
+  gsr_plan_desc plan{};
+  int chunk = 0;
+  int TX = 0, TY = 0, T = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t* blk_cnt = nullptr;
+  uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
+  uint32_t* hist = nullptr;
+  uint32_t* counts = nullptr;
+  uint32_t* tile_cnt = nullptr;
+  float* grad2d = nullptr;
+  size_t max_blocks = 0, max_sblocks = 0, max_chunks = 0;
+};
+
+namespace {
+
+gsr_status fail(gsr_ctx* c, gsr_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+gsr_status hip_fail(gsr_ctx* c, hipError_t e, const char* what) {
+  return fail(c, GSR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+bool pow2_tile(int x) { return x == 8 || x == 16 || x == 32; }
+
+int auto_chunk(const gsr_plan_desc& p) {
+  if (p.chunk > 0) return p.chunk;
+  // ~64+ chunks per view for parallelism, chunk >= 256 so the per-chunk
+  // dense tile pass stays small relative to the chunk's pairs.
+  long per_view = std::max<long>(1, p.max_pairs / std::max(1, p.max_views));
+  long c = 256;
+  while (c < 4096 && per_view / c > 256) c *= 2;
+  return (int)c;
+}
+
+// RAII guard that makes ctx->device current and restores the caller's.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+namespace gsr {
+
+StateLayout state_layout(const gsr_plan_desc& p) {
+  StateLayout L{};
+  const int TX = (p.width + p.tile_w - 1) / p.tile_w, TY = (p.height + p.tile_h - 1) / p.tile_h;
+  const size_t P = (size_t)p.max_pairs, V = (size_t)p.max_views;
+  const size_t px = V * (size_t)p.width * (size_t)p.height;
+  size_t o = 0;
+  L.hdr = o; o = align256(o + STATE_HEADER_BYTES);
+  L.zkey = o; o = align256(o + P * 4);
+  L.rect = o; o = align256(o + P * 8);
+  L.rec = o; o = align256(o + P * 48);
+  L.order = o; o = align256(o + P * 4);
+  L.ranges = o; o = align256(o + V * (size_t)TX * TY * 8);
+  L.inst = o; o = align256(o + (size_t)p.max_instances * 4);
+  L.tfinal = o; o = align256(o + px * 4);
+  L.last = o; o = align256(o + px * 4);
+  L.total = o;
+  return L;
+}
+
+StateDev state_ptrs(void* base, const gsr_plan_desc& p) {
+  const StateLayout L = state_layout(p);
+  char* b = (char*)base;
+  StateDev s;
+  s.hdr = (StateHeader*)(b + L.hdr);
+  s.zkey = (uint32_t*)(b + L.zkey);
+  s.rect = (uint2*)(b + L.rect);
+  s.rec = (float4*)(b + L.rec);
+  s.order = (uint32_t*)(b + L.order);
+  s.ranges = (uint2*)(b + L.ranges);
+  s.inst = (uint32_t*)(b + L.inst);
+  s.tfinal = (float*)(b + L.tfinal);
+  s.last = (uint32_t*)(b + L.last);
+  s.cap = (unsigned long long)p.max_instances;
+  return s;
+}
+
+}  // namespace gsr
+
+namespace {
+
+gsr_status check_plan(gsr_ctx* c, const gsr_plan_desc* p) {
+  if (!p) return fail(c, GSR_E_INVALID_ARG, "plan is NULL");
+  if (p->max_pairs < 1 || p->max_pairs > 0x7FFFFFFFL)
+    return fail(c, GSR_E_INVALID_ARG, "max_pairs must be in [1, 2^31-1]");
+  if (p->max_instances < 1 || p->max_instances > 0xFFFFFFFEL)
+    return fail(c, GSR_E_INVALID_ARG, "max_instances must be in [1, 2^32-2]");
+  if (p->max_views < 1 || p->max_views > GSR_MAX_VIEWS)
+    return fail(c, GSR_E_INVALID_ARG, "max_views must be in [1, %d]", GSR_MAX_VIEWS);
+  if (p->width < 1 || p->height < 1 || p->width > 16384 || p->height > 16384)
+    return fail(c, GSR_E_INVALID_ARG, "image size must be in [1, 16384]");
+  if (!pow2_tile(p->tile_w) || !pow2_tile(p->tile_h) || p->tile_w * p->tile_h < 64 ||
+      p->tile_w * p->tile_h > 512 || (p->tile_w == 32 && p->tile_h == 32) ||
+      (p->tile_w == 8 && p->tile_h == 32))
+    return fail(c, GSR_E_INVALID_ARG,
+                "tile shape must be one of 8x8, 16x8, 8x16, 16x16, 32x8, 32x16, 16x32");
+  const long TX = (p->width + p->tile_w - 1) / p->tile_w, TY = (p->height + p->tile_h - 1) / p->tile_h;
+  if ((TX + 1) * (TY + 1) * 4 > 60 * 1024)
+    return fail(c, GSR_E_INVALID_ARG, "too many tiles per view (%ld x %ld)", TX, TY);
+  if (p->chunk < 0) return fail(c, GSR_E_INVALID_ARG, "chunk must be >= 0");
+  return GSR_OK;
+}
+
+struct CallTabs {
+  ProjTab pt;
+  SortTab stb;
+  BinTab bt;
+  SetTab set;
+  int P = 0;
+  unsigned long long grad_mask = 0;
+};
+
+gsr_status build_tabs(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw, CallTabs& t) {
+  if (!sc || !vw) return fail(c, GSR_E_INVALID_ARG, "scene/views is NULL");
+  if (!sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits || !sc->colors ||
+      !sc->set_offsets)
+    return fail(c, GSR_E_INVALID_ARG, "scene array is NULL");
+  if (sc->n_sets < 1 || sc->n_sets > GSR_MAX_SETS)
+    return fail(c, GSR_E_INVALID_ARG, "n_sets must be in [1, %d]", GSR_MAX_SETS);
+  if (sc->sh_degree < 0 || sc->sh_degree > 3)
+    return fail(c, GSR_E_INVALID_ARG, "sh_degree must be 0..3");
+  if (sc->sh_degree > 0 && sc->sh_stride < (sc->sh_degree + 1) * (sc->sh_degree + 1))
+    return fail(c, GSR_E_INVALID_ARG, "sh_stride too small for sh_degree");
+  if (!vw->viewmats || !vw->intrinsics || !vw->view_set)
+    return fail(c, GSR_E_INVALID_ARG, "views array is NULL");
+  const gsr_plan_desc& p = c->plan;
+  if (vw->n_views < 1 || vw->n_views > p.max_views)
+    return fail(c, GSR_E_CAPACITY, "n_views %d outside [1, %d]", vw->n_views, p.max_views);
+  if (vw->width != p.width || vw->height != p.height)
+    return fail(c, GSR_E_INVALID_ARG, "image size %dx%d differs from the plan's %dx%d", vw->width,
+                vw->height, p.width, p.height);
+  if (sc->set_offsets[0] != 0) return fail(c, GSR_E_INVALID_ARG, "set_offsets[0] must be 0");
+  for (int s = 0; s < sc->n_sets; ++s)
+    if (sc->set_offsets[s + 1] < sc->set_offsets[s])
+      return fail(c, GSR_E_INVALID_ARG, "set_offsets must be non-decreasing");
+  if (sc->set_offsets[sc->n_sets] > 0x7FFFFFFFL)
+    return fail(c, GSR_E_INVALID_ARG, "too many Gaussians");
+  const int nv = vw->n_views;
+  memset(&t.pt, 0, sizeof t.pt);
+  memset(&t.stb, 0, sizeof t.stb);
+  memset(&t.bt, 0, sizeof t.bt);
+  memset(&t.set, 0, sizeof t.set);
+  long P = 0;
+  t.pt.nv = nv;
+  t.pt.W = p.width; t.pt.H = p.height; t.pt.TW = p.tile_w; t.pt.TH = p.tile_h;
+  t.pt.TX = c->TX; t.pt.TY = c->TY;
+  t.stb.nv = nv;
+  t.bt.nv = nv; t.bt.chunk = c->chunk; t.bt.TX = c->TX; t.bt.TY = c->TY; t.bt.T = c->T;
+  int blk = 0, sblk = 0, cblk = 0;
+  t.grad_mask = 0;
+  for (int v = 0; v < nv; ++v) {
+    const int s = vw->view_set[v];
+    if (s < 0 || s >= sc->n_sets) return fail(c, GSR_E_INVALID_ARG, "view_set[%d] = %d out of range", v, s);
+    const long n = sc->set_offsets[s + 1] - sc->set_offsets[s];
+    t.pt.pair_off[v] = (int)P;
+    t.pt.blk_off[v] = blk;
+    t.pt.g_off[v] = (int)sc->set_offsets[s];
+    t.stb.sblk_off[v] = sblk;
+    t.bt.cblk_off[v] = cblk;
+    P += n;
+    if (P > p.max_pairs)
+      return fail(c, GSR_E_CAPACITY, "pairs exceed plan max_pairs %lld", (long long)p.max_pairs);
+    blk += ceil_div(n, PROJ_BLOCK);
+    sblk += ceil_div(n, SORT_TILE);
+    cblk += ceil_div(n, c->chunk);
+    if (!vw->needs_grad || vw->needs_grad[v]) t.grad_mask |= 1ull << v;
+  }
+  t.pt.pair_off[nv] = (int)P;
+  t.pt.blk_off[nv] = blk;
+  t.stb.sblk_off[nv] = sblk;
+  t.bt.cblk_off[nv] = cblk;
+  t.pt.P = (int)P;
+  t.P = (int)P;
+  if ((size_t)blk > c->max_blocks || (size_t)sblk > c->max_sblocks || (size_t)cblk > c->max_chunks)
+    return fail(c, GSR_E_CAPACITY, "block tables exceed the plan");
+  // sets, for the projection backward
+  SetTab& st = t.set;
+  st.ns = sc->n_sets;
+  st.W = p.width; st.H = p.height;
+  int sb = 0, nvs = 0;
+  for (int s = 0; s < sc->n_sets; ++s) {
+    st.set_goff[s] = (int)sc->set_offsets[s];
+    st.set_blk[s] = sb;
+    sb += ceil_div(sc->set_offsets[s + 1] - sc->set_offsets[s], PROJ_BLOCK);
+    st.set_voff[s] = nvs;
+    for (int v = 0; v < nv; ++v)
+      if (vw->view_set[v] == s && ((t.grad_mask >> v) & 1ull)) st.view_by_set[nvs++] = v;
+  }
+  st.set_goff[sc->n_sets] = (int)sc->set_offsets[sc->n_sets];
+  st.set_blk[sc->n_sets] = sb;
+  st.set_voff[sc->n_sets] = nvs;
+  for (int v = 0; v <= nv; ++v) st.pair_off[v] = t.pt.pair_off[v];
+  return GSR_OK;
+}
+
+SceneDev scene_dev(const gsr_scene* sc) {
+  SceneDev d;
+  d.means = sc->means;
+  d.log_scales = sc->log_scales;
+  d.quats = sc->quats;
+  d.opac = sc->opacity_logits;
+  d.colors = sc->colors;
+  d.sh_degree = sc->sh_degree;
+  d.sh_stride = sc->sh_degree > 0 ? sc->sh_stride : 1;
+  return d;
+}
+
+CamDev cam_dev(const gsr_views* vw, const gsr_settings* s) {
+  CamDev c;
+  c.viewmats = vw->viewmats;
+  c.intrinsics = vw->intrinsics;
+  c.z_near = s ? s->z_near : 0.2f;
+  c.bg0 = s ? s->bg[0] : 0.f;
+  c.bg1 = s ? s->bg[1] : 0.f;
+  c.bg2 = s ? s->bg[2] : 0.f;
+  return c;
+}
+
+void free_ws(gsr_ctx* c) {
+  if (c->ws) (void)hipFree(c->ws);
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  c->planned = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gsr_status_string(gsr_status s) {
+  switch (s) {
+    case GSR_OK: return "ok";
+    case GSR_E_INVALID_ARG: return "invalid argument";
+    case GSR_E_NOT_PLANNED: return "not planned";
+    case GSR_E_CAPACITY: return "capacity exceeded";
+    case GSR_E_OVERFLOW: return "instance overflow";
+    case GSR_E_DEVICE: return "device error";
+    case GSR_E_OOM: return "out of device memory";
+    case GSR_E_UNIMPLEMENTED: return "unimplemented";
+  }
+  return "unknown status";
+}
+
+const char* gsr_last_error(const gsr_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+gsr_status gsr_create(gsr_ctx** out, int device) {
+  if (!out) return GSR_E_INVALID_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return GSR_E_DEVICE;
+  }
+  if (device < 0 || device >= n) return GSR_E_DEVICE;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return GSR_E_DEVICE;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return GSR_E_DEVICE;
+  gsr_ctx* c = new (std::nothrow) gsr_ctx();
+  if (!c) return GSR_E_OOM;
+  c->device = device;
+  *out = c;
+  return GSR_OK;
+}
+
+void gsr_destroy(gsr_ctx* c) {
+  if (!c) return;
+  {
+    DeviceGuard g(c->device);
+    free_ws(c);
+  }
+  delete c;
+}
+
+gsr_status gsr_state_bytes(const gsr_plan_desc* p, size_t* out) {
+  if (!out) return GSR_E_INVALID_ARG;
+  gsr_status s = check_plan(nullptr, p);
+  if (s != GSR_OK) return s;
+  *out = state_layout(*p).total;
+  return GSR_OK;
+}
+
+gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
+  if (!c) return GSR_E_INVALID_ARG;
+  gsr_status s = check_plan(c, p);
+  if (s != GSR_OK) return s;
+  DeviceGuard g(c->device);
+  free_ws(c);
+  c->plan = *p;
+  c->chunk = auto_chunk(*p);
+  c->TX = (p->width + p->tile_w - 1) / p->tile_w;
+  c->TY = (p->height + p->tile_h - 1) / p->tile_h;
+  c->T = c->TX * c->TY;
+  const size_t P = (size_t)p->max_pairs, V = (size_t)p->max_views;
+  c->max_blocks = P / PROJ_BLOCK + V + 1;
+  c->max_sblocks = P / SORT_TILE + V + 1;
+  c->max_chunks = P / (size_t)c->chunk + V + 1;
+  size_t o = 0;
+  const size_t o_blk = o; o = align256(o + c->max_blocks * 4);
+  const size_t o_ka = o; o = align256(o + P * 4);
+  const size_t o_va = o; o = align256(o + P * 4);
+  const size_t o_kb = o; o = align256(o + P * 4);
+  const size_t o_vb = o; o = align256(o + P * 4);
+  const size_t o_hist = o; o = align256(o + c->max_sblocks * RADIX * 4);
+  const size_t o_cnt = o; o = align256(o + c->max_chunks * (size_t)c->T * 4);
+  const size_t o_tc = o; o = align256(o + V * (size_t)c->T * 4);
+  const size_t o_g2 = o; o = align256(o + P * GRAD2D * 4);
+  void* ws = nullptr;
+  hipError_t e = hipMalloc(&ws, o);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, GSR_E_OOM, "workspace of %zu bytes: %s", o, hipGetErrorString(e));
+  }
+  char* b = (char*)ws;
+  c->ws = ws;
+  c->ws_bytes = o;
+  c->blk_cnt = (uint32_t*)(b + o_blk);
+  c->ka = (uint32_t*)(b + o_ka);
+  c->va = (uint32_t*)(b + o_va);
+  c->kb = (uint32_t*)(b + o_kb);
+  c->vb = (uint32_t*)(b + o_vb);
+  c->hist = (uint32_t*)(b + o_hist);
+  c->counts = (uint32_t*)(b + o_cnt);
+  c->tile_cnt = (uint32_t*)(b + o_tc);
+  c->grad2d = (float*)(b + o_g2);
+  c->planned = true;
+  return GSR_OK;
+}
+
+gsr_status gsr_forward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
+                       const gsr_settings* set, void* state, const gsr_images* out,
+                       void* stream) {
+  if (!c) return GSR_E_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_E_NOT_PLANNED, "gsr_plan first");
+  if (!state || ((uintptr_t)state & 255)) return fail(c, GSR_E_INVALID_ARG, "state must be non-NULL and 256-byte aligned");
+  if (!out || !out->color || !out->depth || !out->alpha)
+    return fail(c, GSR_E_INVALID_ARG, "output image is NULL");
+  CallTabs t;
+  gsr_status s = build_tabs(c, sc, vw, t);
+  if (s != GSR_OK) return s;
+  DeviceGuard g(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  StateDev sd = state_ptrs(state, c->plan);
+  const SceneDev scd = scene_dev(sc);
+  const CamDev cam = cam_dev(vw, set);
+  hipError_t e;
+  if ((e = launch_project(t.pt, scd, cam, sd, c->blk_cnt, st)) != hipSuccess) return hip_fail(c, e, "project");
+  if ((e = launch_compact(t.pt, sd, c->blk_cnt, c->ka, c->va, st)) != hipSuccess) return hip_fail(c, e, "compact");
+  if ((e = launch_depth_sort(t.stb, sd, c->ka, c->va, c->kb, c->vb, c->hist, st)) != hipSuccess)
+    return hip_fail(c, e, "depth sort");
+  if ((e = launch_binning(t.bt, sd, c->counts, c->tile_cnt, st)) != hipSuccess) return hip_fail(c, e, "binning");
+  if ((e = launch_render_fwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
+                             c->plan.tile_h, c->TX, c->TY, cam, sd, out->color, out->depth,
+                             out->alpha, out->n_eval, st)) != hipSuccess)
+    return hip_fail(c, e, "render forward");
+  return GSR_OK;
+}
+
+gsr_status gsr_backward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
+                        const gsr_settings* set, const void* state, const gsr_grad_images* gin,
+                        const gsr_grads* out, void* stream) {
+  if (!c) return GSR_E_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_E_NOT_PLANNED, "gsr_plan first");
+  if (!state || ((uintptr_t)state & 255)) return fail(c, GSR_E_INVALID_ARG, "state must be non-NULL and 256-byte aligned");
+  if (!out || !out->d_means || !out->d_log_scales || !out->d_quats || !out->d_opacity_logits ||
+      !out->d_colors || !out->d_pose)
+    return fail(c, GSR_E_INVALID_ARG, "gradient output is NULL");
+  CallTabs t;
+  gsr_status s = build_tabs(c, sc, vw, t);
+  if (s != GSR_OK) return s;
+  DeviceGuard g(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  StateDev sd = state_ptrs(const_cast<void*>(state), c->plan);
+  const SceneDev scd = scene_dev(sc);
+  const CamDev cam = cam_dev(vw, set);
+  const float* gc = gin ? gin->color : nullptr;
+  const float* gd = gin ? gin->depth : nullptr;
+  const float* ga = gin ? gin->alpha : nullptr;
+  hipError_t e;
+  if ((e = launch_zero_grad2d(t.P, sd, c->grad2d, out->d_pose, vw->n_views, st)) != hipSuccess)
+    return hip_fail(c, e, "zero");
+  if ((e = launch_render_bwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
+                             c->plan.tile_h, c->TX, c->TY, t.grad_mask, cam, sd, gc, gd, ga,
+                             c->grad2d, st)) != hipSuccess)
+    return hip_fail(c, e, "render backward");
+  if ((e = launch_project_bwd(t.set, scd, cam, sd, c->grad2d, *out, t.P, st)) != hipSuccess)
+    return hip_fail(c, e, "projection backward");
+  return GSR_OK;
+}
+
+gsr_status gsr_poll(gsr_ctx* c, const void* state, gsr_counts* out, void* stream) {
+  if (!c || !state || !out) return GSR_E_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_E_NOT_PLANNED, "gsr_plan first");
+  DeviceGuard g(c->device);
+  StateHeader h;
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e == hipSuccess) e = hipMemcpy(&h, state, sizeof h, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "poll");
+  out->visible_pairs = h.vis_total;
+  out->instances = (int64_t)h.inst_total;
+  out->capacity = c->plan.max_instances;
+  out->overflow = (int32_t)h.overflow;
+  out->n_views = 0;
+  if (h.overflow)
+    return fail(c, GSR_E_OVERFLOW, "forward needed %llu instances, plan holds %lld",
+                (unsigned long long)h.inst_total, (long long)c->plan.max_instances);
+  return GSR_OK;
+}
+
+gsr_status gsr_debug_export(gsr_ctx* c, const void* state, int32_t n_views, gsr_debug* d,
+                            void* stream) {
+  if (!c || !state || !d) return GSR_E_INVALID_ARG;
+  if (!c->planned) return fail(c, GSR_E_NOT_PLANNED, "gsr_plan first");
+  if (n_views < 1 || n_views > c->plan.max_views) return fail(c, GSR_E_INVALID_ARG, "n_views");
+  DeviceGuard g(c->device);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "debug sync");
+  StateDev sd = state_ptrs(const_cast<void*>(state), c->plan);
+  StateHeader h;
+  if ((e = hipMemcpy(&h, sd.hdr, sizeof h, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug hdr");
+  const size_t np = (size_t)std::max<int64_t>(0, std::min<int64_t>(d->n_pairs, c->plan.max_pairs));
+  const size_t px = (size_t)n_views * c->plan.width * c->plan.height;
+  struct Cp { void* dst; const void* src; size_t bytes; };
+  std::vector<Cp> cps;
+  if (d->zkeys) cps.push_back({d->zkeys, sd.zkey, np * 4});
+  if (d->order) cps.push_back({d->order, sd.order, std::min<size_t>(np, h.vis_total) * 4});
+  if (d->ranges) cps.push_back({d->ranges, sd.ranges, (size_t)n_views * c->T * 8});
+  if (d->inst) {
+    const size_t ni = (size_t)std::min<unsigned long long>(
+        std::min<unsigned long long>(h.inst_total, sd.cap), (unsigned long long)std::max<int64_t>(0, d->n_inst));
+    cps.push_back({d->inst, sd.inst, ni * 4});
+  }
+  if (d->t_final) cps.push_back({d->t_final, sd.tfinal, px * 4});
+  if (d->last) cps.push_back({d->last, sd.last, px * 4});
+  for (auto& x : cps)
+    if (x.bytes && (e = hipMemcpy(x.dst, x.src, x.bytes, hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(c, e, "debug copy");
+  if (d->rects && np) {
+    std::vector<uint2> r(np);
+    std::vector<uint32_t> z(np);
+    if ((e = hipMemcpy(r.data(), sd.rect, np * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug rect");
+    if ((e = hipMemcpy(z.data(), sd.zkey, np * 4, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug zkey");
+    for (size_t i = 0; i < np; ++i) {
+      const bool vis = z[i] != CULLED;
+      d->rects[4 * i + 0] = vis ? (uint16_t)(r[i].x & 0xFFFF) : 0;
+      d->rects[4 * i + 1] = vis ? (uint16_t)(r[i].x >> 16) : 0;
+      d->rects[4 * i + 2] = vis ? (uint16_t)(r[i].y & 0xFFFF) : 0;
+      d->rects[4 * i + 3] = vis ? (uint16_t)(r[i].y >> 16) : 0;
+    }
+  }
+  if (d->vis_off)
+    for (int v = 0; v <= n_views; ++v) d->vis_off[v] = h.vis_off[v];
+  return GSR_OK;
+}
+
+gsr_status gsr_apply_pose_delta(const float* vin, const float* delta, float* vout, int32_t nv,
+                                void* stream) {
+  if (!vin || !delta || !vout || nv < 1) return GSR_E_INVALID_ARG;
+  hipError_t e = launch_pose_delta(vin, delta, vout, nv, (hipStream_t)stream);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
+gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* sc,
+                        const gsr_views* vw, const gsr_settings* set, gsr_plan_desc* best,
+                        float* best_ms, void* stream) {
+  (void)device; (void)base; (void)sc; (void)vw; (void)set; (void)best; (void)best_ms; (void)stream;
+  return GSR_E_UNIMPLEMENTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal declarations shared by the HIP translation units of libgsr.
+// Host code builds small per-kernel tables of the call's structure (which
+// view renders which Gaussian set, block offsets); they travel as kernel
+// arguments so a launch needs no host-to-device copy and can be captured.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsr.h"
+
+namespace gsr {
+
+constexpr int MAXV = GSR_MAX_VIEWS;
+constexpr int MAXS = GSR_MAX_SETS;
+
+constexpr int PROJ_BLOCK = 256;   // pairs per projection / compaction block
+constexpr int SORT_THREADS = 256;
+constexpr int SORT_ITEMS = 8;
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;  // keys per radix-sort block
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int GRAD2D = 10;        // u, v, A, B, C, sigma, r, g, b, z
+constexpr uint32_t CULLED = 0xFFFFFFFFu;
+
+// Pair p of view v is Gaussian (set_goff[view_set[v]] + p - pair_off[v]).
+struct ProjTab {
+  int nv;
+  int P;                      // total pairs of the call
+  int W, H, TW, TH, TX, TY;
+  int pair_off[MAXV + 1];
+  int blk_off[MAXV + 1];      // PROJ_BLOCK-pair blocks per view, prefix
+  int g_off[MAXV];            // first global Gaussian of the view's set
+};
+
+struct SortTab {
+  int nv;
+  int sblk_off[MAXV + 1];     // SORT_TILE blocks per view, prefix (upper bound)
+};
+
+struct BinTab {
+  int nv;
+  int chunk;                  // pairs per chunk
+  int TX, TY, T;              // tiles per view = T
+  int cblk_off[MAXV + 1];     // chunks per view, prefix (upper bound)
+};
+
+struct SetTab {
+  int ns;
+  int set_goff[MAXS + 1];     // Gaussian offsets of the sets
+  int set_blk[MAXS + 1];      // PROJ_BLOCK-Gaussian blocks per set, prefix
+  int set_voff[MAXS + 1];     // views of each set in view_by_set
+  int view_by_set[MAXV];      // view ids grouped by set (grad-needing only)
+  int pair_off[MAXV + 1];
+  int W, H;
+};
+
+struct SceneDev {
+  const float* means;
+  const float* log_scales;
+  const float* quats;
+  const float* opac;
+  const float* colors;
+  int sh_degree;
+  int sh_stride;
+};
+
+struct CamDev {
+  const float* viewmats;    // [V,12]
+  const float* intrinsics;  // [V,4]
+  float z_near;
+  float bg0, bg1, bg2;
+};
+
+// Device header at the start of every saved-state buffer.
+struct StateHeader {
+  unsigned long long inst_total;  // sum of tile counts (may exceed capacity)
+  unsigned int overflow;
+  unsigned int vis_total;
+  unsigned int vis_off[MAXV + 1]; // visible-pair offsets per view (compacted order)
+};
+constexpr size_t STATE_HEADER_BYTES = 512;
+static_assert(sizeof(StateHeader) <= STATE_HEADER_BYTES, "header");
+
+// Byte offsets of the arrays inside a saved-state buffer (all 256-aligned).
+struct StateLayout {
+  size_t hdr, zkey, rect, rec, order, ranges, inst, tfinal, last, total;
+};
+
+// Pointers into a saved-state buffer.
+struct StateDev {
+  StateHeader* hdr;
+  uint32_t* zkey;     // [P]
+  uint2* rect;        // [P] packed (x0 | y0 << 16, x1 | y1 << 16)
+  float4* rec;        // [P][3]: (u, v, A, B), (C, sigma, z, -), (r, g, b, -)
+  uint32_t* order;    // [P] pair ids in (view, depth, id) order
+  uint2* ranges;      // [V*T]
+  uint32_t* inst;     // [cap]
+  float* tfinal;      // [V*H*W]
+  uint32_t* last;     // [V*H*W]
+  unsigned long long cap;
+};
+
+StateLayout state_layout(const gsr_plan_desc& p);
+StateDev state_ptrs(void* base, const gsr_plan_desc& p);
+
+// ------------------------------------------------------------------ launches
+hipError_t launch_project(const ProjTab& t, const SceneDev& sc, const CamDev& cam,
+                          StateDev st, uint32_t* blk_cnt, hipStream_t s);
+hipError_t launch_compact(const ProjTab& t, StateDev st, uint32_t* blk_cnt,
+                          uint32_t* keys_out, uint32_t* vals_out, hipStream_t s);
+hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
+                             uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s);
+hipError_t launch_binning(const BinTab& t, StateDev st, uint32_t* counts, uint32_t* tile_cnt,
+                          hipStream_t s);
+hipError_t launch_render_fwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
+                             const CamDev& cam, StateDev st, float* color, float* depth,
+                             float* alpha, int32_t* n_eval, hipStream_t s);
+hipError_t launch_render_bwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
+                             unsigned long long grad_mask, const CamDev& cam, StateDev st,
+                             const float* g_color, const float* g_depth, const float* g_alpha,
+                             float* grad2d, hipStream_t s);
+hipError_t launch_zero_grad2d(int P, StateDev st, float* grad2d, float* d_pose, int nv,
+                              hipStream_t s);
+hipError_t launch_project_bwd(const SetTab& t, const SceneDev& sc, const CamDev& cam,
+                              StateDev st, const float* grad2d, const gsr_grads& g,
+                              int n_total, hipStream_t s);
+hipError_t launch_pose_delta(const float* vin, const float* delta, float* vout, int nv,
+                             hipStream_t s);
+
+}  // namespace gsr

@@ -1,0 +1,383 @@
+// Projection of (view, Gaussian) pairs, visible-pair compaction and the
+// pose-delta update.
+//
+// One thread per pair.  Each thread evaluates the key path in FP32 with no
+// fused multiply-add and a fixed operation order (it decides culling, the
+// tile rectangle and the depth key and must match an FP32 re-evaluation bit
+// for bit), then, for visible pairs, the screen-space record in FP64 rounded
+// once to FP32 (the 2D conic of an elongated splat loses digits to
+// cancellation in FP32).  Reads are coalesced AoS rows of the FP32 parameter
+// arrays; writes are one 48-byte record, one 8-byte rect and one 4-byte key
+// per pair, and one visible count per 256-pair block for the ordered
+// compaction that follows.
+#include "common.h"
+
+namespace gsr {
+
+// Real spherical harmonic normalisation constants (Condon-Shortley phase):
+// 1/(2 sqrt(pi)), sqrt(3/(4 pi)), sqrt(15/pi)/2, sqrt(5/pi)/4, sqrt(15/pi)/4,
+// sqrt(35/(2 pi))/4, sqrt(105/pi)/2, sqrt(21/(2 pi))/4, sqrt(7/pi)/4,
+// sqrt(105/pi)/4.
+#define SHK0 0.28209479177387814f
+#define SHK1 0.4886025119029199f
+#define SHK2A 1.0925484305920792f
+#define SHK2B 0.31539156525252005f
+#define SHK2C 0.5462742152960396f
+#define SHK3A 0.5900435899266435f
+#define SHK3B 2.890611442640554f
+#define SHK3C 0.4570457994644658f
+#define SHK3D 0.3731763325901154f
+#define SHK3E 1.445305721320277f
+
+// Basis values Y[k], k < (D+1)^2, at a unit direction.
+template <int D>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
+  Y[0] = SHK0;
+  if (D >= 1) { Y[1] = -SHK1 * y; Y[2] = SHK1 * z; Y[3] = -SHK1 * x; }
+  if (D >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = SHK2A * x * y; Y[5] = -SHK2A * y * z; Y[6] = SHK2B * (2.f * zz - xx - yy);
+    Y[7] = -SHK2A * x * z; Y[8] = SHK2C * (xx - yy);
+    if (D >= 3) {
+      Y[9] = -SHK3A * y * (3.f * xx - yy);
+      Y[10] = SHK3B * x * y * z;
+      Y[11] = -SHK3C * y * (4.f * zz - xx - yy);
+      Y[12] = SHK3D * z * (2.f * zz - 3.f * xx - 3.f * yy);
+      Y[13] = -SHK3C * x * (4.f * zz - xx - yy);
+      Y[14] = SHK3E * z * (xx - yy);
+      Y[15] = -SHK3A * x * (xx - 3.f * yy);
+    }
+  }
+}
+
+struct KeyResult {
+  float p2;
+  uint32_t x0, y0, x1, y1;
+};
+
+// The FP32 key path.  Every +, -, *, / and sqrt is one IEEE FP32 operation
+// in the order written (contraction disabled); exp and log run in FP64 on
+// the FP32 inputs and are rounded once.  Returns false when culled.
+__device__ __forceinline__ bool key_path(const float* m, const float* ls, const float* q, float o,
+                                      const float* Rc, const float* tc, float fx, float fy,
+                                      float cx, float cy, int W, int H, int TW, int TH,
+                                      int TX, int TY, float z_near, KeyResult& kr) {
+#pragma clang fp contract(off)
+  const float p0 = ((Rc[0] * m[0] + Rc[1] * m[1]) + Rc[2] * m[2]) + tc[0];
+  const float p1 = ((Rc[3] * m[0] + Rc[4] * m[1]) + Rc[5] * m[2]) + tc[1];
+  const float p2 = ((Rc[6] * m[0] + Rc[7] * m[1]) + Rc[8] * m[2]) + tc[2];
+  if (!(p2 > z_near)) return false;
+  const float s0 = (float)exp((double)ls[0]);
+  const float s1 = (float)exp((double)ls[1]);
+  const float s2 = (float)exp((double)ls[2]);
+  const float qn = sqrtf(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
+  if (!(qn > 0.f)) return false;
+  const float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float xy = x * y, xz = x * z, yz = y * z;
+  const float wx = w * x, wy = w * y, wz = w * z;
+  const float R00 = 1.f - 2.f * (yy + zz), R01 = 2.f * (xy - wz), R02 = 2.f * (xz + wy);
+  const float R10 = 2.f * (xy + wz), R11 = 1.f - 2.f * (xx + zz), R12 = 2.f * (yz - wx);
+  const float R20 = 2.f * (xz - wy), R21 = 2.f * (yz + wx), R22 = 1.f - 2.f * (xx + yy);
+  const float M00 = R00 * s0, M01 = R01 * s1, M02 = R02 * s2;
+  const float M10 = R10 * s0, M11 = R11 * s1, M12 = R12 * s2;
+  const float M20 = R20 * s0, M21 = R21 * s1, M22 = R22 * s2;
+  float S[3][3];
+  S[0][0] = (M00 * M00 + M01 * M01) + M02 * M02;
+  S[0][1] = (M00 * M10 + M01 * M11) + M02 * M12;
+  S[0][2] = (M00 * M20 + M01 * M21) + M02 * M22;
+  S[1][1] = (M10 * M10 + M11 * M11) + M12 * M12;
+  S[1][2] = (M10 * M20 + M11 * M21) + M12 * M22;
+  S[2][2] = (M20 * M20 + M21 * M21) + M22 * M22;
+  S[1][0] = S[0][1]; S[2][0] = S[0][2]; S[2][1] = S[1][2];
+  float Wm[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      Wm[i][k] = (Rc[3 * i] * S[0][k] + Rc[3 * i + 1] * S[1][k]) + Rc[3 * i + 2] * S[2][k];
+  float V[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j)
+      V[i][j] = (Wm[i][0] * Rc[3 * j] + Wm[i][1] * Rc[3 * j + 1]) + Wm[i][2] * Rc[3 * j + 2];
+  const float rx = p0 / p2, ry = p1 / p2;
+  const float u = fx * rx + cx;
+  const float v = fy * ry + cy;
+  const float limx = 1.3f * ((0.5f * (float)W) / fx);
+  const float limy = 1.3f * ((0.5f * (float)H) / fy);
+  const float rxc = rx < -limx ? -limx : (rx > limx ? limx : rx);
+  const float ryc = ry < -limy ? -limy : (ry > limy ? limy : ry);
+  const float j00 = fx / p2, j02 = -(fx * rxc) / p2;
+  const float j11 = fy / p2, j12 = -(fy * ryc) / p2;
+  const float T00 = j00 * V[0][0] + j02 * V[0][2];
+  const float T01 = j00 * V[0][1] + j02 * V[1][2];
+  const float T02 = j00 * V[0][2] + j02 * V[2][2];
+  const float T11 = j11 * V[1][1] + j12 * V[1][2];
+  const float T12 = j11 * V[1][2] + j12 * V[2][2];
+  const float a = (T00 * j00 + T02 * j02) + 0.3f;
+  const float b = T01 * j11 + T02 * j12;
+  const float c = (T11 * j11 + T12 * j12) + 0.3f;
+  const float det = a * c - b * b;
+  if (!(det > 0.f)) return false;
+  const float sigma = (float)(1.0 / (1.0 + exp(-(double)o)));
+  const double t = 255.0 * (double)sigma;
+  if (!(t > 1.0)) return false;
+  const float k2 = (float)(2.0 * log(t));
+  const float ex = sqrtf(k2 * a);
+  const float ey = sqrtf(k2 * c);
+  if (!(isfinite(u) && isfinite(v) && isfinite(ex) && isfinite(ey))) return false;
+  const float itw = 1.0f / (float)TW, ith = 1.0f / (float)TH;
+  const float fX = (float)TX, fY = (float)TY;
+  float fx0 = floorf((u - ex) * itw);
+  float fx1 = floorf((u + ex) * itw) + 1.f;
+  float fy0 = floorf((v - ey) * ith);
+  float fy1 = floorf((v + ey) * ith) + 1.f;
+  fx0 = fx0 < 0.f ? 0.f : (fx0 > fX ? fX : fx0);
+  fx1 = fx1 < 0.f ? 0.f : (fx1 > fX ? fX : fx1);
+  fy0 = fy0 < 0.f ? 0.f : (fy0 > fY ? fY : fy0);
+  fy1 = fy1 < 0.f ? 0.f : (fy1 > fY ? fY : fy1);
+  kr.x0 = (uint32_t)fx0; kr.x1 = (uint32_t)fx1;
+  kr.y0 = (uint32_t)fy0; kr.y1 = (uint32_t)fy1;
+  if (kr.x1 <= kr.x0 || kr.y1 <= kr.y0) return false;
+  kr.p2 = p2;
+  return true;
+}
+
+template <int SHD>
+__global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, CamDev cam,
+                                                        StateDev st, uint32_t* blk_cnt) {
+  const int b = blockIdx.x;
+  const int v = find_seg(t.blk_off, t.nv, b);
+  const int local = (b - t.blk_off[v]) * PROJ_BLOCK + (int)threadIdx.x;
+  const int n = t.pair_off[v + 1] - t.pair_off[v];
+  bool vis = false;
+  if (local < n) {
+    const int pair = t.pair_off[v] + local;
+    const long gi = (long)t.g_off[v] + local;
+    const float* vm = cam.viewmats + 12 * v;
+    const float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
+    const float tc[3] = {vm[3], vm[7], vm[11]};
+    const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
+    const float m[3] = {sc.means[3 * gi], sc.means[3 * gi + 1], sc.means[3 * gi + 2]};
+    const float ls[3] = {sc.log_scales[3 * gi], sc.log_scales[3 * gi + 1],
+                         sc.log_scales[3 * gi + 2]};
+    const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
+    const float q[4] = {q4.x, q4.y, q4.z, q4.w};
+    const float o = sc.opac[gi];
+    KeyResult kr;
+    vis = key_path(m, ls, q, o, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX,
+                   t.TY, cam.z_near, kr);
+    st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
+    if (vis) {
+      st.rect[pair] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
+      // ---- screen-space record in FP64
+      const double s0 = exp((double)ls[0]), s1 = exp((double)ls[1]), s2 = exp((double)ls[2]);
+      double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
+      const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+      qw /= qn; qx /= qn; qy /= qn; qz /= qn;
+      double R[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
+                        {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
+                        {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
+      const double sv[3] = {s0, s1, s2};
+      double M[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sv[j];
+      double S[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          S[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
+      double Wd[3][3], V[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+          Wd[i][k] = (double)Rc[3 * i] * S[0][k] + (double)Rc[3 * i + 1] * S[1][k] +
+                     (double)Rc[3 * i + 2] * S[2][k];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          V[i][j] = Wd[i][0] * Rc[3 * j] + Wd[i][1] * Rc[3 * j + 1] + Wd[i][2] * Rc[3 * j + 2];
+      double p[3];
+      for (int i = 0; i < 3; ++i)
+        p[i] = (double)Rc[3 * i] * m[0] + (double)Rc[3 * i + 1] * m[1] +
+               (double)Rc[3 * i + 2] * m[2] + (double)tc[i];
+      const double fx = in.x, fy = in.y;
+      const double rx = p[0] / p[2], ry = p[1] / p[2];
+      const double limx = 1.3 * (0.5 * t.W) / fx, limy = 1.3 * (0.5 * t.H) / fy;
+      const double rxc = fmin(fmax(rx, -limx), limx), ryc = fmin(fmax(ry, -limy), limy);
+      const double j00 = fx / p[2], j02 = -fx * rxc / p[2];
+      const double j11 = fy / p[2], j12 = -fy * ryc / p[2];
+      const double T00 = j00 * V[0][0] + j02 * V[2][0], T01 = j00 * V[0][1] + j02 * V[2][1];
+      const double T02 = j00 * V[0][2] + j02 * V[2][2];
+      const double T11 = j11 * V[1][1] + j12 * V[2][1], T12 = j11 * V[1][2] + j12 * V[2][2];
+      const double a = T00 * j00 + T02 * j02 + 0.3;
+      const double bb = T01 * j11 + T02 * j12;
+      const double c = T11 * j11 + T12 * j12 + 0.3;
+      const double det = a * c - bb * bb;
+      const double u = fx * rx + (double)in.z, vv = fy * ry + (double)in.w;
+      const double sig = 1.0 / (1.0 + exp(-(double)o));
+      float col[3];
+      if (SHD == 0) {
+        col[0] = sc.colors[3 * gi]; col[1] = sc.colors[3 * gi + 1]; col[2] = sc.colors[3 * gi + 2];
+      } else {
+        // camera centre o_cam = -Rc^T tc; direction d = (mu - o_cam)/|mu - o_cam|
+        const float ox = -(Rc[0] * tc[0] + Rc[3] * tc[1] + Rc[6] * tc[2]);
+        const float oy = -(Rc[1] * tc[0] + Rc[4] * tc[1] + Rc[7] * tc[2]);
+        const float oz = -(Rc[2] * tc[0] + Rc[5] * tc[1] + Rc[8] * tc[2]);
+        float dx = m[0] - ox, dy = m[1] - oy, dz = m[2] - oz;
+        const float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+        dx *= inv; dy *= inv; dz *= inv;
+        constexpr int NB = (SHD + 1) * (SHD + 1);
+        float Y[16];
+        sh_eval<SHD>(dx, dy, dz, Y);
+        const float* k = sc.colors + (long)3 * sc.sh_stride * gi;
+        float r = 0.5f, g = 0.5f, bl = 0.5f;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          r += Y[i] * k[3 * i]; g += Y[i] * k[3 * i + 1]; bl += Y[i] * k[3 * i + 2];
+        }
+        col[0] = fmaxf(r, 0.f); col[1] = fmaxf(g, 0.f); col[2] = fmaxf(bl, 0.f);
+      }
+      float4* rp = st.rec + 3 * (long)pair;
+      rp[0] = make_float4((float)u, (float)vv, (float)(c / det), (float)(-bb / det));
+      rp[1] = make_float4((float)(a / det), (float)sig, (float)p[2], 0.f);
+      rp[2] = make_float4(col[0], col[1], col[2], 0.f);
+    }
+  }
+  const int cnt = __syncthreads_count(vis);
+  if (threadIdx.x == 0) blk_cnt[b] = (uint32_t)cnt;
+}
+
+// Exclusive scan of the per-block visible counts (one workgroup) and the
+// per-view offsets of the compacted, view-major visible-pair list.
+__global__ __launch_bounds__(1024) void k_scan_blocks(ProjTab t, uint32_t* blk, StateHeader* hdr) {
+  __shared__ unsigned long long sh[17];
+  const int nb = t.blk_off[t.nv];
+  unsigned long long carry = 0;
+  for (int base = 0; base < nb; base += 1024 * 4) {
+    const int i0 = base + 4 * (int)threadIdx.x;
+    uint32_t x[4];
+    unsigned long long s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      x[k] = (i0 + k < nb) ? blk[i0 + k] : 0u;
+      s += x[k];
+    }
+    unsigned long long tot;
+    unsigned long long pre = wg_excl_scan<1024>(s, sh, &tot) + carry;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (i0 + k < nb) blk[i0 + k] = (uint32_t)pre;
+      pre += x[k];
+    }
+    carry += tot;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    hdr->vis_total = (uint32_t)carry;
+    hdr->vis_off[t.nv] = (uint32_t)carry;
+  }
+  for (int v = threadIdx.x; v < t.nv; v += 1024)
+    hdr->vis_off[v] = (t.blk_off[v] < nb) ? blk[t.blk_off[v]] : (uint32_t)carry;
+}
+
+// Ordered compaction: visible pairs keep their (view-major, id) order.
+__global__ __launch_bounds__(PROJ_BLOCK) void k_compact(ProjTab t, StateDev st,
+                                                        const uint32_t* blk_scan,
+                                                        uint32_t* kout, uint32_t* vout) {
+  const int b = blockIdx.x;
+  const int v = find_seg(t.blk_off, t.nv, b);
+  const int local = (b - t.blk_off[v]) * PROJ_BLOCK + (int)threadIdx.x;
+  const int n = t.pair_off[v + 1] - t.pair_off[v];
+  bool vis = false;
+  uint32_t key = CULLED;
+  const int pair = t.pair_off[v] + local;
+  if (local < n) {
+    key = st.zkey[pair];
+    vis = key != CULLED;
+  }
+  const unsigned long long m = __ballot(vis);
+  const int lane = lane_id(), w = threadIdx.x >> 6;
+  const int rank = __popcll(m & ((1ull << lane) - 1ull));
+  __shared__ int wc[PROJ_BLOCK / 64];
+  if (lane == 0) wc[w] = __popcll(m);
+  __syncthreads();
+  if (vis) {
+    uint32_t pos = blk_scan[b] + rank;
+    for (int i = 0; i < w; ++i) pos += wc[i];
+    kout[pos] = key;
+    vout[pos] = (uint32_t)pair;
+  }
+}
+
+// viewmats_out[v] = Exp(xi_v) [R|t] with xi = (rho, phi) (FP64 internally).
+__global__ void k_pose_delta(const float* vin, const float* delta, float* vout, int nv) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  const double r0 = delta[6 * v], r1 = delta[6 * v + 1], r2 = delta[6 * v + 2];
+  const double w0 = delta[6 * v + 3], w1 = delta[6 * v + 4], w2 = delta[6 * v + 5];
+  const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+  double A, B, C;  // sin(th)/th, (1-cos th)/th^2, (th - sin th)/th^3
+  if (th < 1e-4) {
+    A = 1.0 - th2 / 6.0 + th2 * th2 / 120.0;
+    B = 0.5 - th2 / 24.0 + th2 * th2 / 720.0;
+    C = 1.0 / 6.0 - th2 / 120.0 + th2 * th2 / 5040.0;
+  } else {
+    A = sin(th) / th;
+    B = (1.0 - cos(th)) / th2;
+    C = (th - sin(th)) / (th2 * th);
+  }
+  const double K[3][3] = {{0, -w2, w1}, {w2, 0, -w0}, {-w1, w0, 0}};
+  double K2[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K2[i][j] = K[i][0] * K[0][j] + K[i][1] * K[1][j] + K[i][2] * K[2][j];
+  double Rm[3][3], Vm[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      const double I = (i == j) ? 1.0 : 0.0;
+      Rm[i][j] = I + A * K[i][j] + B * K2[i][j];
+      Vm[i][j] = I + B * K[i][j] + C * K2[i][j];
+    }
+  const double rho[3] = {r0, r1, r2};
+  double tt[3];
+  for (int i = 0; i < 3; ++i) tt[i] = Vm[i][0] * rho[0] + Vm[i][1] * rho[1] + Vm[i][2] * rho[2];
+  double in[3][4];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 4; ++j) in[i][j] = vin[12 * v + 4 * i + j];
+  double out[3][4];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 4; ++j)
+      out[i][j] = Rm[i][0] * in[0][j] + Rm[i][1] * in[1][j] + Rm[i][2] * in[2][j] +
+                  (j == 3 ? tt[i] : 0.0);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 4; ++j) vout[12 * v + 4 * i + j] = (float)out[i][j];
+}
+
+hipError_t launch_project(const ProjTab& t, const SceneDev& sc, const CamDev& cam, StateDev st,
+                          uint32_t* blk_cnt, hipStream_t s) {
+  const int nb = t.blk_off[t.nv];
+  if (nb == 0) return hipSuccess;
+  switch (sc.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project<0>, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+    default: hipLaunchKernelGGL(k_project<3>, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const ProjTab& t, StateDev st, uint32_t* blk_cnt, uint32_t* kout,
+                          uint32_t* vout, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, t, blk_cnt, st.hdr);
+  const int nb = t.blk_off[t.nv];
+  if (nb > 0)
+    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, st, blk_cnt, kout, vout);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_delta(const float* vin, const float* delta, float* vout, int nv,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_delta, dim3((nv + 63) / 64), dim3(64), 0, s, vin, delta, vout, nv);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

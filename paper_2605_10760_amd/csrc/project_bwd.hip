@@ -1,0 +1,302 @@
+// Chain rule from the per-pair screen-space gradients to the Gaussian
+// parameters and each view's pose.
+//
+// One thread per Gaussian; it loops over the grad-needing views of its set
+// (uniform across the workgroup, whose Gaussians all belong to one set),
+// recomputes the projection in FP32, accumulates the parameter gradients in
+// registers and writes them once (no atomics, so summing over views is
+// deterministic).  Each view's 6-DoF pose gradient is reduced over the
+// workgroup (DPP wave sums, then LDS) into one atomic per component.
+#include "common.h"
+
+namespace gsr {
+
+#define SHK0 0.28209479177387814f
+#define SHK1 0.4886025119029199f
+#define SHK2A 1.0925484305920792f
+#define SHK2B 0.31539156525252005f
+#define SHK2C 0.5462742152960396f
+#define SHK3A 0.5900435899266435f
+#define SHK3B 2.890611442640554f
+#define SHK3C 0.4570457994644658f
+#define SHK3D 0.3731763325901154f
+#define SHK3E 1.445305721320277f
+
+// Real SH basis (as in the forward) and its partial derivatives with respect
+// to the direction components, as polynomials on R^3.
+template <int D>
+__device__ __forceinline__ void sh_eval_grad(float x, float y, float z, float* Y, float (*dY)[3]) {
+  Y[0] = SHK0; dY[0][0] = dY[0][1] = dY[0][2] = 0.f;
+  if (D >= 1) {
+    Y[1] = -SHK1 * y; dY[1][0] = 0.f; dY[1][1] = -SHK1; dY[1][2] = 0.f;
+    Y[2] = SHK1 * z;  dY[2][0] = 0.f; dY[2][1] = 0.f;   dY[2][2] = SHK1;
+    Y[3] = -SHK1 * x; dY[3][0] = -SHK1; dY[3][1] = 0.f; dY[3][2] = 0.f;
+  }
+  if (D >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = SHK2A * x * y;  dY[4][0] = SHK2A * y; dY[4][1] = SHK2A * x; dY[4][2] = 0.f;
+    Y[5] = -SHK2A * y * z; dY[5][0] = 0.f; dY[5][1] = -SHK2A * z; dY[5][2] = -SHK2A * y;
+    Y[6] = SHK2B * (2.f * zz - xx - yy);
+    dY[6][0] = -2.f * SHK2B * x; dY[6][1] = -2.f * SHK2B * y; dY[6][2] = 4.f * SHK2B * z;
+    Y[7] = -SHK2A * x * z; dY[7][0] = -SHK2A * z; dY[7][1] = 0.f; dY[7][2] = -SHK2A * x;
+    Y[8] = SHK2C * (xx - yy); dY[8][0] = 2.f * SHK2C * x; dY[8][1] = -2.f * SHK2C * y; dY[8][2] = 0.f;
+    if (D >= 3) {
+      Y[9] = -SHK3A * y * (3.f * xx - yy);
+      dY[9][0] = -6.f * SHK3A * x * y; dY[9][1] = -SHK3A * (3.f * xx - 3.f * yy); dY[9][2] = 0.f;
+      Y[10] = SHK3B * x * y * z;
+      dY[10][0] = SHK3B * y * z; dY[10][1] = SHK3B * x * z; dY[10][2] = SHK3B * x * y;
+      Y[11] = -SHK3C * y * (4.f * zz - xx - yy);
+      dY[11][0] = 2.f * SHK3C * x * y; dY[11][1] = -SHK3C * (4.f * zz - xx - 3.f * yy);
+      dY[11][2] = -8.f * SHK3C * y * z;
+      Y[12] = SHK3D * z * (2.f * zz - 3.f * xx - 3.f * yy);
+      dY[12][0] = -6.f * SHK3D * x * z; dY[12][1] = -6.f * SHK3D * y * z;
+      dY[12][2] = SHK3D * (6.f * zz - 3.f * xx - 3.f * yy);
+      Y[13] = -SHK3C * x * (4.f * zz - xx - yy);
+      dY[13][0] = -SHK3C * (4.f * zz - 3.f * xx - yy); dY[13][1] = 2.f * SHK3C * x * y;
+      dY[13][2] = -8.f * SHK3C * x * z;
+      Y[14] = SHK3E * z * (xx - yy);
+      dY[14][0] = 2.f * SHK3E * x * z; dY[14][1] = -2.f * SHK3E * y * z; dY[14][2] = SHK3E * (xx - yy);
+      Y[15] = -SHK3A * x * (xx - 3.f * yy);
+      dY[15][0] = -SHK3A * (3.f * xx - 3.f * yy); dY[15][1] = 6.f * SHK3A * x * y; dY[15][2] = 0.f;
+    }
+  }
+}
+
+template <int SHD>
+__global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamDev cam, StateDev st,
+                                                     const float* grad2d, gsr_grads out) {
+  constexpr int NB = (SHD + 1) * (SHD + 1);
+  __shared__ float red[2][4][6];
+  const int b = blockIdx.x;
+  const int s = find_seg(t.set_blk, t.ns, b);
+  const int local = (b - t.set_blk[s]) * 256 + (int)threadIdx.x;
+  const int nset = t.set_goff[s + 1] - t.set_goff[s];
+  const bool valid = local < nset;
+  const long gi = (long)t.set_goff[s] + (valid ? local : 0);
+
+  float m[3] = {0.f, 0.f, 0.f}, sv[3] = {1.f, 1.f, 1.f}, qh[4] = {1.f, 0.f, 0.f, 0.f};
+  float qn = 1.f, R[3][3], M[3][3], S3[3][3];
+  if (valid) {
+    for (int k = 0; k < 3; ++k) {
+      m[k] = sc.means[3 * gi + k];
+      sv[k] = expf(sc.log_scales[3 * gi + k]);
+    }
+    const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
+    qn = sqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
+    qh[0] = q4.x / qn; qh[1] = q4.y / qn; qh[2] = q4.z / qn; qh[3] = q4.w / qn;
+  }
+  {
+    const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+    R[0][0] = 1.f - 2.f * (y * y + z * z); R[0][1] = 2.f * (x * y - w * z); R[0][2] = 2.f * (x * z + w * y);
+    R[1][0] = 2.f * (x * y + w * z); R[1][1] = 1.f - 2.f * (x * x + z * z); R[1][2] = 2.f * (y * z - w * x);
+    R[2][0] = 2.f * (x * z - w * y); R[2][1] = 2.f * (y * z + w * x); R[2][2] = 1.f - 2.f * (x * x + y * y);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sv[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) S3[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
+
+  float gm[3] = {0.f, 0.f, 0.f};
+  float GS3[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  float gsig = 0.f;
+  float gk[NB][3];
+  for (int i = 0; i < NB; ++i) gk[i][0] = gk[i][1] = gk[i][2] = 0.f;
+
+  int parity = 0;
+  for (int vi = t.set_voff[s]; vi < t.set_voff[s + 1]; ++vi, parity ^= 1) {
+    const int v = t.view_by_set[vi];
+    float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int pair = t.pair_off[v] + local;
+    if (valid && st.zkey[pair] != CULLED) {
+      const float* vm = cam.viewmats + 12 * v;
+      const float Rc[3][3] = {{vm[0], vm[1], vm[2]}, {vm[4], vm[5], vm[6]}, {vm[8], vm[9], vm[10]}};
+      const float tc[3] = {vm[3], vm[7], vm[11]};
+      const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
+      const float fx = in.x, fy = in.y;
+      const float* g10 = grad2d + (size_t)GRAD2D * pair;
+      const float gu = g10[0], gv = g10[1], gA = g10[2], gB = g10[3], gC = g10[4];
+      const float gs = g10[5], gz = g10[9];
+      float gc[3] = {g10[6], g10[7], g10[8]};
+      const float4 r0 = st.rec[3 * (size_t)pair], r1 = st.rec[3 * (size_t)pair + 1];
+      const float A = r0.z, B = r0.w, C = r1.x;
+
+      float p[3];
+      for (int i = 0; i < 3; ++i) p[i] = Rc[i][0] * m[0] + Rc[i][1] * m[1] + Rc[i][2] * m[2] + tc[i];
+      float Wm[3][3], V[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+          Wm[i][k] = Rc[i][0] * S3[0][k] + Rc[i][1] * S3[1][k] + Rc[i][2] * S3[2][k];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          V[i][j] = Wm[i][0] * Rc[j][0] + Wm[i][1] * Rc[j][1] + Wm[i][2] * Rc[j][2];
+      const float iz = 1.f / p[2], iz2 = iz * iz;
+      const float rx = p[0] * iz, ry = p[1] * iz;
+      const float limx = 1.3f * (0.5f * (float)t.W) / fx, limy = 1.3f * (0.5f * (float)t.H) / fy;
+      const bool inx = !(rx < -limx || rx > limx), iny = !(ry < -limy || ry > limy);
+      const float rxc = inx ? rx : (rx < 0.f ? -limx : limx);
+      const float ryc = iny ? ry : (ry < 0.f ? -limy : limy);
+      const float j00 = fx * iz, j02 = -fx * rxc * iz, j11 = fy * iz, j12 = -fy * ryc * iz;
+
+      // conic -> 2D covariance:  G_S2 = -Q G_Q Q
+      const float hB = 0.5f * gB;
+      const float X00 = gA * A + hB * B, X01 = gA * B + hB * C;
+      const float X10 = hB * A + gC * B, X11 = hB * B + gC * C;
+      const float s00 = -(A * X00 + B * X10);
+      const float s01 = -0.5f * ((A * X01 + B * X11) + (B * X00 + C * X10));
+      const float s11 = -(B * X01 + C * X11);
+      // 2D -> camera covariance (J^T G J) and Jacobian (2 G J V)
+      float GV[3][3];
+      GV[0][0] = j00 * j00 * s00;
+      GV[0][1] = j00 * j11 * s01;
+      GV[0][2] = j00 * (j02 * s00 + j12 * s01);
+      GV[1][1] = j11 * j11 * s11;
+      GV[1][2] = j11 * (j02 * s01 + j12 * s11);
+      GV[2][2] = j02 * j02 * s00 + 2.f * j02 * j12 * s01 + j12 * j12 * s11;
+      GV[1][0] = GV[0][1]; GV[2][0] = GV[0][2]; GV[2][1] = GV[1][2];
+      float JV0[3], JV1[3];
+      for (int k = 0; k < 3; ++k) {
+        JV0[k] = j00 * V[0][k] + j02 * V[2][k];
+        JV1[k] = j11 * V[1][k] + j12 * V[2][k];
+      }
+      const float GJ00 = 2.f * (s00 * JV0[0] + s01 * JV1[0]);
+      const float GJ02 = 2.f * (s00 * JV0[2] + s01 * JV1[2]);
+      const float GJ11 = 2.f * (s01 * JV0[1] + s11 * JV1[1]);
+      const float GJ12 = 2.f * (s01 * JV0[2] + s11 * JV1[2]);
+      // camera-space mean
+      float gp[3];
+      gp[0] = gu * fx * iz;
+      gp[1] = gv * fy * iz;
+      gp[2] = -(gu * fx * p[0] + gv * fy * p[1]) * iz2 + gz;
+      gp[2] += -(GJ00 * fx + GJ11 * fy) * iz2;
+      gp[2] += GJ02 * fx * rxc * iz2 + GJ12 * fy * ryc * iz2;
+      if (inx) {
+        gp[0] += -GJ02 * fx * iz2;
+        gp[2] += GJ02 * fx * p[0] * iz2 * iz;
+      }
+      if (iny) {
+        gp[1] += -GJ12 * fy * iz2;
+        gp[2] += GJ12 * fy * p[1] * iz2 * iz;
+      }
+      for (int k = 0; k < 3; ++k) gm[k] += Rc[0][k] * gp[0] + Rc[1][k] * gp[1] + Rc[2][k] * gp[2];
+      // world covariance: Rc^T G_V Rc
+      float Y3[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          Y3[i][j] = GV[i][0] * Rc[0][j] + GV[i][1] * Rc[1][j] + GV[i][2] * Rc[2][j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          GS3[i][j] += Rc[0][i] * Y3[0][j] + Rc[1][i] * Y3[1][j] + Rc[2][i] * Y3[2][j];
+      gsig += gs;
+      // pose: rho <- dL/dp (+ SH term below), phi <- p x dL/dp + covariance rotation
+      pose[0] = gp[0]; pose[1] = gp[1]; pose[2] = gp[2];
+      pose[3] = p[1] * gp[2] - p[2] * gp[1];
+      pose[4] = p[2] * gp[0] - p[0] * gp[2];
+      pose[5] = p[0] * gp[1] - p[1] * gp[0];
+      float VG[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          VG[i][j] = V[i][0] * GV[0][j] + V[i][1] * GV[1][j] + V[i][2] * GV[2][j];
+      // M = V G - G V = VG - VG^T
+      pose[3] += 2.f * (VG[1][2] - VG[2][1]);
+      pose[4] += 2.f * (VG[2][0] - VG[0][2]);
+      pose[5] += 2.f * (VG[0][1] - VG[1][0]);
+      // colour
+      if (SHD == 0) {
+        gk[0][0] += gc[0]; gk[0][1] += gc[1]; gk[0][2] += gc[2];
+      } else {
+        const float ox = -(Rc[0][0] * tc[0] + Rc[1][0] * tc[1] + Rc[2][0] * tc[2]);
+        const float oy = -(Rc[0][1] * tc[0] + Rc[1][1] * tc[1] + Rc[2][1] * tc[2]);
+        const float oz = -(Rc[0][2] * tc[0] + Rc[1][2] * tc[1] + Rc[2][2] * tc[2]);
+        float d[3] = {m[0] - ox, m[1] - oy, m[2] - oz};
+        const float dist = sqrtf(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        const float idist = 1.f / dist;
+        d[0] *= idist; d[1] *= idist; d[2] *= idist;
+        float Y[16], dY[16][3];
+        sh_eval_grad<SHD>(d[0], d[1], d[2], Y, dY);
+        const float* kk = sc.colors + (long)3 * sc.sh_stride * gi;
+        float raw[3] = {0.5f, 0.5f, 0.5f};
+        for (int i = 0; i < NB; ++i)
+          for (int c = 0; c < 3; ++c) raw[c] += Y[i] * kk[3 * i + c];
+        for (int c = 0; c < 3; ++c) gc[c] = raw[c] > 0.f ? gc[c] : 0.f;
+        float gdir[3] = {0.f, 0.f, 0.f};
+        for (int i = 0; i < NB; ++i) {
+          const float e = gc[0] * kk[3 * i] + gc[1] * kk[3 * i + 1] + gc[2] * kk[3 * i + 2];
+          gdir[0] += e * dY[i][0]; gdir[1] += e * dY[i][1]; gdir[2] += e * dY[i][2];
+          gk[i][0] += Y[i] * gc[0]; gk[i][1] += Y[i] * gc[1]; gk[i][2] += Y[i] * gc[2];
+        }
+        const float dd = d[0] * gdir[0] + d[1] * gdir[1] + d[2] * gdir[2];
+        float gmd[3];
+        for (int k = 0; k < 3; ++k) {
+          gmd[k] = (gdir[k] - d[k] * dd) * idist;
+          gm[k] += gmd[k];
+        }
+        for (int i = 0; i < 3; ++i) pose[i] += Rc[i][0] * gmd[0] + Rc[i][1] * gmd[1] + Rc[i][2] * gmd[2];
+      }
+    }
+    // workgroup reduction of the pose gradient of view v
+    const int w = threadIdx.x >> 6;
+    for (int k = 0; k < 6; ++k) {
+      const float tot = wave_total(pose[k]);
+      if (lane_id() == 0) red[parity][w][k] = tot;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      const float tot = red[parity][0][threadIdx.x] + red[parity][1][threadIdx.x] +
+                        red[parity][2][threadIdx.x] + red[parity][3][threadIdx.x];
+      if (tot != 0.f) atomicAdd(out.d_pose + 6 * v + threadIdx.x, tot);
+    }
+  }
+  if (!valid) return;
+  // covariance -> scales and rotation:  Sigma = M M^T, M = R diag(s)
+  float GM[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k)
+      GM[i][k] = 2.f * (GS3[i][0] * M[0][k] + GS3[i][1] * M[1][k] + GS3[i][2] * M[2][k]);
+  float GR[3][3];
+  for (int k = 0; k < 3; ++k) {
+    const float gsk = GM[0][k] * R[0][k] + GM[1][k] * R[1][k] + GM[2][k] * R[2][k];
+    out.d_log_scales[3 * gi + k] = gsk * sv[k];
+    for (int i = 0; i < 3; ++i) GR[i][k] = GM[i][k] * sv[k];
+  }
+  const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  float gq[4];
+  gq[0] = 2.f * (-z * GR[0][1] + y * GR[0][2] + z * GR[1][0] - x * GR[1][2] - y * GR[2][0] + x * GR[2][1]);
+  gq[1] = 2.f * (y * GR[0][1] + z * GR[0][2] + y * GR[1][0] - 2.f * x * GR[1][1] - w * GR[1][2] +
+                 z * GR[2][0] + w * GR[2][1] - 2.f * x * GR[2][2]);
+  gq[2] = 2.f * (-2.f * y * GR[0][0] + x * GR[0][1] + w * GR[0][2] + x * GR[1][0] + z * GR[1][2] -
+                 w * GR[2][0] + z * GR[2][1] - 2.f * y * GR[2][2]);
+  gq[3] = 2.f * (-2.f * z * GR[0][0] - w * GR[0][1] + x * GR[0][2] + w * GR[1][0] -
+                 2.f * z * GR[1][1] + y * GR[1][2] + x * GR[2][0] + y * GR[2][1]);
+  const float dq = qh[0] * gq[0] + qh[1] * gq[1] + qh[2] * gq[2] + qh[3] * gq[3];
+  const float4 gq4 = make_float4((gq[0] - qh[0] * dq) / qn, (gq[1] - qh[1] * dq) / qn,
+                                 (gq[2] - qh[2] * dq) / qn, (gq[3] - qh[3] * dq) / qn);
+  *reinterpret_cast<float4*>(out.d_quats + 4 * gi) = gq4;
+  for (int k = 0; k < 3; ++k) out.d_means[3 * gi + k] = gm[k];
+  const float sg = 1.f / (1.f + expf(-sc.opac[gi]));
+  out.d_opacity_logits[gi] = gsig * sg * (1.f - sg);
+  if (SHD == 0) {
+    for (int c = 0; c < 3; ++c) out.d_colors[3 * gi + c] = gk[0][c];
+  } else {
+    float* dk = out.d_colors + (long)3 * sc.sh_stride * gi;
+    for (int i = 0; i < NB; ++i)
+      for (int c = 0; c < 3; ++c) dk[3 * i + c] = gk[i][c];
+    for (int i = 3 * NB; i < 3 * sc.sh_stride; ++i) dk[i] = 0.f;
+  }
+}
+
+hipError_t launch_project_bwd(const SetTab& t, const SceneDev& sc, const CamDev& cam, StateDev st,
+                              const float* grad2d, const gsr_grads& g, int n_total,
+                              hipStream_t s) {
+  (void)n_total;
+  const int nb = t.set_blk[t.ns];
+  if (nb == 0) return hipSuccess;
+  switch (sc.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(nb), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(nb), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(nb), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(nb), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsr

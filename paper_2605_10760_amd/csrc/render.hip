@@ -1,0 +1,288 @@
+// Per-tile compositing, forward and backward.
+//
+// One workgroup per (view, tile), one thread per pixel.  The tile's sorted
+// instance list is walked in batches of NT entries: each thread gathers one
+// 48-byte record into LDS, then every thread walks the batch (all lanes read
+// the same LDS word, a broadcast).  The forward stops the whole tile when
+// every pixel has terminated.  The backward walks each tile's list from the
+// largest last-contributor position down, recovers each pixel's
+// transmittance by division (T_j = T_{j+1} / (1 - alpha_j)) instead of
+// storing per-pixel lists, reduces each entry's ten splat gradients over
+// the wave with DPP row operations, accumulates the waves in LDS and issues
+// one global atomic per (tile, entry, component).
+#include "common.h"
+
+namespace gsr {
+
+constexpr float ALPHA_MAX = 0.99f;
+constexpr float ALPHA_MIN = 1.0f / 255.0f;
+constexpr float T_MIN = 1e-4f;
+
+// Exponent of a splat at a pixel sample point.  Contraction is off so the
+// forward and the backward evaluate it with identical roundings and take
+// identical skip decisions.
+__device__ __forceinline__ float splat_power(const float4& a, const float4& b, float fx, float fy,
+                                             float& dx, float& dy) {
+#pragma clang fp contract(off)
+  dx = a.x - fx;
+  dy = a.y - fy;
+  return -0.5f * (a.z * dx * dx + b.x * dy * dy) - a.w * dx * dy;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_render_fwd(int W, int H, int TX, int TY, CamDev cam,
+                                                       StateDev st, float* color, float* depth,
+                                                       float* alpha, int32_t* n_eval) {
+  constexpr int NT = TW * TH;
+  __shared__ float4 s0[NT], s1[NT], s2[NT];
+  const int T = TX * TY;
+  const int g = blockIdx.x;
+  const int v = g / T, tl = g - v * T;
+  const int ty = tl / TX, tx = tl - ty * TX;
+  const int tid = threadIdx.x;
+  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+  const bool inside = px < W && py < H;
+  uint2 rg = st.ranges[g];
+  if (st.hdr->overflow) rg = make_uint2(0u, 0u);
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  float Tc = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dz = 0.f;
+  uint32_t last = 0;
+  int ne = 0;
+  bool done = !inside;
+  for (uint32_t base = rg.x; base < rg.y; base += NT) {
+    if (__syncthreads_count(!done) == 0) break;
+    const uint32_t idx = base + tid;
+    if (idx < rg.y) {
+      const float4* r = st.rec + 3 * (size_t)st.inst[idx];
+      s0[tid] = r[0];
+      s1[tid] = r[1];
+      s2[tid] = r[2];
+    }
+    __syncthreads();
+    const int n = (int)min((uint32_t)NT, rg.y - base);
+    if (!done) {
+      for (int j = 0; j < n; ++j) {
+        const float4 a = s0[j], b = s1[j];
+        float dx, dy;
+        const float power = splat_power(a, b, fx, fy, dx, dy);
+        ++ne;
+        if (power > 0.f) continue;
+        const float al = fminf(ALPHA_MAX, b.y * __expf(power));
+        if (al < ALPHA_MIN) continue;
+        const float Tn = Tc * (1.f - al);
+        if (Tn < T_MIN) {
+          done = true;
+          break;
+        }
+        const float wgt = al * Tc;
+        const float4 c = s2[j];
+        c0 += c.x * wgt;
+        c1 += c.y * wgt;
+        c2 += c.z * wgt;
+        dz += b.z * wgt;
+        Tc = Tn;
+        last = base - rg.x + (uint32_t)j + 1u;
+      }
+    }
+  }
+  if (inside) {
+    const size_t HW = (size_t)W * H, p = (size_t)py * W + px;
+    color[(3 * (size_t)v + 0) * HW + p] = c0 + Tc * cam.bg0;
+    color[(3 * (size_t)v + 1) * HW + p] = c1 + Tc * cam.bg1;
+    color[(3 * (size_t)v + 2) * HW + p] = c2 + Tc * cam.bg2;
+    depth[v * HW + p] = dz;
+    alpha[v * HW + p] = 1.f - Tc;
+    st.tfinal[v * HW + p] = Tc;
+    st.last[v * HW + p] = last;
+    if (n_eval) n_eval[v * HW + p] = ne;
+  }
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void k_render_bwd(int W, int H, int TX, int TY,
+                                                       unsigned long long grad_mask, CamDev cam,
+                                                       StateDev st, const float* gcol,
+                                                       const float* gdep, const float* galp,
+                                                       float* grad2d) {
+  constexpr int NT = TW * TH;
+  __shared__ float4 s0[NT], s1[NT], s2[NT];
+  __shared__ uint32_t sp[NT];
+  __shared__ float sg[NT][GRAD2D];
+  __shared__ uint32_t smax;
+  const int T = TX * TY;
+  const int g = blockIdx.x;
+  const int v = g / T, tl = g - v * T;
+  if (!((grad_mask >> v) & 1ull)) return;
+  if (st.hdr->overflow) return;
+  const uint2 rg = st.ranges[g];
+  if (rg.x == rg.y) return;
+  const int ty = tl / TX, tx = tl - ty * TX;
+  const int tid = threadIdx.x;
+  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+  const bool inside = px < W && py < H;
+  const size_t HW = (size_t)W * H, p = (size_t)py * W + px;
+  float Tc = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gd = 0.f, ga = 0.f;
+  uint32_t lastp = 0;
+  if (inside) {
+    Tc = st.tfinal[v * HW + p];
+    lastp = st.last[v * HW + p];
+    if (gcol) {
+      g0 = gcol[(3 * (size_t)v + 0) * HW + p];
+      g1 = gcol[(3 * (size_t)v + 1) * HW + p];
+      g2 = gcol[(3 * (size_t)v + 2) * HW + p];
+    }
+    if (gdep) gd = gdep[v * HW + p];
+    if (galp) ga = galp[v * HW + p];
+  }
+  const float Tf = Tc;
+  float S0 = Tf * cam.bg0, S1 = Tf * cam.bg1, S2 = Tf * cam.bg2, SD = 0.f;
+  if (tid == 0) smax = 0;
+  __syncthreads();
+  if (lastp) atomicMax(&smax, lastp);
+  __syncthreads();
+  const int maxlast = (int)smax;
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  const int lane = lane_id();
+  for (int end = maxlast; end > 0; end -= NT) {
+    const int start = max(0, end - NT);
+    __syncthreads();
+    if (start + tid < end) {
+      const uint32_t pr = st.inst[rg.x + start + tid];
+      const float4* r = st.rec + 3 * (size_t)pr;
+      s0[tid] = r[0];
+      s1[tid] = r[1];
+      s2[tid] = r[2];
+      sp[tid] = pr;
+    }
+#pragma unroll
+    for (int k = 0; k < GRAD2D; ++k) sg[tid][k] = 0.f;
+    __syncthreads();
+    for (int j = end - start - 1; j >= 0; --j) {
+      float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gs = 0.f;
+      float gr = 0.f, gg = 0.f, gb = 0.f, gz = 0.f;
+      bool act = (start + j) < (int)lastp;
+      if (act) {
+        const float4 a = s0[j], b = s1[j];
+        float dx, dy;
+        const float power = splat_power(a, b, fx, fy, dx, dy);
+        const float G = __expf(power);
+        const float raw = b.y * G;
+        const float al = fminf(ALPHA_MAX, raw);
+        if (power > 0.f || al < ALPHA_MIN) {
+          act = false;
+        } else {
+          const float inv = 1.f / (1.f - al);
+          const float Tb = Tc * inv;
+          const float wgt = al * Tb;
+          const float4 c = s2[j];
+          const float dA = (c.x * Tb - S0 * inv) * g0 + (c.y * Tb - S1 * inv) * g1 +
+                           (c.z * Tb - S2 * inv) * g2 + (b.z * Tb - SD * inv) * gd +
+                           Tf * inv * ga;
+          S0 += c.x * wgt;
+          S1 += c.y * wgt;
+          S2 += c.z * wgt;
+          SD += b.z * wgt;
+          gr = wgt * g0;
+          gg = wgt * g1;
+          gb = wgt * g2;
+          gz = wgt * gd;
+          if (raw <= ALPHA_MAX) {
+            gs = G * dA;
+            const float gp = al * dA;
+            gu = -gp * (a.z * dx + a.w * dy);
+            gv = -gp * (a.w * dx + b.x * dy);
+            gA = -0.5f * gp * dx * dx;
+            gB = -gp * dx * dy;
+            gC = -0.5f * gp * dy * dy;
+          }
+          Tc = Tb;
+        }
+      }
+      if (__ballot(act) != 0ull) {
+        const float r0 = wave_total(gu), r1 = wave_total(gv), r2 = wave_total(gA);
+        const float r3 = wave_total(gB), r4 = wave_total(gC), r5 = wave_total(gs);
+        const float r6 = wave_total(gr), r7 = wave_total(gg), r8 = wave_total(gb);
+        const float r9 = wave_total(gz);
+        if (lane == 0) {
+          float* d = sg[j];
+          atomicAdd(d + 0, r0); atomicAdd(d + 1, r1); atomicAdd(d + 2, r2);
+          atomicAdd(d + 3, r3); atomicAdd(d + 4, r4); atomicAdd(d + 5, r5);
+          atomicAdd(d + 6, r6); atomicAdd(d + 7, r7); atomicAdd(d + 8, r8);
+          atomicAdd(d + 9, r9);
+        }
+      }
+    }
+    __syncthreads();
+    if (start + tid < end) {
+      float* dst = grad2d + (size_t)GRAD2D * sp[tid];
+#pragma unroll
+      for (int k = 0; k < GRAD2D; ++k) {
+        const float x = sg[tid][k];
+        if (x != 0.f) atomicAdd(dst + k, x);
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero_grad2d(int P, StateDev st, float* grad2d,
+                                                     float* d_pose, int nv) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < 6 * nv; k += 256) d_pose[k] = 0.f;
+  if (i >= P || i >= (int)st.hdr->vis_total) return;
+  float* d = grad2d + (size_t)GRAD2D * st.order[i];
+#pragma unroll
+  for (int k = 0; k < GRAD2D; ++k) d[k] = 0.f;
+}
+
+template <int TW, int TH>
+static void fwd_t(int nv, int W, int H, int TX, int TY, const CamDev& cam, StateDev st,
+                  float* color, float* depth, float* alpha, int32_t* n_eval, hipStream_t s) {
+  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(nv * TX * TY), dim3(TW * TH), 0, s, W, H, TX,
+                     TY, cam, st, color, depth, alpha, n_eval);
+}
+
+template <int TW, int TH>
+static void bwd_t(int nv, int W, int H, int TX, int TY, unsigned long long mask,
+                  const CamDev& cam, StateDev st, const float* gc, const float* gd,
+                  const float* ga, float* grad2d, hipStream_t s) {
+  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(nv * TX * TY), dim3(TW * TH), 0, s, W, H, TX,
+                     TY, mask, cam, st, gc, gd, ga, grad2d);
+}
+
+#define GSR_TILE_SWITCH(F, ...)                                  \
+  do {                                                           \
+    if (TW == 16 && TH == 16) F<16, 16>(__VA_ARGS__);            \
+    else if (TW == 8 && TH == 8) F<8, 8>(__VA_ARGS__);           \
+    else if (TW == 16 && TH == 8) F<16, 8>(__VA_ARGS__);         \
+    else if (TW == 8 && TH == 16) F<8, 16>(__VA_ARGS__);         \
+    else if (TW == 32 && TH == 8) F<32, 8>(__VA_ARGS__);         \
+    else if (TW == 32 && TH == 16) F<32, 16>(__VA_ARGS__);       \
+    else if (TW == 16 && TH == 32) F<16, 32>(__VA_ARGS__);       \
+    else return hipErrorInvalidValue;                            \
+  } while (0)
+
+hipError_t launch_render_fwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
+                             const CamDev& cam, StateDev st, float* color, float* depth,
+                             float* alpha, int32_t* n_eval, hipStream_t s) {
+  GSR_TILE_SWITCH(fwd_t, nv, W, H, TX, TY, cam, st, color, depth, alpha, n_eval, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_bwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
+                             unsigned long long grad_mask, const CamDev& cam, StateDev st,
+                             const float* g_color, const float* g_depth, const float* g_alpha,
+                             float* grad2d, hipStream_t s) {
+  GSR_TILE_SWITCH(bwd_t, nv, W, H, TX, TY, grad_mask, cam, st, g_color, g_depth, g_alpha, grad2d,
+                  s);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_grad2d(int P, StateDev st, float* grad2d, float* d_pose, int nv,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_grad2d, dim3(max(1, (P + 255) / 256)), dim3(256), 0, s, P, st, grad2d,
+                     d_pose, nv);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

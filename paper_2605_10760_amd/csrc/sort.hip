@@ -1,0 +1,163 @@
+// Depth sort of the visible pairs: a stable LSD radix sort, 8-bit digits,
+// segmented by view.
+//
+// The (tile, depth) key of a tile instance is sorted least-significant digit
+// first.  Every instance of a pair shares the pair's depth, so the four
+// depth digits are sorted on the visible pairs (before duplication, far
+// fewer elements); the tile digit is the last pass and is done by the
+// binning kernels.  Each view's visible pairs form a contiguous segment, so
+// sorting segments independently equals sorting by (view, depth).
+//
+// A pass is three kernels: per-block digit histograms (LDS atomics), one
+// workgroup per view turning the [block][digit] counts into scatter bases
+// in (digit, block) order, and a scatter where each 256-key round is ranked
+// stably inside the block by wave64 ballots over the digit bits.
+#include "common.h"
+
+namespace gsr {
+
+__device__ __forceinline__ void sort_block_range(const SortTab& t, const StateHeader* hdr,
+                                                 int b, int& v, int& lo, int& hi) {
+  v = find_seg(t.sblk_off, t.nv, b);
+  const int lb = b - t.sblk_off[v];
+  const int seg_lo = (int)hdr->vis_off[v], seg_hi = (int)hdr->vis_off[v + 1];
+  lo = seg_lo + lb * SORT_TILE;
+  hi = min(seg_hi, lo + SORT_TILE);
+}
+
+template <int SH>
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(SortTab t, const StateHeader* hdr,
+                                                             const uint32_t* keys,
+                                                             uint32_t* hist) {
+  __shared__ uint32_t cnt[RADIX];
+  int v, lo, hi;
+  sort_block_range(t, hdr, blockIdx.x, v, lo, hi);
+  cnt[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < SORT_ITEMS; ++r) {
+    const int i = lo + r * SORT_THREADS + (int)threadIdx.x;
+    if (i < hi) atomicAdd(&cnt[(keys[i] >> SH) & (RADIX - 1)], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)blockIdx.x * RADIX + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// One workgroup per view; thread d owns digit d.
+__global__ __launch_bounds__(RADIX) void k_radix_scan(SortTab t, const StateHeader* hdr,
+                                                      uint32_t* hist) {
+  __shared__ unsigned long long sh[RADIX / 64 + 1];
+  const int v = blockIdx.x;
+  const int n = (int)(hdr->vis_off[v + 1] - hdr->vis_off[v]);
+  const int nb = (n + SORT_TILE - 1) / SORT_TILE;
+  uint32_t* h = hist + (size_t)t.sblk_off[v] * RADIX + threadIdx.x;
+  uint32_t tot = 0;
+  int b = 0;
+  for (; b + 8 <= nb; b += 8) {
+    uint32_t x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = h[(size_t)(b + k) * RADIX];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) tot += x[k];
+  }
+  for (; b < nb; ++b) tot += h[(size_t)b * RADIX];
+  unsigned long long all;
+  uint32_t run = hdr->vis_off[v] + (uint32_t)wg_excl_scan<RADIX>(tot, sh, &all);
+  b = 0;
+  for (; b + 8 <= nb; b += 8) {
+    uint32_t x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = h[(size_t)(b + k) * RADIX];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      h[(size_t)(b + k) * RADIX] = run;
+      run += x[k];
+    }
+  }
+  for (; b < nb; ++b) {
+    const uint32_t x = h[(size_t)b * RADIX];
+    h[(size_t)b * RADIX] = run;
+    run += x;
+  }
+}
+
+// Stable scatter.  Keys of round r are the 256 consecutive keys
+// lo + r*256 + tid; within a round lower threads go first, earlier rounds go
+// before later ones, so equal digits keep their input order.
+template <int SH, bool KEYS_OUT>
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
+    SortTab t, const StateHeader* hdr, const uint32_t* hist, const uint32_t* kin,
+    const uint32_t* vin, uint32_t* kout, uint32_t* vout) {
+  constexpr int NW = SORT_THREADS / 64;
+  __shared__ uint32_t whist[NW][RADIX];
+  __shared__ uint32_t run[RADIX];
+  int v, lo, hi;
+  sort_block_range(t, hdr, blockIdx.x, v, lo, hi);
+  if (lo >= hi) return;
+  const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
+  run[tid] = hist[(size_t)blockIdx.x * RADIX + tid];
+#pragma unroll
+  for (int i = 0; i < NW; ++i) whist[i][tid] = 0;
+  __syncthreads();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  for (int r = 0; r < SORT_ITEMS; ++r) {
+    const int i = lo + r * SORT_THREADS + tid;
+    if (lo + r * SORT_THREADS >= hi) break;  // uniform
+    const bool valid = i < hi;
+    const uint32_t k = valid ? kin[i] : 0u;
+    const uint32_t val = valid ? vin[i] : 0u;
+    const uint32_t d = (k >> SH) & (RADIX - 1);
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < RADIX_BITS; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const unsigned long long bb = __ballot(on);
+      peers &= on ? bb : ~bb;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) whist[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + (uint32_t)rank;
+      for (int j = 0; j < w; ++j) pos += whist[j][d];
+      if (KEYS_OUT) kout[pos] = k;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      add += whist[j][tid];
+      whist[j][tid] = 0;
+    }
+    run[tid] += add;
+    __syncthreads();
+  }
+}
+
+hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
+                             uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s) {
+  const int nb = t.sblk_off[t.nv];
+  if (nb == 0) return hipSuccess;
+  const dim3 g(nb), blk(SORT_THREADS);
+  // pass 0: A -> B
+  hipLaunchKernelGGL(k_radix_hist<0>, g, blk, 0, s, t, st.hdr, ka, hist);
+  hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
+  hipLaunchKernelGGL((k_radix_scatter<0, true>), g, blk, 0, s, t, st.hdr, hist, ka, va, kb, vb);
+  // pass 1: B -> A
+  hipLaunchKernelGGL(k_radix_hist<8>, g, blk, 0, s, t, st.hdr, kb, hist);
+  hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
+  hipLaunchKernelGGL((k_radix_scatter<8, true>), g, blk, 0, s, t, st.hdr, hist, kb, vb, ka, va);
+  // pass 2: A -> B
+  hipLaunchKernelGGL(k_radix_hist<16>, g, blk, 0, s, t, st.hdr, ka, hist);
+  hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
+  hipLaunchKernelGGL((k_radix_scatter<16, true>), g, blk, 0, s, t, st.hdr, hist, ka, va, kb, vb);
+  // pass 3: B -> state order (values only)
+  hipLaunchKernelGGL(k_radix_hist<24>, g, blk, 0, s, t, st.hdr, kb, hist);
+  hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
+  hipLaunchKernelGGL((k_radix_scatter<24, false>), g, blk, 0, s, t, st.hdr, hist, kb, vb,
+                     (uint32_t*)nullptr, st.order);
+  return hipGetLastError();
+}
+
+}  // namespace gsr

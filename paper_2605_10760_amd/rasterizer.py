@@ -1,0 +1,309 @@
+"""Python front end of libgsr: device memory and streams come from PyTorch,
+every computation runs in the library's HIP kernels.
+
+    rast = Rasterizer(width, height, max_pairs, max_views)
+    color, depth, alpha, state = rast.forward(scene, views)
+    grads = rast.backward(scene, views, state, grad_color, grad_depth, grad_alpha)
+
+`scene` is a SceneTensors (FP32 CUDA tensors, host set offsets), `views` a
+ViewTensors (CUDA view matrices and intrinsics, host view->set map).
+`rasterize()` wraps both in a torch.autograd.Function that also returns the
+gradient of each view's SE(3) pose delta.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class SceneTensors:
+    means: torch.Tensor          # [N,3]
+    log_scales: torch.Tensor     # [N,3]
+    quats: torch.Tensor          # [N,4] (w,x,y,z)
+    opacity_logits: torch.Tensor # [N]
+    colors: torch.Tensor         # [N,3] or [N,K,3]
+    set_offsets: np.ndarray      # int64 [S+1] (host)
+    sh_degree: int = 0
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @property
+    def sh_stride(self) -> int:
+        return 1 if self.colors.dim() == 2 else int(self.colors.shape[1])
+
+    @staticmethod
+    def from_numpy(sc, device="cuda") -> "SceneTensors":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return SceneTensors(t(sc.means), t(sc.log_scales), t(sc.quats), t(sc.opacity_logits),
+                            t(sc.colors), np.asarray(sc.set_offsets, np.int64), int(sc.sh_degree))
+
+
+@dataclass
+class ViewTensors:
+    viewmats: torch.Tensor       # [V,3,4] world->camera
+    intrinsics: torch.Tensor     # [V,4]
+    view_set: np.ndarray         # int32 [V] (host)
+    width: int
+    height: int
+    needs_grad: np.ndarray = field(default=None)  # uint8 [V] (host) or None
+
+    @property
+    def n(self) -> int:
+        return int(self.viewmats.shape[0])
+
+    @staticmethod
+    def from_numpy(vw, device="cuda") -> "ViewTensors":
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return ViewTensors(t(vw.viewmats), t(vw.intrinsics), np.asarray(vw.view_set, np.int32),
+                           int(vw.width), int(vw.height),
+                           np.asarray(vw.needs_grad, np.uint8) if vw.needs_grad is not None else None)
+
+    def select(self, idx) -> "ViewTensors":
+        idx = np.atleast_1d(np.asarray(idx))
+        ti = torch.as_tensor(idx, device=self.viewmats.device)
+        return ViewTensors(self.viewmats[ti].contiguous(), self.intrinsics[ti].contiguous(),
+                           self.view_set[idx].copy(), self.width, self.height,
+                           None if self.needs_grad is None else self.needs_grad[idx].copy())
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype not in (torch.float32, torch.int32, torch.uint8) or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA float32/int32/uint8 tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def pairs_of(scene: SceneTensors, views: ViewTensors) -> int:
+    so = scene.set_offsets
+    return int(sum(so[s + 1] - so[s] for s in views.view_set))
+
+
+class Rasterizer:
+    """A libgsr context with one plan (image size, tile shape, capacities)."""
+
+    def __init__(self, width: int, height: int, max_pairs: int, max_views: int = 1,
+                 max_instances: int | None = None, tile=(16, 16), device: int | None = None,
+                 chunk: int = 0):
+        self.lib = L.load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = C.c_void_p()
+        st = self.lib.gsr_create(C.byref(h), self.device)
+        if st != L.GSR_OK:
+            raise L.GsrError(st, "gsr_create failed (no gfx950 device?)")
+        self.ctx = h
+        if max_instances is None:
+            max_instances = max(1 << 20, 24 * int(max_pairs))
+        self.desc = L.PlanDesc(int(max_pairs), int(max_instances), int(max_views), int(width),
+                               int(height), int(tile[0]), int(tile[1]), int(chunk))
+        self._plan()
+
+    def _plan(self):
+        self._check(self.lib.gsr_plan(self.ctx, C.byref(self.desc)))
+        n = C.c_size_t()
+        self._check(self.lib.gsr_state_bytes(C.byref(self.desc), C.byref(n)))
+        self.state_bytes = int(n.value)
+
+    def replan(self, **kw):
+        for k, v in kw.items():
+            setattr(self.desc, k, int(v))
+        self._plan()
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.gsr_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != L.GSR_OK:
+            raise L.GsrError(st, self.lib.gsr_last_error(self.ctx).decode())
+
+    @property
+    def tile(self):
+        return (self.desc.tile_w, self.desc.tile_h)
+
+    def new_state(self) -> torch.Tensor:
+        # torch's caching allocator returns 512-byte aligned blocks
+        return torch.empty(self.state_bytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    # ------------------------------------------------------------- marshalling
+    @staticmethod
+    def _scene(scene: SceneTensors):
+        so = np.ascontiguousarray(scene.set_offsets, np.int64)
+        s = L.Scene(_ptr(scene.means), _ptr(scene.log_scales), _ptr(scene.quats),
+                    _ptr(scene.opacity_logits), _ptr(scene.colors),
+                    so.ctypes.data_as(C.POINTER(C.c_int64)), int(so.shape[0] - 1),
+                    int(scene.sh_degree), int(scene.sh_stride), 0)
+        return s, so
+
+    @staticmethod
+    def _views(views: ViewTensors):
+        vs = np.ascontiguousarray(views.view_set, np.int32)
+        ng = None if views.needs_grad is None else np.ascontiguousarray(views.needs_grad, np.uint8)
+        v = L.Views(_ptr(views.viewmats), _ptr(views.intrinsics),
+                    vs.ctypes.data_as(C.POINTER(C.c_int32)),
+                    ng.ctypes.data_as(C.POINTER(C.c_uint8)) if ng is not None else None,
+                    views.n, int(views.width), int(views.height), 0)
+        return v, (vs, ng)
+
+    @staticmethod
+    def _settings(z_near=0.2, bg=(0.0, 0.0, 0.0)):
+        return L.Settings(float(z_near), (C.c_float * 3)(*[float(b) for b in bg]))
+
+    # ------------------------------------------------------------------ calls
+    def forward(self, scene: SceneTensors, views: ViewTensors, z_near=0.2, bg=(0.0, 0.0, 0.0),
+                state: torch.Tensor | None = None, out=None, n_eval=False, stream=None):
+        """Render all views.  Returns (color [V,3,H,W], depth [V,H,W],
+        alpha [V,H,W], state) (+ n_eval [V,H,W] int32 if n_eval)."""
+        dev = scene.means.device
+        V, H, W = views.n, views.height, views.width
+        if out is None:
+            out = (torch.empty((V, 3, H, W), dtype=torch.float32, device=dev),
+                   torch.empty((V, H, W), dtype=torch.float32, device=dev),
+                   torch.empty((V, H, W), dtype=torch.float32, device=dev))
+        ne = torch.empty((V, H, W), dtype=torch.int32, device=dev) if n_eval else None
+        if state is None:
+            state = self.new_state()
+        sc, keep1 = self._scene(scene)
+        vw, keep2 = self._views(views)
+        st = self._settings(z_near, bg)
+        img = L.Images(_ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(ne))
+        self._check(self.lib.gsr_forward(self.ctx, C.byref(sc), C.byref(vw), C.byref(st),
+                                         C.c_void_p(state.data_ptr()), C.byref(img),
+                                         _stream(stream)))
+        if n_eval:
+            return out[0], out[1], out[2], state, ne
+        return out[0], out[1], out[2], state
+
+    def backward(self, scene: SceneTensors, views: ViewTensors, state: torch.Tensor,
+                 grad_color=None, grad_depth=None, grad_alpha=None, z_near=0.2,
+                 bg=(0.0, 0.0, 0.0), out=None, stream=None):
+        """Gradients of sum(g_c*color + g_d*depth + g_a*alpha) for the forward
+        that wrote `state`.  Returns a dict of tensors."""
+        dev = scene.means.device
+        if out is None:
+            out = dict(d_means=torch.empty_like(scene.means),
+                       d_log_scales=torch.empty_like(scene.log_scales),
+                       d_quats=torch.empty_like(scene.quats),
+                       d_opacity_logits=torch.empty_like(scene.opacity_logits),
+                       d_colors=torch.empty_like(scene.colors),
+                       d_pose=torch.empty((views.n, 6), dtype=torch.float32, device=dev))
+        sc, keep1 = self._scene(scene)
+        vw, keep2 = self._views(views)
+        st = self._settings(z_near, bg)
+        gi = L.GradImages(_ptr(grad_color), _ptr(grad_depth), _ptr(grad_alpha))
+        g = L.Grads(_ptr(out["d_means"]), _ptr(out["d_log_scales"]), _ptr(out["d_quats"]),
+                    _ptr(out["d_opacity_logits"]), _ptr(out["d_colors"]), _ptr(out["d_pose"]))
+        self._check(self.lib.gsr_backward(self.ctx, C.byref(sc), C.byref(vw), C.byref(st),
+                                          C.c_void_p(state.data_ptr()), C.byref(gi), C.byref(g),
+                                          _stream(stream)))
+        return out
+
+    def poll(self, state: torch.Tensor, raise_on_overflow=True, stream=None) -> dict:
+        c = L.Counts()
+        st = self.lib.gsr_poll(self.ctx, C.c_void_p(state.data_ptr()), C.byref(c), _stream(stream))
+        if st not in (L.GSR_OK, L.GSR_E_OVERFLOW) or (st == L.GSR_E_OVERFLOW and raise_on_overflow):
+            self._check(st)
+        return dict(visible_pairs=c.visible_pairs, instances=c.instances, capacity=c.capacity,
+                    overflow=bool(c.overflow))
+
+    def fit_capacity(self, scene: SceneTensors, views: ViewTensors, z_near=0.2, margin=1.25):
+        """Run one forward, and re-plan with more instance capacity if it
+        overflowed (synchronises; for set-up, not for captured steps)."""
+        _, _, _, state = self.forward(scene, views, z_near=z_near)
+        c = self.poll(state, raise_on_overflow=False)
+        if c["overflow"] or c["instances"] * margin > self.desc.max_instances * 4:
+            self.replan(max_instances=min(0xFFFFFFFE, max(1 << 20, int(c["instances"] * margin))))
+        return c
+
+    def debug_export(self, state: torch.Tensor, n_views: int, n_pairs: int, n_inst: int,
+                     stream=None) -> dict:
+        TX = -(-self.desc.width // self.desc.tile_w)
+        TY = -(-self.desc.height // self.desc.tile_h)
+        H, W = self.desc.height, self.desc.width
+        z = np.zeros(n_pairs, np.uint32)
+        rects = np.zeros((n_pairs, 4), np.uint16)
+        order = np.zeros(n_pairs, np.uint32)
+        vis_off = np.zeros(n_views + 1, np.int64)
+        inst = np.zeros(max(1, n_inst), np.uint32)
+        ranges = np.zeros((n_views * TX * TY, 2), np.uint32)
+        tf = np.zeros((n_views, H, W), np.float32)
+        last = np.zeros((n_views, H, W), np.uint32)
+        vp = lambda a: C.c_void_p(a.ctypes.data)
+        d = L.Debug(vp(z), vp(rects), vp(order), vp(vis_off), vp(inst), vp(ranges), vp(tf),
+                    vp(last), int(n_pairs), int(n_inst))
+        self._check(self.lib.gsr_debug_export(self.ctx, C.c_void_p(state.data_ptr()),
+                                              int(n_views), C.byref(d), _stream(stream)))
+        return dict(zkeys=z, rects=rects, order=order[:int(vis_off[-1])], vis_off=vis_off,
+                    inst=inst[:n_inst], ranges=ranges, t_final=tf, last=last, TX=TX, TY=TY)
+
+
+def apply_pose_delta(viewmats: torch.Tensor, delta: torch.Tensor, out: torch.Tensor | None = None,
+                     stream=None) -> torch.Tensor:
+    """Exp(delta[v]) @ viewmats[v] on the device (left SE(3) update)."""
+    lib = L.load()
+    if out is None:
+        out = torch.empty_like(viewmats)
+    st = lib.gsr_apply_pose_delta(_ptr(viewmats.contiguous()), _ptr(delta.contiguous()),
+                                  _ptr(out), int(viewmats.shape[0]), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_apply_pose_delta failed")
+    return out
+
+
+class _RasterizeFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_delta, viewmats,
+                intrinsics, meta):
+        rast, set_offsets, view_set, needs_grad, sh_degree, z_near, bg, W, H = meta
+        vm = apply_pose_delta(viewmats, pose_delta) if pose_delta is not None else viewmats
+        scene = SceneTensors(means.contiguous(), log_scales.contiguous(), quats.contiguous(),
+                             opacity_logits.contiguous(), colors.contiguous(), set_offsets,
+                             sh_degree)
+        views = ViewTensors(vm.contiguous(), intrinsics.contiguous(), view_set, W, H, needs_grad)
+        color, depth, alpha, state = rast.forward(scene, views, z_near=z_near, bg=bg)
+        ctx.meta = meta
+        ctx.scene = scene
+        ctx.views = views
+        ctx.state = state
+        ctx.has_pose = pose_delta is not None
+        return color, depth, alpha
+
+    @staticmethod
+    def backward(ctx, gc, gd, ga):
+        rast, _, _, _, _, z_near, bg, _, _ = ctx.meta
+        c = lambda t: None if t is None else t.contiguous()
+        g = rast.backward(ctx.scene, ctx.views, ctx.state, c(gc), c(gd), c(ga), z_near=z_near,
+                          bg=bg)
+        return (g["d_means"], g["d_log_scales"], g["d_quats"], g["d_opacity_logits"],
+                g["d_colors"], g["d_pose"] if ctx.has_pose else None, None, None, None)
+
+
+def rasterize(rast: Rasterizer, means, log_scales, quats, opacity_logits, colors, viewmats,
+              intrinsics, set_offsets, view_set, width, height, pose_delta=None, sh_degree=0,
+              needs_grad=None, z_near=0.2, bg=(0.0, 0.0, 0.0)):
+    """Differentiable render of V views.  Returns (color [V,3,H,W], depth
+    [V,H,W], alpha [V,H,W]).  If `pose_delta` [V,6] is given (normally zeros
+    with requires_grad), each view is rendered at Exp(pose_delta) @ viewmat
+    and pose_delta.grad is the left-perturbation pose gradient there."""
+    meta = (rast, np.asarray(set_offsets, np.int64), np.asarray(view_set, np.int32),
+            None if needs_grad is None else np.asarray(needs_grad, np.uint8), int(sh_degree),
+            float(z_near), tuple(float(b) for b in bg), int(width), int(height))
+    return _RasterizeFn.apply(means, log_scales, quats, opacity_logits, colors, pose_delta,
+                              viewmats, intrinsics, meta)

@@ -1,0 +1,80 @@
+"""The C ABI library loads, exports every symbol include/gsr.h declares, and
+its host-only entry points and error paths behave (no GPU needed)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gsr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsr_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_bound_entry_points():
+    from paper_2605_10760_amd import _lib
+    assert declared_functions() == sorted(_lib.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(line.split()[-1] for line in out.splitlines() if line.strip())
+    for name in declared_functions():
+        assert name in exported, name
+        assert getattr(lib, name) is not None
+
+
+def test_create_without_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    h = C.c_void_p(123)
+    assert lib.gsr_create(C.byref(h), 0) == _lib.GSR_E_DEVICE
+    assert not h.value
+    assert lib.gsr_status_string(_lib.GSR_E_DEVICE) == b"device error"
+
+
+def _desc(**kw):
+    from paper_2605_10760_amd import _lib
+    d = dict(max_pairs=1000, max_instances=10000, max_views=2, width=128, height=96,
+             tile_w=16, tile_h=16, chunk=0)
+    d.update(kw)
+    return _lib.PlanDesc(*[d[k] for k in ("max_pairs", "max_instances", "max_views", "width",
+                                          "height", "tile_w", "tile_h", "chunk")])
+
+
+def test_state_bytes_host_only_and_validation():
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    n = C.c_size_t()
+    assert lib.gsr_state_bytes(C.byref(_desc()), C.byref(n)) == _lib.GSR_OK
+    # header + keys + rects + records + order + ranges + instances + 2 per-pixel planes
+    assert n.value >= 512 + 1000 * (4 + 8 + 48 + 4) + 2 * 48 * 8 + 10000 * 4 + 2 * 2 * 128 * 96 * 4
+    assert n.value % 256 == 0
+    for bad in (dict(max_pairs=0), dict(max_views=65), dict(tile_w=12), dict(tile_w=32, tile_h=32),
+                dict(width=0), dict(max_instances=0), dict(chunk=-1)):
+        assert lib.gsr_state_bytes(C.byref(_desc(**bad)), C.byref(n)) == _lib.GSR_E_INVALID_ARG, bad
+    assert lib.gsr_state_bytes(None, C.byref(n)) == _lib.GSR_E_INVALID_ARG
+
+
+def test_null_context_paths():
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    assert lib.gsr_plan(None, C.byref(_desc())) == _lib.GSR_E_INVALID_ARG
+    assert lib.gsr_forward(None, None, None, None, None, None, None) == _lib.GSR_E_INVALID_ARG
+    assert lib.gsr_backward(None, None, None, None, None, None, None, None) == _lib.GSR_E_INVALID_ARG
+    assert lib.gsr_poll(None, None, None, None) == _lib.GSR_E_INVALID_ARG
+    assert lib.gsr_apply_pose_delta(None, None, None, 1, None) == _lib.GSR_E_INVALID_ARG
+    assert lib.gsr_last_error(None) == b"no context"
+    lib.gsr_destroy(None)

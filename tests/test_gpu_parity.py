@@ -1,0 +1,380 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact: culling, depth keys, tile rects, the sorted instance list and
+tile ranges.  Images: colour and alpha within 1e-5 absolute, depth within
+1e-5 * max(1, z_max), on pixels without an ambiguous FP32/FP64 decision.
+Gradients: per tensor, max-abs and 2-norm of the error within 1e-3 of the
+reference's max-abs and 2-norm, upstream gradients zeroed on ambiguous
+pixels."""
+import numpy as np
+import pytest
+
+from gpu_harness import announce, gpu_forward, grad_rel_err, pair_to_gauss, to_gpu
+from oracle.render import Settings, render_backward, render_pixels, render_view
+from oracle.keypath32 import keypath
+from synth.scenes import multi_agent, room_plain, small_plain, tiny_scene
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-5
+GRAD_TOL = 1e-3
+
+
+def _oracle_views(scene, views, st=Settings(), keep=False):
+    return [render_view(scene, views, k, st, keep=keep) for k in range(views.n)]
+
+
+def _scene_case(name):
+    if name == "small-plain":
+        wl = small_plain(0)
+        return wl.scene, wl.views
+    if name.startswith("tiny"):
+        seed = int(name.split("-")[1])
+        return tiny_scene(seed, n=60, width=70, height=45, pose_noise=0.15 * (seed % 2))
+    if name == "multi-agent-small":
+        wl = multi_agent(scale=0.002, keyframes=3, width=160, height=120)
+        return wl.scene, wl.views
+    if name == "sh3":
+        return tiny_scene(5, n=80, width=96, height=64, sh_degree=3, pose_noise=0.2)
+    raise KeyError(name)
+
+
+CASES = ["small-plain", "tiny-0", "tiny-1", "tiny-2", "multi-agent-small", "sh3"]
+
+
+def _check_keys(scene, views, g, orc, st=Settings()):
+    dbg = g["dbg"]
+    vid, gid = pair_to_gauss(scene, views)
+    so = scene.set_offsets
+    T = dbg["TX"] * dbg["TY"]
+    off = 0
+    straddle = set()
+    for k, r in enumerate(orc):
+        kp = r["setup"]["kp"]
+        n = kp["visible"].shape[0]
+        zk = dbg["zkeys"][off:off + n]
+        vis = zk != 0xFFFFFFFF
+        s0 = so[views.view_set[k]]
+        straddle |= set((s0 + np.nonzero(kp["straddle"])[0]).tolist())
+        ok = ~kp["straddle"]
+        np.testing.assert_array_equal(vis[ok], kp["visible"][ok], err_msg=f"culling, view {k}")
+        both = vis & kp["visible"] & ok
+        np.testing.assert_array_equal(zk[both], kp["zbits"][both], err_msg=f"depth bits, view {k}")
+        np.testing.assert_array_equal(dbg["rects"][off:off + n][both].astype(np.int64),
+                                      kp["rect"][both], err_msg=f"rects, view {k}")
+        off += n
+    # sorted instances: (global tile, depth bits, Gaussian) per instance
+    inst = dbg["inst"].astype(np.int64)
+    tile_of = np.zeros(inst.shape[0], np.int64)
+    for t in range(views.n * T):
+        lo, hi = dbg["ranges"][t]
+        tile_of[lo:hi] = t
+    g_keys = (tile_of.astype(np.uint64) << np.uint64(32)) | dbg["zkeys"][inst].astype(np.uint64)
+    g_vals = gid[inst]
+    o_keys = np.concatenate([r["keys"] for r in orc])
+    o_vals = np.concatenate([r["vals"] for r in orc])
+    if straddle:
+        sel_g = ~np.isin(g_vals, list(straddle))
+        sel_o = ~np.isin(o_vals, list(straddle))
+        g_keys, g_vals, o_keys, o_vals = g_keys[sel_g], g_vals[sel_g], o_keys[sel_o], o_vals[sel_o]
+    else:
+        assert g["counts"]["instances"] == o_keys.shape[0]
+        # the oracle's ranges are per view; shift to global positions
+        base = np.cumsum([0] + [r["keys"].shape[0] for r in orc])
+        o_rng = np.concatenate([np.where(r["ranges"][:, 1:2] > r["ranges"][:, :1],
+                                         r["ranges"] + base[k], 0) for k, r in enumerate(orc)])
+        np.testing.assert_array_equal(dbg["ranges"].astype(np.int64), o_rng, err_msg="tile ranges")
+    np.testing.assert_array_equal(g_keys, o_keys, err_msg="sorted keys")
+    np.testing.assert_array_equal(g_vals, o_vals, err_msg="sorted values")
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_binning_bit_exact(case):
+    announce(f"binning {case}")
+    scene, views = _scene_case(case)
+    g = gpu_forward(scene, views)
+    orc = _oracle_views(scene, views)
+    _check_keys(scene, views, g, orc)
+
+
+def _check_images(views, g, orc):
+    for k, r in enumerate(orc):
+        ok = ~r["ambiguous"]
+        zmax = max(1.0, float(np.max(r["setup"]["pr"]["z"], initial=0.0)))
+        dc = np.abs(g["color"][k] - r["color"])[:, ok].max(initial=0.0)
+        da = np.abs(g["alpha"][k] - r["alpha"])[ok].max(initial=0.0)
+        dd = np.abs(g["depth"][k] - r["depth"])[ok].max(initial=0.0)
+        assert dc <= IMG_TOL, f"colour err {dc} view {k}"
+        assert da <= IMG_TOL, f"alpha err {da} view {k}"
+        assert dd <= IMG_TOL * zmax, f"depth err {dd} view {k}"
+        np.testing.assert_array_equal(g["n_eval"][k][ok], r["n_eval"][ok])
+        assert r["ambiguous"].mean() <= 1e-3
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_forward_images(case):
+    announce(f"forward {case}")
+    scene, views = _scene_case(case)
+    g = gpu_forward(scene, views)
+    orc = _oracle_views(scene, views)
+    _check_images(views, g, orc)
+    dbg = g["dbg"]
+    for k, r in enumerate(orc):
+        ok = ~r["ambiguous"]
+        np.testing.assert_array_equal(dbg["last"][k][ok], r["last"][ok])
+
+
+def _upstream(views, seed, orc):
+    rng = np.random.default_rng(seed)
+    V, H, W = views.n, views.height, views.width
+    gc = rng.normal(size=(V, 3, H, W)).astype(np.float32)
+    gd = (0.3 * rng.normal(size=(V, H, W))).astype(np.float32)
+    ga = rng.normal(size=(V, H, W)).astype(np.float32)
+    for k, r in enumerate(orc):
+        amb = r["ambiguous"]
+        gc[k][:, amb] = 0
+        gd[k][amb] = 0
+        ga[k][amb] = 0
+    return gc, gd, ga
+
+
+def _gpu_backward(g, gc, gd, ga):
+    import torch
+    t = lambda a: torch.from_numpy(a).cuda()
+    out = g["rast"].backward(g["scene_t"], g["views_t"], g["state"], t(gc), t(gd), t(ga))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+GMAP = dict(d_means="d_means", d_log_scales="d_log_scales", d_quats="d_quats",
+            d_opacity_logits="d_opacity", d_colors="d_colors", d_pose="d_pose")
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_backward_gradients(case):
+    announce(f"backward {case}")
+    scene, views = _scene_case(case)
+    g = gpu_forward(scene, views, export=False)
+    orc = _oracle_views(scene, views)
+    gc, gd, ga = _upstream(views, 7, orc)
+    got = _gpu_backward(g, gc, gd, ga)
+    ref = render_backward(scene, views, gc, gd, ga)
+    for k_gpu, k_ref in GMAP.items():
+        e_inf, e_2 = grad_rel_err(got[k_gpu], ref[k_ref])
+        assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+
+
+def test_batched_equals_per_view():
+    """All views in one call == one call per view (bit-identical forward)."""
+    announce("batched vs per-view")
+    scene, views = _scene_case("multi-agent-small")
+    gb = gpu_forward(scene, views, export=False)
+    for k in range(views.n):
+        gk = gpu_forward(scene, views.select([k]), export=False)
+        np.testing.assert_array_equal(gb["color"][k], gk["color"][0])
+        np.testing.assert_array_equal(gb["depth"][k], gk["depth"][0])
+        np.testing.assert_array_equal(gb["alpha"][k], gk["alpha"][0])
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (16, 8), (8, 16), (32, 8), (32, 16), (16, 32)])
+def test_tile_shape_bit_identical(tile):
+    announce(f"tile shape {tile}")
+    scene, views = _scene_case("small-plain")
+    g0 = gpu_forward(scene, views, export=False)
+    g1 = gpu_forward(scene, views, tile=tile, export=False)
+    for key in ("color", "depth", "alpha"):
+        np.testing.assert_array_equal(g0[key], g1[key])
+
+
+def test_tile_shape_keys_bit_exact():
+    announce("tile shape 8x8 keys")
+    scene, views = _scene_case("tiny-0")
+    g = gpu_forward(scene, views, tile=(8, 8))
+    orc = _oracle_views(scene, views, Settings(tile_w=8, tile_h=8))
+    _check_keys(scene, views, g, orc, Settings(tile_w=8, tile_h=8))
+
+
+def test_forward_deterministic():
+    announce("determinism")
+    scene, views = _scene_case("multi-agent-small")
+    a = gpu_forward(scene, views, export=False)
+    b = gpu_forward(scene, views, export=False, rast=a["rast"])
+    for key in ("color", "depth", "alpha", "n_eval"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_edge_cases_empty_and_ragged():
+    """Everything culled; an empty set; a ragged 37x23 image; one Gaussian."""
+    announce("edge cases")
+    sc, vw = tiny_scene(2, n=10, width=37, height=23)
+    sc.means[:, 2] = -5.0                       # all behind the camera
+    g = gpu_forward(sc, vw)
+    assert g["counts"]["visible_pairs"] == 0 and g["counts"]["instances"] == 0
+    assert np.all(g["alpha"] == 0) and np.all(g["color"] == 0)
+    # one Gaussian, ragged image, plus an empty set rendered by a second view
+    sc1, vw1 = tiny_scene(4, n=1, width=37, height=23)
+    sc1.set_offsets = np.array([0, 1, 1], np.int64)
+    from synth.scenes import Views
+    vw2 = Views(np.concatenate([vw1.viewmats] * 2), np.concatenate([vw1.intrinsics] * 2),
+                np.array([0, 1], np.int32), 37, 23)
+    g = gpu_forward(sc1, vw2)
+    orc = _oracle_views(sc1, vw2)
+    _check_keys(sc1, vw2, g, orc)
+    _check_images(vw2, g, orc)
+    assert np.all(g["alpha"][1] == 0)
+
+
+def test_overflow_reported():
+    """A plan too small for the instances reports GSR_E_OVERFLOW via poll."""
+    announce("overflow")
+    from paper_2605_10760_amd import Rasterizer
+    scene, views = _scene_case("small-plain")
+    st_, vt = to_gpu(scene, views)
+    r = Rasterizer(views.width, views.height, scene.n, 1, max_instances=100)
+    c, d, a, state = r.forward(st_, vt)
+    cnt = r.poll(state, raise_on_overflow=False)
+    assert cnt["overflow"] and cnt["instances"] > 100
+    from paper_2605_10760_amd import GsrError
+    with pytest.raises(GsrError):
+        r.poll(state)
+    r.fit_capacity(st_, vt)
+    c, d, a, state = r.forward(st_, vt)
+    assert not r.poll(state)["overflow"]
+
+
+def test_pose_delta_kernel():
+    announce("pose delta")
+    import torch
+    from oracle.se3 import apply_left
+    from paper_2605_10760_amd import apply_pose_delta
+    rng = np.random.default_rng(3)
+    vm = np.stack([np.concatenate([np.linalg.qr(rng.normal(size=(3, 3)))[0],
+                                   rng.normal(size=(3, 1))], 1) for _ in range(5)]).astype(np.float32)
+    xi = (rng.normal(size=(5, 6)) * np.array([[0.1, 0.1, 0.1, 0.3, 0.3, 0.3]])).astype(np.float32)
+    xi[0] = 0
+    xi[1, 3:] = 1e-6
+    out = apply_pose_delta(torch.from_numpy(vm).cuda(), torch.from_numpy(xi).cuda()).cpu().numpy()
+    for k in range(5):
+        np.testing.assert_allclose(out[k], apply_left(xi[k], vm[k]), atol=2e-6)
+
+
+def test_autograd_function_matches_backward():
+    announce("autograd")
+    import torch
+    from paper_2605_10760_amd import rasterize
+    scene, views = _scene_case("tiny-1")
+    g = gpu_forward(scene, views, export=False)
+    st_, vt = g["scene_t"], g["views_t"]
+    params = [p.clone().requires_grad_(True) for p in
+              (st_.means, st_.log_scales, st_.quats, st_.opacity_logits, st_.colors)]
+    pose = torch.zeros((views.n, 6), device="cuda", requires_grad=True)
+    c, d, a = rasterize(g["rast"], *params, vt.viewmats, vt.intrinsics, scene.set_offsets,
+                        views.view_set, views.width, views.height, pose_delta=pose)
+    rng = np.random.default_rng(1)
+    w = [torch.from_numpy(rng.normal(size=x.shape).astype(np.float32)).cuda() for x in (c, d, a)]
+    loss = (c * w[0]).sum() + (d * w[1]).sum() + (a * w[2]).sum()
+    loss.backward()
+    ref = g["rast"].backward(st_, vt, g["state"], w[0], w[1], w[2])
+    for p, key in zip(params, ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors")):
+        e_inf, e_2 = grad_rel_err(p.grad.cpu().numpy(), ref[key].cpu().numpy())
+        assert e_inf <= 1e-5, (key, e_inf)
+    e_inf, _ = grad_rel_err(pose.grad.cpu().numpy(), ref["d_pose"].cpu().numpy())
+    assert e_inf <= 1e-5
+
+
+# ----------------------------------------------------------------- full size
+def _sampled_full_size_checks(scene, views, view_ids, n_gauss=3000, n_pix=192, seed=0):
+    g = gpu_forward(scene, views)
+    dbg = g["dbg"]
+    rng = np.random.default_rng(seed)
+    so = scene.set_offsets
+    T = dbg["TX"] * dbg["TY"]
+    inst = dbg["inst"].astype(np.int64)
+    # global properties: I = sum of rect areas; each tile's list ascending in
+    # (depth bits, pair id); ranges partition [0, I)
+    r = dbg["rects"].astype(np.int64)
+    vis = dbg["zkeys"] != 0xFFFFFFFF
+    areas = ((r[:, 2] - r[:, 0]) * (r[:, 3] - r[:, 1]))[vis]
+    assert areas.sum() == g["counts"]["instances"] == inst.shape[0]
+    rg = dbg["ranges"].astype(np.int64)
+    nz = rg[:, 1] > rg[:, 0]
+    assert np.all(rg[nz][1:, 0] == rg[nz][:-1, 1]) and rg[nz][0, 0] == 0
+    assert rg[nz][-1, 1] == inst.shape[0]
+    z = dbg["zkeys"][inst].astype(np.uint64)
+    key = (z << np.uint64(32)) | inst.astype(np.uint64)
+    tile_of = np.repeat(np.nonzero(nz)[0], (rg[nz, 1] - rg[nz, 0]))
+    same = tile_of[1:] == tile_of[:-1]
+    assert np.all(key[1:][same] > key[:-1][same])
+    off = np.concatenate([[0], np.cumsum([so[s + 1] - so[s] for s in views.view_set])])
+    for k in view_ids:
+        s = views.view_set[k]
+        n = int(so[s + 1] - so[s])
+        idx = rng.choice(n, size=min(n_gauss, n), replace=False)
+        kp = keypath(scene.means[so[s] + idx], scene.log_scales[so[s] + idx],
+                     scene.quats[so[s] + idx], scene.opacity_logits[so[s] + idx],
+                     views.viewmats[k], views.intrinsics[k], views.width, views.height)
+        zk = dbg["zkeys"][off[k] + idx]
+        ok = ~kp["straddle"]
+        np.testing.assert_array_equal((zk != 0xFFFFFFFF)[ok], kp["visible"][ok])
+        both = kp["visible"] & ok
+        np.testing.assert_array_equal(zk[both], kp["zbits"][both])
+        np.testing.assert_array_equal(dbg["rects"][off[k] + idx][both].astype(np.int64),
+                                      kp["rect"][both])
+        px = rng.integers(0, views.width, n_pix)
+        py = rng.integers(0, views.height, n_pix)
+        ro = render_pixels(scene, views, k, px, py)
+        ok = ~ro["ambiguous"]
+        zmax = max(1.0, float(ro["depth"].max() / max(ro["alpha"].max(), 1e-9)))
+        dc = np.abs(g["color"][k][:, py, px].T - ro["color"])[ok].max()
+        da = np.abs(g["alpha"][k][py, px] - ro["alpha"])[ok].max()
+        dd = np.abs(g["depth"][k][py, px] - ro["depth"])[ok].max()
+        assert dc <= IMG_TOL and da <= IMG_TOL and dd <= IMG_TOL * 10 * zmax, (k, dc, da, dd)
+    return g
+
+
+@pytest.mark.slow
+def test_room_plain_full_size_sampled():
+    """300k Gaussians, one 1200x680 view: global binning properties, sampled
+    Gaussians' keys and sampled pixels against the oracle."""
+    announce("room 300k 1200x680 full size")
+    wl = room_plain()
+    _sampled_full_size_checks(wl.scene, wl.views, [0])
+
+
+@pytest.mark.slow
+def test_multi_agent_full_size_sampled():
+    """Six submaps (50k..600k) x 8 keyframes at 640x480 in one batch."""
+    announce("multi-agent 1.67M x 8 640x480 full size")
+    wl = multi_agent()
+    _sampled_full_size_checks(wl.scene, wl.views, [0, 47], n_pix=96)
+
+
+@pytest.mark.slow
+def test_room_plain_window_gradients():
+    """Full-size 1200x680 view, upstream gradient on a 40x24 window: the
+    oracle's gradient of that window (every Gaussian reaching it)."""
+    announce("room 300k gradient window")
+    wl = room_plain(n=300_000)
+    scene, views = wl.scene, wl.views
+    g = gpu_forward(scene, views, export=False)
+    rng = np.random.default_rng(4)
+    H, W = views.height, views.width
+    gc = np.zeros((1, 3, H, W), np.float32)
+    gd = np.zeros((1, H, W), np.float32)
+    ga = np.zeros((1, H, W), np.float32)
+    y0, x0 = 320, 576
+    gc[0, :, y0:y0 + 24, x0:x0 + 40] = rng.normal(size=(3, 24, 40))
+    gd[0, y0:y0 + 24, x0:x0 + 40] = 0.3 * rng.normal(size=(24, 40))
+    ga[0, y0:y0 + 24, x0:x0 + 40] = rng.normal(size=(24, 40))
+    TX = -(-W // 16)
+    tiles = sorted({(y // 16) * TX + x // 16 for y in range(y0, y0 + 24) for x in range(x0, x0 + 40)})
+    rv = render_view(scene, views, 0, tiles=tiles)
+    amb = rv["ambiguous"]
+    gc[0][:, amb] = 0
+    gd[0][amb] = 0
+    ga[0][amb] = 0
+    got = _gpu_backward(g, gc, gd, ga)
+    ref = render_backward(scene, views, gc, gd, ga)
+    for k_gpu, k_ref in GMAP.items():
+        e_inf, e_2 = grad_rel_err(got[k_gpu], ref[k_ref])
+        assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
