@@ -1,0 +1,391 @@
+#!/usr/bin/env python
+"""Throughput of the differentiable Gaussian-splatting rasterizer on one GPU.
+
+Default workload: agents' submaps of uneven sizes (50k, 120k, 200k, 300k,
+400k, 600k Gaussians) x 8 keyframes each at 640x480, one fwd+bwd
+optimisation step per iteration: forward render of all 48 views, the L1
+colour + depth loss gradient of the mapping loss (weights 0.95 / 0.25,
+Sec. III-A Eq. (map_loss)), the backward to every Gaussian parameter and
+every keyframe pose, and an Adam update.
+
+  batched : all sets x views in one launch sequence, captured once as a
+            HIP graph (torch.cuda.CUDAGraph) and replayed
+  plain   : a per-view loop, each view with its own projection, sort and
+            backward, run eagerly
+
+Prints ONE JSON line.  `value` is batched fwd+bwd views/s; the line also
+carries Gaussian-pixel evaluations/s, the plain loop's rates, per-stage
+times, the roofline of the dominant kernel and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Arithmetic per list entry examined, counted from the compositing
+# definition (one op per +, -, *, min, compare, exp): offset (2), quadratic
+# form (9), exp (1), opacity and clamp (2), skip test (1), transmittance
+# update and stop test (3); for a blended entry the weight (1) and four
+# multiply-adds into colour and depth (8).
+OPS_FWD_EXAMINED = 18
+OPS_FWD_BLENDED = 9
+# Backward per blended entry walked: the forward's 18 to recover alpha, the
+# transmittance division (2), dL/dalpha over three colours, depth and alpha
+# (16), suffix-sum updates (8), colour/depth gradients (4), the unclamped
+# branch (14) and the ten wave reductions amortised per lane (10).
+OPS_BWD_BLENDED = 72
+
+WORKLOADS = ("multi-agent", "room", "room-1m", "fused", "small")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=WORKLOADS, default="multi-agent")
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-graph", action="store_true", help="time the batched step eagerly")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def make_workload(name):
+    from synth import scenes
+    if name == "multi-agent":
+        return scenes.multi_agent()
+    if name == "room":
+        return scenes.room_plain()
+    if name == "room-1m":
+        return scenes.room_plain(seed=20, n=1_000_000)
+    if name == "fused":
+        # the fwd+bwd keyframes of the fused-map configuration (the 16
+        # forward-only novel views are rendered by the same kernels)
+        return scenes.fused_map(n_novel=0, n_keyframes=32)
+    return scenes.small_plain(0)
+
+
+class Step:
+    """One optimisation step on preallocated buffers (capture-safe)."""
+
+    def __init__(self, torch, rast, sc, vw, tc, td, lr_scale=1.0):
+        self.t = torch
+        self.rast, self.sc, self.vw, self.tc, self.td = rast, sc, vw, tc, td
+        V, H, W = vw.n, vw.height, vw.width
+        dev = sc.means.device
+        self.state = rast.new_state()
+        self.out = (torch.empty((V, 3, H, W), device=dev), torch.empty((V, H, W), device=dev),
+                    torch.empty((V, H, W), device=dev))
+        self.gc = torch.empty((V, 3, H, W), device=dev)
+        self.gd = torch.empty((V, H, W), device=dev)
+        params = [sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sc.colors]
+        self.grads = dict(d_means=torch.zeros_like(sc.means), d_log_scales=torch.zeros_like(sc.log_scales),
+                          d_quats=torch.zeros_like(sc.quats),
+                          d_opacity_logits=torch.zeros_like(sc.opacity_logits),
+                          d_colors=torch.zeros_like(sc.colors),
+                          d_pose=torch.zeros((V, 6), device=dev))
+        for p, k in zip(params, ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors")):
+            p.grad = self.grads[k]
+        lrs = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)
+        self.opt = torch.optim.Adam([{"params": [p], "lr": lr * lr_scale} for p, lr in zip(params, lrs)],
+                                    capturable=True, foreach=True)
+        self.wc = 0.95 / (V * 3 * H * W)
+        self.wd = 0.25 / (V * H * W)
+
+    def __call__(self):
+        t = self.t
+        c, d, a, _ = self.rast.forward(self.sc, self.vw, state=self.state, out=self.out)
+        # L1 mapping loss gradient (Eq. (map_loss) weights), computed by torch
+        t.sub(c, self.tc, out=self.gc)
+        self.gc.sign_().mul_(self.wc)
+        t.sub(d, self.td, out=self.gd)
+        self.gd.sign_().mul_(self.wd)
+        self.rast.backward(self.sc, self.vw, self.state, self.gc, self.gd, None, out=self.grads)
+        self.opt.step()
+
+
+def time_cpu_baseline(wl, seconds):
+    """The CPU oracle (FP64 NumPy, one thread) on a bounded sample of the
+    same workload: one keyframe of the largest submap with its full
+    projection, binning, sort and projection backward, and compositing
+    forward+backward on an evenly spaced sample of its tiles; the per-view
+    time is extrapolated to all tiles."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.composite import composite, pixel_grid
+    from oracle.project64 import project_backward
+    from oracle.render import Settings, bin_view, setup_view, splat_grads
+    sc, vw = wl.scene, wl.views
+    sizes = np.diff(sc.set_offsets)
+    k = int(np.nonzero(vw.view_set == int(np.argmax(sizes)))[0][0])
+    one = vw.select([k])
+    H, W = one.height, one.width
+    st = Settings()
+    TX, TY = -(-W // 16), -(-H // 16)
+    rng = np.random.default_rng(0)
+    t_start = time.perf_counter()
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        su = setup_view(sc, one, 0, st)
+        keys, vals, rng_t = bin_view(su, 0, st, W, H)
+        t_setup = time.perf_counter() - t0
+        nv = su["vis"].shape[0]
+        acc = {key: np.zeros(nv) for key in ("u", "v", "A", "B", "C", "sigma", "z")}
+        acc["color"] = np.zeros((nv, 3))
+        order = np.argsort((np.arange(TX * TY) * 0.6180339887) % 1.0)
+        n_done, t_tiles = 0, 0.0
+        budget = max(2.0, seconds - 1.5 * t_setup)
+        while n_done < TX * TY and t_tiles < budget:
+            t = int(order[n_done])
+            ty, tx = divmod(t, TX)
+            xx, yy, sx, sy = pixel_grid(tx * 16, ty * 16, min(tx * 16 + 16, W), min(ty * 16 + 16, H))
+            lo, hi = rng_t[t]
+            lst = su["local"][vals[lo:hi] - su["g0"]]
+            t1 = time.perf_counter()
+            r = composite(sx, sy, su["rec"], lst, np.zeros(3), keep=True)
+            g = splat_grads(r, rng.normal(size=(sx.shape[0], 3)), rng.normal(size=sx.shape[0]),
+                            np.zeros(sx.shape[0]))
+            for key in acc:
+                np.add.at(acc[key], r["order"], g[key])
+            t_tiles += time.perf_counter() - t1
+            n_done += 1
+        t0 = time.perf_counter()
+        sl = su["g0"] + su["vis"]
+        project_backward(su["pr"], acc["u"], acc["v"], np.stack([acc["A"], acc["B"], acc["C"]], 1),
+                         acc["sigma"], acc["color"], acc["z"], sc.colors[sl], sc.sh_degree)
+        t_pb = time.perf_counter() - t0
+    per_view = t_setup + t_pb + t_tiles / n_done * TX * TY
+    return dict(value=1.0 / per_view, unit="views/s", cores=1, kind="oracle",
+                sample=f"one {W}x{H} keyframe of the {int(sizes.max())}-Gaussian submap: full "
+                       f"projection, binning, sort and projection backward, compositing fwd+bwd "
+                       f"on {n_done} of {TX * TY} tiles, extrapolated to the whole view "
+                       f"({time.perf_counter() - t_start:.1f} s of CPU work, FP64 NumPy, 1 thread)")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the rasterizer's multi-GPU form (views or "
+              "submaps sharded over GPUs with an all-reduce of Gaussian gradients) is not "
+              "built; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2605_10760_amd import Rasterizer, SceneTensors, ViewTensors
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    tile = tuple(int(x) for x in args.tile.split("x"))
+    wl = make_workload(args.workload)
+    sc_np, vw_np = wl.scene, wl.views
+    V, H, W = vw_np.n, vw_np.height, vw_np.width
+    sc = SceneTensors.from_numpy(sc_np)
+    vw = ViewTensors.from_numpy(vw_np)
+    tc = torch.from_numpy(wl.target_color).cuda()
+    td = torch.from_numpy(wl.target_depth if wl.target_depth is not None
+                          else np.zeros((V, H, W), np.float32)).cuda()
+    so = sc_np.set_offsets
+    P = int(sum(so[s + 1] - so[s] for s in vw_np.view_set))
+    rast = Rasterizer(W, H, P, V, tile=tile)
+    rast.fit_capacity(sc, vw)
+
+    # ---- counts for the metric (untimed forward)
+    c, d, a, state, ne = rast.forward(sc, vw, n_eval=True)
+    counts = rast.poll(state)
+    dbg = rast.debug_export(state, V, P, 0)
+    n_eval = ne.cpu().numpy().astype(np.int64)
+    last = dbg["last"].astype(np.int64)
+    evals_fwd = int(n_eval.sum())
+    evals_bwd = int(last.sum())
+    TX, TY = dbg["TX"], dbg["TY"]
+
+    def tile_max(x):
+        pad = np.zeros((V, TY * tile[1], TX * tile[0]), np.int64)
+        pad[:, :H, :W] = x
+        return pad.reshape(V, TY, tile[1], TX, tile[0]).max(axis=(2, 4))
+
+    E_fwd = int(tile_max(n_eval).sum())      # list entries staged per tile, forward
+    E_bwd = int(tile_max(last).sum())        # list entries walked per tile, backward
+    del state, c, d, a, ne
+
+    # ---- batched step: warmup, graph capture, timed replays
+    step = Step(torch, rast, sc, vw, tc, td)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(max(1, args.warmup)):
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(2):
+            graph.replay()
+    run = graph.replay if graph is not None else step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    post = rast.poll(step.state, raise_on_overflow=False)
+    if post["overflow"]:
+        print(json.dumps({"error": "instance capacity overflow during the timed steps"}))
+        sys.exit(3)
+
+    # ---- per-stage times (eager steps with HIP events on the same stream)
+    rast.profile(True)
+    stage_acc = {}
+    n_prof = max(3, min(args.steps, 10))
+    for _ in range(n_prof):
+        step()
+        for k_, v_ in rast.stage_ms().items():
+            stage_acc[k_] = stage_acc.get(k_, 0.0) + v_ / n_prof
+    rast.profile(False)
+    torch.cuda.synchronize()
+
+    # ---- plain per-view loop
+    plain = None
+    if not args.no_plain:
+        per_view = [vw.select([k]) for k in range(V)]
+        max_set = int(max(so[s_ + 1] - so[s_] for s_ in vw_np.view_set))
+        r1 = Rasterizer(W, H, max_set, 1, tile=tile,
+                        max_instances=max(rast.desc.max_instances // max(1, V) * 4, 1 << 20))
+        for k in range(V):
+            r1.fit_capacity(sc, per_view[k])
+        st1 = r1.new_state()
+        o1 = (torch.empty((1, 3, H, W), device="cuda"), torch.empty((1, H, W), device="cuda"),
+              torch.empty((1, H, W), device="cuda"))
+        g1 = {k_: torch.empty_like(v_) for k_, v_ in step.grads.items()}
+        g1["d_pose"] = torch.empty((1, 6), device="cuda")
+        gcv = torch.empty((1, 3, H, W), device="cuda")
+        gdv = torch.empty((1, H, W), device="cuda")
+        tot = step.grads
+
+        def plain_step():
+            for g_ in tot.values():
+                g_.zero_()
+            for k in range(V):
+                c1, d1, _, _ = r1.forward(sc, per_view[k], state=st1, out=o1)
+                torch.sub(c1, tc[k:k + 1], out=gcv)
+                gcv.sign_().mul_(step.wc)
+                torch.sub(d1, td[k:k + 1], out=gdv)
+                gdv.sign_().mul_(step.wd)
+                r1.backward(sc, per_view[k], st1, gcv, gdv, None, out=g1)
+                for key in ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors"):
+                    tot[key].add_(g1[key])
+                tot["d_pose"][k].copy_(g1["d_pose"][0])
+            step.opt.step()
+
+        plain_step()
+        torch.cuda.synchronize()
+        ps = args.plain_steps if args.plain_steps is not None else max(2, args.steps // 4)
+        t0 = time.perf_counter()
+        for _ in range(ps):
+            plain_step()
+        torch.cuda.synchronize()
+        pdt = (time.perf_counter() - t0) / ps
+        plain = dict(views_per_s=V / pdt, evals_per_s=(evals_fwd + evals_bwd) / pdt,
+                     ms_per_step=pdt * 1e3, steps=ps)
+
+    # ---- algorithmic work per stage (measured counts)
+    nv_pairs = counts["visible_pairs"]
+    I = counts["instances"]
+    rgb = sc_np.sh_degree == 0
+    par = 56 if rgb else 4 * (3 + 3 + 4 + 1 + 3 * sc.sh_stride)
+    npx = V * H * W
+    chunk_T = rast.desc.chunk or 0
+    alg_bytes = {
+        "project": 12 * P + 4 * P + (par - 12 + 48 + 8) * nv_pairs,
+        "compact": 4 * P + 8 * nv_pairs,
+        "depth_sort": 4 * 24 * nv_pairs,
+        "binning": 2 * 12 * nv_pairs + 4 * I,
+        "render_fwd": 52 * E_fwd + 28 * npx,
+        "render_bwd": 52 * E_bwd + 80 * E_bwd + 28 * npx,
+        "project_bwd": (40 + 32 + 4) * nv_pairs + 2 * par * sc_np.n,
+    }
+    blended = evals_bwd
+    alg_ops = {
+        "render_fwd": OPS_FWD_EXAMINED * evals_fwd + OPS_FWD_BLENDED * blended,
+        "render_bwd": OPS_BWD_BLENDED * evals_bwd,
+    }
+    stages = {}
+    for name, ms in stage_acc.items():
+        if ms <= 0:
+            continue
+        e = dict(ms=round(ms, 4))
+        if name in alg_bytes:
+            e["algorithmic_GBps"] = round(alg_bytes[name] / (ms * 1e-3) / 1e9, 1)
+        if name in alg_ops:
+            e["algorithmic_TOPs"] = round(alg_ops[name] / (ms * 1e-3) / 1e12, 2)
+        stages[name] = e
+    dom = max(stage_acc, key=lambda k_: stage_acc[k_])
+    dms = stage_acc[dom]
+    if dom in alg_ops:
+        ach = alg_ops[dom] / (dms * 1e-3) / 1e12
+        roof = dict(bound="alu", kernel=dom, achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
+                    unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=None,
+                    ms=round(dms, 4))
+    else:
+        ach = alg_bytes.get(dom, 0) / (dms * 1e-3) / 1e9
+        roof = dict(bound="hbm", kernel=dom, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, ms=round(dms, 4))
+    step_bytes = sum(alg_bytes.values())
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = time_cpu_baseline(wl, args.cpu_seconds)
+
+    views_per_s = V / dt
+    line = {
+        "metric": "fwd+bwd views/sec and Gaussian-pixel evals/sec, batched vs plain, 1 MI355X",
+        "value": round(views_per_s, 2),
+        "unit": "views/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "views": V, "width": W, "height": H,
+                   "gaussians": int(sc_np.n), "sets": int(sc_np.n_sets),
+                   "sh_degree": int(sc_np.sh_degree), "tile": f"{tile[0]}x{tile[1]}",
+                   "form": "batched, hip graph replay" if graph is not None else "batched, eager"},
+        "evals_per_s": round((evals_fwd + evals_bwd) / dt, 1),
+        "evals": {"forward": evals_fwd, "backward": evals_bwd},
+        "counts": {"pairs": P, "visible_pairs": int(nv_pairs), "instances": int(I)},
+        "step_algorithmic_GB": round(step_bytes / 1e9, 3),
+        "step_hbm_roofline_frac": round(step_bytes / (dt * HBM_PEAK_GBS * 1e9), 4),
+        "plain": plain,
+        "stages_ms": stages,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

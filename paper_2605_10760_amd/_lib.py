@@ -18,7 +18,11 @@ GSR_E_OVERFLOW, GSR_E_DEVICE, GSR_E_OOM, GSR_E_UNIMPLEMENTED = 4, 5, 6, 7
 
 EXPORTED = ("gsr_create", "gsr_destroy", "gsr_plan", "gsr_state_bytes", "gsr_forward",
             "gsr_backward", "gsr_poll", "gsr_debug_export", "gsr_apply_pose_delta",
-            "gsr_autotune", "gsr_status_string", "gsr_last_error")
+            "gsr_autotune", "gsr_profile_enable", "gsr_profile_read", "gsr_status_string",
+            "gsr_last_error")
+
+STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "render_bwd",
+          "project_bwd")
 
 
 class PlanDesc(C.Structure):
@@ -107,6 +111,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gsr_autotune.argtypes = [C.c_int, P(PlanDesc), P(Scene), P(Views), P(Settings),
                                  P(PlanDesc), P(C.c_float), vp]
     lib.gsr_autotune.restype = C.c_int
+    lib.gsr_profile_enable.argtypes = [vp, C.c_int]
+    lib.gsr_profile_enable.restype = C.c_int
+    lib.gsr_profile_read.argtypes = [vp, P(C.c_float), C.c_int32]
+    lib.gsr_profile_read.restype = C.c_int
     lib.gsr_status_string.argtypes = [C.c_int]
     lib.gsr_status_string.restype = C.c_char_p
     lib.gsr_last_error.argtypes = [vp]

@@ -28,6 +28,9 @@ struct gsr_ctx {
   uint32_t* tile_cnt = nullptr;
   float* grad2d = nullptr;
   size_t max_blocks = 0, max_sblocks = 0, max_chunks = 0;
+  bool prof = false;
+  hipEvent_t ev[GSR_NUM_STAGES][2] = {};
+  bool ev_used[GSR_NUM_STAGES] = {};
 };
 
 namespace {
@@ -258,6 +261,24 @@ CamDev cam_dev(const gsr_views* vw, const gsr_settings* s) {
   return c;
 }
 
+// Records a stage's start/stop event when profiling is on and the stream is
+// not being captured.
+struct StageMark {
+  gsr_ctx* c;
+  int id;
+  hipStream_t s;
+  bool on;
+  StageMark(gsr_ctx* c_, int id_, hipStream_t s_) : c(c_), id(id_), s(s_), on(false) {
+    if (!c->prof) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+    on = hipEventRecord(c->ev[id][0], s) == hipSuccess;
+  }
+  ~StageMark() {
+    if (on && hipEventRecord(c->ev[id][1], s) == hipSuccess) c->ev_used[id] = true;
+  }
+};
+
 void free_ws(gsr_ctx* c) {
   if (c->ws) (void)hipFree(c->ws);
   c->ws = nullptr;
@@ -309,6 +330,9 @@ void gsr_destroy(gsr_ctx* c) {
   {
     DeviceGuard g(c->device);
     free_ws(c);
+    for (int i = 0; i < GSR_NUM_STAGES; ++i)
+      for (int j = 0; j < 2; ++j)
+        if (c->ev[i][j]) (void)hipEventDestroy(c->ev[i][j]);
   }
   delete c;
 }
@@ -385,15 +409,30 @@ gsr_status gsr_forward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   const SceneDev scd = scene_dev(sc);
   const CamDev cam = cam_dev(vw, set);
   hipError_t e;
-  if ((e = launch_project(t.pt, scd, cam, sd, c->blk_cnt, st)) != hipSuccess) return hip_fail(c, e, "project");
-  if ((e = launch_compact(t.pt, sd, c->blk_cnt, c->ka, c->va, st)) != hipSuccess) return hip_fail(c, e, "compact");
-  if ((e = launch_depth_sort(t.stb, sd, c->ka, c->va, c->kb, c->vb, c->hist, st)) != hipSuccess)
-    return hip_fail(c, e, "depth sort");
-  if ((e = launch_binning(t.bt, sd, c->counts, c->tile_cnt, st)) != hipSuccess) return hip_fail(c, e, "binning");
-  if ((e = launch_render_fwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
-                             c->plan.tile_h, c->TX, c->TY, cam, sd, out->color, out->depth,
-                             out->alpha, out->n_eval, st)) != hipSuccess)
-    return hip_fail(c, e, "render forward");
+  {
+    StageMark m(c, GSR_STAGE_PROJECT, st);
+    if ((e = launch_project(t.pt, scd, cam, sd, c->blk_cnt, st)) != hipSuccess) return hip_fail(c, e, "project");
+  }
+  {
+    StageMark m(c, GSR_STAGE_COMPACT, st);
+    if ((e = launch_compact(t.pt, sd, c->blk_cnt, c->ka, c->va, st)) != hipSuccess) return hip_fail(c, e, "compact");
+  }
+  {
+    StageMark m(c, GSR_STAGE_DEPTH_SORT, st);
+    if ((e = launch_depth_sort(t.stb, sd, c->ka, c->va, c->kb, c->vb, c->hist, st)) != hipSuccess)
+      return hip_fail(c, e, "depth sort");
+  }
+  {
+    StageMark m(c, GSR_STAGE_BINNING, st);
+    if ((e = launch_binning(t.bt, sd, c->counts, c->tile_cnt, st)) != hipSuccess) return hip_fail(c, e, "binning");
+  }
+  {
+    StageMark m(c, GSR_STAGE_RENDER_FWD, st);
+    if ((e = launch_render_fwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
+                               c->plan.tile_h, c->TX, c->TY, cam, sd, out->color, out->depth,
+                               out->alpha, out->n_eval, st)) != hipSuccess)
+      return hip_fail(c, e, "render forward");
+  }
   return GSR_OK;
 }
 
@@ -418,14 +457,23 @@ gsr_status gsr_backward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   const float* gd = gin ? gin->depth : nullptr;
   const float* ga = gin ? gin->alpha : nullptr;
   hipError_t e;
-  if ((e = launch_zero_grad2d(t.P, sd, c->grad2d, out->d_pose, vw->n_views, st)) != hipSuccess)
-    return hip_fail(c, e, "zero");
-  if ((e = launch_render_bwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
-                             c->plan.tile_h, c->TX, c->TY, t.grad_mask, cam, sd, gc, gd, ga,
-                             c->grad2d, st)) != hipSuccess)
-    return hip_fail(c, e, "render backward");
-  if ((e = launch_project_bwd(t.set, scd, cam, sd, c->grad2d, *out, t.P, st)) != hipSuccess)
-    return hip_fail(c, e, "projection backward");
+  {
+    StageMark m(c, GSR_STAGE_ZERO, st);
+    if ((e = launch_zero_grad2d(t.P, sd, c->grad2d, out->d_pose, vw->n_views, st)) != hipSuccess)
+      return hip_fail(c, e, "zero");
+  }
+  {
+    StageMark m(c, GSR_STAGE_RENDER_BWD, st);
+    if ((e = launch_render_bwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
+                               c->plan.tile_h, c->TX, c->TY, t.grad_mask, cam, sd, gc, gd, ga,
+                               c->grad2d, st)) != hipSuccess)
+      return hip_fail(c, e, "render backward");
+  }
+  {
+    StageMark m(c, GSR_STAGE_PROJECT_BWD, st);
+    if ((e = launch_project_bwd(t.set, scd, cam, sd, c->grad2d, *out, t.P, st)) != hipSuccess)
+      return hip_fail(c, e, "projection backward");
+  }
   return GSR_OK;
 }
 
@@ -494,6 +542,34 @@ gsr_status gsr_debug_export(gsr_ctx* c, const void* state, int32_t n_views, gsr_
   return GSR_OK;
 }
 
+gsr_status gsr_profile_enable(gsr_ctx* c, int enable) {
+  if (!c) return GSR_E_INVALID_ARG;
+  DeviceGuard g(c->device);
+  if (enable && !c->ev[0][0]) {
+    for (int i = 0; i < GSR_NUM_STAGES; ++i)
+      for (int j = 0; j < 2; ++j) {
+        hipError_t e = hipEventCreate(&c->ev[i][j]);
+        if (e != hipSuccess) return hip_fail(c, e, "event create");
+      }
+  }
+  c->prof = enable != 0;
+  for (int i = 0; i < GSR_NUM_STAGES; ++i) c->ev_used[i] = false;
+  return GSR_OK;
+}
+
+gsr_status gsr_profile_read(gsr_ctx* c, float* ms, int32_t n) {
+  if (!c || !ms || n < 0) return GSR_E_INVALID_ARG;
+  DeviceGuard g(c->device);
+  for (int i = 0; i < n; ++i) {
+    ms[i] = 0.f;
+    if (i >= GSR_NUM_STAGES || !c->ev_used[i]) continue;
+    hipError_t e = hipEventSynchronize(c->ev[i][1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms[i], c->ev[i][0], c->ev[i][1]);
+    if (e != hipSuccess) return hip_fail(c, e, "profile read");
+  }
+  return GSR_OK;
+}
+
 gsr_status gsr_apply_pose_delta(const float* vin, const float* delta, float* vout, int32_t nv,
                                 void* stream) {
   if (!vin || !delta || !vout || nv < 1) return GSR_E_INVALID_ARG;
@@ -504,8 +580,93 @@ gsr_status gsr_apply_pose_delta(const float* vin, const float* delta, float* vou
 gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* sc,
                         const gsr_views* vw, const gsr_settings* set, gsr_plan_desc* best,
                         float* best_ms, void* stream) {
-  (void)device; (void)base; (void)sc; (void)vw; (void)set; (void)best; (void)best_ms; (void)stream;
-  return GSR_E_UNIMPLEMENTED;
+  if (!base || !sc || !vw || !best || !best_ms) return GSR_E_INVALID_ARG;
+  if (check_plan(nullptr, base) != GSR_OK) return GSR_E_INVALID_ARG;
+  static const int cand[][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {32, 8}, {32, 16}, {16, 32}};
+  hipStream_t st = (hipStream_t)stream;
+  DeviceGuard g(device);
+  const int V = vw->n_views, W = vw->width, H = vw->height;
+  const long N = sc->set_offsets[sc->n_sets];
+  const long kcol = sc->sh_degree > 0 ? (long)sc->sh_stride * 3 : 3;
+  const size_t px = (size_t)V * W * H;
+  // outputs, a constant upstream gradient and gradient buffers (set-up only)
+  const size_t n_img = 5 * px, n_grad = (size_t)N * (3 + 3 + 4 + 1 + kcol) + 6 * (size_t)V;
+  float* buf = nullptr;
+  if (hipMalloc(&buf, (n_img + 5 * px + n_grad) * sizeof(float)) != hipSuccess) return GSR_E_OOM;
+  float* up = buf + n_img;
+  float* gb = up + 5 * px;
+  {
+    std::vector<float> ones(5 * px, 1.0f / (float)px);
+    if (hipMemcpy(up, ones.data(), ones.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(buf);
+      return GSR_E_DEVICE;
+    }
+  }
+  gsr_images img{buf, buf + 3 * px, buf + 4 * px, nullptr};
+  gsr_grad_images gin{up, up + 3 * px, up + 4 * px};
+  gsr_grads gr{gb, gb + 3 * N, gb + 6 * N, gb + 10 * N, gb + 11 * N, gb + 11 * N + kcol * N};
+  float best_t = 1e30f;
+  gsr_plan_desc best_p = *base;
+  gsr_status result = GSR_E_INVALID_ARG;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  for (auto& c : cand) {
+    gsr_plan_desc p = *base;
+    p.tile_w = c[0];
+    p.tile_h = c[1];
+    if (check_plan(nullptr, &p) != GSR_OK) continue;
+    gsr_ctx* ctx = nullptr;
+    if (gsr_create(&ctx, device) != GSR_OK) { result = GSR_E_DEVICE; break; }
+    void* state = nullptr;
+    size_t sb = 0;
+    float t_ms = -1.f;
+    for (int attempt = 0; attempt < 2 && t_ms < 0.f; ++attempt) {
+      if (gsr_plan(ctx, &p) != GSR_OK) break;
+      gsr_state_bytes(&p, &sb);
+      if (state) (void)hipFree(state);
+      state = nullptr;
+      if (hipMalloc(&state, sb) != hipSuccess) { state = nullptr; break; }
+      if (gsr_forward(ctx, sc, vw, set, state, &img, st) != GSR_OK) break;
+      gsr_counts cnt;
+      gsr_status ps = gsr_poll(ctx, state, &cnt, st);
+      if (ps == GSR_E_OVERFLOW) {
+        p.max_instances = std::min<int64_t>(0xFFFFFFFEL, cnt.instances + cnt.instances / 8 + 1024);
+        continue;
+      }
+      if (ps != GSR_OK) break;
+      if (gsr_backward(ctx, sc, vw, set, state, &gin, &gr, st) != GSR_OK) break;
+      float tmin = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        (void)hipEventRecord(e0, st);
+        gsr_forward(ctx, sc, vw, set, state, &img, st);
+        gsr_backward(ctx, sc, vw, set, state, &gin, &gr, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        tmin = std::min(tmin, ms);
+      }
+      t_ms = tmin;
+    }
+    if (state) (void)hipFree(state);
+    gsr_destroy(ctx);
+    if (t_ms >= 0.f) {
+      result = GSR_OK;
+      if (t_ms < best_t) {
+        best_t = t_ms;
+        best_p = p;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(buf);
+  if (result == GSR_OK) {
+    *best = best_p;
+    *best_ms = best_t;
+  }
+  return result;
 }
 
 }  // extern "C"

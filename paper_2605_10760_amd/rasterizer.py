@@ -232,6 +232,17 @@ class Rasterizer:
             self.replan(max_instances=min(0xFFFFFFFE, max(1 << 20, int(c["instances"] * margin))))
         return c
 
+    def profile(self, enable: bool = True):
+        """Record per-stage HIP events in later forward/backward calls."""
+        self._check(self.lib.gsr_profile_enable(self.ctx, int(enable)))
+
+    def stage_ms(self) -> dict:
+        """Milliseconds per stage of the most recent calls (synchronises)."""
+        n = len(L.STAGES)
+        buf = (C.c_float * n)()
+        self._check(self.lib.gsr_profile_read(self.ctx, buf, n))
+        return {name: float(buf[i]) for i, name in enumerate(L.STAGES)}
+
     def debug_export(self, state: torch.Tensor, n_views: int, n_pairs: int, n_inst: int,
                      stream=None) -> dict:
         TX = -(-self.desc.width // self.desc.tile_w)
@@ -252,6 +263,28 @@ class Rasterizer:
                                               int(n_views), C.byref(d), _stream(stream)))
         return dict(zkeys=z, rects=rects, order=order[:int(vis_off[-1])], vis_off=vis_off,
                     inst=inst[:n_inst], ranges=ranges, t_final=tf, last=last, TX=TX, TY=TY)
+
+
+def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = None,
+             max_instances: int | None = None, z_near=0.2, device: int | None = None,
+             stream=None):
+    """Time forward+backward of this call for every supported tile shape
+    (native, in libgsr) and return (best (tile_w, tile_h), its ms)."""
+    lib = L.load()
+    dev = torch.cuda.current_device() if device is None else int(device)
+    P = pairs_of(scene, views) if max_pairs is None else int(max_pairs)
+    base = L.PlanDesc(P, int(max_instances or max(1 << 20, 24 * P)), views.n, views.width,
+                      views.height, 16, 16, 0)
+    sc, keep1 = Rasterizer._scene(scene)
+    vw, keep2 = Rasterizer._views(views)
+    st = Rasterizer._settings(z_near)
+    best = L.PlanDesc()
+    ms = C.c_float()
+    status = lib.gsr_autotune(dev, C.byref(base), C.byref(sc), C.byref(vw), C.byref(st),
+                              C.byref(best), C.byref(ms), _stream(stream))
+    if status != L.GSR_OK:
+        raise L.GsrError(status, "gsr_autotune failed")
+    return (best.tile_w, best.tile_h), float(ms.value)
 
 
 def apply_pose_delta(viewmats: torch.Tensor, delta: torch.Tensor, out: torch.Tensor | None = None,

@@ -378,3 +378,69 @@ def test_room_plain_window_gradients():
     for k_gpu, k_ref in GMAP.items():
         e_inf, e_2 = grad_rel_err(got[k_gpu], ref[k_ref])
         assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+
+
+def test_profile_stages_and_autotune():
+    announce("profile + autotune")
+    from paper_2605_10760_amd import autotune
+    scene, views = _scene_case("small-plain")
+    g = gpu_forward(scene, views, export=False)
+    r = g["rast"]
+    r.profile(True)
+    c, d, a, state = r.forward(g["scene_t"], g["views_t"])
+    import torch
+    gc = torch.ones_like(c)
+    r.backward(g["scene_t"], g["views_t"], state, gc, None, None)
+    ms = r.stage_ms()
+    r.profile(False)
+    assert all(v > 0 for v in ms.values()), ms
+    tile, t_ms = autotune(g["scene_t"], g["views_t"])
+    assert tile in [(16, 16), (16, 8), (8, 16), (8, 8), (32, 8), (32, 16), (16, 32)]
+    assert t_ms > 0
+    g2 = gpu_forward(scene, views, tile=tile, export=False)
+    np.testing.assert_array_equal(g2["color"], g["color"])
+
+
+def test_graph_replay_matches_eager():
+    """forward+backward captured once in a HIP graph and replayed several
+    times, with eager work in between, reproduce the eager results."""
+    announce("graph replay")
+    import torch
+    scene, views = _scene_case("multi-agent-small")
+    g = gpu_forward(scene, views, export=False)
+    r, st_, vt = g["rast"], g["scene_t"], g["views_t"]
+    V, H, W = views.n, views.height, views.width
+    state = r.new_state()
+    out = (torch.empty((V, 3, H, W), device="cuda"), torch.empty((V, H, W), device="cuda"),
+           torch.empty((V, H, W), device="cuda"))
+    rng = np.random.default_rng(2)
+    gc = torch.from_numpy(rng.normal(size=(V, 3, H, W)).astype(np.float32)).cuda()
+    gd = torch.from_numpy(rng.normal(size=(V, H, W)).astype(np.float32)).cuda()
+    grads = r.backward(st_, vt, g["state"], gc, gd, None)
+    ref = {k: v.clone() for k, v in grads.items()}
+    eager_color = g["color"]
+
+    def step():
+        r.forward(st_, vt, state=state, out=out)
+        r.backward(st_, vt, state, gc, gd, None, out=grads)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(4):
+        for v_ in grads.values():
+            v_.fill_(float("nan"))
+        out[0].fill_(-1.0)
+        r.forward(st_, vt)          # unrelated eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out[0].cpu().numpy(), eager_color)
+        for k in ref:
+            e_inf, _ = grad_rel_err(grads[k].cpu().numpy(), ref[k].cpu().numpy())
+            assert e_inf <= 1e-5, (rep, k, e_inf)
