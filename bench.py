@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -192,6 +194,14 @@ def main():
     from paper_2605_10760_amd import Rasterizer, SceneTensors, ViewTensors
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy kernel of known size: 1 GiB read + 1 GiB written per launch
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tile = tuple(int(x) for x in args.tile.split("x"))
     wl = make_workload(args.workload)
     sc_np, vw_np = wl.scene, wl.views

@@ -59,11 +59,12 @@ bool pow2_tile(int x) { return x == 8 || x == 16 || x == 32; }
 
 int auto_chunk(const gsr_plan_desc& p) {
   if (p.chunk > 0) return p.chunk;
-  // ~64+ chunks per view for parallelism, chunk >= 256 so the per-chunk
-  // dense tile pass stays small relative to the chunk's pairs.
+  // Chunks of 256..2048 depth-sorted pairs: about a thousand per view so the
+  // one-wave-per-chunk scatter has enough waves, while the dense per-chunk
+  // tile histogram (one counter per tile) stays a fraction of the instances.
   long per_view = std::max<long>(1, p.max_pairs / std::max(1, p.max_views));
   long c = 256;
-  while (c < 4096 && per_view / c > 256) c *= 2;
+  while (c < 2048 && per_view / c > 1024) c *= 2;
   return (int)c;
 }
 

@@ -224,6 +224,237 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(int W, int H, int TX, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// One wave per tile, PPL = TW*TH/64 pixels per lane.  Each record staged in
+// LDS is read once per lane and used for its PPL pixels; the forward's early
+// exit is a wave ballot, and the backward reduces each entry's ten splat
+// gradients once per tile (one DPP wave reduction) and issues the atomics
+// from ten lanes.
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(64) void k_render_fwd_w(int W, int H, int TX, int TY, CamDev cam,
+                                                     StateDev st, float* color, float* depth,
+                                                     float* alpha, int32_t* n_eval) {
+  constexpr int PPL = TW * TH / 64;
+  __shared__ float4 s0[B], s1[B], s2[B];
+  const int T = TX * TY;
+  const int g = blockIdx.x;
+  const int v = g / T, tl = g - v * T;
+  const int ty = tl / TX, tx = tl - ty * TX;
+  const int lane = threadIdx.x;
+  float fxp[PPL], fyp[PPL], Tc[PPL], c0[PPL], c1[PPL], c2[PPL], dz[PPL];
+  uint32_t last[PPL];
+  int ne[PPL];
+  bool done[PPL];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int p = lane + 64 * k;
+    const int px = tx * TW + (p % TW), py = ty * TH + (p / TW);
+    done[k] = !(px < W && py < H);
+    fxp[k] = (float)px + 0.5f;
+    fyp[k] = (float)py + 0.5f;
+    Tc[k] = 1.f;
+    c0[k] = c1[k] = c2[k] = dz[k] = 0.f;
+    last[k] = 0;
+    ne[k] = 0;
+  }
+  uint2 rg = st.ranges[g];
+  if (st.hdr->overflow) rg = make_uint2(0u, 0u);
+  for (uint32_t base = rg.x; base < rg.y; base += B) {
+    bool live = false;
+#pragma unroll
+    for (int k = 0; k < PPL; ++k) live |= !done[k];
+    if (__ballot(live) == 0ull) break;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < B / 64; ++r) {
+      const uint32_t idx = base + lane + 64 * r;
+      if (idx < rg.y) {
+        const float4* rp = st.rec + 3 * (size_t)st.inst[idx];
+        s0[lane + 64 * r] = rp[0];
+        s1[lane + 64 * r] = rp[1];
+        s2[lane + 64 * r] = rp[2];
+      }
+    }
+    __syncthreads();
+    const int n = (int)min((uint32_t)B, rg.y - base);
+    for (int j = 0; j < n; ++j) {
+      const float4 a = s0[j], b = s1[j];
+      float wgt[PPL];
+      bool blend = false;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        wgt[k] = 0.f;
+        if (done[k]) continue;
+        float dx, dy;
+        const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
+        ++ne[k];
+        if (power > 0.f) continue;
+        const float al = fminf(ALPHA_MAX, b.y * __expf(power));
+        if (al < ALPHA_MIN) continue;
+        const float Tn = Tc[k] * (1.f - al);
+        if (Tn < T_MIN) {
+          done[k] = true;
+          continue;
+        }
+        wgt[k] = al * Tc[k];
+        Tc[k] = Tn;
+        last[k] = base - rg.x + (uint32_t)j + 1u;
+        blend = true;
+      }
+      if (__ballot(blend) != 0ull) {
+        const float4 c = s2[j];
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          c0[k] += c.x * wgt[k];
+          c1[k] += c.y * wgt[k];
+          c2[k] += c.z * wgt[k];
+          dz[k] += b.z * wgt[k];
+        }
+      }
+    }
+  }
+  const size_t HW = (size_t)W * H;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int p = lane + 64 * k;
+    const int px = tx * TW + (p % TW), py = ty * TH + (p / TW);
+    if (!(px < W && py < H)) continue;
+    const size_t q = (size_t)py * W + px;
+    color[(3 * (size_t)v + 0) * HW + q] = c0[k] + Tc[k] * cam.bg0;
+    color[(3 * (size_t)v + 1) * HW + q] = c1[k] + Tc[k] * cam.bg1;
+    color[(3 * (size_t)v + 2) * HW + q] = c2[k] + Tc[k] * cam.bg2;
+    depth[v * HW + q] = dz[k];
+    alpha[v * HW + q] = 1.f - Tc[k];
+    st.tfinal[v * HW + q] = Tc[k];
+    st.last[v * HW + q] = last[k];
+    if (n_eval) n_eval[v * HW + q] = ne[k];
+  }
+}
+
+template <int TW, int TH, int B>
+__global__ __launch_bounds__(64) void k_render_bwd_w(int W, int H, int TX, int TY,
+                                                     unsigned long long grad_mask, CamDev cam,
+                                                     StateDev st, const float* gcol,
+                                                     const float* gdep, const float* galp,
+                                                     float* grad2d) {
+  constexpr int PPL = TW * TH / 64;
+  __shared__ float4 s0[B], s1[B], s2[B];
+  __shared__ uint32_t sp[B];
+  const int T = TX * TY;
+  const int g = blockIdx.x;
+  const int v = g / T, tl = g - v * T;
+  if (!((grad_mask >> v) & 1ull)) return;
+  if (st.hdr->overflow) return;
+  const uint2 rg = st.ranges[g];
+  if (rg.x == rg.y) return;
+  const int ty = tl / TX, tx = tl - ty * TX;
+  const int lane = threadIdx.x;
+  const size_t HW = (size_t)W * H;
+  float fxp[PPL], fyp[PPL], Tc[PPL], Tf[PPL], g0[PPL], g1[PPL], g2[PPL], gd[PPL], ga[PPL];
+  float S0[PPL], S1[PPL], S2[PPL], SD[PPL];
+  uint32_t lastp[PPL];
+  uint32_t mylast = 0;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int p = lane + 64 * k;
+    const int px = tx * TW + (p % TW), py = ty * TH + (p / TW);
+    fxp[k] = (float)px + 0.5f;
+    fyp[k] = (float)py + 0.5f;
+    Tc[k] = 1.f; lastp[k] = 0;
+    g0[k] = g1[k] = g2[k] = gd[k] = ga[k] = 0.f;
+    if (px < W && py < H) {
+      const size_t q = (size_t)py * W + px;
+      Tc[k] = st.tfinal[v * HW + q];
+      lastp[k] = st.last[v * HW + q];
+      if (gcol) {
+        g0[k] = gcol[(3 * (size_t)v + 0) * HW + q];
+        g1[k] = gcol[(3 * (size_t)v + 1) * HW + q];
+        g2[k] = gcol[(3 * (size_t)v + 2) * HW + q];
+      }
+      if (gdep) gd[k] = gdep[v * HW + q];
+      if (galp) ga[k] = galp[v * HW + q];
+    }
+    Tf[k] = Tc[k];
+    S0[k] = Tf[k] * cam.bg0;
+    S1[k] = Tf[k] * cam.bg1;
+    S2[k] = Tf[k] * cam.bg2;
+    SD[k] = 0.f;
+    mylast = max(mylast, lastp[k]);
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) mylast = max(mylast, (uint32_t)__shfl_xor((int)mylast, d, 64));
+  const int maxlast = (int)mylast;
+  for (int end = maxlast; end > 0; end -= B) {
+    const int start = max(0, end - B);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < B / 64; ++r) {
+      const int i = start + lane + 64 * r;
+      if (i < end) {
+        const uint32_t pr = st.inst[rg.x + i];
+        const float4* rp = st.rec + 3 * (size_t)pr;
+        s0[lane + 64 * r] = rp[0];
+        s1[lane + 64 * r] = rp[1];
+        s2[lane + 64 * r] = rp[2];
+        sp[lane + 64 * r] = pr;
+      }
+    }
+    __syncthreads();
+    for (int j = end - start - 1; j >= 0; --j) {
+      const int pos = start + j;
+      const float4 a = s0[j], b = s1[j], c = s2[j];
+      float acc[GRAD2D];
+#pragma unroll
+      for (int i = 0; i < GRAD2D; ++i) acc[i] = 0.f;
+      bool act = false;
+#pragma unroll
+      for (int k = 0; k < PPL; ++k) {
+        if (pos >= (int)lastp[k]) continue;
+        float dx, dy;
+        const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
+        const float G = __expf(power);
+        const float raw = b.y * G;
+        const float al = fminf(ALPHA_MAX, raw);
+        if (power > 0.f || al < ALPHA_MIN) continue;
+        act = true;
+        const float inv = 1.f / (1.f - al);
+        const float Tb = Tc[k] * inv;
+        const float wgt = al * Tb;
+        const float dA = (c.x * Tb - S0[k] * inv) * g0[k] + (c.y * Tb - S1[k] * inv) * g1[k] +
+                         (c.z * Tb - S2[k] * inv) * g2[k] + (b.z * Tb - SD[k] * inv) * gd[k] +
+                         Tf[k] * inv * ga[k];
+        S0[k] += c.x * wgt;
+        S1[k] += c.y * wgt;
+        S2[k] += c.z * wgt;
+        SD[k] += b.z * wgt;
+        acc[6] += wgt * g0[k];
+        acc[7] += wgt * g1[k];
+        acc[8] += wgt * g2[k];
+        acc[9] += wgt * gd[k];
+        if (raw <= ALPHA_MAX) {
+          const float gp = al * dA;
+          acc[5] += G * dA;
+          acc[0] -= gp * (a.z * dx + a.w * dy);
+          acc[1] -= gp * (a.w * dx + b.x * dy);
+          acc[2] -= 0.5f * gp * dx * dx;
+          acc[3] -= gp * dx * dy;
+          acc[4] -= 0.5f * gp * dy * dy;
+        }
+        Tc[k] = Tb;
+      }
+      if (__ballot(act) != 0ull) {
+        float r[GRAD2D];
+#pragma unroll
+        for (int i = 0; i < GRAD2D; ++i) r[i] = wave_total(acc[i]);
+        float mine = 0.f;
+#pragma unroll
+        for (int i = 0; i < GRAD2D; ++i) mine = (lane == i) ? r[i] : mine;
+        if (lane < GRAD2D && mine != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + lane, mine);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_zero_grad2d(int P, StateDev st, float* grad2d,
                                                      float* d_pose, int nv) {
   const int i = blockIdx.x * 256 + threadIdx.x;
