@@ -59,12 +59,10 @@ bool pow2_tile(int x) { return x == 8 || x == 16 || x == 32; }
 
 int auto_chunk(const gsr_plan_desc& p) {
   if (p.chunk > 0) return p.chunk;
-  // Chunks of 256..2048 depth-sorted pairs: about a thousand per view so the
-  // one-wave-per-chunk scatter has enough waves, while the dense per-chunk
-  // tile histogram (one counter per tile) stays a fraction of the instances.
-  long per_view = std::max<long>(1, p.max_pairs / std::max(1, p.max_views));
-  long c = 256;
-  while (c < 2048 && per_view / c > 1024) c *= 2;
+  // 64..256 depth-sorted pairs per chunk: small batches (one view) need many
+  // chunks to fill the GPU; large ones use longer per-tile runs per chunk.
+  long c = 64;
+  while (c < 256 && p.max_pairs / c > 65536) c *= 2;
   return (int)c;
 }
 
@@ -389,6 +387,15 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   c->counts = (uint32_t*)(b + o_cnt);
   c->tile_cnt = (uint32_t*)(b + o_tc);
   c->grad2d = (float*)(b + o_g2);
+  // The per-pair screen-space gradient rows start at zero and every
+  // backward leaves them at zero (the projection backward clears what it
+  // reads), so no clearing pass is needed per call.
+  e = hipMemset(c->grad2d, 0, P * GRAD2D * 4);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_ws(c);
+    return hip_fail(c, e, "workspace clear");
+  }
   c->planned = true;
   return GSR_OK;
 }
@@ -460,7 +467,7 @@ gsr_status gsr_backward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   hipError_t e;
   {
     StageMark m(c, GSR_STAGE_ZERO, st);
-    if ((e = launch_zero_grad2d(t.P, sd, c->grad2d, out->d_pose, vw->n_views, st)) != hipSuccess)
+    if ((e = launch_zero_pose(out->d_pose, vw->n_views, st)) != hipSuccess)
       return hip_fail(c, e, "zero");
   }
   {

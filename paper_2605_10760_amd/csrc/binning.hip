@@ -27,8 +27,10 @@ __device__ __forceinline__ void chunk_range(const BinTab& t, const StateHeader* 
 
 __global__ __launch_bounds__(256) void k_bin_count(BinTab t, StateDev st, uint32_t* counts) {
   extern __shared__ int dif[];  // (TY+1) x (TX+1)
+  const int b = xcd_remap(blockIdx.x, t.cblk_off[t.nv]);
+  if (b < 0) return;
   int v, lo, hi;
-  chunk_range(t, st.hdr, blockIdx.x, v, lo, hi);
+  chunk_range(t, st.hdr, b, v, lo, hi);
   if (lo >= hi) return;
   const int TX = t.TX, TY = t.TY, SX = TX + 1;
   const int nd = (TY + 1) * SX;
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(256) void k_bin_count(BinTab t, StateDev st, uint32
     }
   }
   __syncthreads();
-  uint32_t* out = counts + (size_t)blockIdx.x * t.T;
+  uint32_t* out = counts + (size_t)b * t.T;
   for (int x = threadIdx.x; x < TX; x += 256) {
     int run = 0;
     for (int y = 0; y < TY; ++y) {
@@ -62,34 +64,60 @@ __global__ __launch_bounds__(256) void k_bin_count(BinTab t, StateDev st, uint32
   }
 }
 
-// Thread per global tile: exclusive prefix of its counts over the view's
-// active chunks (in place) and the tile's total.
-__global__ __launch_bounds__(256) void k_bin_colscan(BinTab t, const StateHeader* hdr,
-                                                     uint32_t* counts, uint32_t* tile_cnt) {
-  const int g = blockIdx.x * 256 + threadIdx.x;
-  if (g >= t.nv * t.T) return;
-  const int v = g / t.T, tl = g - v * t.T;
-  const int n = (int)(hdr->vis_off[v + 1] - hdr->vis_off[v]);
-  const int nc = (n + t.chunk - 1) / t.chunk;
-  uint32_t* c = counts + (size_t)t.cblk_off[v] * t.T + tl;
+// Exclusive prefix of each tile's counts over its view's active chunks (in
+// place) and the tile's total.  A workgroup covers 64 consecutive tiles
+// (lanes: coalesced rows) x 16 segments of the chunk range (waves), so the
+// dependent walk down a column is 16x shorter.
+constexpr int CS_TILES = 64, CS_SEGS = 16;
+__global__ __launch_bounds__(CS_TILES* CS_SEGS) void k_bin_colscan(BinTab t,
+                                                                  const StateHeader* hdr,
+                                                                  uint32_t* counts,
+                                                                  uint32_t* tile_cnt) {
+  __shared__ uint32_t part[CS_SEGS][CS_TILES];
+  const int lane = threadIdx.x & (CS_TILES - 1), seg = threadIdx.x / CS_TILES;
+  const int g = blockIdx.x * CS_TILES + lane;
+  const bool ok = g < t.nv * t.T;
+  int nc = 0, k0 = 0, k1 = 0;
+  uint32_t* c = counts;
+  if (ok) {
+    const int v = g / t.T, tl = g - v * t.T;
+    const int n = (int)(hdr->vis_off[v + 1] - hdr->vis_off[v]);
+    nc = (n + t.chunk - 1) / t.chunk;
+    k0 = (int)((long)nc * seg / CS_SEGS);
+    k1 = (int)((long)nc * (seg + 1) / CS_SEGS);
+    c = counts + (size_t)t.cblk_off[v] * t.T + tl;
+  }
+  uint32_t sum = 0;
+  int k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    uint32_t x[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) x[j] = c[(size_t)(k + j) * t.T];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) sum += x[j];
+  }
+  for (; k < k1; ++k) sum += c[(size_t)k * t.T];
+  part[seg][lane] = sum;
+  __syncthreads();
   uint32_t run = 0;
-  int k = 0;
-  for (; k + 8 <= nc; k += 8) {
-    uint32_t x[8];
+  for (int s2 = 0; s2 < seg; ++s2) run += part[s2][lane];
+  if (ok && seg == CS_SEGS - 1) tile_cnt[g] = run + sum;
+  k = k0;
+  for (; k + 4 <= k1; k += 4) {
+    uint32_t x[4];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) x[j] = c[(size_t)(k + j) * t.T];
+    for (int j = 0; j < 4; ++j) x[j] = c[(size_t)(k + j) * t.T];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < 4; ++j) {
       c[(size_t)(k + j) * t.T] = run;
       run += x[j];
     }
   }
-  for (; k < nc; ++k) {
+  for (; k < k1; ++k) {
     const uint32_t x = c[(size_t)k * t.T];
     c[(size_t)k * t.T] = run;
     run += x;
   }
-  tile_cnt[g] = run;
 }
 
 // One workgroup: tile ranges from the per-tile totals; total instance count
@@ -133,12 +161,14 @@ __global__ __launch_bounds__(1024) void k_tile_scan(BinTab t, StateDev st,
 __global__ __launch_bounds__(64) void k_bin_scatter(BinTab t, StateDev st,
                                                     const uint32_t* counts) {
   extern __shared__ uint32_t cur[];  // [T]
+  const int b = xcd_remap(blockIdx.x, t.cblk_off[t.nv]);
+  if (b < 0) return;
   int v, lo, hi;
-  chunk_range(t, st.hdr, blockIdx.x, v, lo, hi);
+  chunk_range(t, st.hdr, b, v, lo, hi);
   if (lo >= hi) return;
   if (st.hdr->overflow) return;
   const int lane = threadIdx.x, TX = t.TX, T = t.T;
-  const uint32_t* cb = counts + (size_t)blockIdx.x * T;
+  const uint32_t* cb = counts + (size_t)b * T;
   const uint2* rg = st.ranges + (size_t)v * T;
   for (int i = lane; i < T; i += 64) cur[i] = rg[i].x + cb[i];
   __syncthreads();
@@ -173,13 +203,13 @@ hipError_t launch_binning(const BinTab& t, StateDev st, uint32_t* counts, uint32
   const int nc = t.cblk_off[t.nv];
   const size_t dif_bytes = (size_t)(t.TX + 1) * (t.TY + 1) * sizeof(int);
   if (nc > 0)
-    hipLaunchKernelGGL(k_bin_count, dim3(nc), dim3(256), dif_bytes, s, t, st, counts);
+    hipLaunchKernelGGL(k_bin_count, dim3(xcd_grid(nc)), dim3(256), dif_bytes, s, t, st, counts);
   const int ntile = t.nv * t.T;
-  hipLaunchKernelGGL(k_bin_colscan, dim3((ntile + 255) / 256), dim3(256), 0, s, t, st.hdr,
-                     counts, tile_cnt);
+  hipLaunchKernelGGL(k_bin_colscan, dim3((ntile + CS_TILES - 1) / CS_TILES),
+                     dim3(CS_TILES * CS_SEGS), 0, s, t, st.hdr, counts, tile_cnt);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, t, st, tile_cnt);
   if (nc > 0)
-    hipLaunchKernelGGL(k_bin_scatter, dim3(nc), dim3(64), (size_t)t.T * sizeof(uint32_t), s, t,
+    hipLaunchKernelGGL(k_bin_scatter, dim3(xcd_grid(nc)), dim3(64), (size_t)t.T * sizeof(uint32_t), s, t,
                        st, counts);
   return hipGetLastError();
 }

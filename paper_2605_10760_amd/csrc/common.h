@@ -8,6 +8,20 @@ namespace gsr {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
+// The dispatcher hands workgroup b to XCD (b mod 8).  For a grid of
+// 8 * ceil(n/8) workgroups this returns the logical index x*ceil(n/8) + b/8 so
+// that every XCD (and its private L2) works through one contiguous eighth of
+// the logical range in order; -1 for the surplus workgroups.  Neighbouring
+// logical items (adjacent tiles, consecutive sort blocks or binning chunks)
+// then share an L2: gathers of the same records hit, and partial-line writes
+// to the same output runs merge before they reach HBM.
+__host__ __device__ __forceinline__ int xcd_grid(int n) { return 8 * ((n + 7) / 8); }
+__device__ __forceinline__ int xcd_remap(int b, int n) {
+  const int per = (n + 7) / 8;
+  const int l = (b & 7) * per + (b >> 3);
+  return l < n ? l : -1;
+}
+
 // Index s with off[s] <= b < off[s+1] for a non-decreasing off[0..n].
 __device__ __forceinline__ int find_seg(const int* off, int n, int b) {
   int lo = 0, hi = n;

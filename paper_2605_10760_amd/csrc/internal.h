@@ -7,7 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/gsr.h"
+#include "gsr.h"
 
 namespace gsr {
 
@@ -120,10 +120,9 @@ hipError_t launch_render_bwd(int nv, int W, int H, int TW, int TH, int TX, int T
                              unsigned long long grad_mask, const CamDev& cam, StateDev st,
                              const float* g_color, const float* g_depth, const float* g_alpha,
                              float* grad2d, hipStream_t s);
-hipError_t launch_zero_grad2d(int P, StateDev st, float* grad2d, float* d_pose, int nv,
-                              hipStream_t s);
+hipError_t launch_zero_pose(float* d_pose, int nv, hipStream_t s);
 hipError_t launch_project_bwd(const SetTab& t, const SceneDev& sc, const CamDev& cam,
-                              StateDev st, const float* grad2d, const gsr_grads& g,
+                              StateDev st, float* grad2d, const gsr_grads& g,
                               int n_total, hipStream_t s);
 hipError_t launch_pose_delta(const float* vin, const float* delta, float* vout, int nv,
                              hipStream_t s);

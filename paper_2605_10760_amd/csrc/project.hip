@@ -148,7 +148,8 @@ __device__ __forceinline__ bool key_path(const float* m, const float* ls, const 
 template <int SHD>
 __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, CamDev cam,
                                                         StateDev st, uint32_t* blk_cnt) {
-  const int b = blockIdx.x;
+  const int b = xcd_remap(blockIdx.x, t.blk_off[t.nv]);
+  if (b < 0) return;
   const int v = find_seg(t.blk_off, t.nv, b);
   const int local = (b - t.blk_off[v]) * PROJ_BLOCK + (int)threadIdx.x;
   const int n = t.pair_off[v + 1] - t.pair_off[v];
@@ -238,8 +239,13 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
         col[0] = fmaxf(r, 0.f); col[1] = fmaxf(g, 0.f); col[2] = fmaxf(bl, 0.f);
       }
       float4* rp = st.rec + 3 * (long)pair;
-      rp[0] = make_float4((float)u, (float)vv, (float)(c / det), (float)(-bb / det));
-      rp[1] = make_float4((float)(a / det), (float)sig, (float)p[2], 0.f);
+      // conic (A, B, C) = (c, -b, a)/det, stored pre-scaled so that the
+      // exponent in base 2 is A' dx^2 + B' dx dy + C' dy^2:
+      // A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2
+      const double L2E = 1.4426950408889634;
+      rp[0] = make_float4((float)u, (float)vv, (float)(-0.5 * L2E * c / det),
+                          (float)(L2E * bb / det));
+      rp[1] = make_float4((float)(-0.5 * L2E * a / det), (float)sig, (float)p[2], 0.f);
       rp[2] = make_float4(col[0], col[1], col[2], 0.f);
     }
   }
@@ -284,7 +290,8 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(ProjTab t, uint32_t* blk, 
 __global__ __launch_bounds__(PROJ_BLOCK) void k_compact(ProjTab t, StateDev st,
                                                         const uint32_t* blk_scan,
                                                         uint32_t* kout, uint32_t* vout) {
-  const int b = blockIdx.x;
+  const int b = xcd_remap(blockIdx.x, t.blk_off[t.nv]);
+  if (b < 0) return;
   const int v = find_seg(t.blk_off, t.nv, b);
   const int local = (b - t.blk_off[v]) * PROJ_BLOCK + (int)threadIdx.x;
   const int n = t.pair_off[v + 1] - t.pair_off[v];
@@ -357,10 +364,10 @@ hipError_t launch_project(const ProjTab& t, const SceneDev& sc, const CamDev& ca
   const int nb = t.blk_off[t.nv];
   if (nb == 0) return hipSuccess;
   switch (sc.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project<0>, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
-    default: hipLaunchKernelGGL(k_project<3>, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+    case 0: hipLaunchKernelGGL(k_project<0>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+    case 1: hipLaunchKernelGGL(k_project<1>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+    case 2: hipLaunchKernelGGL(k_project<2>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+    default: hipLaunchKernelGGL(k_project<3>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
   }
   return hipGetLastError();
 }
@@ -370,7 +377,7 @@ hipError_t launch_compact(const ProjTab& t, StateDev st, uint32_t* blk_cnt, uint
   hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, t, blk_cnt, st.hdr);
   const int nb = t.blk_off[t.nv];
   if (nb > 0)
-    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(PROJ_BLOCK), 0, s, t, st, blk_cnt, kout, vout);
+    hipLaunchKernelGGL(k_compact, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, st, blk_cnt, kout, vout);
   return hipGetLastError();
 }
 

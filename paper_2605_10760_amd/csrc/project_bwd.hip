@@ -64,10 +64,11 @@ __device__ __forceinline__ void sh_eval_grad(float x, float y, float z, float* Y
 
 template <int SHD>
 __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamDev cam, StateDev st,
-                                                     const float* grad2d, gsr_grads out) {
+                                                     float* grad2d, gsr_grads out) {
   constexpr int NB = (SHD + 1) * (SHD + 1);
   __shared__ float red[2][4][6];
-  const int b = blockIdx.x;
+  const int b = xcd_remap(blockIdx.x, t.set_blk[t.ns]);
+  if (b < 0) return;
   const int s = find_seg(t.set_blk, t.ns, b);
   const int local = (b - t.set_blk[s]) * 256 + (int)threadIdx.x;
   const int nset = t.set_goff[s + 1] - t.set_goff[s];
@@ -113,12 +114,18 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
       const float tc[3] = {vm[3], vm[7], vm[11]};
       const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
       const float fx = in.x, fy = in.y;
-      const float* g10 = grad2d + (size_t)GRAD2D * pair;
-      const float gu = g10[0], gv = g10[1], gA = g10[2], gB = g10[3], gC = g10[4];
-      const float gs = g10[5], gz = g10[9];
-      float gc[3] = {g10[6], g10[7], g10[8]};
+      float2* g10 = reinterpret_cast<float2*>(grad2d + (size_t)GRAD2D * pair);
+      const float2 q0 = g10[0], q1 = g10[1], q2 = g10[2], q3 = g10[3], q4 = g10[4];
+      // consume and clear the row: rows are zero between backward calls
+#pragma unroll
+      for (int k = 0; k < GRAD2D / 2; ++k) g10[k] = make_float2(0.f, 0.f);
+      const float gu = q0.x, gv = q0.y, gA = q1.x, gB = q1.y, gC = q2.x;
+      const float gs = q2.y, gz = q4.y;
+      float gc[3] = {q3.x, q3.y, q4.x};
       const float4 r0 = st.rec[3 * (size_t)pair], r1 = st.rec[3 * (size_t)pair + 1];
-      const float A = r0.z, B = r0.w, C = r1.x;
+      // unscale the stored conic (see the projection's record)
+      constexpr float LN2 = 0.6931471805599453f;
+      const float A = -2.f * LN2 * r0.z, B = -LN2 * r0.w, C = -2.f * LN2 * r1.x;
 
       float p[3];
       for (int i = 0; i < 3; ++i) p[i] = Rc[i][0] * m[0] + Rc[i][1] * m[1] + Rc[i][2] * m[2] + tc[i];
@@ -285,16 +292,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
 }
 
 hipError_t launch_project_bwd(const SetTab& t, const SceneDev& sc, const CamDev& cam, StateDev st,
-                              const float* grad2d, const gsr_grads& g, int n_total,
+                              float* grad2d, const gsr_grads& g, int n_total,
                               hipStream_t s) {
   (void)n_total;
   const int nb = t.set_blk[t.ns];
   if (nb == 0) return hipSuccess;
   switch (sc.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(nb), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
-    case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(nb), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
-    case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(nb), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
-    default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(nb), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
+    case 0: hipLaunchKernelGGL(k_project_bwd<0>, dim3(xcd_grid(nb)), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
+    case 1: hipLaunchKernelGGL(k_project_bwd<1>, dim3(xcd_grid(nb)), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
+    case 2: hipLaunchKernelGGL(k_project_bwd<2>, dim3(xcd_grid(nb)), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
+    default: hipLaunchKernelGGL(k_project_bwd<3>, dim3(xcd_grid(nb)), dim3(256), 0, s, t, sc, cam, st, grad2d, g); break;
   }
   return hipGetLastError();
 }

@@ -18,25 +18,37 @@ constexpr float ALPHA_MAX = 0.99f;
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float T_MIN = 1e-4f;
 
-// Exponent of a splat at a pixel sample point.  Contraction is off so the
-// forward and the backward evaluate it with identical roundings and take
-// identical skip decisions.
+constexpr float LN2 = 0.6931471805599453f;
+
+// Exponent of a splat at a pixel sample point, in base 2: the record holds
+// the conic pre-scaled by -log2(e)/2 (A, C) and -log2(e) (B), so
+// G = 2^p with p = A' dx^2 + B' dx dy + C' dy^2.  The operation sequence is
+// spelled out (explicit fma, no other contraction) so the forward and the
+// backward take identical skip decisions.
 __device__ __forceinline__ float splat_power(const float4& a, const float4& b, float fx, float fy,
                                              float& dx, float& dy) {
 #pragma clang fp contract(off)
   dx = a.x - fx;
   dy = a.y - fy;
-  return -0.5f * (a.z * dx * dx + b.x * dy * dy) - a.w * dx * dy;
+  return fmaf(a.z * dx, dx, fmaf(a.w * dx, dy, (b.x * dy) * dy));
 }
 
+__device__ __forceinline__ float exp2_fast(float p) { return __builtin_amdgcn_exp2f(p); }
+
+// 1/x by the hardware reciprocal (about 1 ulp); the backward's transmittance
+// recovery T_j = T_{j+1} / (1 - alpha_j) uses it instead of an IEEE division
+// (1 - alpha_j >= 0.01, so x is far from denormal).
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_fwd(int W, int H, int TX, int TY, CamDev cam,
+__global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H, int TX, int TY, CamDev cam,
                                                        StateDev st, float* color, float* depth,
                                                        float* alpha, int32_t* n_eval) {
   constexpr int NT = TW * TH;
   __shared__ float4 s0[NT], s1[NT], s2[NT];
   const int T = TX * TY;
-  const int g = blockIdx.x;
+  const int g = xcd_remap(blockIdx.x, ntiles);
+  if (g < 0) return;
   const int v = g / T, tl = g - v * T;
   const int ty = tl / TX, tx = tl - ty * TX;
   const int tid = threadIdx.x;
@@ -67,7 +79,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int W, int H, int TX, int
         const float power = splat_power(a, b, fx, fy, dx, dy);
         ++ne;
         if (power > 0.f) continue;
-        const float al = fminf(ALPHA_MAX, b.y * __expf(power));
+        const float al = fminf(ALPHA_MAX, b.y * exp2_fast(power));
         if (al < ALPHA_MIN) continue;
         const float Tn = Tc * (1.f - al);
         if (Tn < T_MIN) {
@@ -99,7 +111,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int W, int H, int TX, int
 }
 
 template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_bwd(int W, int H, int TX, int TY,
+__global__ __launch_bounds__(TW* TH) void k_render_bwd(int ntiles, int W, int H, int TX, int TY,
                                                        unsigned long long grad_mask, CamDev cam,
                                                        StateDev st, const float* gcol,
                                                        const float* gdep, const float* galp,
@@ -110,7 +122,8 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(int W, int H, int TX, int
   __shared__ float sg[NT][GRAD2D];
   __shared__ uint32_t smax;
   const int T = TX * TY;
-  const int g = blockIdx.x;
+  const int g = xcd_remap(blockIdx.x, ntiles);
+  if (g < 0) return;
   const int v = g / T, tl = g - v * T;
   if (!((grad_mask >> v) & 1ull)) return;
   if (st.hdr->overflow) return;
@@ -165,13 +178,13 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(int W, int H, int TX, int
         const float4 a = s0[j], b = s1[j];
         float dx, dy;
         const float power = splat_power(a, b, fx, fy, dx, dy);
-        const float G = __expf(power);
+        const float G = exp2_fast(power);
         const float raw = b.y * G;
         const float al = fminf(ALPHA_MAX, raw);
         if (power > 0.f || al < ALPHA_MIN) {
           act = false;
         } else {
-          const float inv = 1.f / (1.f - al);
+          const float inv = rcp_fast(1.f - al);
           const float Tb = Tc * inv;
           const float wgt = al * Tb;
           const float4 c = s2[j];
@@ -189,8 +202,9 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(int W, int H, int TX, int
           if (raw <= ALPHA_MAX) {
             gs = G * dA;
             const float gp = al * dA;
-            gu = -gp * (a.z * dx + a.w * dy);
-            gv = -gp * (a.w * dx + b.x * dy);
+            // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.
+            gu = gp * LN2 * (2.f * a.z * dx + a.w * dy);
+            gv = gp * LN2 * (a.w * dx + 2.f * b.x * dy);
             gA = -0.5f * gp * dx * dx;
             gB = -gp * dx * dy;
             gC = -0.5f * gp * dy * dy;
@@ -230,17 +244,24 @@ __global__ __launch_bounds__(TW* TH) void k_render_bwd(int W, int H, int TX, int
 // exit is a wave ballot, and the backward reduces each entry's ten splat
 // gradients once per tile (one DPP wave reduction) and issues the atomics
 // from ten lanes.
-template <int TW, int TH, int B>
-__global__ __launch_bounds__(64) void k_render_fwd_w(int W, int H, int TX, int TY, CamDev cam,
-                                                     StateDev st, float* color, float* depth,
-                                                     float* alpha, int32_t* n_eval) {
+template <int TW, int TH, int B, int TPW>
+__global__ __launch_bounds__(64 * TPW) void k_render_fwd_w(int ntiles, int W, int H, int TX, int TY,
+                                                           CamDev cam, StateDev st, float* color,
+                                                           float* depth, float* alpha,
+                                                           int32_t* n_eval) {
   constexpr int PPL = TW * TH / 64;
-  __shared__ float4 s0[B], s1[B], s2[B];
+  __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
   const int T = TX * TY;
-  const int g = blockIdx.x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
+  if (blk < 0) return;
+  const int g = blk * TPW + wv;
+  if (g >= ntiles) return;
+  float4* s0 = L0[wv];
+  float4* s1 = L1[wv];
+  float4* s2 = L2[wv];
   const int v = g / T, tl = g - v * T;
   const int ty = tl / TX, tx = tl - ty * TX;
-  const int lane = threadIdx.x;
   float fxp[PPL], fyp[PPL], Tc[PPL], c0[PPL], c1[PPL], c2[PPL], dz[PPL];
   uint32_t last[PPL];
   int ne[PPL];
@@ -264,7 +285,9 @@ __global__ __launch_bounds__(64) void k_render_fwd_w(int W, int H, int TX, int T
 #pragma unroll
     for (int k = 0; k < PPL; ++k) live |= !done[k];
     if (__ballot(live) == 0ull) break;
-    __syncthreads();
+    // Each wave stages its own tile's batch in its own LDS slice: LDS
+    // operations of one wave complete in issue order, so no workgroup
+    // barrier is needed between staging and use.
 #pragma unroll
     for (int r = 0; r < B / 64; ++r) {
       const uint32_t idx = base + lane + 64 * r;
@@ -275,7 +298,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_w(int W, int H, int TX, int T
         s2[lane + 64 * r] = rp[2];
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     const int n = (int)min((uint32_t)B, rg.y - base);
     for (int j = 0; j < n; ++j) {
       const float4 a = s0[j], b = s1[j];
@@ -289,7 +312,7 @@ __global__ __launch_bounds__(64) void k_render_fwd_w(int W, int H, int TX, int T
         const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
         ++ne[k];
         if (power > 0.f) continue;
-        const float al = fminf(ALPHA_MAX, b.y * __expf(power));
+        const float al = fminf(ALPHA_MAX, b.y * exp2_fast(power));
         if (al < ALPHA_MIN) continue;
         const float Tn = Tc[k] * (1.f - al);
         if (Tn < T_MIN) {
@@ -331,24 +354,32 @@ __global__ __launch_bounds__(64) void k_render_fwd_w(int W, int H, int TX, int T
   }
 }
 
-template <int TW, int TH, int B>
-__global__ __launch_bounds__(64) void k_render_bwd_w(int W, int H, int TX, int TY,
-                                                     unsigned long long grad_mask, CamDev cam,
-                                                     StateDev st, const float* gcol,
-                                                     const float* gdep, const float* galp,
-                                                     float* grad2d) {
+template <int TW, int TH, int B, int TPW>
+__global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, int H, int TX, int TY,
+                                                           unsigned long long grad_mask, CamDev cam,
+                                                           StateDev st, const float* gcol,
+                                                           const float* gdep, const float* galp,
+                                                           float* grad2d) {
   constexpr int PPL = TW * TH / 64;
-  __shared__ float4 s0[B], s1[B], s2[B];
-  __shared__ uint32_t sp[B];
+  __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
+  __shared__ uint32_t LP[TPW][B];
   const int T = TX * TY;
-  const int g = blockIdx.x;
+  const int wv = threadIdx.x >> 6;
+  const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
+  if (blk < 0) return;
+  const int g = blk * TPW + wv;
+  if (g >= ntiles) return;
+  float4* s0 = L0[wv];
+  float4* s1 = L1[wv];
+  float4* s2 = L2[wv];
+  uint32_t* sp = LP[wv];
   const int v = g / T, tl = g - v * T;
   if (!((grad_mask >> v) & 1ull)) return;
   if (st.hdr->overflow) return;
   const uint2 rg = st.ranges[g];
   if (rg.x == rg.y) return;
   const int ty = tl / TX, tx = tl - ty * TX;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   const size_t HW = (size_t)W * H;
   float fxp[PPL], fyp[PPL], Tc[PPL], Tf[PPL], g0[PPL], g1[PPL], g2[PPL], gd[PPL], ga[PPL];
   float S0[PPL], S1[PPL], S2[PPL], SD[PPL];
@@ -386,7 +417,6 @@ __global__ __launch_bounds__(64) void k_render_bwd_w(int W, int H, int TX, int T
   const int maxlast = (int)mylast;
   for (int end = maxlast; end > 0; end -= B) {
     const int start = max(0, end - B);
-    __syncthreads();
 #pragma unroll
     for (int r = 0; r < B / 64; ++r) {
       const int i = start + lane + 64 * r;
@@ -399,7 +429,7 @@ __global__ __launch_bounds__(64) void k_render_bwd_w(int W, int H, int TX, int T
         sp[lane + 64 * r] = pr;
       }
     }
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
     for (int j = end - start - 1; j >= 0; --j) {
       const int pos = start + j;
       const float4 a = s0[j], b = s1[j], c = s2[j];
@@ -412,12 +442,12 @@ __global__ __launch_bounds__(64) void k_render_bwd_w(int W, int H, int TX, int T
         if (pos >= (int)lastp[k]) continue;
         float dx, dy;
         const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
-        const float G = __expf(power);
+        const float G = exp2_fast(power);
         const float raw = b.y * G;
         const float al = fminf(ALPHA_MAX, raw);
         if (power > 0.f || al < ALPHA_MIN) continue;
         act = true;
-        const float inv = 1.f / (1.f - al);
+        const float inv = rcp_fast(1.f - al);
         const float Tb = Tc[k] * inv;
         const float wgt = al * Tb;
         const float dA = (c.x * Tb - S0[k] * inv) * g0[k] + (c.y * Tb - S1[k] * inv) * g1[k] +
@@ -434,8 +464,9 @@ __global__ __launch_bounds__(64) void k_render_bwd_w(int W, int H, int TX, int T
         if (raw <= ALPHA_MAX) {
           const float gp = al * dA;
           acc[5] += G * dA;
-          acc[0] -= gp * (a.z * dx + a.w * dy);
-          acc[1] -= gp * (a.w * dx + b.x * dy);
+          // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.
+          acc[0] += gp * LN2 * (2.f * a.z * dx + a.w * dy);
+          acc[1] += gp * LN2 * (a.w * dx + 2.f * b.x * dy);
           acc[2] -= 0.5f * gp * dx * dx;
           acc[3] -= gp * dx * dy;
           acc[4] -= 0.5f * gp * dy * dy;
@@ -455,21 +486,18 @@ __global__ __launch_bounds__(64) void k_render_bwd_w(int W, int H, int TX, int T
   }
 }
 
-__global__ __launch_bounds__(256) void k_zero_grad2d(int P, StateDev st, float* grad2d,
-                                                     float* d_pose, int nv) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x == 0)
-    for (int k = threadIdx.x; k < 6 * nv; k += 256) d_pose[k] = 0.f;
-  if (i >= P || i >= (int)st.hdr->vis_total) return;
-  float* d = grad2d + (size_t)GRAD2D * st.order[i];
-#pragma unroll
-  for (int k = 0; k < GRAD2D; ++k) d[k] = 0.f;
+// Clears the pose gradients (the per-pair screen-space gradient rows are
+// kept at zero between backward calls: the projection backward clears the
+// rows it consumes).
+__global__ __launch_bounds__(256) void k_zero_pose(float* d_pose, int nv) {
+  for (int k = threadIdx.x; k < 6 * nv; k += 256) d_pose[k] = 0.f;
 }
 
 template <int TW, int TH>
 static void fwd_t(int nv, int W, int H, int TX, int TY, const CamDev& cam, StateDev st,
                   float* color, float* depth, float* alpha, int32_t* n_eval, hipStream_t s) {
-  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(nv * TX * TY), dim3(TW * TH), 0, s, W, H, TX,
+  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(xcd_grid(nv * TX * TY)), dim3(TW * TH), 0, s,
+                     nv * TX * TY, W, H, TX,
                      TY, cam, st, color, depth, alpha, n_eval);
 }
 
@@ -477,7 +505,8 @@ template <int TW, int TH>
 static void bwd_t(int nv, int W, int H, int TX, int TY, unsigned long long mask,
                   const CamDev& cam, StateDev st, const float* gc, const float* gd,
                   const float* ga, float* grad2d, hipStream_t s) {
-  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(nv * TX * TY), dim3(TW * TH), 0, s, W, H, TX,
+  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(xcd_grid(nv * TX * TY)), dim3(TW * TH), 0, s,
+                     nv * TX * TY, W, H, TX,
                      TY, mask, cam, st, gc, gd, ga, grad2d);
 }
 
@@ -509,10 +538,8 @@ hipError_t launch_render_bwd(int nv, int W, int H, int TW, int TH, int TX, int T
   return hipGetLastError();
 }
 
-hipError_t launch_zero_grad2d(int P, StateDev st, float* grad2d, float* d_pose, int nv,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_grad2d, dim3(max(1, (P + 255) / 256)), dim3(256), 0, s, P, st, grad2d,
-                     d_pose, nv);
+hipError_t launch_zero_pose(float* d_pose, int nv, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_pose, dim3(1), dim3(256), 0, s, d_pose, nv);
   return hipGetLastError();
 }
 

@@ -30,8 +30,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(SortTab t, const St
                                                              const uint32_t* keys,
                                                              uint32_t* hist) {
   __shared__ uint32_t cnt[RADIX];
+  const int b = xcd_remap(blockIdx.x, t.sblk_off[t.nv]);
+  if (b < 0) return;
   int v, lo, hi;
-  sort_block_range(t, hdr, blockIdx.x, v, lo, hi);
+  sort_block_range(t, hdr, b, v, lo, hi);
   cnt[threadIdx.x] = 0;
   __syncthreads();
 #pragma unroll
@@ -40,7 +42,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(SortTab t, const St
     if (i < hi) atomicAdd(&cnt[(keys[i] >> SH) & (RADIX - 1)], 1u);
   }
   __syncthreads();
-  hist[(size_t)blockIdx.x * RADIX + threadIdx.x] = cnt[threadIdx.x];
+  hist[(size_t)b * RADIX + threadIdx.x] = cnt[threadIdx.x];
 }
 
 // One workgroup per view; thread d owns digit d.
@@ -91,11 +93,13 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
   constexpr int NW = SORT_THREADS / 64;
   __shared__ uint32_t whist[NW][RADIX];
   __shared__ uint32_t run[RADIX];
+  const int b = xcd_remap(blockIdx.x, t.sblk_off[t.nv]);
+  if (b < 0) return;
   int v, lo, hi;
-  sort_block_range(t, hdr, blockIdx.x, v, lo, hi);
+  sort_block_range(t, hdr, b, v, lo, hi);
   if (lo >= hi) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-  run[tid] = hist[(size_t)blockIdx.x * RADIX + tid];
+  run[tid] = hist[(size_t)b * RADIX + tid];
 #pragma unroll
   for (int i = 0; i < NW; ++i) whist[i][tid] = 0;
   __syncthreads();
@@ -139,7 +143,7 @@ hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32
                              uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s) {
   const int nb = t.sblk_off[t.nv];
   if (nb == 0) return hipSuccess;
-  const dim3 g(nb), blk(SORT_THREADS);
+  const dim3 g(xcd_grid(nb)), blk(SORT_THREADS);
   // pass 0: A -> B
   hipLaunchKernelGGL(k_radix_hist<0>, g, blk, 0, s, t, st.hdr, ka, hist);
   hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
