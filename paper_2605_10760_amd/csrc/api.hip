@@ -24,8 +24,7 @@ struct gsr_ctx {
   uint32_t* blk_cnt = nullptr;
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   uint32_t* hist = nullptr;
-  uint32_t* counts = nullptr;
-  uint32_t* tile_cnt = nullptr;
+  BinWork bw{};
   float* grad2d = nullptr;
   size_t max_blocks = 0, max_sblocks = 0, max_chunks = 0;
   bool prof = false;
@@ -139,8 +138,9 @@ gsr_status check_plan(gsr_ctx* c, const gsr_plan_desc* p) {
     return fail(c, GSR_E_INVALID_ARG,
                 "tile shape must be one of 8x8, 16x8, 8x16, 16x16, 32x8, 32x16, 16x32");
   const long TX = (p->width + p->tile_w - 1) / p->tile_w, TY = (p->height + p->tile_h - 1) / p->tile_h;
-  if ((TX + 1) * (TY + 1) * 4 > 60 * 1024)
-    return fail(c, GSR_E_INVALID_ARG, "too many tiles per view (%ld x %ld)", TX, TY);
+  if (TX > MAX_COLS || TY > MAX_ROWS)
+    return fail(c, GSR_E_INVALID_ARG, "too many tiles per view (%ld x %ld, at most %d x %d)", TX,
+                TY, MAX_COLS, MAX_ROWS);
   if (p->chunk < 0) return fail(c, GSR_E_INVALID_ARG, "chunk must be >= 0");
   return GSR_OK;
 }
@@ -366,7 +366,11 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   const size_t o_kb = o; o = align256(o + P * 4);
   const size_t o_vb = o; o = align256(o + P * 4);
   const size_t o_hist = o; o = align256(o + c->max_sblocks * RADIX * 4);
-  const size_t o_cnt = o; o = align256(o + c->max_chunks * (size_t)c->T * 4);
+  const size_t o_cnt = o; o = align256(o + c->max_chunks * (size_t)c->TY * 4);
+  const size_t o_rt = o; o = align256(o + V * (size_t)c->TY * 4);
+  const size_t o_rr = o; o = align256(o + V * (size_t)c->TY * 8);
+  const size_t o_rf = o; o = align256(o + 4);
+  const size_t o_rows = o; o = align256(o + (size_t)p->max_instances * 8);
   const size_t o_tc = o; o = align256(o + V * (size_t)c->T * 4);
   const size_t o_g2 = o; o = align256(o + P * GRAD2D * 4);
   void* ws = nullptr;
@@ -384,8 +388,13 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   c->kb = (uint32_t*)(b + o_kb);
   c->vb = (uint32_t*)(b + o_vb);
   c->hist = (uint32_t*)(b + o_hist);
-  c->counts = (uint32_t*)(b + o_cnt);
-  c->tile_cnt = (uint32_t*)(b + o_tc);
+  c->bw.counts = (uint32_t*)(b + o_cnt);
+  c->bw.row_tot = (uint32_t*)(b + o_rt);
+  c->bw.row_rg = (uint2*)(b + o_rr);
+  c->bw.row_flag = (unsigned int*)(b + o_rf);
+  c->bw.rows = (uint2*)(b + o_rows);
+  c->bw.row_cap = (unsigned long long)p->max_instances;
+  c->bw.tile_cnt = (uint32_t*)(b + o_tc);
   c->grad2d = (float*)(b + o_g2);
   // The per-pair screen-space gradient rows start at zero and every
   // backward leaves them at zero (the projection backward clears what it
@@ -432,7 +441,7 @@ gsr_status gsr_forward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   }
   {
     StageMark m(c, GSR_STAGE_BINNING, st);
-    if ((e = launch_binning(t.bt, sd, c->counts, c->tile_cnt, st)) != hipSuccess) return hip_fail(c, e, "binning");
+    if ((e = launch_binning(t.bt, sd, c->bw, st)) != hipSuccess) return hip_fail(c, e, "binning");
   }
   {
     StageMark m(c, GSR_STAGE_RENDER_FWD, st);

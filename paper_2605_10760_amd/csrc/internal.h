@@ -22,6 +22,8 @@ constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int GRAD2D = 10;        // u, v, A, B, C, sigma, r, g, b, z
 constexpr uint32_t CULLED = 0xFFFFFFFFu;
+constexpr int MAX_ROWS = 512;     // tile rows per view (binning LDS arrays)
+constexpr int MAX_COLS = 512;     // tile columns per view
 
 // Pair p of view v is Gaussian (set_goff[view_set[v]] + p - pair_off[v]).
 struct ProjTab {
@@ -77,6 +79,7 @@ struct StateHeader {
   unsigned long long inst_total;  // sum of tile counts (may exceed capacity)
   unsigned int overflow;
   unsigned int vis_total;
+  unsigned long long row_total;   // (pair, tile row) entries of the binning
   unsigned int vis_off[MAXV + 1]; // visible-pair offsets per view (compacted order)
 };
 constexpr size_t STATE_HEADER_BYTES = 512;
@@ -92,13 +95,24 @@ struct StateDev {
   StateHeader* hdr;
   uint32_t* zkey;     // [P]
   uint2* rect;        // [P] packed (x0 | y0 << 16, x1 | y1 << 16)
-  float4* rec;        // [P][3]: (u, v, A, B), (C, sigma, z, -), (r, g, b, -)
+  float4* rec;        // [P][3]: (u, v, A', B'), (C', sigma, z, ex), (r, g, b, ey)
   uint32_t* order;    // [P] pair ids in (view, depth, id) order
   uint2* ranges;      // [V*T]
   uint32_t* inst;     // [cap]
   float* tfinal;      // [V*H*W]
   uint32_t* last;     // [V*H*W]
   unsigned long long cap;
+};
+
+// Binning workspace (context-owned).
+struct BinWork {
+  uint32_t* counts;     // [chunks][TY] per-chunk row counts -> exclusive bases
+  uint32_t* row_tot;    // [V*TY] entries per (view, row)
+  uint2* row_rg;        // [V*TY] row list ranges
+  unsigned int* row_flag;
+  uint2* rows;          // [row_cap] (pair id, x0 | x1 << 16)
+  unsigned long long row_cap;
+  uint32_t* tile_cnt;   // [V*T]
 };
 
 StateLayout state_layout(const gsr_plan_desc& p);
@@ -111,8 +125,7 @@ hipError_t launch_compact(const ProjTab& t, StateDev st, uint32_t* blk_cnt,
                           uint32_t* keys_out, uint32_t* vals_out, hipStream_t s);
 hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
                              uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s);
-hipError_t launch_binning(const BinTab& t, StateDev st, uint32_t* counts, uint32_t* tile_cnt,
-                          hipStream_t s);
+hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStream_t s);
 hipError_t launch_render_fwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
                              const CamDev& cam, StateDev st, float* color, float* depth,
                              float* alpha, int32_t* n_eval, hipStream_t s);

@@ -50,6 +50,12 @@ __device__ __forceinline__ void sh_eval(float x, float y, float z, float* Y) {
   }
 }
 
+// Camera-space depth of a mean, in the key path's FP32 order.
+__device__ __forceinline__ float cam_depth32(const float* m, const float* Rc, const float* tc) {
+#pragma clang fp contract(off)
+  return ((Rc[6] * m[0] + Rc[7] * m[1]) + Rc[8] * m[2]) + tc[2];
+}
+
 struct KeyResult {
   float p2;
   uint32_t x0, y0, x1, y1;
@@ -65,7 +71,7 @@ __device__ __forceinline__ bool key_path(const float* m, const float* ls, const 
 #pragma clang fp contract(off)
   const float p0 = ((Rc[0] * m[0] + Rc[1] * m[1]) + Rc[2] * m[2]) + tc[0];
   const float p1 = ((Rc[3] * m[0] + Rc[4] * m[1]) + Rc[5] * m[2]) + tc[1];
-  const float p2 = ((Rc[6] * m[0] + Rc[7] * m[1]) + Rc[8] * m[2]) + tc[2];
+  const float p2 = cam_depth32(m, Rc, tc);
   if (!(p2 > z_near)) return false;
   const float s0 = (float)exp((double)ls[0]);
   const float s1 = (float)exp((double)ls[1]);
@@ -162,14 +168,19 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
     const float tc[3] = {vm[3], vm[7], vm[11]};
     const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
     const float m[3] = {sc.means[3 * gi], sc.means[3 * gi + 1], sc.means[3 * gi + 2]};
-    const float ls[3] = {sc.log_scales[3 * gi], sc.log_scales[3 * gi + 1],
-                         sc.log_scales[3 * gi + 2]};
-    const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
-    const float q[4] = {q4.x, q4.y, q4.z, q4.w};
-    const float o = sc.opac[gi];
+    // the other parameters are read only for Gaussians in front of the camera
+    float ls[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, o = 0.f;
     KeyResult kr;
-    vis = key_path(m, ls, q, o, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX,
-                   t.TY, cam.z_near, kr);
+    if (cam_depth32(m, Rc, tc) > cam.z_near) {
+      ls[0] = sc.log_scales[3 * gi];
+      ls[1] = sc.log_scales[3 * gi + 1];
+      ls[2] = sc.log_scales[3 * gi + 2];
+      const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
+      q[0] = q4.x; q[1] = q4.y; q[2] = q4.z; q[3] = q4.w;
+      o = sc.opac[gi];
+      vis = key_path(m, ls, q, o, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX,
+                     t.TY, cam.z_near, kr);
+    }
     st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
     if (vis) {
       st.rect[pair] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
@@ -238,6 +249,14 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
         }
         col[0] = fmaxf(r, 0.f); col[1] = fmaxf(g, 0.f); col[2] = fmaxf(bl, 0.f);
       }
+      // half-extents of the alpha >= 1/255 ellipse, widened by a margin far
+      // above FP32 rounding: every pixel outside this box has alpha < 1/255,
+      // so the compositing kernels may skip the splat there without changing
+      // any result
+      const double t255 = 255.0 * sig;
+      const double k2d = t255 > 1.0 ? 2.0 * log(t255) : 0.0;
+      const float exr = (float)(sqrt(k2d * a) * (1.0 + 1e-4) + 1e-2);
+      const float eyr = (float)(sqrt(k2d * c) * (1.0 + 1e-4) + 1e-2);
       float4* rp = st.rec + 3 * (long)pair;
       // conic (A, B, C) = (c, -b, a)/det, stored pre-scaled so that the
       // exponent in base 2 is A' dx^2 + B' dx dy + C' dy^2:
@@ -245,8 +264,8 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
       const double L2E = 1.4426950408889634;
       rp[0] = make_float4((float)u, (float)vv, (float)(-0.5 * L2E * c / det),
                           (float)(L2E * bb / det));
-      rp[1] = make_float4((float)(-0.5 * L2E * a / det), (float)sig, (float)p[2], 0.f);
-      rp[2] = make_float4(col[0], col[1], col[2], 0.f);
+      rp[1] = make_float4((float)(-0.5 * L2E * a / det), (float)sig, (float)p[2], exr);
+      rp[2] = make_float4(col[0], col[1], col[2], eyr);
     }
   }
   const int cnt = __syncthreads_count(vis);

@@ -262,14 +262,16 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd_w(int ntiles, int W, in
   float4* s2 = L2[wv];
   const int v = g / T, tl = g - v * T;
   const int ty = tl / TX, tx = tl - ty * TX;
+  // lane l of step k shades pixel (l % 8, l / 8) of the k-th 8x8 block
+  constexpr int BX = TW / 8;
   float fxp[PPL], fyp[PPL], Tc[PPL], c0[PPL], c1[PPL], c2[PPL], dz[PPL];
   uint32_t last[PPL];
   int ne[PPL];
   bool done[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    const int p = lane + 64 * k;
-    const int px = tx * TW + (p % TW), py = ty * TH + (p / TW);
+    const int px = tx * TW + 8 * (k % BX) + (lane & 7);
+    const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
     done[k] = !(px < W && py < H);
     fxp[k] = (float)px + 0.5f;
     fyp[k] = (float)py + 0.5f;
@@ -302,12 +304,20 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd_w(int ntiles, int W, in
     const int n = (int)min((uint32_t)B, rg.y - base);
     for (int j = 0; j < n; ++j) {
       const float4 a = s0[j], b = s1[j];
+      const float ey = s2[j].w;
       float wgt[PPL];
       bool blend = false;
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         wgt[k] = 0.f;
         if (done[k]) continue;
+        // the whole 8x8 block lies outside the splat's alpha >= 1/255 box
+        const float bx0 = (float)(tx * TW + 8 * (k % BX)) + 0.5f;
+        const float by0 = (float)(ty * TH + 8 * (k / BX)) + 0.5f;
+        if (a.x + b.w < bx0 || a.x - b.w > bx0 + 7.f || a.y + ey < by0 || a.y - ey > by0 + 7.f) {
+          ++ne[k];
+          continue;
+        }
         float dx, dy;
         const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
         ++ne[k];
@@ -339,8 +349,8 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd_w(int ntiles, int W, in
   const size_t HW = (size_t)W * H;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    const int p = lane + 64 * k;
-    const int px = tx * TW + (p % TW), py = ty * TH + (p / TW);
+    const int px = tx * TW + 8 * (k % BX) + (lane & 7);
+    const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
     if (!(px < W && py < H)) continue;
     const size_t q = (size_t)py * W + px;
     color[(3 * (size_t)v + 0) * HW + q] = c0[k] + Tc[k] * cam.bg0;
@@ -385,10 +395,11 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
   float S0[PPL], S1[PPL], S2[PPL], SD[PPL];
   uint32_t lastp[PPL];
   uint32_t mylast = 0;
+  constexpr int BX = TW / 8;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    const int p = lane + 64 * k;
-    const int px = tx * TW + (p % TW), py = ty * TH + (p / TW);
+    const int px = tx * TW + 8 * (k % BX) + (lane & 7);
+    const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
     fxp[k] = (float)px + 0.5f;
     fyp[k] = (float)py + 0.5f;
     Tc[k] = 1.f; lastp[k] = 0;
@@ -440,6 +451,10 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         if (pos >= (int)lastp[k]) continue;
+        const float bx0 = (float)(tx * TW + 8 * (k % BX)) + 0.5f;
+        const float by0 = (float)(ty * TH + 8 * (k / BX)) + 0.5f;
+        if (a.x + b.w < bx0 || a.x - b.w > bx0 + 7.f || a.y + c.w < by0 || a.y - c.w > by0 + 7.f)
+          continue;
         float dx, dy;
         const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
         const float G = exp2_fast(power);
