@@ -372,6 +372,10 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   const size_t o_rf = o; o = align256(o + 4);
   const size_t o_rows = o; o = align256(o + (size_t)p->max_instances * 8);
   const size_t o_tc = o; o = align256(o + V * (size_t)c->T * 4);
+  const size_t seg_cap = (size_t)p->max_instances / SEG + V * (size_t)c->TY + 1;
+  const size_t o_so = o; o = align256(o + (V * (size_t)c->TY + 1) * 4);
+  const size_t o_sr = o; o = align256(o + seg_cap * 4);
+  const size_t o_sc = o; o = align256(o + seg_cap * (size_t)c->TX * 4);
   const size_t o_g2 = o; o = align256(o + P * GRAD2D * 4);
   void* ws = nullptr;
   hipError_t e = hipMalloc(&ws, o);
@@ -395,6 +399,13 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   c->bw.rows = (uint2*)(b + o_rows);
   c->bw.row_cap = (unsigned long long)p->max_instances;
   c->bw.tile_cnt = (uint32_t*)(b + o_tc);
+  c->bw.seg_off = (uint32_t*)(b + o_so);
+  c->bw.seg_row = (uint32_t*)(b + o_sr);
+  c->bw.seg_cnt = (uint32_t*)(b + o_sc);
+  c->bw.seg_cap = seg_cap;
+  // per-segment kernels loop over the device-side segment count; a few
+  // workgroups per CU (256 CUs) keep every CU busy
+  c->bw.seg_grid = (int)std::min<size_t>(2048, 8 * ((seg_cap + 7) / 8));
   c->grad2d = (float*)(b + o_g2);
   // The per-pair screen-space gradient rows start at zero and every
   // backward leaves them at zero (the projection backward clears what it

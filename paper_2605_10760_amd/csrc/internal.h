@@ -24,6 +24,7 @@ constexpr int GRAD2D = 10;        // u, v, A, B, C, sigma, r, g, b, z
 constexpr uint32_t CULLED = 0xFFFFFFFFu;
 constexpr int MAX_ROWS = 512;     // tile rows per view (binning LDS arrays)
 constexpr int MAX_COLS = 512;     // tile columns per view
+constexpr int SEG = 1024;         // row-list entries per tile-binning segment
 
 // Pair p of view v is Gaussian (set_goff[view_set[v]] + p - pair_off[v]).
 struct ProjTab {
@@ -113,6 +114,11 @@ struct BinWork {
   uint2* rows;          // [row_cap] (pair id, x0 | x1 << 16)
   unsigned long long row_cap;
   uint32_t* tile_cnt;   // [V*T]
+  uint32_t* seg_off;    // [V*TY+1] first level-2 segment of each row list
+  uint32_t* seg_row;    // [seg_cap] row of each segment
+  uint32_t* seg_cnt;    // [seg_cap][TX] per-segment tile counts -> exclusive bases
+  unsigned long long seg_cap;
+  int seg_grid;         // workgroups of the per-segment kernels (multiple of 8)
 };
 
 StateLayout state_layout(const gsr_plan_desc& p);

@@ -1,15 +1,18 @@
 // Per-tile compositing, forward and backward.
 //
-// One workgroup per (view, tile), one thread per pixel.  The tile's sorted
-// instance list is walked in batches of NT entries: each thread gathers one
-// 48-byte record into LDS, then every thread walks the batch (all lanes read
-// the same LDS word, a broadcast).  The forward stops the whole tile when
-// every pixel has terminated.  The backward walks each tile's list from the
-// largest last-contributor position down, recovers each pixel's
-// transmittance by division (T_j = T_{j+1} / (1 - alpha_j)) instead of
-// storing per-pixel lists, reduces each entry's ten splat gradients over
-// the wave with DPP row operations, accumulates the waves in LDS and issues
-// one global atomic per (tile, entry, component).
+// Forward: one workgroup per (view, tile), one thread per pixel.  The tile's
+// sorted instance list is walked in batches of NT entries: each thread
+// gathers one 48-byte record into LDS, then every thread walks the batch
+// (all lanes read the same LDS word, a broadcast).  The whole tile stops
+// once every pixel has terminated.
+//
+// Backward: one wave per (view, tile), PPL = TW*TH/64 pixels per lane, TPW
+// tiles per workgroup with a private LDS slice each (no workgroup barrier).
+// Each tile's list is walked from the largest last-contributor position
+// down; every pixel recovers its transmittance by division
+// (T_j = T_{j+1} / (1 - alpha_j)) instead of storing per-pixel lists, the
+// ten splat gradients of an entry are summed over the wave with DPP row
+// operations, and ten lanes issue one global atomic each per (tile, entry).
 #include "common.h"
 
 namespace gsr {
@@ -110,260 +113,9 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
   }
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_bwd(int ntiles, int W, int H, int TX, int TY,
-                                                       unsigned long long grad_mask, CamDev cam,
-                                                       StateDev st, const float* gcol,
-                                                       const float* gdep, const float* galp,
-                                                       float* grad2d) {
-  constexpr int NT = TW * TH;
-  __shared__ float4 s0[NT], s1[NT], s2[NT];
-  __shared__ uint32_t sp[NT];
-  __shared__ float sg[NT][GRAD2D];
-  __shared__ uint32_t smax;
-  const int T = TX * TY;
-  const int g = xcd_remap(blockIdx.x, ntiles);
-  if (g < 0) return;
-  const int v = g / T, tl = g - v * T;
-  if (!((grad_mask >> v) & 1ull)) return;
-  if (st.hdr->overflow) return;
-  const uint2 rg = st.ranges[g];
-  if (rg.x == rg.y) return;
-  const int ty = tl / TX, tx = tl - ty * TX;
-  const int tid = threadIdx.x;
-  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
-  const bool inside = px < W && py < H;
-  const size_t HW = (size_t)W * H, p = (size_t)py * W + px;
-  float Tc = 1.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, gd = 0.f, ga = 0.f;
-  uint32_t lastp = 0;
-  if (inside) {
-    Tc = st.tfinal[v * HW + p];
-    lastp = st.last[v * HW + p];
-    if (gcol) {
-      g0 = gcol[(3 * (size_t)v + 0) * HW + p];
-      g1 = gcol[(3 * (size_t)v + 1) * HW + p];
-      g2 = gcol[(3 * (size_t)v + 2) * HW + p];
-    }
-    if (gdep) gd = gdep[v * HW + p];
-    if (galp) ga = galp[v * HW + p];
-  }
-  const float Tf = Tc;
-  float S0 = Tf * cam.bg0, S1 = Tf * cam.bg1, S2 = Tf * cam.bg2, SD = 0.f;
-  if (tid == 0) smax = 0;
-  __syncthreads();
-  if (lastp) atomicMax(&smax, lastp);
-  __syncthreads();
-  const int maxlast = (int)smax;
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  const int lane = lane_id();
-  for (int end = maxlast; end > 0; end -= NT) {
-    const int start = max(0, end - NT);
-    __syncthreads();
-    if (start + tid < end) {
-      const uint32_t pr = st.inst[rg.x + start + tid];
-      const float4* r = st.rec + 3 * (size_t)pr;
-      s0[tid] = r[0];
-      s1[tid] = r[1];
-      s2[tid] = r[2];
-      sp[tid] = pr;
-    }
-#pragma unroll
-    for (int k = 0; k < GRAD2D; ++k) sg[tid][k] = 0.f;
-    __syncthreads();
-    for (int j = end - start - 1; j >= 0; --j) {
-      float gu = 0.f, gv = 0.f, gA = 0.f, gB = 0.f, gC = 0.f, gs = 0.f;
-      float gr = 0.f, gg = 0.f, gb = 0.f, gz = 0.f;
-      bool act = (start + j) < (int)lastp;
-      if (act) {
-        const float4 a = s0[j], b = s1[j];
-        float dx, dy;
-        const float power = splat_power(a, b, fx, fy, dx, dy);
-        const float G = exp2_fast(power);
-        const float raw = b.y * G;
-        const float al = fminf(ALPHA_MAX, raw);
-        if (power > 0.f || al < ALPHA_MIN) {
-          act = false;
-        } else {
-          const float inv = rcp_fast(1.f - al);
-          const float Tb = Tc * inv;
-          const float wgt = al * Tb;
-          const float4 c = s2[j];
-          const float dA = (c.x * Tb - S0 * inv) * g0 + (c.y * Tb - S1 * inv) * g1 +
-                           (c.z * Tb - S2 * inv) * g2 + (b.z * Tb - SD * inv) * gd +
-                           Tf * inv * ga;
-          S0 += c.x * wgt;
-          S1 += c.y * wgt;
-          S2 += c.z * wgt;
-          SD += b.z * wgt;
-          gr = wgt * g0;
-          gg = wgt * g1;
-          gb = wgt * g2;
-          gz = wgt * gd;
-          if (raw <= ALPHA_MAX) {
-            gs = G * dA;
-            const float gp = al * dA;
-            // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.
-            gu = gp * LN2 * (2.f * a.z * dx + a.w * dy);
-            gv = gp * LN2 * (a.w * dx + 2.f * b.x * dy);
-            gA = -0.5f * gp * dx * dx;
-            gB = -gp * dx * dy;
-            gC = -0.5f * gp * dy * dy;
-          }
-          Tc = Tb;
-        }
-      }
-      if (__ballot(act) != 0ull) {
-        const float r0 = wave_total(gu), r1 = wave_total(gv), r2 = wave_total(gA);
-        const float r3 = wave_total(gB), r4 = wave_total(gC), r5 = wave_total(gs);
-        const float r6 = wave_total(gr), r7 = wave_total(gg), r8 = wave_total(gb);
-        const float r9 = wave_total(gz);
-        if (lane == 0) {
-          float* d = sg[j];
-          atomicAdd(d + 0, r0); atomicAdd(d + 1, r1); atomicAdd(d + 2, r2);
-          atomicAdd(d + 3, r3); atomicAdd(d + 4, r4); atomicAdd(d + 5, r5);
-          atomicAdd(d + 6, r6); atomicAdd(d + 7, r7); atomicAdd(d + 8, r8);
-          atomicAdd(d + 9, r9);
-        }
-      }
-    }
-    __syncthreads();
-    if (start + tid < end) {
-      float* dst = grad2d + (size_t)GRAD2D * sp[tid];
-#pragma unroll
-      for (int k = 0; k < GRAD2D; ++k) {
-        const float x = sg[tid][k];
-        if (x != 0.f) atomicAdd(dst + k, x);
-      }
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// One wave per tile, PPL = TW*TH/64 pixels per lane.  Each record staged in
-// LDS is read once per lane and used for its PPL pixels; the forward's early
-// exit is a wave ballot, and the backward reduces each entry's ten splat
-// gradients once per tile (one DPP wave reduction) and issues the atomics
-// from ten lanes.
-template <int TW, int TH, int B, int TPW>
-__global__ __launch_bounds__(64 * TPW) void k_render_fwd_w(int ntiles, int W, int H, int TX, int TY,
-                                                           CamDev cam, StateDev st, float* color,
-                                                           float* depth, float* alpha,
-                                                           int32_t* n_eval) {
-  constexpr int PPL = TW * TH / 64;
-  __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
-  const int T = TX * TY;
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
-  if (blk < 0) return;
-  const int g = blk * TPW + wv;
-  if (g >= ntiles) return;
-  float4* s0 = L0[wv];
-  float4* s1 = L1[wv];
-  float4* s2 = L2[wv];
-  const int v = g / T, tl = g - v * T;
-  const int ty = tl / TX, tx = tl - ty * TX;
-  // lane l of step k shades pixel (l % 8, l / 8) of the k-th 8x8 block
-  constexpr int BX = TW / 8;
-  float fxp[PPL], fyp[PPL], Tc[PPL], c0[PPL], c1[PPL], c2[PPL], dz[PPL];
-  uint32_t last[PPL];
-  int ne[PPL];
-  bool done[PPL];
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const int px = tx * TW + 8 * (k % BX) + (lane & 7);
-    const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
-    done[k] = !(px < W && py < H);
-    fxp[k] = (float)px + 0.5f;
-    fyp[k] = (float)py + 0.5f;
-    Tc[k] = 1.f;
-    c0[k] = c1[k] = c2[k] = dz[k] = 0.f;
-    last[k] = 0;
-    ne[k] = 0;
-  }
-  uint2 rg = st.ranges[g];
-  if (st.hdr->overflow) rg = make_uint2(0u, 0u);
-  for (uint32_t base = rg.x; base < rg.y; base += B) {
-    bool live = false;
-#pragma unroll
-    for (int k = 0; k < PPL; ++k) live |= !done[k];
-    if (__ballot(live) == 0ull) break;
-    // Each wave stages its own tile's batch in its own LDS slice: LDS
-    // operations of one wave complete in issue order, so no workgroup
-    // barrier is needed between staging and use.
-#pragma unroll
-    for (int r = 0; r < B / 64; ++r) {
-      const uint32_t idx = base + lane + 64 * r;
-      if (idx < rg.y) {
-        const float4* rp = st.rec + 3 * (size_t)st.inst[idx];
-        s0[lane + 64 * r] = rp[0];
-        s1[lane + 64 * r] = rp[1];
-        s2[lane + 64 * r] = rp[2];
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-    const int n = (int)min((uint32_t)B, rg.y - base);
-    for (int j = 0; j < n; ++j) {
-      const float4 a = s0[j], b = s1[j];
-      const float ey = s2[j].w;
-      float wgt[PPL];
-      bool blend = false;
-#pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        wgt[k] = 0.f;
-        if (done[k]) continue;
-        // the whole 8x8 block lies outside the splat's alpha >= 1/255 box
-        const float bx0 = (float)(tx * TW + 8 * (k % BX)) + 0.5f;
-        const float by0 = (float)(ty * TH + 8 * (k / BX)) + 0.5f;
-        if (a.x + b.w < bx0 || a.x - b.w > bx0 + 7.f || a.y + ey < by0 || a.y - ey > by0 + 7.f) {
-          ++ne[k];
-          continue;
-        }
-        float dx, dy;
-        const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
-        ++ne[k];
-        if (power > 0.f) continue;
-        const float al = fminf(ALPHA_MAX, b.y * exp2_fast(power));
-        if (al < ALPHA_MIN) continue;
-        const float Tn = Tc[k] * (1.f - al);
-        if (Tn < T_MIN) {
-          done[k] = true;
-          continue;
-        }
-        wgt[k] = al * Tc[k];
-        Tc[k] = Tn;
-        last[k] = base - rg.x + (uint32_t)j + 1u;
-        blend = true;
-      }
-      if (__ballot(blend) != 0ull) {
-        const float4 c = s2[j];
-#pragma unroll
-        for (int k = 0; k < PPL; ++k) {
-          c0[k] += c.x * wgt[k];
-          c1[k] += c.y * wgt[k];
-          c2[k] += c.z * wgt[k];
-          dz[k] += b.z * wgt[k];
-        }
-      }
-    }
-  }
-  const size_t HW = (size_t)W * H;
-#pragma unroll
-  for (int k = 0; k < PPL; ++k) {
-    const int px = tx * TW + 8 * (k % BX) + (lane & 7);
-    const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
-    if (!(px < W && py < H)) continue;
-    const size_t q = (size_t)py * W + px;
-    color[(3 * (size_t)v + 0) * HW + q] = c0[k] + Tc[k] * cam.bg0;
-    color[(3 * (size_t)v + 1) * HW + q] = c1[k] + Tc[k] * cam.bg1;
-    color[(3 * (size_t)v + 2) * HW + q] = c2[k] + Tc[k] * cam.bg2;
-    depth[v * HW + q] = dz[k];
-    alpha[v * HW + q] = 1.f - Tc[k];
-    st.tfinal[v * HW + q] = Tc[k];
-    st.last[v * HW + q] = last[k];
-    if (n_eval) n_eval[v * HW + q] = ne[k];
-  }
-}
-
+// One wave per tile.  Lane l shades pixel (l % 8, l / 8) of each of the
+// tile's PPL 8x8 blocks; a record staged in LDS is read once per lane and
+// used for its PPL pixels.
 template <int TW, int TH, int B, int TPW>
 __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, int H, int TX, int TY,
                                                            unsigned long long grad_mask, CamDev cam,
@@ -451,10 +203,6 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
         if (pos >= (int)lastp[k]) continue;
-        const float bx0 = (float)(tx * TW + 8 * (k % BX)) + 0.5f;
-        const float by0 = (float)(ty * TH + 8 * (k / BX)) + 0.5f;
-        if (a.x + b.w < bx0 || a.x - b.w > bx0 + 7.f || a.y + c.w < by0 || a.y - c.w > by0 + 7.f)
-          continue;
         float dx, dy;
         const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
         const float G = exp2_fast(power);
@@ -516,13 +264,17 @@ static void fwd_t(int nv, int W, int H, int TX, int TY, const CamDev& cam, State
                      TY, cam, st, color, depth, alpha, n_eval);
 }
 
+constexpr int BWD_BATCH = 128;  // entries staged per wave
+constexpr int BWD_TPW = 4;      // tiles (waves) per workgroup
+
 template <int TW, int TH>
 static void bwd_t(int nv, int W, int H, int TX, int TY, unsigned long long mask,
                   const CamDev& cam, StateDev st, const float* gc, const float* gd,
                   const float* ga, float* grad2d, hipStream_t s) {
-  hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(xcd_grid(nv * TX * TY)), dim3(TW * TH), 0, s,
-                     nv * TX * TY, W, H, TX,
-                     TY, mask, cam, st, gc, gd, ga, grad2d);
+  const int ntiles = nv * TX * TY;
+  hipLaunchKernelGGL((k_render_bwd_w<TW, TH, BWD_BATCH, BWD_TPW>),
+                     dim3(xcd_grid((ntiles + BWD_TPW - 1) / BWD_TPW)), dim3(64 * BWD_TPW), 0, s,
+                     ntiles, W, H, TX, TY, mask, cam, st, gc, gd, ga, grad2d);
 }
 
 #define GSR_TILE_SWITCH(F, ...)                                  \
