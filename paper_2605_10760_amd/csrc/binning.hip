@@ -12,13 +12,14 @@
 //                per chunk takes its pairs 64 at a time and appends
 //                (pair id, x0, x1) to every row the rect spans, ranked inside
 //                each row by a wave ballot (lane order = depth order).
+//   Both scatters keep their per-bucket cursors in registers (bucket k in
+//   lane k % 64 of register k / 64), read and advanced with readlane.
 //   tile level : each row list (still in depth order) is cut into segments
 //                of SEG entries; per segment the number of entries covering
 //                each tile of the row, an exclusive scan down each tile's
 //                segments, a scan over all tiles (the tile ranges), and a
-//                scatter that groups a segment's instances by tile in LDS
-//                and copies them out so that each tile's share is stored as
-//                one contiguous run.
+//                scatter where one wave per segment ranks each entry inside
+//                every tile it covers by a wave ballot.
 #include "common.h"
 
 namespace gsr {
@@ -169,51 +170,54 @@ __global__ __launch_bounds__(1024) void k_range_scan(int n, const uint32_t* cnt,
 
 // One wave per chunk: append every pair, in order, to each row it spans.
 // Row entries are (pair id, x0 | x1 << 16).  Each step takes 64 consecutive
-// pairs (lane order = depth order); for every row the step touches, a ballot
-// gives the mask of lanes spanning it, so lane l's slot in that row is the
-// row cursor plus the number of lower lanes in the mask.
-__global__ __launch_bounds__(64) void k_row_scatter(BinTab t, StateDev st, const uint32_t* counts,
-                                                    const uint2* row_rg, uint2* rows,
-                                                    unsigned long long row_cap,
-                                                    const unsigned int* row_flag) {
-  __shared__ uint32_t cur[MAX_ROWS];
-  __shared__ unsigned long long msk[MAX_ROWS];
-  const int b = xcd_remap(blockIdx.x, t.cblk_off[t.nv]);
-  if (b < 0) return;
+// pairs (lane order = depth order); for every row, a ballot gives the mask
+// of lanes spanning it, so lane l's slot in that row is the row cursor plus
+// the number of lower lanes in the mask.  The cursor of row y lives in lane
+// y % 64 of register cur[y / 64]: no LDS, no barriers.
+__global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, const uint32_t* counts,
+                                                     const uint2* row_rg, uint2* rows,
+                                                     unsigned long long row_cap,
+                                                     const unsigned int* row_flag) {
+  constexpr int NG = MAX_ROWS / 64;
+  const int nc = t.cblk_off[t.nv];
+  const int b = xcd_remap(blockIdx.x, (nc + 3) / 4) * 4 +
+                __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (b < 0 || b >= nc) return;
   int v, lo, hi;
   chunk_range(t, st.hdr, b, v, lo, hi);
   if (lo >= hi || *row_flag) return;
-  const int lane = threadIdx.x, TY = t.TY;
-  for (int y = lane; y < TY; y += 64)
-    cur[y] = row_rg[(size_t)v * TY + y].x + counts[(size_t)b * TY + y];
+  const int lane = threadIdx.x & 63, TY = t.TY;
+  uint32_t cur[NG];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int y = g * 64 + lane;
+    cur[g] = y < TY ? row_rg[(size_t)v * TY + y].x + counts[(size_t)b * TY + y] : 0u;
+  }
   const unsigned long long lt = (1ull << lane) - 1ull;
-  __builtin_amdgcn_wave_barrier();
   for (int base = lo; base < hi; base += 64) {
     const int i = base + lane;
     const bool valid = i < hi;
     const uint32_t pair = valid ? st.order[i] : 0u;
     const uint2 r = valid ? st.rect[pair] : make_uint2(0u, 0u);
-    const int y0 = valid ? (int)(r.x >> 16) : TY, y1 = valid ? (int)(r.y >> 16) : 0;
-    const uint32_t xs = (r.x & 0xFFFF) | (r.y << 16);
-    int ylo = y0, yhi = y1;
+    const int y0 = (int)(r.x >> 16), y1 = valid ? (int)(r.y >> 16) : 0;
+    const uint2 ent = make_uint2(pair, (r.x & 0xFFFF) | (r.y << 16));
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-      ylo = min(ylo, __shfl_xor(ylo, d, 64));
-      yhi = max(yhi, __shfl_xor(yhi, d, 64));
+    for (int g = 0; g < NG; ++g) {
+      if (g * 64 >= TY) break;
+      const int ye = min(64, TY - g * 64);
+      for (int yi = 0; yi < ye; ++yi) {
+        const int y = g * 64 + yi;
+        const bool cov = y0 <= y && y < y1;
+        const unsigned long long m = __ballot(cov);
+        if (m == 0ull) continue;
+        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)cur[g], yi);
+        if (cov) {
+          const uint32_t pos = c0 + (uint32_t)__popcll(m & lt);
+          if (pos < row_cap) rows[pos] = ent;
+        }
+        if (lane == yi) cur[g] = c0 + (uint32_t)__popcll(m);
+      }
     }
-    for (int y = ylo; y < yhi; ++y) {
-      const unsigned long long m = __ballot(y0 <= y && y < y1);
-      if (lane == 0) msk[y] = m;
-    }
-    // LDS operations of one wave complete in issue order
-    __builtin_amdgcn_wave_barrier();
-    for (int y = y0; y < y1; ++y) {
-      const uint32_t pos = cur[y] + (uint32_t)__popcll(msk[y] & lt);
-      if (pos < row_cap) rows[pos] = make_uint2(pair, xs);
-    }
-    __builtin_amdgcn_wave_barrier();
-    for (int y = ylo + lane; y < yhi; y += 64) cur[y] += (uint32_t)__popcll(msk[y]);
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -320,120 +324,61 @@ __global__ __launch_bounds__(256) void k_seg_colscan(int nrows, int TX, const ui
   tile_cnt[g] = run;
 }
 
-// Per segment (grid-stride): the segment is cut into batches of up to 256
-// entries (one per thread) whose tile instances fit an LDS buffer.  A
-// batch's instances are first placed in the buffer grouped by tile (each
-// tile's part in list order, ranked with per-wave ballots), then copied out
-// slot by slot, so consecutive lanes store to consecutive addresses of one
-// tile's list: a tile's share of a batch is one contiguous run.
-constexpr int TS_THREADS = 256, TS_WAVES = TS_THREADS / 64, TS_BUF = 4096;
-static_assert(TS_BUF >= MAX_COLS, "one row entry must always fit a batch");
-__global__ __launch_bounds__(TS_THREADS) void k_tile_scatter(BinTab t, StateDev st,
-                                                             const uint32_t* seg_off,
-                                                             const uint32_t* seg_row,
-                                                             const uint32_t* seg_cnt,
-                                                             const uint2* row_rg,
-                                                             const uint2* rows) {
-  __shared__ uint32_t buf[TS_BUF];                       // pair ids, grouped by tile
-  __shared__ uint16_t bcol[TS_BUF];                      // tile column of each slot
-  __shared__ unsigned long long wm[TS_WAVES][MAX_COLS];  // per-wave spanning masks
-  __shared__ uint32_t woff[TS_WAVES][MAX_COLS];          // first slot per (wave, column)
-  __shared__ uint32_t cur[MAX_COLS];                     // next list position per tile
-  __shared__ uint32_t dst[MAX_COLS];                     // list position of slot 0's run
-  __shared__ uint32_t wtot[TS_WAVES];
-  __shared__ int wlo[TS_WAVES], whi[TS_WAVES], wfit[TS_WAVES];
-  __shared__ uint32_t batch_tot;
+// One wave per segment (grid-stride over the device-side segment count),
+// 64 entries per step (lane order = list order).  For every tile column a
+// ballot gives the lanes whose entry covers it; lane l stores its pair at
+// the column's cursor plus the number of lower lanes in the mask.  The
+// cursor of column x lives in lane x % 64 of register cur[x / 64]: no LDS,
+// no barriers.  Consecutive covering lanes store consecutive words of one
+// tile's list, and a column's runs of consecutive steps are adjacent.
+constexpr int TS_WAVES = 4;
+__global__ __launch_bounds__(64 * TS_WAVES) void k_tile_scatter(BinTab t, StateDev st,
+                                                                const uint32_t* seg_off,
+                                                                const uint32_t* seg_row,
+                                                                const uint32_t* seg_cnt,
+                                                                const uint2* row_rg,
+                                                                const uint2* rows) {
+  constexpr int NG = MAX_COLS / 64;
   if (st.hdr->overflow) return;
   const int nrows = t.nv * t.TY;
   const uint32_t nseg = seg_off[nrows];
-  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-  const int TX = t.TX;
+  const int lane = threadIdx.x & 63, TX = t.TX;
+  const uint32_t nw = gridDim.x * TS_WAVES;
   const unsigned long long lt = (1ull << lane) - 1ull;
-  for (uint32_t s = (uint32_t)xcd_remap(blockIdx.x, gridDim.x); s < nseg; s += gridDim.x) {
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  for (uint32_t s = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * TS_WAVES + wave; s < nseg;
+       s += nw) {
     int r;
     uint32_t lo, hi;
     seg_range(seg_off, seg_row, row_rg, s, r, lo, hi);
-    const uint2* trg = st.ranges + (size_t)r * TX;
-    // every thread has passed the previous segment's last read of cur
-    __syncthreads();
-    for (int x = tid; x < TX; x += TS_THREADS) cur[x] = trg[x].x + seg_cnt[(size_t)s * TX + x];
-    uint2 e = lo + (uint32_t)tid < hi ? rows[lo + tid] : make_uint2(0u, 0u);
-    for (uint32_t base = lo; base < hi;) {
-      const bool valid = base + (uint32_t)tid < hi;
-      const int x0 = (int)(e.y & 0xFFFF), x1 = (int)(e.y >> 16);
-      const uint32_t wid = valid ? (uint32_t)(x1 - x0) : 0u;
-      // inclusive prefix of the widths over the batch, in list order
-      uint32_t incl = wave_incl_scan(wid);
-      if (lane == 63) wtot[w] = incl;
-      __syncthreads();
-      for (int q = 0; q < w; ++q) incl += wtot[q];
-      // the prefix is non-decreasing, so the entries that fit are a prefix
-      // of the batch (at least one: a width is at most MAX_COLS)
-      const bool fit = valid && incl <= (uint32_t)TS_BUF;
-      int clo = fit ? x0 : TX, chi = fit ? x1 : 0;
+    uint32_t cur[NG];
 #pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) {
-        clo = min(clo, __shfl_xor(clo, d, 64));
-        chi = max(chi, __shfl_xor(chi, d, 64));
-      }
-      for (int x = clo; x < chi; ++x) {
-        const unsigned long long m = __ballot(fit && x0 <= x && x < x1);
-        if (lane == 0) wm[w][x] = m;
-      }
-      const unsigned long long fm = __ballot(fit);
-      if (lane == 0) {
-        wlo[w] = clo;
-        whi[w] = chi;
-        wfit[w] = __popcll(fm);
-      }
-      __syncthreads();
-      uint32_t nfit = 0;
+    for (int g = 0; g < NG; ++g) {
+      const int x = g * 64 + lane;
+      cur[g] = x < TX ? st.ranges[(size_t)r * TX + x].x + seg_cnt[(size_t)s * TX + x] : 0u;
+    }
+    for (uint32_t base = lo; base < hi; base += 64) {
+      const uint32_t i = base + lane;
+      const bool valid = i < hi;
+      const uint2 e = valid ? rows[i] : make_uint2(0u, 0u);
+      const int x0 = (int)(e.y & 0xFFFF), x1 = valid ? (int)(e.y >> 16) : 0;
 #pragma unroll
-      for (int q = 0; q < TS_WAVES; ++q) nfit += (uint32_t)wfit[q];
-      // wave 0: per-column counts, slot bases and list destinations
-      if (w == 0) {
-        uint32_t carry = 0;
-        for (int xb = 0; xb < TX; xb += 64) {
-          const int x = xb + lane;
-          uint32_t c[TS_WAVES], n = 0;
-#pragma unroll
-          for (int q = 0; q < TS_WAVES; ++q) {
-            c[q] = (x < TX && x >= wlo[q] && x < whi[q]) ? (uint32_t)__popcll(wm[q][x]) : 0u;
-            n += c[q];
+      for (int g = 0; g < NG; ++g) {
+        if (g * 64 >= TX) break;
+        const int xe = min(64, TX - g * 64);
+        for (int xi = 0; xi < xe; ++xi) {
+          const int x = g * 64 + xi;
+          const bool cov = x0 <= x && x < x1;
+          const unsigned long long m = __ballot(cov);
+          if (m == 0ull) continue;
+          const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)cur[g], xi);
+          if (cov) {
+            const uint32_t pos = c0 + (uint32_t)__popcll(m & lt);
+            if (pos < st.cap) st.inst[pos] = e.x;
           }
-          const uint32_t inc = wave_incl_scan(n) + carry;
-          if (x < TX) {
-            uint32_t o = inc - n;
-            const uint32_t c0 = cur[x];
-            dst[x] = c0 - o;  // slot k of column x goes to list position dst[x] + k
-            cur[x] = c0 + n;
-#pragma unroll
-            for (int q = 0; q < TS_WAVES; ++q) {
-              woff[q][x] = o;
-              o += c[q];
-            }
-          }
-          carry = __shfl(inc, 63, 64);
+          if (lane == xi) cur[g] = c0 + (uint32_t)__popcll(m);
         }
-        if (lane == 0) batch_tot = carry;
       }
-      __syncthreads();
-      if (fit)
-        for (int x = x0; x < x1; ++x) {
-          const uint32_t slot = woff[w][x] + (uint32_t)__popcll(wm[w][x] & lt);
-          buf[slot] = e.x;
-          bcol[slot] = (uint16_t)x;
-        }
-      // next batch's entries are in flight while this one is copied out
-      const uint32_t nb = base + nfit;
-      e = nb + (uint32_t)tid < hi ? rows[nb + tid] : make_uint2(0u, 0u);
-      __syncthreads();
-      const uint32_t n = batch_tot;
-      for (uint32_t k = (uint32_t)tid; k < n; k += TS_THREADS) {
-        const uint32_t pos = dst[bcol[k]] + k;
-        if (pos < st.cap) st.inst[pos] = buf[k];
-      }
-      base = nb;
     }
   }
 }
@@ -450,8 +395,8 @@ hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStr
                      w.row_cap, &st.hdr->row_total, w.row_flag, (const unsigned int*)nullptr,
                      (const unsigned long long*)nullptr);
   if (nc > 0)
-    hipLaunchKernelGGL(k_row_scatter, dim3(xcd_grid(nc)), dim3(64), 0, s, t, st, w.counts,
-                       w.row_rg, w.rows, w.row_cap, w.row_flag);
+    hipLaunchKernelGGL(k_row_scatter, dim3(xcd_grid((nc + 3) / 4)), dim3(256), 0, s, t, st,
+                       w.counts, w.row_rg, w.rows, w.row_cap, w.row_flag);
   // level 2: tiles, per row segment
   hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, s, nrows, w.row_rg, w.seg_off,
                      w.seg_row, w.row_flag);
@@ -462,8 +407,8 @@ hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStr
   hipLaunchKernelGGL(k_range_scan, dim3(1), dim3(1024), 0, s, t.nv * t.T, w.tile_cnt, st.ranges,
                      st.cap, &st.hdr->inst_total, &st.hdr->overflow, w.row_flag,
                      &st.hdr->row_total);
-  hipLaunchKernelGGL(k_tile_scatter, dim3(w.seg_grid), dim3(TS_THREADS), 0, s, t, st, w.seg_off,
-                     w.seg_row, w.seg_cnt, w.row_rg, w.rows);
+  hipLaunchKernelGGL(k_tile_scatter, dim3(w.seg_grid), dim3(64 * TS_WAVES), 0, s, t, st,
+                     w.seg_off, w.seg_row, w.seg_cnt, w.row_rg, w.rows);
   return hipGetLastError();
 }
 
