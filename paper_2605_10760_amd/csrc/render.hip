@@ -75,29 +75,30 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
     }
     __syncthreads();
     const int n = (int)min((uint32_t)NT, rg.y - base);
-    if (!done) {
-      for (int j = 0; j < n; ++j) {
-        const float4 a = s0[j], b = s1[j];
-        float dx, dy;
-        const float power = splat_power(a, b, fx, fy, dx, dy);
-        ++ne;
-        if (power > 0.f) continue;
-        const float al = fminf(ALPHA_MAX, b.y * exp2_fast(power));
-        if (al < ALPHA_MIN) continue;
-        const float Tn = Tc * (1.f - al);
-        if (Tn < T_MIN) {
-          done = true;
-          break;
-        }
-        const float wgt = al * Tc;
-        const float4 c = s2[j];
-        c0 += c.x * wgt;
-        c1 += c.y * wgt;
-        c2 += c.z * wgt;
-        dz += b.z * wgt;
-        Tc = Tn;
-        last = base - rg.x + (uint32_t)j + 1u;
-      }
+    // Branch-free per pixel: every lane evaluates every entry and a finished
+    // or skipped pixel takes a zero weight (adding an exact zero leaves the
+    // sums unchanged), so the loop carries no divergent control flow; a wave
+    // leaves the batch once all its pixels have finished.
+    for (int j = 0; j < n; ++j) {
+      if (__ballot(!done) == 0ull) break;
+      const float4 a = s0[j], b = s1[j];
+      float dx, dy;
+      const float power = splat_power(a, b, fx, fy, dx, dy);
+      const float al = fminf(ALPHA_MAX, b.y * exp2_fast(power));
+      const bool use = !done && !(power > 0.f || al < ALPHA_MIN);
+      ne += done ? 0 : 1;
+      const float Tn = Tc * (1.f - al);
+      const bool stop = use && Tn < T_MIN;
+      const bool ok = use && !stop;
+      done = done || stop;
+      const float wgt = ok ? al * Tc : 0.f;
+      const float4 c = s2[j];
+      c0 += c.x * wgt;
+      c1 += c.y * wgt;
+      c2 += c.z * wgt;
+      dz += b.z * wgt;
+      Tc = ok ? Tn : Tc;
+      last = ok ? base - rg.x + (uint32_t)j + 1u : last;
     }
   }
   if (inside) {
@@ -200,19 +201,22 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
 #pragma unroll
       for (int i = 0; i < GRAD2D; ++i) acc[i] = 0.f;
       bool act = false;
+      // Branch-free per pixel: an entry a pixel does not blend gets zero
+      // weight and zero gradients (selected, never multiplied, so an
+      // infinite exp2 of a skipped entry cannot leak in); adding exact zeros
+      // leaves every sum unchanged.
 #pragma unroll
       for (int k = 0; k < PPL; ++k) {
-        if (pos >= (int)lastp[k]) continue;
         float dx, dy;
         const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
         const float G = exp2_fast(power);
         const float raw = b.y * G;
         const float al = fminf(ALPHA_MAX, raw);
-        if (power > 0.f || al < ALPHA_MIN) continue;
-        act = true;
+        const bool ok = pos < (int)lastp[k] && !(power > 0.f || al < ALPHA_MIN);
+        act = act || ok;
         const float inv = rcp_fast(1.f - al);
         const float Tb = Tc[k] * inv;
-        const float wgt = al * Tb;
+        const float wgt = ok ? al * Tb : 0.f;
         const float dA = (c.x * Tb - S0[k] * inv) * g0[k] + (c.y * Tb - S1[k] * inv) * g1[k] +
                          (c.z * Tb - S2[k] * inv) * g2[k] + (b.z * Tb - SD[k] * inv) * gd[k] +
                          Tf[k] * inv * ga[k];
@@ -224,17 +228,16 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
         acc[7] += wgt * g1[k];
         acc[8] += wgt * g2[k];
         acc[9] += wgt * gd[k];
-        if (raw <= ALPHA_MAX) {
-          const float gp = al * dA;
-          acc[5] += G * dA;
-          // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.
-          acc[0] += gp * LN2 * (2.f * a.z * dx + a.w * dy);
-          acc[1] += gp * LN2 * (a.w * dx + 2.f * b.x * dy);
-          acc[2] -= 0.5f * gp * dx * dx;
-          acc[3] -= gp * dx * dy;
-          acc[4] -= 0.5f * gp * dy * dy;
-        }
-        Tc[k] = Tb;
+        const bool unc = ok && raw <= ALPHA_MAX;
+        const float gp = unc ? al * dA : 0.f;
+        acc[5] += unc ? G * dA : 0.f;
+        // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.
+        acc[0] += gp * LN2 * (2.f * a.z * dx + a.w * dy);
+        acc[1] += gp * LN2 * (a.w * dx + 2.f * b.x * dy);
+        acc[2] -= 0.5f * gp * dx * dx;
+        acc[3] -= gp * dx * dy;
+        acc[4] -= 0.5f * gp * dy * dy;
+        Tc[k] = ok ? Tb : Tc[k];
       }
       if (__ballot(act) != 0ull) {
         float r[GRAD2D];
