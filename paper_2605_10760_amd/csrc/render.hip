@@ -114,6 +114,57 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
   }
 }
 
+// Wave sums of ten values at once, by a transposing butterfly: at each
+// exchange a lane keeps half of its values and hands the other half to its
+// partner, so the number of values per lane halves as the partial sums
+// double (10 -> 5 -> 3 -> 2 -> 1 over lane bits 0..3, then bits 4 and 5 on
+// the single value).  Lane l < 16 ends with the total of value sum10_index(l)
+// (-1: no value); lanes 16..63 hold copies.  About 45 lane operations
+// instead of 70 for ten separate reductions.
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                               0xF, 0xF, false));
+}
+__host__ __device__ constexpr int sum10_index(int l) {
+  const int b0 = l & 1, b1 = (l >> 1) & 1, b2 = (l >> 2) & 1, b3 = (l >> 3) & 1;
+  const int xi = b3 + 2 * b2, m = xi + 3 * b1;
+  return (l < 16 && xi < 3 && m < 5) ? m + 5 * b0 : -1;
+}
+__device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane) {
+  const bool b0 = lane & 1, b1 = (lane >> 1) & 1, b2 = (lane >> 2) & 1, b3 = (lane >> 3) & 1;
+  // lane bit 0 (quad_perm [1,0,3,2]): keep values 0..4 (b0 = 0) or 5..9
+  float w[6];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const float keep = b0 ? v[i + 5] : v[i], send = b0 ? v[i] : v[i + 5];
+    w[i] = keep + dpp_mov<0xB1>(send);
+  }
+  w[5] = 0.f;
+  // lane bit 1 (quad_perm [2,3,0,1]): keep w 0..2 or 3..5
+  float x[4];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float keep = b1 ? w[i + 3] : w[i], send = b1 ? w[i] : w[i + 3];
+    x[i] = keep + dpp_mov<0x4E>(send);
+  }
+  x[3] = 0.f;
+  // lane bit 2 (row_shl:4 from lane l+4, row_shr:4 from lane l-4)
+  float y[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float keep = b2 ? x[i + 2] : x[i], send = b2 ? x[i] : x[i + 2];
+    const float up = dpp_mov<0x104>(send), dn = dpp_mov<0x114>(send);
+    y[i] = keep + (b2 ? dn : up);
+  }
+  // lane bit 3 (row_ror:8)
+  float z = (b3 ? y[1] : y[0]) + dpp_mov<0x128>(b3 ? y[0] : y[1]);
+  // lane bits 4 and 5: the same value index in both partners
+  z += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, z), 0x401F));
+  z += __shfl_xor(z, 32, 64);
+  return z;
+}
+
 // One wave per tile.  Lane l shades pixel (l % 8, l / 8) of each of the
 // tile's PPL 8x8 blocks; a record staged in LDS is read once per lane and
 // used for its PPL pixels.
@@ -144,8 +195,11 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
   const int ty = tl / TX, tx = tl - ty * TX;
   const int lane = threadIdx.x & 63;
   const size_t HW = (size_t)W * H;
-  float fxp[PPL], fyp[PPL], Tc[PPL], Tf[PPL], g0[PPL], g1[PPL], g2[PPL], gd[PPL], ga[PPL];
-  float S0[PPL], S1[PPL], S2[PPL], SD[PPL];
+  // Per pixel: Q = sum over the entries behind the current one (and the
+  // background) of the upstream-weighted colour and depth, minus T_final
+  // times the upstream alpha gradient; then dL/dalpha_j = T_j cg_j - Q / (1 -
+  // alpha_j) with cg_j = c_j . dL/dC + z_j dL/dD, and Q += w_j cg_j.
+  float fxp[PPL], fyp[PPL], Tc[PPL], g0[PPL], g1[PPL], g2[PPL], gd[PPL], Q[PPL];
   uint32_t lastp[PPL];
   uint32_t mylast = 0;
   constexpr int BX = TW / 8;
@@ -156,7 +210,8 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
     fxp[k] = (float)px + 0.5f;
     fyp[k] = (float)py + 0.5f;
     Tc[k] = 1.f; lastp[k] = 0;
-    g0[k] = g1[k] = g2[k] = gd[k] = ga[k] = 0.f;
+    g0[k] = g1[k] = g2[k] = gd[k] = 0.f;
+    float ga = 0.f;
     if (px < W && py < H) {
       const size_t q = (size_t)py * W + px;
       Tc[k] = st.tfinal[v * HW + q];
@@ -167,13 +222,9 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
         g2[k] = gcol[(3 * (size_t)v + 2) * HW + q];
       }
       if (gdep) gd[k] = gdep[v * HW + q];
-      if (galp) ga[k] = galp[v * HW + q];
+      if (galp) ga = galp[v * HW + q];
     }
-    Tf[k] = Tc[k];
-    S0[k] = Tf[k] * cam.bg0;
-    S1[k] = Tf[k] * cam.bg1;
-    S2[k] = Tf[k] * cam.bg2;
-    SD[k] = 0.f;
+    Q[k] = Tc[k] * (cam.bg0 * g0[k] + cam.bg1 * g1[k] + cam.bg2 * g2[k]) - Tc[k] * ga;
     mylast = max(mylast, lastp[k]);
   }
 #pragma unroll
@@ -217,13 +268,9 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
         const float inv = rcp_fast(1.f - al);
         const float Tb = Tc[k] * inv;
         const float wgt = ok ? al * Tb : 0.f;
-        const float dA = (c.x * Tb - S0[k] * inv) * g0[k] + (c.y * Tb - S1[k] * inv) * g1[k] +
-                         (c.z * Tb - S2[k] * inv) * g2[k] + (b.z * Tb - SD[k] * inv) * gd[k] +
-                         Tf[k] * inv * ga[k];
-        S0[k] += c.x * wgt;
-        S1[k] += c.y * wgt;
-        S2[k] += c.z * wgt;
-        SD[k] += b.z * wgt;
+        const float cg = c.x * g0[k] + c.y * g1[k] + c.z * g2[k] + b.z * gd[k];
+        const float dA = Tb * cg - inv * Q[k];
+        Q[k] += wgt * cg;
         acc[6] += wgt * g0[k];
         acc[7] += wgt * g1[k];
         acc[8] += wgt * g2[k];
@@ -231,22 +278,30 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
         const bool unc = ok && raw <= ALPHA_MAX;
         const float gp = unc ? al * dA : 0.f;
         acc[5] += unc ? G * dA : 0.f;
-        // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.
-        acc[0] += gp * LN2 * (2.f * a.z * dx + a.w * dy);
-        acc[1] += gp * LN2 * (a.w * dx + 2.f * b.x * dy);
-        acc[2] -= 0.5f * gp * dx * dx;
-        acc[3] -= gp * dx * dy;
-        acc[4] -= 0.5f * gp * dy * dy;
+        // moments of gp over dx, dy: the conic and mean gradients are
+        // linear in them (applied once per entry after the wave sum)
+        const float gpx = gp * dx, gpy = gp * dy;
+        acc[0] += gpx;
+        acc[1] += gpy;
+        acc[2] += gpx * dx;
+        acc[3] += gpx * dy;
+        acc[4] += gpy * dy;
         Tc[k] = ok ? Tb : Tc[k];
       }
       if (__ballot(act) != 0ull) {
-        float r[GRAD2D];
-#pragma unroll
-        for (int i = 0; i < GRAD2D; ++i) r[i] = wave_total(acc[i]);
-        float mine = 0.f;
-#pragma unroll
-        for (int i = 0; i < GRAD2D; ++i) mine = (lane == i) ? r[i] : mine;
-        if (lane < GRAD2D && mine != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + lane, mine);
+        static_assert(GRAD2D == 10, "ten splat gradients");
+        const float tot = wave_sum10(acc, lane);
+        const int idx = sum10_index(lane);
+        // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.; the
+        // moment sums 0 and 1 sit in lanes 0 and 8
+        const float m0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 0));
+        const float m1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 8));
+        float out = tot;
+        out = idx == 0 ? LN2 * (2.f * a.z * m0 + a.w * m1) : out;
+        out = idx == 1 ? LN2 * (a.w * m0 + 2.f * b.x * m1) : out;
+        out = (idx == 2 || idx == 4) ? -0.5f * tot : out;
+        out = idx == 3 ? -tot : out;
+        if (idx >= 0 && out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
       }
     }
   }
