@@ -43,12 +43,39 @@ __device__ __forceinline__ float exp2_fast(float p) { return __builtin_amdgcn_ex
 // (1 - alpha_j >= 0.01, so x is far from denormal).
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Whether the splat's alpha >= 1/255 region can reach a pixel centre of the
+// box [x0, x1] x [y0, y1].  The region is the ellipse
+// a dx^2 + b dx dy + c dy^2 <= t (a = -A', b = -B', c = -C', dx = x - u,
+// dy = y - v); taking t so that its y half-extent equals the record's
+// conservative ey (which carries a margin) gives an ellipse containing the
+// region.  Within the rows y0..y1 its x extent is reached at the clamped
+// dy of the ellipse's leftmost / rightmost points (the right boundary
+// x(dy) = u + (-b dy + sqrt(4ac - b^2) sqrt(ey^2 - dy^2)) / 2a is concave,
+// the left one convex), and the comparison carries a further margin for
+// the FP32 arithmetic.  NaN inputs give true.
+__device__ __forceinline__ bool reaches(const float4& r0, float Cs, float ex, float ey, float x0,
+                                        float x1, float y0, float y1) {
+  const float a = -r0.z, b = -r0.w, c = -Cs;
+  const float lo = fmaxf(y0 - r0.y, -ey), hi = fminf(y1 - r0.y, ey);
+  if (lo > hi) return false;
+  const float sd = sqrtf(fmaxf(4.f * a * c - b * b, 0.f));
+  const float ys = b * ey / (2.f * sqrtf(a * c));
+  const float yr = fminf(fmaxf(-ys, lo), hi), yl = fminf(fmaxf(ys, lo), hi);
+  const float wr = sd * sqrtf(fmaxf((ey - yr) * (ey + yr), 0.f));
+  const float wl = sd * sqrtf(fmaxf((ey - yl) * (ey + yl), 0.f));
+  const float h = 0.5f / a;
+  const float xr = r0.x + (wr - b * yr) * h, xl = r0.x - (wl + b * yl) * h;
+  const float m = 0.05f + 1e-3f * ex;
+  return !(xr + m < x0 || xl - m > x1);
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H, int TX, int TY, CamDev cam,
                                                        StateDev st, float* color, float* depth,
                                                        float* alpha, int32_t* n_eval) {
   constexpr int NT = TW * TH;
   __shared__ float4 s0[NT], s1[NT], s2[NT];
+  __shared__ uint32_t smask[NT];
   const int T = TX * TY;
   const int g = xcd_remap(blockIdx.x, ntiles);
   if (g < 0) return;
@@ -61,17 +88,30 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
   if (st.hdr->overflow) rg = make_uint2(0u, 0u);
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   float Tc = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dz = 0.f;
-  uint32_t last = 0;
-  int ne = 0;
+  uint32_t last = 0, stopn = 0;
   bool done = !inside;
+  // wave w shades tile rows [w RW, (w + 1) RW); pixel-centre box of the tile
+  constexpr int NWV = NT / 64, RW = 64 / TW;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const float x0c = (float)(tx * TW) + 0.5f, x1c = x0c + (float)(TW - 1);
+  const float y0c = (float)(ty * TH) + 0.5f;
   for (uint32_t base = rg.x; base < rg.y; base += NT) {
     if (__syncthreads_count(!done) == 0) break;
     const uint32_t idx = base + tid;
     if (idx < rg.y) {
       const float4* r = st.rec + 3 * (size_t)st.inst[idx];
-      s0[tid] = r[0];
-      s1[tid] = r[1];
-      s2[tid] = r[2];
+      const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+      // bit w: the entry can reach a pixel of wave w's rows
+      uint32_t m = 0;
+#pragma unroll
+      for (int w = 0; w < NWV; ++w)
+        m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c, x1c, y0c + (float)(w * RW),
+                               y0c + (float)(w * RW + RW - 1))
+             << w;
+      s0[tid] = r0;
+      s1[tid] = r1;
+      s2[tid] = r2;
+      smask[tid] = m;
     }
     __syncthreads();
     const int n = (int)min((uint32_t)NT, rg.y - base);
@@ -79,26 +119,39 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
     // or skipped pixel takes a zero weight (adding an exact zero leaves the
     // sums unchanged), so the loop carries no divergent control flow; a wave
     // leaves the batch once all its pixels have finished.
-    for (int j = 0; j < n; ++j) {
-      if (__ballot(!done) == 0ull) break;
-      const float4 a = s0[j], b = s1[j];
-      float dx, dy;
-      const float power = splat_power(a, b, fx, fy, dx, dy);
-      const float al = fminf(ALPHA_MAX, b.y * exp2_fast(power));
-      const bool use = !done && !(power > 0.f || al < ALPHA_MIN);
-      ne += done ? 0 : 1;
-      const float Tn = Tc * (1.f - al);
-      const bool stop = use && Tn < T_MIN;
-      const bool ok = use && !stop;
-      done = done || stop;
-      const float wgt = ok ? al * Tc : 0.f;
-      const float4 c = s2[j];
-      c0 += c.x * wgt;
-      c1 += c.y * wgt;
-      c2 += c.z * wgt;
-      dz += b.z * wgt;
-      Tc = ok ? Tn : Tc;
-      last = ok ? base - rg.x + (uint32_t)j + 1u : last;
+    // The wave walks only the entries that can reach alpha >= 1/255 in its
+    // rows: 64 entries at a time, the set bits of a ballot over their reach
+    // masks, in list order.
+    bool live = true;
+    for (int jb = 0; jb < n && live; jb += 64) {
+      const uint32_t mv = jb + lane < n ? smask[jb + lane] : 0u;
+      unsigned long long rel = __ballot((mv >> wv) & 1u);
+      while (rel) {
+        if (__ballot(!done) == 0ull) {
+          live = false;
+          break;
+        }
+        const int j = jb + (int)__builtin_ctzll(rel);
+        rel &= rel - 1ull;
+        const float4 a = s0[j], b = s1[j];
+        float dx, dy;
+        const float power = splat_power(a, b, fx, fy, dx, dy);
+        const float al = fminf(ALPHA_MAX, b.y * exp2_fast(power));
+        const bool use = !done && !(power > 0.f || al < ALPHA_MIN);
+        const float Tn = Tc * (1.f - al);
+        const bool stop = use && Tn < T_MIN;
+        const bool ok = use && !stop;
+        stopn = stop ? base - rg.x + (uint32_t)j + 1u : stopn;
+        done = done || stop;
+        const float wgt = ok ? al * Tc : 0.f;
+        const float4 c = s2[j];
+        c0 += c.x * wgt;
+        c1 += c.y * wgt;
+        c2 += c.z * wgt;
+        dz += b.z * wgt;
+        Tc = ok ? Tn : Tc;
+        last = ok ? base - rg.x + (uint32_t)j + 1u : last;
+      }
     }
   }
   if (inside) {
@@ -110,7 +163,8 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
     alpha[v * HW + p] = 1.f - Tc;
     st.tfinal[v * HW + p] = Tc;
     st.last[v * HW + p] = last;
-    if (n_eval) n_eval[v * HW + p] = ne;
+    // entries examined: up to and including the stopping one, else the list
+    if (n_eval) n_eval[v * HW + p] = (int)(stopn ? stopn : rg.y - rg.x);
   }
 }
 
@@ -232,76 +286,93 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
   const int maxlast = (int)mylast;
   for (int end = maxlast; end > 0; end -= B) {
     const int start = max(0, end - B);
+    uint32_t mr[B / 64];  // 1 if the entry this lane staged in round r reaches the tile
 #pragma unroll
     for (int r = 0; r < B / 64; ++r) {
       const int i = start + lane + 64 * r;
+      mr[r] = 0u;
       if (i < end) {
         const uint32_t pr = st.inst[rg.x + i];
         const float4* rp = st.rec + 3 * (size_t)pr;
-        s0[lane + 64 * r] = rp[0];
-        s1[lane + 64 * r] = rp[1];
-        s2[lane + 64 * r] = rp[2];
+        const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
+        // whether the entry can reach a pixel of the tile at all
+        const float bx = (float)(tx * TW) + 0.5f, by = (float)(ty * TH) + 0.5f;
+        const uint32_t m =
+            (uint32_t)reaches(r0, r1.x, r1.w, r2.w, bx, bx + (float)(TW - 1), by, by + (float)(TH - 1));
+        s0[lane + 64 * r] = r0;
+        s1[lane + 64 * r] = r1;
+        s2[lane + 64 * r] = r2;
         sp[lane + 64 * r] = pr;
+        mr[r] = m;
       }
     }
     __builtin_amdgcn_wave_barrier();
-    for (int j = end - start - 1; j >= 0; --j) {
-      const int pos = start + j;
-      const float4 a = s0[j], b = s1[j], c = s2[j];
-      float acc[GRAD2D];
+    // Back to front over the staged entries that can reach the tile (set
+    // bits of a ballot per staging round).
 #pragma unroll
-      for (int i = 0; i < GRAD2D; ++i) acc[i] = 0.f;
-      bool act = false;
-      // Branch-free per pixel: an entry a pixel does not blend gets zero
-      // weight and zero gradients (selected, never multiplied, so an
-      // infinite exp2 of a skipped entry cannot leak in); adding exact zeros
-      // leaves every sum unchanged.
+    for (int r = B / 64 - 1; r >= 0; --r) {
+      unsigned long long rel = __ballot(mr[r] != 0u);
+      while (rel) {
+        const int jj = 63 - (int)__builtin_clzll(rel);
+        rel &= ~(1ull << jj);
+        const int j = 64 * r + jj;
+        const int pos = start + j;
+        const float4 a = s0[j], b = s1[j], c = s2[j];
+        float acc[GRAD2D];
 #pragma unroll
-      for (int k = 0; k < PPL; ++k) {
-        float dx, dy;
-        const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
-        const float G = exp2_fast(power);
-        const float raw = b.y * G;
-        const float al = fminf(ALPHA_MAX, raw);
-        const bool ok = pos < (int)lastp[k] && !(power > 0.f || al < ALPHA_MIN);
-        act = act || ok;
-        const float inv = rcp_fast(1.f - al);
-        const float Tb = Tc[k] * inv;
-        const float wgt = ok ? al * Tb : 0.f;
-        const float cg = c.x * g0[k] + c.y * g1[k] + c.z * g2[k] + b.z * gd[k];
-        const float dA = Tb * cg - inv * Q[k];
-        Q[k] += wgt * cg;
-        acc[6] += wgt * g0[k];
-        acc[7] += wgt * g1[k];
-        acc[8] += wgt * g2[k];
-        acc[9] += wgt * gd[k];
-        const bool unc = ok && raw <= ALPHA_MAX;
-        const float gp = unc ? al * dA : 0.f;
-        acc[5] += unc ? G * dA : 0.f;
-        // moments of gp over dx, dy: the conic and mean gradients are
-        // linear in them (applied once per entry after the wave sum)
-        const float gpx = gp * dx, gpy = gp * dy;
-        acc[0] += gpx;
-        acc[1] += gpy;
-        acc[2] += gpx * dx;
-        acc[3] += gpx * dy;
-        acc[4] += gpy * dy;
-        Tc[k] = ok ? Tb : Tc[k];
-      }
-      if (__ballot(act) != 0ull) {
-        static_assert(GRAD2D == 10, "ten splat gradients");
-        const float tot = wave_sum10(acc, lane);
-        const int idx = sum10_index(lane);
-        // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.; the
-        // moment sums 0 and 1 sit in lanes 0 and 8
-        const float m0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 0));
-        const float m1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 8));
-        float out = tot;
-        out = idx == 0 ? LN2 * (2.f * a.z * m0 + a.w * m1) : out;
-        out = idx == 1 ? LN2 * (a.w * m0 + 2.f * b.x * m1) : out;
-        out = (idx == 2 || idx == 4) ? -0.5f * tot : out;
-        out = idx == 3 ? -tot : out;
-        if (idx >= 0 && out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
+        for (int i = 0; i < GRAD2D; ++i) acc[i] = 0.f;
+        bool act = false;
+        // Branch-free per pixel: an entry a pixel does not blend gets zero
+        // weight and zero gradients (selected, never multiplied, so an
+        // infinite exp2 of a skipped entry cannot leak in); adding exact zeros
+        // leaves every sum unchanged.
+#pragma unroll
+        for (int k = 0; k < PPL; ++k) {
+          float dx, dy;
+          const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
+          const float G = exp2_fast(power);
+          const float raw = b.y * G;
+          const float al = fminf(ALPHA_MAX, raw);
+          const bool ok = pos < (int)lastp[k] && !(power > 0.f || al < ALPHA_MIN);
+          act = act || ok;
+          const float inv = rcp_fast(1.f - al);
+          const float Tb = Tc[k] * inv;
+          const float wgt = ok ? al * Tb : 0.f;
+          const float cg = c.x * g0[k] + c.y * g1[k] + c.z * g2[k] + b.z * gd[k];
+          const float dA = Tb * cg - inv * Q[k];
+          Q[k] += wgt * cg;
+          acc[6] += wgt * g0[k];
+          acc[7] += wgt * g1[k];
+          acc[8] += wgt * g2[k];
+          acc[9] += wgt * gd[k];
+          const bool unc = ok && raw <= ALPHA_MAX;
+          const float gp = unc ? al * dA : 0.f;
+          acc[5] += unc ? G * dA : 0.f;
+          // moments of gp over dx, dy: the conic and mean gradients are
+          // linear in them (applied once per entry after the wave sum)
+          const float gpx = gp * dx, gpy = gp * dy;
+          acc[0] += gpx;
+          acc[1] += gpy;
+          acc[2] += gpx * dx;
+          acc[3] += gpx * dy;
+          acc[4] += gpy * dy;
+          Tc[k] = ok ? Tb : Tc[k];
+        }
+        if (__ballot(act) != 0ull) {
+          static_assert(GRAD2D == 10, "ten splat gradients");
+          const float tot = wave_sum10(acc, lane);
+          const int idx = sum10_index(lane);
+          // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.; the
+          // moment sums 0 and 1 sit in lanes 0 and 8
+          const float m0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 0));
+          const float m1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 8));
+          float out = tot;
+          out = idx == 0 ? LN2 * (2.f * a.z * m0 + a.w * m1) : out;
+          out = idx == 1 ? LN2 * (a.w * m0 + 2.f * b.x * m1) : out;
+          out = (idx == 2 || idx == 4) ? -0.5f * tot : out;
+          out = idx == 3 ? -tot : out;
+          if (idx >= 0 && out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
+        }
       }
     }
   }

@@ -122,6 +122,10 @@ def test_forward_images(case):
     for k, r in enumerate(orc):
         ok = ~r["ambiguous"]
         np.testing.assert_array_equal(dbg["last"][k][ok], r["last"][ok])
+        # final transmittance, relative: a blended entry left out anywhere in
+        # a pixel's list would change it by a factor (1 - alpha) <= 254/255
+        tf, to = dbg["t_final"][k][ok].astype(np.float64), r["T_final"][ok]
+        assert np.all(np.abs(tf - to) <= 1e-4 * to + 1e-9), f"T_final view {k}"
 
 
 def _upstream(views, seed, orc):
