@@ -11,7 +11,8 @@
 // A pass is three kernels: per-block digit histograms (LDS atomics), one
 // workgroup per view turning the [block][digit] counts into scatter bases
 // in (digit, block) order, and a scatter where each 256-key round is ranked
-// stably inside the block by wave64 ballots over the digit bits.
+// stably inside the block by wave64 ballots over the digit bits, the block
+// is reordered by digit in LDS and written out in runs.
 #include "common.h"
 
 namespace gsr {
@@ -85,32 +86,60 @@ __global__ __launch_bounds__(RADIX) void k_radix_scan(SortTab t, const StateHead
 
 // Stable scatter.  Keys of round r are the 256 consecutive keys
 // lo + r*256 + tid; within a round lower threads go first, earlier rounds go
-// before later ones, so equal digits keep their input order.
+// before later ones, so equal digits keep their input order.  The block's
+// keys are first placed in LDS in digit order (each key's slot is its
+// digit's offset within the block plus its stable rank), then written out
+// slot by slot: a digit's run of the block (about 8 keys) is stored by
+// consecutive lanes to consecutive addresses instead of one scattered store
+// per key.
 template <int SH, bool KEYS_OUT>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     SortTab t, const StateHeader* hdr, const uint32_t* hist, const uint32_t* kin,
     const uint32_t* vin, uint32_t* kout, uint32_t* vout) {
   constexpr int NW = SORT_THREADS / 64;
   __shared__ uint32_t whist[NW][RADIX];
-  __shared__ uint32_t run[RADIX];
+  __shared__ uint32_t cnt[RADIX];    // keys of each digit placed so far
+  __shared__ uint32_t loff[RADIX];   // first slot of each digit in the block
+  __shared__ uint32_t goff[RADIX];   // output position of the block's first key of each digit
+  __shared__ uint32_t lk[SORT_TILE], lv[SORT_TILE];
+  __shared__ unsigned long long sh[NW + 1];
   const int b = xcd_remap(blockIdx.x, t.sblk_off[t.nv]);
   if (b < 0) return;
   int v, lo, hi;
   sort_block_range(t, hdr, b, v, lo, hi);
   if (lo >= hi) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
-  run[tid] = hist[(size_t)b * RADIX + tid];
+  const int n = hi - lo;
+  // the block's digit counts, from the keys themselves (the histogram pass
+  // holds the global bases)
+  cnt[tid] = 0;
 #pragma unroll
   for (int i = 0; i < NW; ++i) whist[i][tid] = 0;
   __syncthreads();
-  const unsigned long long lt = (1ull << lane) - 1ull;
+  uint32_t key[SORT_ITEMS], val[SORT_ITEMS];
+#pragma unroll
   for (int r = 0; r < SORT_ITEMS; ++r) {
-    const int i = lo + r * SORT_THREADS + tid;
-    if (lo + r * SORT_THREADS >= hi) break;  // uniform
-    const bool valid = i < hi;
-    const uint32_t k = valid ? kin[i] : 0u;
-    const uint32_t val = valid ? vin[i] : 0u;
-    const uint32_t d = (k >> SH) & (RADIX - 1);
+    const int i = r * SORT_THREADS + tid;
+    key[r] = i < n ? kin[lo + i] : 0u;
+    val[r] = i < n ? vin[lo + i] : 0u;
+    if (i < n) atomicAdd(&cnt[(key[r] >> SH) & (RADIX - 1)], 1u);
+  }
+  __syncthreads();
+  {
+    unsigned long long tot;
+    const uint32_t c = cnt[tid];
+    const uint32_t o = (uint32_t)wg_excl_scan<SORT_THREADS>(c, sh, &tot);
+    loff[tid] = o;
+    goff[tid] = hist[(size_t)b * RADIX + tid];
+    cnt[tid] = 0;
+  }
+  __syncthreads();
+  const unsigned long long lt = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int r = 0; r < SORT_ITEMS; ++r) {
+    if (r * SORT_THREADS >= n) break;  // uniform
+    const bool valid = r * SORT_THREADS + tid < n;
+    const uint32_t d = (key[r] >> SH) & (RADIX - 1);
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int bit = 0; bit < RADIX_BITS; ++bit) {
@@ -122,10 +151,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     if (valid && rank == 0) whist[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t pos = run[d] + (uint32_t)rank;
-      for (int j = 0; j < w; ++j) pos += whist[j][d];
-      if (KEYS_OUT) kout[pos] = k;
-      vout[pos] = val;
+      uint32_t slot = loff[d] + cnt[d] + (uint32_t)rank;
+      for (int j = 0; j < w; ++j) slot += whist[j][d];
+      lk[slot] = key[r];
+      lv[slot] = val[r];
     }
     __syncthreads();
     uint32_t add = 0;
@@ -134,8 +163,20 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
       add += whist[j][tid];
       whist[j][tid] = 0;
     }
-    run[tid] += add;
+    cnt[tid] += add;
     __syncthreads();
+  }
+  // slot e holds a key of digit d: its output position is goff[d] + e - loff[d]
+#pragma unroll
+  for (int r = 0; r < SORT_ITEMS; ++r) {
+    const int e = r * SORT_THREADS + tid;
+    if (e < n) {
+      const uint32_t k = lk[e];
+      const uint32_t d = (k >> SH) & (RADIX - 1);
+      const uint32_t pos = goff[d] + (uint32_t)e - loff[d];
+      if (KEYS_OUT) kout[pos] = k;
+      vout[pos] = lv[e];
+    }
   }
 }
 
