@@ -184,18 +184,19 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
     st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
     if (vis) {
       st.rect[pair] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
-      // ---- screen-space record in FP64
-      const double s0 = exp((double)ls[0]), s1 = exp((double)ls[1]), s2 = exp((double)ls[2]);
-      double qw = q[0], qx = q[1], qy = q[2], qz = q[3];
-      const double qn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-      qw /= qn; qx /= qn; qy /= qn; qz /= qn;
-      double R[3][3] = {{1 - 2 * (qy * qy + qz * qz), 2 * (qx * qy - qw * qz), 2 * (qx * qz + qw * qy)},
-                        {2 * (qx * qy + qw * qz), 1 - 2 * (qx * qx + qz * qz), 2 * (qy * qz - qw * qx)},
-                        {2 * (qx * qz - qw * qy), 2 * (qy * qz + qw * qx), 1 - 2 * (qx * qx + qy * qy)}};
-      const double sv[3] = {s0, s1, s2};
+      // ---- screen-space record in FP64.  Scales, rotation and opacity are
+      // formed in FP32 first: their rounding perturbs the parameters by ~1e-7
+      // relative, while the products below, where elongated splats cancel,
+      // run in FP64.
+      const float sv[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+      const float qi = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      const float qw = q[0] * qi, qx = q[1] * qi, qy = q[2] * qi, qz = q[3] * qi;
+      const float R[3][3] = {{1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy)},
+                             {2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx)},
+                             {2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
       double M[3][3];
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sv[j];
+        for (int j = 0; j < 3; ++j) M[i][j] = (double)R[i][j] * (double)sv[j];
       double S[3][3];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
@@ -213,11 +214,12 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
         p[i] = (double)Rc[3 * i] * m[0] + (double)Rc[3 * i + 1] * m[1] +
                (double)Rc[3 * i + 2] * m[2] + (double)tc[i];
       const double fx = in.x, fy = in.y;
-      const double rx = p[0] / p[2], ry = p[1] / p[2];
+      const double ip2 = 1.0 / p[2];
+      const double rx = p[0] * ip2, ry = p[1] * ip2;
       const double limx = 1.3 * (0.5 * t.W) / fx, limy = 1.3 * (0.5 * t.H) / fy;
       const double rxc = fmin(fmax(rx, -limx), limx), ryc = fmin(fmax(ry, -limy), limy);
-      const double j00 = fx / p[2], j02 = -fx * rxc / p[2];
-      const double j11 = fy / p[2], j12 = -fy * ryc / p[2];
+      const double j00 = fx * ip2, j02 = -fx * rxc * ip2;
+      const double j11 = fy * ip2, j12 = -fy * ryc * ip2;
       const double T00 = j00 * V[0][0] + j02 * V[2][0], T01 = j00 * V[0][1] + j02 * V[2][1];
       const double T02 = j00 * V[0][2] + j02 * V[2][2];
       const double T11 = j11 * V[1][1] + j12 * V[2][1], T12 = j11 * V[1][2] + j12 * V[2][2];
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
       const double c = T11 * j11 + T12 * j12 + 0.3;
       const double det = a * c - bb * bb;
       const double u = fx * rx + (double)in.z, vv = fy * ry + (double)in.w;
-      const double sig = 1.0 / (1.0 + exp(-(double)o));
+      const float sigf = 1.f / (1.f + expf(-o));
       float col[3];
       if (SHD == 0) {
         col[0] = sc.colors[3 * gi]; col[1] = sc.colors[3 * gi + 1]; col[2] = sc.colors[3 * gi + 2];
@@ -253,18 +255,18 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
       // above FP32 rounding: every pixel outside this box has alpha < 1/255,
       // so the compositing kernels may skip the splat there without changing
       // any result
-      const double t255 = 255.0 * sig;
-      const double k2d = t255 > 1.0 ? 2.0 * log(t255) : 0.0;
-      const float exr = (float)(sqrt(k2d * a) * (1.0 + 1e-4) + 1e-2);
-      const float eyr = (float)(sqrt(k2d * c) * (1.0 + 1e-4) + 1e-2);
+      const float t255 = 255.f * sigf;
+      const float k2 = t255 > 1.f ? 2.f * logf(t255) : 0.f;
+      const float exr = sqrtf(k2 * (float)a) * (1.f + 1e-4f) + 1e-2f;
+      const float eyr = sqrtf(k2 * (float)c) * (1.f + 1e-4f) + 1e-2f;
       float4* rp = st.rec + 3 * (long)pair;
       // conic (A, B, C) = (c, -b, a)/det, stored pre-scaled so that the
       // exponent in base 2 is A' dx^2 + B' dx dy + C' dy^2:
       // A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2
       const double L2E = 1.4426950408889634;
-      rp[0] = make_float4((float)u, (float)vv, (float)(-0.5 * L2E * c / det),
-                          (float)(L2E * bb / det));
-      rp[1] = make_float4((float)(-0.5 * L2E * a / det), (float)sig, (float)p[2], exr);
+      const double h = L2E / det;
+      rp[0] = make_float4((float)u, (float)vv, (float)(-0.5 * h * c), (float)(h * bb));
+      rp[1] = make_float4((float)(-0.5 * h * a), sigf, (float)p[2], exr);
       rp[2] = make_float4(col[0], col[1], col[2], eyr);
     }
   }
