@@ -12,7 +12,7 @@ import pytest
 from gpu_harness import announce, gpu_forward, grad_rel_err, pair_to_gauss, to_gpu
 from oracle.render import Settings, render_backward, render_pixels, render_view
 from oracle.keypath32 import keypath
-from synth.scenes import multi_agent, room_plain, small_plain, tiny_scene
+from synth.scenes import fused_map, multi_agent, room_plain, small_plain, tiny_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -379,6 +379,110 @@ def test_room_plain_window_gradients():
     ga[0][amb] = 0
     got = _gpu_backward(g, gc, gd, ga)
     ref = render_backward(scene, views, gc, gd, ga)
+    for k_gpu, k_ref in GMAP.items():
+        e_inf, e_2 = grad_rel_err(got[k_gpu], ref[k_ref])
+        assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+
+
+def _window_upstream(scene, views, k, y0, x0, h, w, seed, st=Settings()):
+    """Upstream gradients that are zero except on an h x w window of view k,
+    with the oracle's ambiguous pixels zeroed."""
+    rng = np.random.default_rng(seed)
+    V, H, W = views.n, views.height, views.width
+    gc = np.zeros((V, 3, H, W), np.float32)
+    gd = np.zeros((V, H, W), np.float32)
+    ga = np.zeros((V, H, W), np.float32)
+    gc[k, :, y0:y0 + h, x0:x0 + w] = rng.normal(size=(3, h, w))
+    gd[k, y0:y0 + h, x0:x0 + w] = 0.3 * rng.normal(size=(h, w))
+    ga[k, y0:y0 + h, x0:x0 + w] = rng.normal(size=(h, w))
+    TX = -(-W // st.tile_w)
+    tiles = sorted({(y // st.tile_h) * TX + x // st.tile_w
+                    for y in range(y0, y0 + h) for x in range(x0, x0 + w)})
+    amb = render_view(scene, views, k, st, tiles=tiles)["ambiguous"]
+    gc[k][:, amb] = 0
+    gd[k][amb] = 0
+    ga[k][amb] = 0
+    return gc, gd, ga
+
+
+@pytest.mark.slow
+def test_room_1m_autograd_full_size():
+    """1M Gaussians, one 1200x680 view, through the autograd Function with a
+    pose delta: sampled pixels against the oracle, and the gradients of an
+    upstream window (every parameter and the pose) against the oracle's."""
+    announce("room 1M 1200x680 autograd full size")
+    import torch
+    from paper_2605_10760_amd import rasterize
+    wl = room_plain(seed=20, n=1_000_000)
+    scene, views = wl.scene, wl.views
+    g = gpu_forward(scene, views, export=False)
+    st_, vt = g["scene_t"], g["views_t"]
+    params = [p.clone().requires_grad_(True) for p in
+              (st_.means, st_.log_scales, st_.quats, st_.opacity_logits, st_.colors)]
+    pose = torch.zeros((1, 6), device="cuda", requires_grad=True)
+    c, d, a = rasterize(g["rast"], *params, vt.viewmats, vt.intrinsics, scene.set_offsets,
+                        views.view_set, views.width, views.height, pose_delta=pose)
+    rng = np.random.default_rng(21)
+    px = rng.integers(0, views.width, 96)
+    py = rng.integers(0, views.height, 96)
+    ro = render_pixels(scene, views, 0, px, py)
+    ok = ~ro["ambiguous"]
+    cn, dn, an = c.detach().cpu().numpy(), d.detach().cpu().numpy(), a.detach().cpu().numpy()
+    assert np.abs(cn[0][:, py, px].T - ro["color"])[ok].max() <= IMG_TOL
+    assert np.abs(an[0][py, px] - ro["alpha"])[ok].max() <= IMG_TOL
+    gc, gd, ga = _window_upstream(scene, views, 0, 300, 560, 24, 40, seed=22)
+    t = lambda x: torch.from_numpy(x).cuda()
+    loss = (c * t(gc)).sum() + (d * t(gd)).sum() + (a * t(ga)).sum()
+    loss.backward()
+    ref = render_backward(scene, views, gc, gd, ga)
+    got = dict(zip(("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors"),
+                   (p.grad.cpu().numpy() for p in params)))
+    got["d_pose"] = pose.grad.cpu().numpy()
+    for k_gpu, k_ref in GMAP.items():
+        e_inf, e_2 = grad_rel_err(got[k_gpu], ref[k_ref])
+        assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+
+
+@pytest.mark.slow
+def test_fused_map_full_size_sampled():
+    """3M Gaussians with SH degree 3, 16 forward-only + 32 fwd+bwd views at
+    1200x680 in one batch: sampled tiles' sorted lists bit-exact and sampled
+    pixels for a forward-only view and a keyframe, and a keyframe's window
+    gradients against the oracle."""
+    announce("fused map 3M SH3 48 x 1200x680 full size")
+    wl = fused_map()
+    scene, views = wl.scene, wl.views
+    g = gpu_forward(scene, views)
+    dbg = g["dbg"]
+    TX, TY = dbg["TX"], dbg["TY"]
+    T = TX * TY
+    N = scene.n
+    rng = np.random.default_rng(31)
+    for k in (3, 20):
+        assert bool(views.needs_grad[k]) == (k >= 16)
+        kp = keypath(scene.means, scene.log_scales, scene.quats, scene.opacity_logits,
+                     views.viewmats[k], views.intrinsics[k], views.width, views.height)
+        vis = kp["visible"]
+        rect = kp["rect"]
+        for t in rng.choice(T, size=40, replace=False):
+            ty, tx = divmod(int(t), TX)
+            cov = vis & (rect[:, 0] <= tx) & (tx < rect[:, 2]) & (rect[:, 1] <= ty) & (ty < rect[:, 3])
+            ids = np.nonzero(cov)[0]
+            if kp["straddle"][ids].any():
+                continue
+            want = ids[np.lexsort((ids, kp["zbits"][ids]))]
+            lo, hi = dbg["ranges"][k * T + t]
+            got = dbg["inst"][lo:hi].astype(np.int64) - k * N
+            np.testing.assert_array_equal(got, want, err_msg=f"view {k} tile {t}")
+        px = rng.integers(0, views.width, 64)
+        py = rng.integers(0, views.height, 64)
+        ro = render_pixels(scene, views, k, px, py)
+        ok = ~ro["ambiguous"]
+        assert np.abs(g["color"][k][:, py, px].T - ro["color"])[ok].max() <= IMG_TOL
+        assert np.abs(g["alpha"][k][py, px] - ro["alpha"])[ok].max() <= IMG_TOL
+    gc, gd, ga = _window_upstream(scene, views, 20, 330, 600, 16, 32, seed=32)
+    got = _gpu_backward(g, gc, gd, ga)
+    ref = render_backward(scene, views, gc, gd, ga, view_ids=[20])
     for k_gpu, k_ref in GMAP.items():
         e_inf, e_2 = grad_rel_err(got[k_gpu], ref[k_ref])
         assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
