@@ -14,6 +14,7 @@ Contents (each module cites the passage it follows):
   smooth     FP64-decided brute-force render for finite differences
   sh         real spherical harmonics to degree 3
   se3        SE(3) exponential, left pose update
+  sim3       Sim(3) correction of Gaussians and the lift of keyframe poses
 
 Parity status: every function is pinned by tests under tests/ (closed
 forms, invariants, brute force, library routines, finite differences).
