@@ -220,6 +220,33 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const void* state, int32_t n_views,
 gsr_status gsr_apply_pose_delta(const float* viewmats_in, const float* delta,
                                 float* viewmats_out, int32_t n_views, void* stream);
 
+/* Sim(3) correction of Gaussian sets (Sec. III-D, Eq. (gauss_update)).  The
+ * Gaussians [set_offsets[k], set_offsets[k+1]) of set k move by
+ * sims[k] = (s, qw, qx, qy, qz, tx, ty, tz) (s > 0; the quaternion is
+ * normalised here): means -> s R means + t, log_scales -> log_scales + ln s,
+ * quats -> q_R * quats (Hamilton product, the norm of quats kept).  Opacity
+ * and colours, SH coefficients of every degree included, are not touched.
+ * Device arrays means [N,3], log_scales [N,3], quats [N,4] (out may alias
+ * in) and sims [n_sets,8]; set_offsets is a HOST array of n_sets+1
+ * non-decreasing offsets starting at 0, n_sets in 1..GSR_MAX_SETS.
+ * Enqueues one kernel on `stream`; GSR_E_INVALID_ARG for null pointers or
+ * bad offsets, GSR_E_DEVICE if the launch fails. */
+gsr_status gsr_sim3_gaussians(const float* means_in, const float* log_scales_in,
+                              const float* quats_in, const int64_t* set_offsets, int32_t n_sets,
+                              const float* sims, float* means_out, float* log_scales_out,
+                              float* quats_out, void* stream);
+
+/* Lift of keyframe poses into the global frame (Sec. III-B, Eq. (mapgba_lift)):
+ * view v of set view_set[v], with sims[view_set[v]] = (s, q, t) and R = R(q),
+ * gets viewmats_out[v] = [Rv R^T | s tv - Rv R^T t].  This is the rigid form
+ * of Tv o C^{-1}: the same camera with its length unit scaled by s, so pixels
+ * are unchanged and camera depths (and the near plane) scale by s.  Device
+ * viewmats [n_views,3,4] (out may alias in) and sims [n_sets,8]; view_set is
+ * a HOST array [n_views] of set indices < n_sets.  Enqueues one kernel;
+ * GSR_E_INVALID_ARG for null pointers or out-of-range sizes. */
+gsr_status gsr_sim3_views(const float* viewmats_in, const float* sims, const int32_t* view_set,
+                          int32_t n_views, int32_t n_sets, float* viewmats_out, void* stream);
+
 /* Time forward+backward of the given call for each candidate tile shape and
  * report the fastest (tile_w, tile_h) in `best` (other fields copied from
  * `base`).  Synchronises; allocates its own temporary context. */

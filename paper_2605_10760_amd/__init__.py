@@ -5,4 +5,4 @@ this package only marshals PyTorch tensors into those calls.
 """
 from ._lib import GsrError, load  # noqa: F401
 from .rasterizer import (Rasterizer, SceneTensors, ViewTensors, apply_pose_delta,  # noqa: F401
-                         autotune, pairs_of, rasterize)
+                         autotune, pairs_of, rasterize, sim3_gaussians, sim3_views)

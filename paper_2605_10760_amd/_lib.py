@@ -19,7 +19,7 @@ GSR_E_OVERFLOW, GSR_E_DEVICE, GSR_E_OOM, GSR_E_UNIMPLEMENTED = 4, 5, 6, 7
 EXPORTED = ("gsr_create", "gsr_destroy", "gsr_plan", "gsr_state_bytes", "gsr_forward",
             "gsr_backward", "gsr_poll", "gsr_debug_export", "gsr_apply_pose_delta",
             "gsr_autotune", "gsr_profile_enable", "gsr_profile_read", "gsr_status_string",
-            "gsr_last_error")
+            "gsr_last_error", "gsr_sim3_gaussians", "gsr_sim3_views")
 
 STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "render_bwd",
           "project_bwd")
@@ -115,6 +115,10 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gsr_profile_enable.restype = C.c_int
     lib.gsr_profile_read.argtypes = [vp, P(C.c_float), C.c_int32]
     lib.gsr_profile_read.restype = C.c_int
+    lib.gsr_sim3_gaussians.argtypes = [vp, vp, vp, P(C.c_int64), C.c_int32, vp, vp, vp, vp, vp]
+    lib.gsr_sim3_gaussians.restype = C.c_int
+    lib.gsr_sim3_views.argtypes = [vp, vp, P(C.c_int32), C.c_int32, C.c_int32, vp, vp]
+    lib.gsr_sim3_views.restype = C.c_int
     lib.gsr_status_string.argtypes = [C.c_int]
     lib.gsr_status_string.restype = C.c_char_p
     lib.gsr_last_error.argtypes = [vp]

@@ -605,6 +605,41 @@ gsr_status gsr_apply_pose_delta(const float* vin, const float* delta, float* vou
   return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
 }
 
+gsr_status gsr_sim3_gaussians(const float* means_in, const float* log_scales_in,
+                              const float* quats_in, const int64_t* set_offsets, int32_t n_sets,
+                              const float* sims, float* means_out, float* log_scales_out,
+                              float* quats_out, void* stream) {
+  if (!means_in || !log_scales_in || !quats_in || !set_offsets || !sims || !means_out ||
+      !log_scales_out || !quats_out || n_sets < 1 || n_sets > GSR_MAX_SETS)
+    return GSR_E_INVALID_ARG;
+  SimSetTab tab{};
+  tab.ns = n_sets;
+  if (set_offsets[0] != 0) return GSR_E_INVALID_ARG;
+  for (int k = 0; k <= n_sets; ++k) {
+    if (k > 0 && set_offsets[k] < set_offsets[k - 1]) return GSR_E_INVALID_ARG;
+    tab.off[k] = set_offsets[k];
+  }
+  if (set_offsets[n_sets] > (int64_t)0x7FFFFFFF * 64) return GSR_E_INVALID_ARG;
+  hipError_t e = launch_sim3_gaussians(tab, means_in, log_scales_in, quats_in, sims, means_out,
+                                       log_scales_out, quats_out, (hipStream_t)stream);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
+gsr_status gsr_sim3_views(const float* viewmats_in, const float* sims, const int32_t* view_set,
+                          int32_t n_views, int32_t n_sets, float* viewmats_out, void* stream) {
+  if (!viewmats_in || !sims || !view_set || !viewmats_out || n_views < 1 ||
+      n_views > GSR_MAX_VIEWS || n_sets < 1 || n_sets > GSR_MAX_SETS)
+    return GSR_E_INVALID_ARG;
+  SimViewTab tab{};
+  tab.nv = n_views;
+  for (int v = 0; v < n_views; ++v) {
+    if (view_set[v] < 0 || view_set[v] >= n_sets) return GSR_E_INVALID_ARG;
+    tab.view_set[v] = view_set[v];
+  }
+  hipError_t e = launch_sim3_views(tab, viewmats_in, sims, viewmats_out, (hipStream_t)stream);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
 gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* sc,
                         const gsr_views* vw, const gsr_settings* set, gsr_plan_desc* best,
                         float* best_ms, void* stream) {

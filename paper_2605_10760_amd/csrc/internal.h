@@ -121,6 +121,16 @@ struct BinWork {
   int seg_grid;         // workgroups of the per-segment kernels (multiple of 8)
 };
 
+// Sim(3) corrections: Gaussian set offsets, and the set of every view.
+struct SimSetTab {
+  int ns;
+  long long off[MAXS + 1];
+};
+struct SimViewTab {
+  int nv;
+  int view_set[MAXV];
+};
+
 StateLayout state_layout(const gsr_plan_desc& p);
 StateDev state_ptrs(void* base, const gsr_plan_desc& p);
 
@@ -145,5 +155,10 @@ hipError_t launch_project_bwd(const SetTab& t, const SceneDev& sc, const CamDev&
                               int n_total, hipStream_t s);
 hipError_t launch_pose_delta(const float* vin, const float* delta, float* vout, int nv,
                              hipStream_t s);
+hipError_t launch_sim3_gaussians(const SimSetTab& tab, const float* m_in, const float* ls_in,
+                                 const float* q_in, const float* sims, float* m_out,
+                                 float* ls_out, float* q_out, hipStream_t s);
+hipError_t launch_sim3_views(const SimViewTab& tab, const float* vin, const float* sims,
+                             float* vout, hipStream_t s);
 
 }  // namespace gsr

@@ -300,6 +300,40 @@ def apply_pose_delta(viewmats: torch.Tensor, delta: torch.Tensor, out: torch.Ten
     return out
 
 
+def sim3_gaussians(means: torch.Tensor, log_scales: torch.Tensor, quats: torch.Tensor,
+                   set_offsets, sims: torch.Tensor, out=None, stream=None):
+    """Sim(3) correction of every Gaussian set on the device (set k moved by
+    sims[k] = (s, qw, qx, qy, qz, tx, ty, tz)); returns (means, log_scales,
+    quats), written to `out` (a 3-tuple, may alias the inputs) if given."""
+    lib = L.load()
+    offs = np.ascontiguousarray(np.asarray(set_offsets, np.int64))
+    if out is None:
+        out = (torch.empty_like(means), torch.empty_like(log_scales), torch.empty_like(quats))
+    st = lib.gsr_sim3_gaussians(_ptr(means.contiguous()), _ptr(log_scales.contiguous()),
+                                _ptr(quats.contiguous()),
+                                offs.ctypes.data_as(C.POINTER(C.c_int64)), int(offs.shape[0] - 1),
+                                _ptr(sims.contiguous()), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]),
+                                _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_sim3_gaussians failed")
+    return out
+
+
+def sim3_views(viewmats: torch.Tensor, sims: torch.Tensor, view_set, out=None, stream=None):
+    """Lift of keyframe poses into the global frame by their sets'
+    similarities (rigid form: the camera's length unit scaled by s)."""
+    lib = L.load()
+    vs = np.ascontiguousarray(np.asarray(view_set, np.int32))
+    if out is None:
+        out = torch.empty_like(viewmats)
+    st = lib.gsr_sim3_views(_ptr(viewmats.contiguous()), _ptr(sims.contiguous()),
+                            vs.ctypes.data_as(C.POINTER(C.c_int32)), int(vs.shape[0]),
+                            int(sims.shape[0]), _ptr(out), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_sim3_views failed")
+    return out
+
+
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_delta, viewmats,

@@ -14,7 +14,7 @@ HEADER = os.path.join(ROOT, "include", "gsr.h")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(gsr_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(gsr_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_bound_entry_points():
@@ -78,3 +78,21 @@ def test_null_context_paths():
     assert lib.gsr_apply_pose_delta(None, None, None, 1, None) == _lib.GSR_E_INVALID_ARG
     assert lib.gsr_last_error(None) == b"no context"
     lib.gsr_destroy(None)
+
+
+def test_sim3_argument_validation():
+    """Host-side checks of the Sim(3) entry points (no kernel is launched)."""
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    E = _lib.GSR_E_INVALID_ARG
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    offs = (C.c_int64 * 3)(0, 5, 3)  # decreasing
+    assert lib.gsr_sim3_gaussians(None, fake, fake, offs, 2, fake, fake, fake, fake, None) == E
+    assert lib.gsr_sim3_gaussians(fake, fake, fake, offs, 2, fake, fake, fake, fake, None) == E
+    offs0 = (C.c_int64 * 2)(1, 5)  # does not start at 0
+    assert lib.gsr_sim3_gaussians(fake, fake, fake, offs0, 1, fake, fake, fake, fake, None) == E
+    assert lib.gsr_sim3_gaussians(fake, fake, fake, offs, 0, fake, fake, fake, fake, None) == E
+    vs = (C.c_int32 * 2)(0, 3)  # set 3 of 2
+    assert lib.gsr_sim3_views(fake, fake, vs, 2, 2, fake, None) == E
+    assert lib.gsr_sim3_views(fake, fake, vs, 0, 2, fake, None) == E
+    assert lib.gsr_sim3_views(None, fake, vs, 2, 4, fake, None) == E
