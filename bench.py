@@ -142,6 +142,9 @@ class Step:
                     torch.empty((V, H, W), device=dev))
         self.gc = torch.empty((V, 3, H, W), device=dev)
         self.gd = torch.empty((V, H, W), device=dev)
+        self.lg = dict(d_color=self.gc, d_depth=self.gd, d_exposure=None)
+        from paper_2605_10760_amd import l1_loss_grad
+        self.l1 = l1_loss_grad
         params = [sc.means, sc.log_scales, sc.quats, sc.opacity_logits, sc.colors]
         self.grads = dict(d_means=torch.zeros_like(sc.means), d_log_scales=torch.zeros_like(sc.log_scales),
                           d_quats=torch.zeros_like(sc.quats),
@@ -155,17 +158,12 @@ class Step:
         # foreach form runs a dozen elementwise passes over the parameters
         self.opt = torch.optim.Adam([{"params": [p], "lr": lr * lr_scale} for p, lr in zip(params, lrs)],
                                     fused=True, capturable=True)
-        self.wc = 0.95 / (V * 3 * H * W)
-        self.wd = 0.25 / (V * H * W)
 
     def __call__(self):
         t = self.t
         c, d, a, _ = self.rast.forward(self.sc, self.vw, state=self.state, out=self.out)
-        # L1 mapping loss gradient (Eq. (map_loss) weights), computed by torch
-        t.sub(c, self.tc, out=self.gc)
-        self.gc.sign_().mul_(self.wc)
-        t.sub(d, self.td, out=self.gd)
-        self.gd.sign_().mul_(self.wd)
+        # L1 mapping loss gradient (Eq. (map_loss) weights), one fused pass
+        self.l1(c, self.tc, d, self.td, None, 0.95, 0.25, out=self.lg)
         self.rast.backward(self.sc, self.vw, self.state, self.gc, self.gd, None, out=self.grads)
         self.opt.step()
 
@@ -243,7 +241,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2605_10760_amd import Rasterizer, SceneTensors, ViewTensors
+    from paper_2605_10760_amd import Rasterizer, SceneTensors, ViewTensors, l1_loss_grad
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -348,6 +346,7 @@ def main():
         g1["d_pose"] = torch.empty((1, 6), device="cuda")
         gcv = torch.empty((1, 3, H, W), device="cuda")
         gdv = torch.empty((1, H, W), device="cuda")
+        lgv = dict(d_color=gcv, d_depth=gdv, d_exposure=None)
         tot = step.grads
 
         def plain_step():
@@ -357,10 +356,9 @@ def main():
                 c1, d1, _, _ = r1.forward(sc, per_view[k], state=st1, out=o1)
                 if vw_np.needs_grad is not None and not vw_np.needs_grad[k]:
                     continue
-                torch.sub(c1, tc[k:k + 1], out=gcv)
-                gcv.sign_().mul_(step.wc)
-                torch.sub(d1, td[k:k + 1], out=gdv)
-                gdv.sign_().mul_(step.wd)
+                # the batch's loss is a mean over all V views: scale by 1/V
+                l1_loss_grad(c1, tc[k:k + 1], d1, td[k:k + 1], None, 0.95 / V, 0.25 / V,
+                             out=lgv)
                 r1.backward(sc, per_view[k], st1, gcv, gdv, None, out=g1)
                 for key in ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors"):
                     tot[key].add_(g1[key])

@@ -247,6 +247,38 @@ gsr_status gsr_sim3_gaussians(const float* means_in, const float* log_scales_in,
 gsr_status gsr_sim3_views(const float* viewmats_in, const float* sims, const int32_t* view_set,
                           int32_t n_views, int32_t n_sets, float* viewmats_out, void* stream);
 
+/* Gradient of the L1 terms of the refinement loss (Sec. III-D, Eq.
+ * (refine_loss)) on the exposure-compensated render I~ = exp(a_v) I^ + b_v:
+ *   L = w_color mean|I~ - I| + w_depth mean|D^ - D|
+ * (means over every channel and pixel of the n_views views; the subgradient
+ * of |.| at 0 is 0).  With exposure == NULL (a = b = 0) and w_color = 0.95,
+ * w_depth = 0.25 it is the L1 part of the mapping loss, Eq. (map_loss).
+ * Device arrays, C-contiguous: color and target_color [V,3,H,W], depth and
+ * target_depth [V,H,W], exposure [V,2] = (a, b) or NULL; outputs (overwritten)
+ * d_color [V,3,H,W], d_depth [V,H,W] or NULL (no depth term: depth inputs
+ * may then be NULL), d_exposure [V,2] = (dL/da, dL/db) or NULL.  Enqueues
+ * two kernels on `stream` (graph-capturable); GSR_E_INVALID_ARG for null
+ * required pointers or bad sizes. */
+gsr_status gsr_l1_loss_grad(const float* color, const float* depth, const float* target_color,
+                            const float* target_depth, const float* exposure, int32_t n_views,
+                            int32_t width, int32_t height, float w_color, float w_depth,
+                            float* d_color, float* d_depth, float* d_exposure, void* stream);
+
+/* Opacity pruning of the refinement (Sec. III-D): keeps the Gaussians with
+ * sigmoid(opacity_logit) >= min_opacity (0.005 in the paper), in their
+ * order, set by set.  `scene` gives the device input arrays and the HOST
+ * set_offsets (n = set_offsets[n_sets] Gaussians; colors rows of 3 floats,
+ * or 3*sh_stride for sh_degree > 0).  Outputs are device arrays with room
+ * for n rows each, not aliasing the inputs: the kept rows of means,
+ * log_scales, quats, opacity logits and colours; set_offsets_out is a HOST
+ * array [n_sets+1] of the pruned set offsets (its last entry = rows kept).
+ * Allocates a small temporary device buffer and synchronises `stream` (set-up
+ * work, not capturable).  GSR_E_INVALID_ARG for null pointers, bad offsets or
+ * min_opacity outside (0, 1). */
+gsr_status gsr_prune(const gsr_scene* scene, float min_opacity, float* means_out,
+                     float* log_scales_out, float* quats_out, float* opacity_out,
+                     float* colors_out, int64_t* set_offsets_out, void* stream);
+
 /* Time forward+backward of the given call for each candidate tile shape and
  * report the fastest (tile_w, tile_h) in `best` (other fields copied from
  * `base`).  Synchronises; allocates its own temporary context. */

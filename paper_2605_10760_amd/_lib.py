@@ -19,7 +19,8 @@ GSR_E_OVERFLOW, GSR_E_DEVICE, GSR_E_OOM, GSR_E_UNIMPLEMENTED = 4, 5, 6, 7
 EXPORTED = ("gsr_create", "gsr_destroy", "gsr_plan", "gsr_state_bytes", "gsr_forward",
             "gsr_backward", "gsr_poll", "gsr_debug_export", "gsr_apply_pose_delta",
             "gsr_autotune", "gsr_profile_enable", "gsr_profile_read", "gsr_status_string",
-            "gsr_last_error", "gsr_sim3_gaussians", "gsr_sim3_views")
+            "gsr_last_error", "gsr_sim3_gaussians", "gsr_sim3_views", "gsr_l1_loss_grad",
+            "gsr_prune")
 
 STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "render_bwd",
           "project_bwd")
@@ -119,6 +120,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gsr_sim3_gaussians.restype = C.c_int
     lib.gsr_sim3_views.argtypes = [vp, vp, P(C.c_int32), C.c_int32, C.c_int32, vp, vp]
     lib.gsr_sim3_views.restype = C.c_int
+    lib.gsr_l1_loss_grad.argtypes = [vp, vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_float, C.c_float, vp, vp, vp, vp]
+    lib.gsr_l1_loss_grad.restype = C.c_int
+    lib.gsr_prune.argtypes = [P(Scene), C.c_float, vp, vp, vp, vp, vp, P(C.c_int64), vp]
+    lib.gsr_prune.restype = C.c_int
     lib.gsr_status_string.argtypes = [C.c_int]
     lib.gsr_status_string.restype = C.c_char_p
     lib.gsr_last_error.argtypes = [vp]

@@ -2,6 +2,7 @@
 // of the forward and backward passes.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -637,6 +638,71 @@ gsr_status gsr_sim3_views(const float* viewmats_in, const float* sims, const int
     tab.view_set[v] = view_set[v];
   }
   hipError_t e = launch_sim3_views(tab, viewmats_in, sims, viewmats_out, (hipStream_t)stream);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
+gsr_status gsr_l1_loss_grad(const float* color, const float* depth, const float* target_color,
+                            const float* target_depth, const float* exposure, int32_t n_views,
+                            int32_t width, int32_t height, float w_color, float w_depth,
+                            float* d_color, float* d_depth, float* d_exposure, void* stream) {
+  if (!color || !target_color || !d_color || n_views < 1 || width < 1 || height < 1)
+    return GSR_E_INVALID_ARG;
+  if (d_depth && (!depth || !target_depth)) return GSR_E_INVALID_ARG;
+  if ((long)width * height > 0x7FFFFFFFL / 3) return GSR_E_INVALID_ARG;
+  const int HW = width * height;
+  // the loss terms are means over every channel / pixel of the batch
+  const float wc = (float)((double)w_color / (3.0 * n_views * (double)HW));
+  const float wd = (float)((double)w_depth / ((double)n_views * HW));
+  hipError_t e = launch_l1_grad(n_views, HW, color, depth, target_color, target_depth, exposure,
+                                wc, wd, d_color, d_depth, d_exposure, (hipStream_t)stream);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
+gsr_status gsr_prune(const gsr_scene* sc, float min_opacity, float* means_out,
+                     float* log_scales_out, float* quats_out, float* opacity_out,
+                     float* colors_out, int64_t* set_offsets_out, void* stream) {
+  if (!sc || !sc->means || !sc->log_scales || !sc->quats || !sc->opacity_logits ||
+      !sc->colors || !sc->set_offsets || !means_out || !log_scales_out || !quats_out ||
+      !opacity_out || !colors_out || !set_offsets_out)
+    return GSR_E_INVALID_ARG;
+  if (sc->n_sets < 1 || sc->n_sets > GSR_MAX_SETS || !(min_opacity > 0.f && min_opacity < 1.f))
+    return GSR_E_INVALID_ARG;
+  if (sc->sh_degree < 0 || sc->sh_degree > 3) return GSR_E_INVALID_ARG;
+  const int cstride = sc->sh_degree > 0 ? 3 * sc->sh_stride : 3;
+  if (sc->sh_degree > 0 && sc->sh_stride < (sc->sh_degree + 1) * (sc->sh_degree + 1))
+    return GSR_E_INVALID_ARG;
+  SimSetTab tab{};
+  tab.ns = sc->n_sets;
+  if (sc->set_offsets[0] != 0) return GSR_E_INVALID_ARG;
+  for (int k = 0; k <= sc->n_sets; ++k) {
+    if (k > 0 && sc->set_offsets[k] < sc->set_offsets[k - 1]) return GSR_E_INVALID_ARG;
+    tab.off[k] = sc->set_offsets[k];
+  }
+  const long n = (long)sc->set_offsets[sc->n_sets];
+  if (n > 0xFFFFFFFFL) return GSR_E_INVALID_ARG;
+  // sigmoid is increasing: keep o >= logit(min_opacity); the FP32 threshold
+  // is the smallest float not below the exact logit, so the FP32 test on an
+  // FP32 logit is exact
+  const double lg = log((double)min_opacity / (1.0 - (double)min_opacity));
+  float thr = (float)lg;
+  if ((double)thr < lg) thr = nextafterf(thr, INFINITY);
+  SceneDev in = scene_dev(sc);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nb = (size_t)((n + 255) / 256);
+  void* tmp = nullptr;
+  if (hipMalloc(&tmp, 4 * (nb + 1) + 8 * (GSR_MAX_SETS + 1) + 256) != hipSuccess) {
+    (void)hipGetLastError();
+    return GSR_E_OOM;
+  }
+  uint32_t* blk = (uint32_t*)tmp;
+  long long* bounds = (long long*)((char*)tmp + ((4 * (nb + 1) + 255) / 256) * 256);
+  hipError_t e = launch_prune(n, in, cstride, thr, tab, blk, bounds, means_out, log_scales_out,
+                              quats_out, opacity_out, colors_out, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(set_offsets_out, bounds, 8 * (size_t)(sc->n_sets + 1),
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(tmp);
   return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
 }
 

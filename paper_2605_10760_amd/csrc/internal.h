@@ -160,5 +160,11 @@ hipError_t launch_sim3_gaussians(const SimSetTab& tab, const float* m_in, const 
                                  float* ls_out, float* q_out, hipStream_t s);
 hipError_t launch_sim3_views(const SimViewTab& tab, const float* vin, const float* sims,
                              float* vout, hipStream_t s);
+hipError_t launch_l1_grad(int nv, int HW, const float* color, const float* depth,
+                          const float* tcol, const float* tdep, const float* expo, float w_col,
+                          float w_dep, float* g_col, float* g_dep, float* g_expo, hipStream_t s);
+hipError_t launch_prune(long n, const SceneDev& in, int color_stride, float thr,
+                        const SimSetTab& sets, uint32_t* blk, long long* bounds, float* m,
+                        float* ls, float* q, float* o, float* col, hipStream_t s);
 
 }  // namespace gsr

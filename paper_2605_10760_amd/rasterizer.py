@@ -334,6 +334,48 @@ def sim3_views(viewmats: torch.Tensor, sims: torch.Tensor, view_set, out=None, s
     return out
 
 
+def l1_loss_grad(color: torch.Tensor, target_color: torch.Tensor, depth: torch.Tensor | None = None,
+                 target_depth: torch.Tensor | None = None, exposure: torch.Tensor | None = None,
+                 w_color: float = 0.95, w_depth: float = 0.25, out: dict | None = None,
+                 stream=None) -> dict:
+    """Gradient of w_color mean|exp(a) I^ + b - I| + w_depth mean|D^ - D| on
+    the device (exposure [V,2] = (a, b) per view, or None for a = b = 0).
+    Returns dict d_color, d_depth (None without depth), d_exposure (None
+    without exposure)."""
+    lib = L.load()
+    V, _, H, W = color.shape
+    if out is None:
+        out = dict(d_color=torch.empty_like(color),
+                   d_depth=torch.empty_like(depth) if depth is not None else None,
+                   d_exposure=torch.empty((V, 2), device=color.device)
+                   if exposure is not None else None)
+    c = lambda t: None if t is None else t.contiguous()
+    st = lib.gsr_l1_loss_grad(_ptr(c(color)), _ptr(c(depth)), _ptr(c(target_color)),
+                              _ptr(c(target_depth)), _ptr(c(exposure)), int(V), int(W), int(H),
+                              float(w_color), float(w_depth), _ptr(out["d_color"]),
+                              _ptr(out["d_depth"]), _ptr(out["d_exposure"]), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_l1_loss_grad failed")
+    return out
+
+
+def prune(scene: SceneTensors, min_opacity: float = 0.005, stream=None) -> SceneTensors:
+    """Opacity pruning on the device: a new SceneTensors with the Gaussians
+    whose sigmoid(opacity) >= min_opacity, in order, and the pruned set
+    offsets (synchronises)."""
+    lib = L.load()
+    s, so = Rasterizer._scene(scene)
+    new = [torch.empty_like(x) for x in (scene.means, scene.log_scales, scene.quats,
+                                         scene.opacity_logits, scene.colors)]
+    offs = np.zeros(so.shape[0], np.int64)
+    st = lib.gsr_prune(C.byref(s), float(min_opacity), *(_ptr(x) for x in new),
+                       offs.ctypes.data_as(C.POINTER(C.c_int64)), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_prune failed")
+    n = int(offs[-1])
+    return SceneTensors(*(x[:n] for x in new), offs, scene.sh_degree)
+
+
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_delta, viewmats,

@@ -96,3 +96,21 @@ def test_sim3_argument_validation():
     assert lib.gsr_sim3_views(fake, fake, vs, 2, 2, fake, None) == E
     assert lib.gsr_sim3_views(fake, fake, vs, 0, 2, fake, None) == E
     assert lib.gsr_sim3_views(None, fake, vs, 2, 4, fake, None) == E
+
+
+def test_refine_argument_validation():
+    """Host-side checks of the loss-gradient and pruning entry points."""
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    E = _lib.GSR_E_INVALID_ARG
+    f = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert lib.gsr_l1_loss_grad(None, None, f, None, None, 1, 4, 4, 1.0, 0.0, f, None, None, None) == E
+    assert lib.gsr_l1_loss_grad(f, None, f, None, None, 0, 4, 4, 1.0, 0.0, f, None, None, None) == E
+    # a depth gradient needs both depth inputs
+    assert lib.gsr_l1_loss_grad(f, None, f, f, None, 1, 4, 4, 1.0, 1.0, f, f, None, None) == E
+    assert lib.gsr_prune(None, 0.005, f, f, f, f, f, None, None) == E
+    offs = (C.c_int64 * 2)(0, 10)
+    sc = _lib.Scene(f, f, f, f, f, C.cast(offs, C.POINTER(C.c_int64)), 1, 0, 1, 0)
+    out = (C.c_int64 * 2)()
+    assert lib.gsr_prune(C.byref(sc), 1.5, f, f, f, f, f, out, None) == E
+    assert lib.gsr_prune(C.byref(sc), 0.005, f, f, f, f, None, out, None) == E

@@ -1,0 +1,70 @@
+"""GPU parity of the refinement extras (Sec. III-D, Eq. (refine_loss)):
+exposure-compensated L1 gradient and opacity pruning, through the C ABI,
+against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_harness import announce
+from oracle.refine import exposure, l1_loss_grad, prune
+from synth.scenes import multi_agent
+
+pytestmark = pytest.mark.gpu
+
+
+def test_l1_loss_grad_matches_oracle():
+    announce("refine l1 grad")
+    import torch
+    from paper_2605_10760_amd import l1_loss_grad as gpu_grad
+    rng = np.random.default_rng(7)
+    V, H, W = 3, 37, 53  # ragged: not a multiple of the 256-pixel blocks
+    c = rng.random((V, 3, H, W)).astype(np.float32)
+    d = (0.5 + 3 * rng.random((V, H, W))).astype(np.float32)
+    tc = rng.random((V, 3, H, W)).astype(np.float32)
+    td = (0.5 + 3 * rng.random((V, H, W))).astype(np.float32)
+    tc[0, 0, :2] = c[0, 0, :2]  # exact zeros of the residual: subgradient 0
+    ex = np.stack([rng.normal(0, 0.3, V), rng.normal(0, 0.1, V)], 1).astype(np.float32)
+    t = lambda a: torch.from_numpy(a).cuda()
+    for expo in (None, ex):
+        a = np.zeros(V) if expo is None else expo[:, 0]
+        b = np.zeros(V) if expo is None else expo[:, 1]
+        got = gpu_grad(t(c), t(tc), t(d), t(td), None if expo is None else t(expo), 1.75, 0.25)
+        torch.cuda.synchronize()
+        ref = l1_loss_grad(c, d, tc, td, a, b, 1.75, 0.25)
+        # residuals the FP32 and FP64 evaluations could sign differently
+        resid = exposure(c, a, b) - tc
+        amb = (np.abs(resid) < 1e-5) & (resid != 0)
+        gc = got["d_color"].cpu().numpy()
+        np.testing.assert_allclose(gc[~amb], ref["d_color"][~amb], rtol=1e-6, atol=0)
+        np.testing.assert_allclose(got["d_depth"].cpu().numpy(), ref["d_depth"], rtol=1e-6, atol=0)
+        if expo is not None:
+            ge = got["d_exposure"].cpu().numpy()
+            scale = np.abs(ref["d_color"]).max() * c[0].size
+            np.testing.assert_allclose(ge[:, 0], ref["d_a"], atol=1e-5 * scale)
+            np.testing.assert_allclose(ge[:, 1], ref["d_b"], atol=1e-5 * scale)
+            assert amb.sum() < 20
+
+
+def test_prune_matches_oracle():
+    announce("refine prune")
+    import torch
+    from paper_2605_10760_amd import SceneTensors, prune as gpu_prune
+    wl = multi_agent(scale=0.01, keyframes=1)
+    sc = wl.scene
+    rng = np.random.default_rng(8)
+    o = sc.opacity_logits.copy()
+    o[rng.random(o.shape[0]) < 0.3] = -6.0  # sigmoid = 0.0025: pruned
+    # logits at and next to logit(0.005) = -5.2933048...
+    o[::97] = np.float32(-5.2933048)
+    o[1::97] = np.nextafter(np.float32(-5.2933048), np.float32(0))
+    o[2::97] = np.nextafter(np.float32(-5.2933048), np.float32(-10))
+    sc.opacity_logits = o
+    st_ = SceneTensors.from_numpy(sc)
+    out = gpu_prune(st_, 0.005)
+    idx, offs = prune(o, sc.set_offsets, 0.005)
+    np.testing.assert_array_equal(out.set_offsets, offs)
+    np.testing.assert_array_equal(out.means.cpu().numpy(), sc.means[idx])
+    np.testing.assert_array_equal(out.log_scales.cpu().numpy(), sc.log_scales[idx])
+    np.testing.assert_array_equal(out.quats.cpu().numpy(), sc.quats[idx])
+    np.testing.assert_array_equal(out.opacity_logits.cpu().numpy(), o[idx])
+    np.testing.assert_array_equal(out.colors.cpu().numpy(), sc.colors[idx])
+    assert 0 < idx.shape[0] < o.shape[0]
