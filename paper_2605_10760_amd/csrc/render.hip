@@ -126,31 +126,55 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
     for (int jb = 0; jb < n && live; jb += 64) {
       const uint32_t mv = jb + lane < n ? smask[jb + lane] : 0u;
       unsigned long long rel = __ballot((mv >> wv) & 1u);
+      // two entries per step: their exponentials and LDS reads overlap; the
+      // second is blended after the first (its weight uses the first's T)
       while (rel) {
         if (__ballot(!done) == 0ull) {
           live = false;
           break;
         }
-        const int j = jb + (int)__builtin_ctzll(rel);
+        const int j0 = jb + (int)__builtin_ctzll(rel);
         rel &= rel - 1ull;
-        const float4 a = s0[j], b = s1[j];
-        float dx, dy;
-        const float power = splat_power(a, b, fx, fy, dx, dy);
-        const float al = fminf(ALPHA_MAX, b.y * exp2_fast(power));
-        const bool use = !done && !(power > 0.f || al < ALPHA_MIN);
-        const float Tn = Tc * (1.f - al);
-        const bool stop = use && Tn < T_MIN;
-        const bool ok = use && !stop;
-        stopn = stop ? base - rg.x + (uint32_t)j + 1u : stopn;
-        done = done || stop;
-        const float wgt = ok ? al * Tc : 0.f;
-        const float4 c = s2[j];
-        c0 += c.x * wgt;
-        c1 += c.y * wgt;
-        c2 += c.z * wgt;
-        dz += b.z * wgt;
-        Tc = ok ? Tn : Tc;
-        last = ok ? base - rg.x + (uint32_t)j + 1u : last;
+        const bool two = rel != 0ull;
+        const int j1 = two ? jb + (int)__builtin_ctzll(rel) : j0;
+        rel = two ? rel & (rel - 1ull) : rel;
+        const float4 a0 = s0[j0], b0 = s1[j0], a1 = s0[j1], b1 = s1[j1];
+        float dx0, dy0, dx1, dy1;
+        const float p0 = splat_power(a0, b0, fx, fy, dx0, dy0);
+        const float p1 = splat_power(a1, b1, fx, fy, dx1, dy1);
+        const float al0 = fminf(ALPHA_MAX, b0.y * exp2_fast(p0));
+        const float al1 = fminf(ALPHA_MAX, b1.y * exp2_fast(p1));
+        const float4 c0v = s2[j0], c1v = s2[j1];
+        {
+          const bool use = !done && !(p0 > 0.f || al0 < ALPHA_MIN);
+          const float Tn = Tc * (1.f - al0);
+          const bool stop = use && Tn < T_MIN;
+          const bool ok = use && !stop;
+          stopn = stop ? base - rg.x + (uint32_t)j0 + 1u : stopn;
+          done = done || stop;
+          const float wgt = ok ? al0 * Tc : 0.f;
+          c0 += c0v.x * wgt;
+          c1 += c0v.y * wgt;
+          c2 += c0v.z * wgt;
+          dz += b0.z * wgt;
+          Tc = ok ? Tn : Tc;
+          last = ok ? base - rg.x + (uint32_t)j0 + 1u : last;
+        }
+        {
+          const bool use = two && !done && !(p1 > 0.f || al1 < ALPHA_MIN);
+          const float Tn = Tc * (1.f - al1);
+          const bool stop = use && Tn < T_MIN;
+          const bool ok = use && !stop;
+          stopn = stop ? base - rg.x + (uint32_t)j1 + 1u : stopn;
+          done = done || stop;
+          const float wgt = ok ? al1 * Tc : 0.f;
+          c0 += c1v.x * wgt;
+          c1 += c1v.y * wgt;
+          c2 += c1v.z * wgt;
+          dz += b1.z * wgt;
+          Tc = ok ? Tn : Tc;
+          last = ok ? base - rg.x + (uint32_t)j1 + 1u : last;
+        }
       }
     }
   }
