@@ -33,7 +33,8 @@ __device__ __forceinline__ float splat_power(const float4& a, const float4& b, f
 #pragma clang fp contract(off)
   dx = a.x - fx;
   dy = a.y - fy;
-  return fmaf(a.z * dx, dx, fmaf(a.w * dx, dy, (b.x * dy) * dy));
+  // dx (A' dx + B' dy) + C' dy^2
+  return fmaf(dx, fmaf(a.z, dx, a.w * dy), (b.x * dy) * dy);
 }
 
 __device__ __forceinline__ float exp2_fast(float p) { return __builtin_amdgcn_exp2f(p); }
@@ -370,8 +371,9 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
           acc[8] += wgt * g2[k];
           acc[9] += wgt * gd[k];
           const bool unc = ok && raw <= ALPHA_MAX;
+          // unclamped: alpha = sigma G, so dL/dsigma = G dA = gp / sigma
           const float gp = unc ? al * dA : 0.f;
-          acc[5] += unc ? G * dA : 0.f;
+          acc[5] += gp;
           // moments of gp over dx, dy: the conic and mean gradients are
           // linear in them (applied once per entry after the wave sum)
           const float gpx = gp * dx, gpy = gp * dy;
@@ -395,6 +397,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
           out = idx == 1 ? LN2 * (a.w * m0 + 2.f * b.x * m1) : out;
           out = (idx == 2 || idx == 4) ? -0.5f * tot : out;
           out = idx == 3 ? -tot : out;
+          out = idx == 5 ? tot / b.y : out;
           if (idx >= 0 && out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
         }
       }

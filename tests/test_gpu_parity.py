@@ -17,6 +17,11 @@ from synth.scenes import fused_map, multi_agent, room_plain, small_plain, tiny_s
 pytestmark = pytest.mark.gpu
 
 IMG_TOL = 1e-5
+# Two runs of the same backward: each pair's screen-space gradient is summed
+# with float atomics from many tiles, in an order that differs between runs,
+# so the parameter gradients agree to rounding of those sums (measured up to
+# 2.3e-5 of a tensor's max-norm), not bit for bit.
+RERUN_TOL = 1e-4
 GRAD_TOL = 1e-3
 
 
@@ -281,9 +286,9 @@ def test_autograd_function_matches_backward():
     ref = g["rast"].backward(st_, vt, g["state"], w[0], w[1], w[2])
     for p, key in zip(params, ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors")):
         e_inf, e_2 = grad_rel_err(p.grad.cpu().numpy(), ref[key].cpu().numpy())
-        assert e_inf <= 1e-5, (key, e_inf)
+        assert e_inf <= RERUN_TOL, (key, e_inf)
     e_inf, _ = grad_rel_err(pose.grad.cpu().numpy(), ref["d_pose"].cpu().numpy())
-    assert e_inf <= 1e-5
+    assert e_inf <= RERUN_TOL
 
 
 # ----------------------------------------------------------------- full size
@@ -551,7 +556,7 @@ def test_graph_replay_matches_eager():
         np.testing.assert_array_equal(out[0].cpu().numpy(), eager_color)
         for k in ref:
             e_inf, _ = grad_rel_err(grads[k].cpu().numpy(), ref[k].cpu().numpy())
-            assert e_inf <= 1e-5, (rep, k, e_inf)
+            assert e_inf <= RERUN_TOL, (rep, k, e_inf)
 
 
 def test_backward_repeatable_and_needs_grad_mask():
@@ -569,7 +574,7 @@ def test_backward_repeatable_and_needs_grad_mask():
     b = _gpu_backward(g, gc, gd, ga)
     for k in a:
         e_inf, _ = grad_rel_err(a[k], b[k])
-        assert e_inf <= 1e-5, k
+        assert e_inf <= RERUN_TOL, k
     assert np.all(a["d_pose"][~views.needs_grad] == 0)
     ref = render_backward(scene, views, gc, gd, ga, view_ids=np.nonzero(views.needs_grad)[0])
     for k_gpu, k_ref in GMAP.items():
