@@ -15,6 +15,8 @@ Contents (each module cites the passage it follows):
   sh         real spherical harmonics to degree 3
   se3        SE(3) exponential, left pose update
   sim3       Sim(3) correction of Gaussians and the lift of keyframe poses
+  refine     exposure-compensated L1 gradient, opacity pruning
+  ssim       SSIM term of the refinement loss and its gradient
 
 Parity status: every function is pinned by tests under tests/ (closed
 forms, invariants, brute force, library routines, finite differences).
