@@ -264,6 +264,30 @@ gsr_status gsr_l1_loss_grad(const float* color, const float* depth, const float*
                             int32_t width, int32_t height, float w_color, float w_depth,
                             float* d_color, float* d_depth, float* d_exposure, void* stream);
 
+/* Workspace bytes gsr_ssim_grad needs for n_views x 3 x height x width
+ * images (host only). */
+gsr_status gsr_ssim_workspace_bytes(int32_t n_views, int32_t width, int32_t height,
+                                    size_t* out_bytes);
+
+/* SSIM term of the refinement loss (Sec. III-D, Eq. (refine_loss)),
+ * L = weight (1 - mean SSIM(I~, I)) with I~ = exp(a_v) I^ + b_v (weight = 0.2
+ * in the paper).  SSIM per colour channel under an 11 x 11 Gaussian window
+ * (sigma 1.5, zero outside the image), C1 = 0.01^2, C2 = 0.03^2, the mean
+ * taken over every pixel, channel and view.  ADDS dL/dI^ into d_color
+ * [V,3,H,W] and, if d_exposure != NULL, dL/d(a, b) into d_exposure [V,2], so
+ * it composes with gsr_l1_loss_grad (which overwrites them); writes the mean
+ * SSIM to ssim_out (one device float) if not NULL.  color, target_color
+ * [V,3,H,W] and exposure [V,2] (or NULL: a = b = 0) are device arrays;
+ * workspace is a 256-byte aligned device buffer of at least
+ * gsr_ssim_workspace_bytes bytes, overwritten.  Enqueues four kernels on
+ * `stream`, allocates nothing and does not synchronise (graph-capturable).
+ * GSR_E_INVALID_ARG for null pointers, a misaligned workspace or sizes out of
+ * range. */
+gsr_status gsr_ssim_grad(const float* color, const float* target_color, const float* exposure,
+                         int32_t n_views, int32_t width, int32_t height, float weight,
+                         void* workspace, float* d_color, float* d_exposure, float* ssim_out,
+                         void* stream);
+
 /* Opacity pruning of the refinement (Sec. III-D): keeps the Gaussians with
  * sigmoid(opacity_logit) >= min_opacity (0.005 in the paper), in their
  * order, set by set.  `scene` gives the device input arrays and the HOST

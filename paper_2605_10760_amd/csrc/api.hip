@@ -658,6 +658,29 @@ gsr_status gsr_l1_loss_grad(const float* color, const float* depth, const float*
   return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
 }
 
+gsr_status gsr_ssim_workspace_bytes(int32_t n_views, int32_t width, int32_t height,
+                                    size_t* out_bytes) {
+  if (!out_bytes || n_views < 1 || width < 1 || height < 1) return GSR_E_INVALID_ARG;
+  if ((double)n_views * width * height * 3 > 2147483647.0) return GSR_E_INVALID_ARG;
+  *out_bytes = ssim_workspace_bytes(n_views, width, height);
+  return GSR_OK;
+}
+
+gsr_status gsr_ssim_grad(const float* color, const float* target_color, const float* exposure,
+                         int32_t n_views, int32_t width, int32_t height, float weight,
+                         void* workspace, float* d_color, float* d_exposure, float* ssim_out,
+                         void* stream) {
+  if (!color || !target_color || !workspace || !d_color || n_views < 1 || width < 1 ||
+      height < 1)
+    return GSR_E_INVALID_ARG;
+  if (((uintptr_t)workspace & 255) != 0) return GSR_E_INVALID_ARG;
+  if ((double)n_views * width * height * 3 > 2147483647.0) return GSR_E_INVALID_ARG;
+  if (3L * n_views > 65535L) return GSR_E_INVALID_ARG;  // grid y
+  hipError_t e = launch_ssim(n_views, width, height, weight, color, target_color, exposure,
+                             workspace, d_color, d_exposure, ssim_out, (hipStream_t)stream);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
 gsr_status gsr_prune(const gsr_scene* sc, float min_opacity, float* means_out,
                      float* log_scales_out, float* quats_out, float* opacity_out,
                      float* colors_out, int64_t* set_offsets_out, void* stream) {

@@ -163,6 +163,10 @@ hipError_t launch_sim3_views(const SimViewTab& tab, const float* vin, const floa
 hipError_t launch_l1_grad(int nv, int HW, const float* color, const float* depth,
                           const float* tcol, const float* tdep, const float* expo, float w_col,
                           float w_dep, float* g_col, float* g_dep, float* g_expo, hipStream_t s);
+size_t ssim_workspace_bytes(int nv, int W, int H);
+hipError_t launch_ssim(int nv, int W, int H, float weight, const float* color,
+                       const float* target, const float* expo, void* ws, float* d_color,
+                       float* d_expo, float* ssim_out, hipStream_t s);
 hipError_t launch_prune(long n, const SceneDev& in, int color_stride, float thr,
                         const SimSetTab& sets, uint32_t* blk, long long* bounds, float* m,
                         float* ls, float* q, float* o, float* col, hipStream_t s);

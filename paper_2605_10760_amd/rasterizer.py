@@ -359,6 +359,30 @@ def l1_loss_grad(color: torch.Tensor, target_color: torch.Tensor, depth: torch.T
     return out
 
 
+def ssim_grad(color: torch.Tensor, target_color: torch.Tensor, d_color: torch.Tensor,
+              exposure: torch.Tensor | None = None, d_exposure: torch.Tensor | None = None,
+              weight: float = 0.2, workspace: torch.Tensor | None = None,
+              ssim_out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """Adds the gradient of weight (1 - SSIM(exp(a) I^ + b, I)) into d_color
+    (and d_exposure if given) on the device; returns the workspace (reuse it
+    across calls to avoid allocations, e.g. under graph capture)."""
+    lib = L.load()
+    V, _, H, W = color.shape
+    if workspace is None:
+        nb = C.c_size_t()
+        st = lib.gsr_ssim_workspace_bytes(int(V), int(W), int(H), C.byref(nb))
+        if st != L.GSR_OK:
+            raise L.GsrError(st, "gsr_ssim_workspace_bytes failed")
+        workspace = torch.empty(int(nb.value), dtype=torch.uint8, device=color.device)
+    c = lambda t: None if t is None else t.contiguous()
+    st = lib.gsr_ssim_grad(_ptr(c(color)), _ptr(c(target_color)), _ptr(c(exposure)), int(V),
+                           int(W), int(H), float(weight), _ptr(workspace), _ptr(d_color),
+                           _ptr(d_exposure), _ptr(ssim_out), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_ssim_grad failed")
+    return workspace
+
+
 def prune(scene: SceneTensors, min_opacity: float = 0.005, stream=None) -> SceneTensors:
     """Opacity pruning on the device: a new SceneTensors with the Gaussians
     whose sigmoid(opacity) >= min_opacity, in order, and the pruned set

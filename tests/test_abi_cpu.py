@@ -114,3 +114,17 @@ def test_refine_argument_validation():
     out = (C.c_int64 * 2)()
     assert lib.gsr_prune(C.byref(sc), 1.5, f, f, f, f, f, out, None) == E
     assert lib.gsr_prune(C.byref(sc), 0.005, f, f, f, f, None, out, None) == E
+
+
+def test_ssim_argument_validation():
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    E = _lib.GSR_E_INVALID_ARG
+    nb = C.c_size_t()
+    assert lib.gsr_ssim_workspace_bytes(2, 64, 48, C.byref(nb)) == _lib.GSR_OK
+    assert nb.value >= 3 * 3 * 2 * 64 * 48 * 4
+    assert lib.gsr_ssim_workspace_bytes(0, 64, 48, C.byref(nb)) == E
+    f = C.c_void_p(0x1000)
+    assert lib.gsr_ssim_grad(None, f, None, 1, 8, 8, 0.2, f, f, None, None, None) == E
+    # misaligned workspace
+    assert lib.gsr_ssim_grad(f, f, None, 1, 8, 8, 0.2, C.c_void_p(0x1004), f, None, None, None) == E

@@ -68,3 +68,33 @@ def test_prune_matches_oracle():
     np.testing.assert_array_equal(out.opacity_logits.cpu().numpy(), o[idx])
     np.testing.assert_array_equal(out.colors.cpu().numpy(), sc.colors[idx])
     assert 0 < idx.shape[0] < o.shape[0]
+
+
+def test_ssim_grad_matches_oracle():
+    announce("refine ssim")
+    import torch
+    from oracle.ssim import ssim, ssim_term_grad
+    from paper_2605_10760_amd import ssim_grad
+    rng = np.random.default_rng(9)
+    V, H, W = 2, 37, 45  # ragged tiles
+    c = rng.random((V, 3, H, W)).astype(np.float32)
+    tgt = np.clip(c + 0.1 * rng.normal(size=c.shape), 0, 1).astype(np.float32)
+    ex = np.array([[0.15, 0.02], [-0.1, -0.03]], np.float32)
+    t = lambda a: torch.from_numpy(a).cuda()
+    # accumulated onto: small enough that the FP32 sum keeps the gradient digits
+    base = (1e-4 * rng.normal(size=c.shape)).astype(np.float32)
+    d_color = t(base.copy())
+    d_exp = t(np.array([[1.0, 2.0], [3.0, 4.0]], np.float32))
+    out = torch.zeros(1, device="cuda")
+    ssim_grad(t(c), t(tgt), d_color, t(ex), d_exp, 0.2, ssim_out=out)
+    torch.cuda.synchronize()
+    ref = ssim_term_grad(c, tgt, ex[:, 0], ex[:, 1], 0.2)
+    xt = np.exp(ex[:, 0])[:, None, None, None] * c + ex[:, 1][:, None, None, None]
+    assert abs(out.item() - ssim(xt, tgt)) <= 2e-5
+    got = d_color.cpu().numpy() - base
+    scale = np.abs(ref["d_color"]).max()
+    assert np.abs(got - ref["d_color"]).max() <= 1e-3 * scale
+    ge = d_exp.cpu().numpy() - np.array([[1.0, 2.0], [3.0, 4.0]])
+    sa = np.abs(ref["d_a"]).max()
+    np.testing.assert_allclose(ge[:, 0], ref["d_a"], atol=1e-3 * sa)
+    np.testing.assert_allclose(ge[:, 1], ref["d_b"], atol=1e-3 * np.abs(ref["d_b"]).max())
