@@ -227,6 +227,68 @@ def time_cpu_baseline(wl, seconds):
                        f"({time.perf_counter() - t_start:.1f} s of CPU work, FP64 NumPy, 1 thread)")
 
 
+def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, reps=10):
+    """HBM-bound kernels beyond the rasterizer (Sim(3) correction, pose lift,
+    refinement loss gradients, pruning) on the same batch: average time per
+    call from torch events on the stream they launch on, algorithmic bytes,
+    and the fraction of the 8 TB/s HBM peak."""
+    import numpy as np
+    from paper_2605_10760_amd import l1_loss_grad, prune, sim3_gaussians, sim3_views, ssim_grad
+    V, _, H, W = out_color.shape
+    N = sc.n
+    rng = np.random.default_rng(0)
+    sims = []
+    for _ in range(len(sc.set_offsets) - 1):
+        q = rng.normal(size=4)
+        sims.append(np.concatenate([[1.1], q / np.linalg.norm(q), rng.normal(0, 0.1, 3)]))
+    sims = torch.from_numpy(np.array(sims, np.float32)).cuda()
+    expo = torch.zeros((V, 2), device="cuda")
+    gs = (torch.empty_like(sc.means), torch.empty_like(sc.log_scales), torch.empty_like(sc.quats))
+    vmo = torch.empty_like(vw.viewmats)
+    gl = dict(d_color=torch.empty_like(out_color), d_depth=torch.empty_like(out_depth),
+              d_exposure=torch.empty((V, 2), device="cuda"))
+    ws = ssim_grad(out_color, tc, gl["d_color"], expo, gl["d_exposure"])
+    px = V * H * W
+    calls = {
+        # 40 B read + 40 B written per Gaussian
+        "sim3_gaussians": (lambda: sim3_gaussians(sc.means, sc.log_scales, sc.quats,
+                                                  sc.set_offsets, sims, out=gs), 80 * N),
+        "sim3_views": (lambda: sim3_views(vw.viewmats, sims, vw.view_set, out=vmo), 96 * V),
+        # colour: read I^, I, write dI^ (3 channels); depth: read 2, write 1
+        "l1_loss_grad": (lambda: l1_loss_grad(out_color, tc, out_depth, td, expo, 1.75, 0.25,
+                                              out=gl), 48 * px),
+        # per pixel and channel: read I^ and I, read-modify-write dI^
+        "ssim_grad": (lambda: ssim_grad(out_color, tc, gl["d_color"], expo, gl["d_exposure"],
+                                        workspace=ws), 16 * 3 * px),
+    }
+    res = {}
+    for name, (fn, nbytes) in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        res[name] = dict(ms=round(ms, 4), algorithmic_GBps=round(gbs, 1),
+                         hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+    # pruning synchronises (host offsets): wall time of one call
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pr = prune(sc, 0.005)
+    ms = (time.perf_counter() - t0) * 1e3
+    kept = pr.n
+    row = 56 if sc.colors.dim() == 2 else 4 * (3 + 3 + 4 + 1 + 3 * sc.sh_stride)
+    nbytes = 4 * N + 2 * row * kept
+    res["prune"] = dict(ms=round(ms, 4), kept=kept, of=N,
+                        algorithmic_GBps=round(nbytes / (ms * 1e-3) / 1e9, 1),
+                        note="includes the host synchronisation for the pruned set offsets")
+    return res
+
+
 def main():
     args = parse()
     if args.digest:
@@ -426,6 +488,8 @@ def main():
         roof["algorithmic_bytes"] = int(alg_bytes.get(dom, 0))
     step_bytes = sum(alg_bytes.values())
 
+    extras = measure_extras(torch, sc, vw, step.out[0], step.out[1], tc, td)
+
     cpu = None
     if not args.no_cpu:
         cpu = time_cpu_baseline(wl, args.cpu_seconds)
@@ -457,6 +521,7 @@ def main():
         "plain": plain,
         "stages_ms": stages,
         "roofline": roof,
+        "extras": extras,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

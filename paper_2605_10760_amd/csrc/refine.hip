@@ -2,14 +2,16 @@
 // gradient of the L1 terms on the exposure-compensated render
 // I~ = exp(a_k) I^ + b_k, and opacity pruning.
 //
-// k_l1_grad: one thread per pixel of one view (a block never spans two
-// views): reads the three colour planes, the depth and the targets once and
-// writes their gradients once (HBM-bound, 40 B per pixel); the per-view sums
-// for (a_k, b_k) are a DPP wave sum, an LDS sum over the block's waves and one
-// atomic per block.
+// k_l1_grad: a few blocks per view stride over its pixels (a block never
+// spans two views): reads the three colour planes, the depth and the targets
+// once and writes their gradients once (HBM-bound, 48 B per pixel); the
+// per-view sums for (a_k, b_k) are a DPP wave sum, an LDS sum over the
+// block's waves and one atomic per block.
 // k_prune_*: ordered stream compaction (per-block counts, one-workgroup scan,
 // wave-ballot ranks) of the Gaussians whose logit is at least the FP32
 // threshold, then a row gather of every parameter array.
+#include <algorithm>
+
 #include "common.h"
 
 namespace gsr {
@@ -18,6 +20,8 @@ __global__ __launch_bounds__(256) void k_zero_f32(float* p, int n) {
   for (int i = threadIdx.x; i < n; i += 256) p[i] = 0.f;
 }
 
+// A view's pixels are spread over blocks_per_view blocks that stride through
+// them, so the exposure sums take few atomics per view.
 __global__ __launch_bounds__(256) void k_l1_grad(int HW, int blocks_per_view, const float* color,
                                                  const float* depth, const float* tcol,
                                                  const float* tdep, const float* expo,
@@ -25,11 +29,11 @@ __global__ __launch_bounds__(256) void k_l1_grad(int HW, int blocks_per_view, co
                                                  float* g_dep, float* g_expo) {
   __shared__ float red[2][4];
   const int v = blockIdx.x / blocks_per_view;
-  const int p = (blockIdx.x - v * blocks_per_view) * 256 + (int)threadIdx.x;
+  const int b0 = blockIdx.x - v * blocks_per_view;
   const float a = expo ? expo[2 * v] : 0.f, b = expo ? expo[2 * v + 1] : 0.f;
   const float ea = expf(a);
   float sa = 0.f, sb = 0.f;
-  if (p < HW) {
+  for (int p = b0 * 256 + (int)threadIdx.x; p < HW; p += blocks_per_view * 256) {
     const size_t base = (size_t)v * 3 * HW + p;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -65,7 +69,8 @@ hipError_t launch_l1_grad(int nv, int HW, const float* color, const float* depth
                           const float* tcol, const float* tdep, const float* expo, float w_col,
                           float w_dep, float* g_col, float* g_dep, float* g_expo, hipStream_t s) {
   if (g_expo) hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, g_expo, 2 * nv);
-  const int bpv = (HW + 255) / 256;
+  // enough blocks to fill the chip, few enough per view for its atomics
+  const int bpv = std::min((HW + 255) / 256, std::max(64, 2048 / nv));
   hipLaunchKernelGGL(k_l1_grad, dim3(nv * bpv), dim3(256), 0, s, HW, bpv, color, depth, tcol,
                      tdep, expo, w_col, w_dep, g_col, g_dep, g_expo);
   return hipGetLastError();

@@ -10,8 +10,10 @@
 //     f3 = dS/dsxy (12 B per pixel and channel to the workspace), and the sum
 //     of S;
 //   k_ssim_grad: blurs of f1..f3 -> d mean(S)/dx = (w*f1 + 2 x w*f2 +
-//     y w*f3) / N, chained through the exposure into d_color and
-//     d_exposure (accumulated).
+//     y w*f3) / N, chained through the exposure into d_color (accumulated);
+//   k_ssim_reduce: per-block partial sums (S, and the exposure gradients)
+//     summed per view in a fixed order: no float atomics on a few hot
+//     addresses.
 #include "common.h"
 
 namespace gsr {
@@ -36,7 +38,7 @@ __device__ __forceinline__ float block_sum_256(float x, float* red) {
 
 __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs A, const float* color,
                                                     const float* target, const float* expo,
-                                                    float* f, float* ssim_sum) {
+                                                    float* f, float* ssim_part) {
   __shared__ float sx[SS_E][SS_E + 1], sy[SS_E][SS_E + 1];
   __shared__ float hm[5][SS_E][SS_T];
   __shared__ float red[4];
@@ -97,13 +99,13 @@ __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs A, const float* col
     f[2 * all + q] = d_sxy;
   }
   const float t = block_sum_256(s, red);
-  if (threadIdx.x == 0) atomicAdd(ssim_sum, t);
+  if (threadIdx.x == 0) ssim_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
 
 __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs A, const float* color,
                                                    const float* target, const float* expo,
                                                    const float* f, float* d_color,
-                                                   float* d_expo) {
+                                                   float* e_part) {
   __shared__ float sf[3][SS_E][SS_E + 1];
   __shared__ float hf[3][SS_E][SS_T];
   __shared__ float red[4];
@@ -156,21 +158,61 @@ __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs A, const float* colo
     sa = g * c;
     sb = g;
   }
-  if (!d_expo) return;  // uniform
+  if (!e_part) return;  // uniform
   const float ta = block_sum_256(sa, red);
   const float tb = block_sum_256(sb, red);
   if (threadIdx.x == 0) {
-    atomicAdd(&d_expo[2 * v], ea * ta);
-    atomicAdd(&d_expo[2 * v + 1], tb);
+    const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    e_part[2 * b] = ea * ta;
+    e_part[2 * b + 1] = tb;
   }
 }
 
-__global__ void k_ssim_init(float* acc) { acc[0] = 0.f; }
+// One workgroup per view: the view's block partials of the exposure sums
+// (added to d_expo) and of S (to s_view[v]).  Sums run in a fixed order
+// (deterministic).
+__global__ __launch_bounds__(256) void k_ssim_reduce(int nb_view, const float* s_part,
+                                                     const float* e_part, float* d_expo,
+                                                     float* s_view) {
+  __shared__ float red[4];
+  const int v = blockIdx.x;
+  const size_t k0 = (size_t)v * 3 * nb_view;
+  float a = 0.f, b = 0.f, t = 0.f;
+  for (int i = threadIdx.x; i < 3 * nb_view; i += 256) {
+    t += s_part[k0 + i];
+    if (e_part) {
+      a += e_part[2 * (k0 + i)];
+      b += e_part[2 * (k0 + i) + 1];
+    }
+  }
+  t = block_sum_256(t, red);
+  if (e_part) {
+    a = block_sum_256(a, red);
+    b = block_sum_256(b, red);
+  }
+  if (threadIdx.x == 0) {
+    s_view[v] = t;
+    if (e_part) {
+      d_expo[2 * v] += a;
+      d_expo[2 * v + 1] += b;
+    }
+  }
+}
 
-__global__ void k_ssim_mean(const float* acc, float inv_n, float* out) { out[0] = acc[0] * inv_n; }
+__global__ __launch_bounds__(64) void k_ssim_mean(int nv, const float* s_view, float inv_n,
+                                                  float* out) {
+  float t = 0.f;
+  for (int v = threadIdx.x; v < nv; v += 64) t += s_view[v];
+  t = wave_total(t);
+  if (threadIdx.x == 0) out[0] = t * inv_n;
+}
+
+static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
 size_t ssim_workspace_bytes(int nv, int W, int H) {
-  return 256 + (size_t)3 * 3 * nv * (size_t)W * H * sizeof(float);
+  const size_t nb = (size_t)((W + SS_T - 1) / SS_T) * ((H + SS_T - 1) / SS_T) * 3 * nv;
+  return align_up(nb * 4) + align_up(nb * 8) + align_up((size_t)nv * 4) +
+         (size_t)3 * 3 * nv * (size_t)W * H * sizeof(float);
 }
 
 hipError_t launch_ssim(int nv, int W, int H, float weight, const float* color,
@@ -186,16 +228,24 @@ hipError_t launch_ssim(int nv, int W, int H, float weight, const float* color,
   A.nv = nv;
   const double n = 3.0 * nv * (double)W * H;
   A.weight_over_n = (float)(weight / n);
-  float* acc = (float*)ws;
-  float* f = (float*)((char*)ws + 256);
   const int TY = (H + SS_T - 1) / SS_T;
-  const dim3 grid(A.TX * TY, 3 * nv);
-  hipLaunchKernelGGL(k_ssim_init, dim3(1), dim3(1), 0, s, acc);
-  hipLaunchKernelGGL(k_ssim_stats, grid, dim3(256), 0, s, A, color, target, expo, f, acc);
+  const int nb_view = A.TX * TY;
+  const size_t nb = (size_t)nb_view * 3 * nv;
+  char* w8 = (char*)ws;
+  float* s_part = (float*)w8;
+  float* e_part = (float*)(w8 + align_up(nb * 4));
+  float* s_view = (float*)(w8 + align_up(nb * 4) + align_up(nb * 8));
+  float* f = (float*)(w8 + align_up(nb * 4) + align_up(nb * 8) + align_up((size_t)nv * 4));
+  const dim3 grid(nb_view, 3 * nv);
+  hipLaunchKernelGGL(k_ssim_stats, grid, dim3(256), 0, s, A, color, target, expo, f, s_part);
   hipLaunchKernelGGL(k_ssim_grad, grid, dim3(256), 0, s, A, color, target, expo, f, d_color,
-                     d_expo);
+                     d_expo ? e_part : (float*)nullptr);
+  if (d_expo || ssim_out)
+    hipLaunchKernelGGL(k_ssim_reduce, dim3(nv), dim3(256), 0, s, nb_view, s_part,
+                       d_expo ? e_part : (const float*)nullptr, d_expo, s_view);
   if (ssim_out)
-    hipLaunchKernelGGL(k_ssim_mean, dim3(1), dim3(1), 0, s, acc, (float)(1.0 / n), ssim_out);
+    hipLaunchKernelGGL(k_ssim_mean, dim3(1), dim3(64), 0, s, nv, s_view, (float)(1.0 / n),
+                       ssim_out);
   return hipGetLastError();
 }
 
