@@ -17,6 +17,7 @@ Contents (each module cites the passage it follows):
   sim3       Sim(3) correction of Gaussians and the lift of keyframe poses
   refine     exposure-compensated L1 gradient, opacity pruning
   ssim       SSIM term of the refinement loss and its gradient
+  dedup      occupancy-aware deduplication of borrowed Gaussians
 
 Parity status: every function is pinned by tests under tests/ (closed
 forms, invariants, brute force, library routines, finite differences).
