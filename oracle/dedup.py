@@ -19,7 +19,8 @@ Definitions, written out: the box's voxels are the product of the per-axis
 index ranges [floor(lo / v), floor(hi / v)]; the segment's voxels are the
 start voxel and, walking the crossings of voxel planes in increasing t
 (computed per axis as (plane - c) / (r - c)), every voxel entered at a
-crossing with t < 1.  Crossings of two planes closer than `tie_eps` in t
+crossing with 0 <= t < 1 (a start on a plane, moving down, leaves its voxel
+at t = 0).  Crossings of two planes closer than `tie_eps` in t
 make the walk order ambiguous; such segments are reported.
 """
 from __future__ import annotations
@@ -68,7 +69,9 @@ def segment_voxels(c, r, v=VOXEL, tie_eps=1e-12):
         planes = range(i0 + 1, i1 + 1) if step > 0 else range(i0, i1, -1)
         for p in planes:
             t = (p * v - c[ax]) / d[ax]
-            if 0.0 < t < 1.0:
+            # t = 0: the start lies on the plane and the segment leaves its
+            # voxel at once (moving down); t in [0, 1) includes that crossing
+            if 0.0 <= t < 1.0:
                 events.append((t, ax, step))
     events.sort()
     ts = [e[0] for e in events]
@@ -92,14 +95,18 @@ def free(depth, viewmats, intrinsics, v=VOXEL):
         vm = np.asarray(viewmats[kf], np.float64).reshape(3, 4)
         R, tt = vm[:, :3], vm[:, 3]
         fx, fy, cx, cy = (float(x) for x in intrinsics[kf])
-        c = -R.T @ tt
+        # R^T products written out in a fixed order (left to right, no fused
+        # multiply-add), so that the camera centre and the end point are
+        # reproducible bit for bit
+        c = np.array([-((R[0, a] * tt[0] + R[1, a] * tt[1]) + R[2, a] * tt[2]) for a in range(3)])
         for j in range(H):
             for i in range(W):
                 dd = dep[kf, j, i]
                 if not dd > 0.0:
                     continue
-                ray = np.array([(i + 0.5 - cx) / fx, (j + 0.5 - cy) / fy, 1.0])
-                rpt = c + dd * (R.T @ ray)
+                ray = ((i + 0.5 - cx) / fx, (j + 0.5 - cy) / fy, 1.0)
+                rpt = np.array([c[a] + dd * ((R[0, a] * ray[0] + R[1, a] * ray[1]) + R[2, a] * ray[2])
+                                for a in range(3)])
                 vox, amb = segment_voxels(c, rpt, v)
                 out |= vox
                 n_amb += int(amb)

@@ -85,3 +85,14 @@ def test_dedup_constructed_cases():
     keep, amb = dedup(src, tgt, tls, depth, vm[None], intr[None], V, 1.0)
     assert amb == 0
     np.testing.assert_array_equal(keep, [False, False, True, True])
+
+
+def test_start_on_a_plane_moving_down():
+    """t in [0, 1) (Eq. (free_carve)): a segment starting on the plane z = 0
+    and moving to z = -0.12 meets voxel 0 at t = 0, then -1, -2 and -3."""
+    vox, amb = segment_voxels(np.zeros(3), np.array([0.0, 0.0, -0.12]), V)
+    assert not amb
+    assert vox == {(0, 0, 0), (0, 0, -1), (0, 0, -2), (0, 0, -3)}
+    # moving up from the same plane: voxels 0, 1, 2
+    vox, _ = segment_voxels(np.zeros(3), np.array([0.0, 0.0, 0.12]), V)
+    assert vox == {(0, 0, 0), (0, 0, 1), (0, 0, 2)}
