@@ -275,6 +275,24 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, reps=10):
         gbs = nbytes / (ms * 1e-3) / 1e9
         res[name] = dict(ms=round(ms, 4), algorithmic_GBps=round(gbs, 1),
                          hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+    # deduplication: the largest submap's Gaussians and keyframe depths as the
+    # target, the next largest submap as the borrowed set (synchronises)
+    from paper_2605_10760_amd import dedup
+    so = sc.set_offsets
+    tgt, src = len(so) - 2, len(so) - 3
+    kfs = [k for k in range(V) if vw.view_set[k] == tgt]
+    ta, tb = int(so[tgt]), int(so[tgt + 1])
+    sa, sb = int(so[src]), int(so[src + 1])
+    dep = out_depth[kfs].contiguous()
+    vm_k, in_k = vw.viewmats[kfs].contiguous(), vw.intrinsics[kfs].contiguous()
+    dedup(sc.means[sa:sb], sc.means[ta:tb], sc.log_scales[ta:tb], dep, vm_k, in_k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    keep, nvox = dedup(sc.means[sa:sb], sc.means[ta:tb], sc.log_scales[ta:tb], dep, vm_k, in_k)
+    ms = (time.perf_counter() - t0) * 1e3
+    res["dedup"] = dict(ms=round(ms, 3), target=tb - ta, borrowed=sb - sa,
+                        kept=int(keep.sum().item()), rays=len(kfs) * H * W, voxels=nvox,
+                        note="voxel 0.05, k 1; includes the host synchronisation")
     # pruning synchronises (host offsets): wall time of one call
     torch.cuda.synchronize()
     t0 = time.perf_counter()

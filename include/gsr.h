@@ -288,6 +288,40 @@ gsr_status gsr_ssim_grad(const float* color, const float* target_color, const fl
                          void* workspace, float* d_color, float* d_exposure, float* ssim_out,
                          void* stream);
 
+/* Occupancy-aware deduplication of borrowed Gaussians (Sec. III-D, Eqs.
+ * (envelope), (free_carve), (dedup)).  With voxel index floor(x / voxel)
+ * per axis (FP64 from the FP32 inputs): occupied voxels are every voxel
+ * meeting a target Gaussian's box [mu - k_env s, mu + k_env s],
+ * s = exp(log_scales); free voxels are every voxel met by the segment from a
+ * keyframe's camera centre to the back-projected depth of one of its pixels
+ * (pixel centres, parameters t in [0, 1); depth <= 0 carves nothing); a
+ * borrowed Gaussian is kept (keep[i] = 1) only if the voxel of its mean is
+ * in neither set.  The paper gives neither voxel nor k_env. */
+typedef struct gsr_dedup_params {
+  double voxel;          /* v > 0, in the map's length unit */
+  double k_env;          /* >= 0 */
+  int64_t table_slots;   /* hash-set slots, a power of two; size it at about
+                            twice the distinct voxels expected */
+} gsr_dedup_params;
+
+/* Workspace bytes of a hash set of table_slots slots (host only). */
+gsr_status gsr_dedup_workspace_bytes(int64_t table_slots, size_t* out_bytes);
+
+/* Device arrays: tgt_means, tgt_log_scales [n_tgt,3]; depth [K,H,W] (camera
+ * depth per pixel), viewmats [K,3,4] world->camera, intrinsics [K,4] for the
+ * target's keyframes; src_means [n_src,3]; keep uint8 [n_src] (out);
+ * workspace 256-byte aligned, >= gsr_dedup_workspace_bytes(table_slots),
+ * overwritten.  Synchronises `stream`; n_voxels (HOST, may be NULL) gets the
+ * number of distinct voxels inserted.  GSR_E_OVERFLOW (keep not valid) when
+ * the hash set ran out of slots; GSR_E_INVALID_ARG for bad parameters, or
+ * (found on the device; keep not valid) a voxel index outside +-2^20 per
+ * axis, a non-finite input, or one box or segment of more than 2^22 voxels. */
+gsr_status gsr_dedup(const gsr_dedup_params* params, const float* tgt_means,
+                     const float* tgt_log_scales, int64_t n_tgt, const float* depth,
+                     const float* viewmats, const float* intrinsics, int32_t n_keyframes,
+                     int32_t width, int32_t height, const float* src_means, int64_t n_src,
+                     uint8_t* keep, void* workspace, int64_t* n_voxels, void* stream);
+
 /* Opacity pruning of the refinement (Sec. III-D): keeps the Gaussians with
  * sigmoid(opacity_logit) >= min_opacity (0.005 in the paper), in their
  * order, set by set.  `scene` gives the device input arrays and the HOST

@@ -20,7 +20,8 @@ EXPORTED = ("gsr_create", "gsr_destroy", "gsr_plan", "gsr_state_bytes", "gsr_for
             "gsr_backward", "gsr_poll", "gsr_debug_export", "gsr_apply_pose_delta",
             "gsr_autotune", "gsr_profile_enable", "gsr_profile_read", "gsr_status_string",
             "gsr_last_error", "gsr_sim3_gaussians", "gsr_sim3_views", "gsr_l1_loss_grad",
-            "gsr_prune", "gsr_ssim_workspace_bytes", "gsr_ssim_grad")
+            "gsr_prune", "gsr_ssim_workspace_bytes", "gsr_ssim_grad",
+            "gsr_dedup_workspace_bytes", "gsr_dedup")
 
 STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "render_bwd",
           "project_bwd")
@@ -68,6 +69,10 @@ class Grads(C.Structure):
 class Counts(C.Structure):
     _fields_ = [("visible_pairs", C.c_int64), ("instances", C.c_int64), ("capacity", C.c_int64),
                 ("overflow", C.c_int32), ("n_views", C.c_int32)]
+
+
+class DedupParams(C.Structure):
+    _fields_ = [("voxel", C.c_double), ("k_env", C.c_double), ("table_slots", C.c_int64)]
 
 
 class Debug(C.Structure):
@@ -128,6 +133,11 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gsr_ssim_grad.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float, vp, vp,
                                   vp, vp, vp]
     lib.gsr_ssim_grad.restype = C.c_int
+    lib.gsr_dedup_workspace_bytes.argtypes = [C.c_int64, P(C.c_size_t)]
+    lib.gsr_dedup_workspace_bytes.restype = C.c_int
+    lib.gsr_dedup.argtypes = [P(DedupParams), vp, vp, C.c_int64, vp, vp, vp, C.c_int32, C.c_int32,
+                              C.c_int32, vp, C.c_int64, vp, vp, P(C.c_int64), vp]
+    lib.gsr_dedup.restype = C.c_int
     lib.gsr_prune.argtypes = [P(Scene), C.c_float, vp, vp, vp, vp, vp, P(C.c_int64), vp]
     lib.gsr_prune.restype = C.c_int
     lib.gsr_status_string.argtypes = [C.c_int]

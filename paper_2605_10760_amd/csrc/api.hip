@@ -681,6 +681,41 @@ gsr_status gsr_ssim_grad(const float* color, const float* target_color, const fl
   return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
 }
 
+gsr_status gsr_dedup_workspace_bytes(int64_t table_slots, size_t* out_bytes) {
+  if (!out_bytes || table_slots < 2 || (table_slots & (table_slots - 1)) != 0)
+    return GSR_E_INVALID_ARG;
+  *out_bytes = dedup_workspace_bytes(table_slots);
+  return GSR_OK;
+}
+
+gsr_status gsr_dedup(const gsr_dedup_params* p, const float* tgt_means,
+                     const float* tgt_log_scales, int64_t n_tgt, const float* depth,
+                     const float* viewmats, const float* intrinsics, int32_t n_keyframes,
+                     int32_t width, int32_t height, const float* src_means, int64_t n_src,
+                     uint8_t* keep, void* workspace, int64_t* n_voxels, void* stream) {
+  if (!p || !workspace || n_tgt < 0 || n_src < 0 || n_keyframes < 0) return GSR_E_INVALID_ARG;
+  if (!(p->voxel > 0.0) || !(p->k_env >= 0.0) || p->table_slots < 2 ||
+      (p->table_slots & (p->table_slots - 1)) != 0)
+    return GSR_E_INVALID_ARG;
+  if ((n_tgt > 0 && (!tgt_means || !tgt_log_scales)) || (n_src > 0 && (!src_means || !keep)))
+    return GSR_E_INVALID_ARG;
+  if (n_keyframes > 0 && (!depth || !viewmats || !intrinsics || width < 1 || height < 1))
+    return GSR_E_INVALID_ARG;
+  if (((uintptr_t)workspace & 255) != 0) return GSR_E_INVALID_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  unsigned int* dc = nullptr;
+  hipError_t e = launch_dedup(p->table_slots, workspace, p->voxel, p->k_env, tgt_means,
+                              tgt_log_scales, n_tgt, depth, viewmats, intrinsics, n_keyframes,
+                              width, height, src_means, n_src, keep, st, &dc);
+  unsigned int h[2] = {0u, 0u};
+  if (e == hipSuccess) e = hipMemcpyAsync(h, dc, sizeof(h), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return GSR_E_DEVICE;
+  if (n_voxels) *n_voxels = (int64_t)h[1];
+  if (h[0] & 2u) return GSR_E_INVALID_ARG;  // inputs outside the voxel key range
+  return (h[0] & 1u) ? GSR_E_OVERFLOW : GSR_OK;
+}
+
 gsr_status gsr_prune(const gsr_scene* sc, float min_opacity, float* means_out,
                      float* log_scales_out, float* quats_out, float* opacity_out,
                      float* colors_out, int64_t* set_offsets_out, void* stream) {

@@ -163,6 +163,11 @@ hipError_t launch_sim3_views(const SimViewTab& tab, const float* vin, const floa
 hipError_t launch_l1_grad(int nv, int HW, const float* color, const float* depth,
                           const float* tcol, const float* tdep, const float* expo, float w_col,
                           float w_dep, float* g_col, float* g_dep, float* g_expo, hipStream_t s);
+size_t dedup_workspace_bytes(long long slots);
+hipError_t launch_dedup(long long slots, void* ws, double v, double kenv, const float* tm,
+                        const float* tls, long long n_tgt, const float* depth, const float* vms,
+                        const float* intr, int nk, int W, int H, const float* sm, long long n_src,
+                        uint8_t* keep, hipStream_t s, unsigned int** counters);
 size_t ssim_workspace_bytes(int nv, int W, int H);
 hipError_t launch_ssim(int nv, int W, int H, float weight, const float* color,
                        const float* target, const float* expo, void* ws, float* d_color,

@@ -128,3 +128,27 @@ def test_ssim_argument_validation():
     assert lib.gsr_ssim_grad(None, f, None, 1, 8, 8, 0.2, f, f, None, None, None) == E
     # misaligned workspace
     assert lib.gsr_ssim_grad(f, f, None, 1, 8, 8, 0.2, C.c_void_p(0x1004), f, None, None, None) == E
+
+
+def test_dedup_argument_validation():
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    E = _lib.GSR_E_INVALID_ARG
+    nb = C.c_size_t()
+    assert lib.gsr_dedup_workspace_bytes(1 << 10, C.byref(nb)) == _lib.GSR_OK
+    assert nb.value >= 12 * 1024
+    assert lib.gsr_dedup_workspace_bytes(1000, C.byref(nb)) == E  # not a power of two
+    f = C.c_void_p(0x1000)
+    n = C.c_int64()
+    bad = [_lib.DedupParams(0.0, 1.0, 1 << 10), _lib.DedupParams(0.05, -1.0, 1 << 10),
+           _lib.DedupParams(0.05, 1.0, 1000)]
+    for prm in bad:
+        assert lib.gsr_dedup(C.byref(prm), f, f, 10, None, None, None, 0, 0, 0, f, 10, f, f,
+                             C.byref(n), None) == E
+    ok = _lib.DedupParams(0.05, 1.0, 1 << 10)
+    # keyframes without depth arrays
+    assert lib.gsr_dedup(C.byref(ok), f, f, 10, None, None, None, 2, 8, 8, f, 10, f, f,
+                         C.byref(n), None) == E
+    # misaligned workspace
+    assert lib.gsr_dedup(C.byref(ok), f, f, 10, None, None, None, 0, 0, 0, f, 10, f,
+                         C.c_void_p(0x1008), C.byref(n), None) == E

@@ -1,0 +1,60 @@
+"""GPU parity of the occupancy-aware deduplication (Eqs. (envelope),
+(free_carve), (dedup)) against the oracle, through the C ABI."""
+import numpy as np
+import pytest
+
+from gpu_harness import announce
+from oracle.dedup import dedup, free, occupied, voxel_of
+from synth.scenes import look_at, pinhole
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed):
+    rng = np.random.default_rng(seed)
+    n_t, n_s = 1500, 2500
+    tm = rng.uniform(-1.5, 1.5, (n_t, 3)).astype(np.float32)
+    tls = rng.normal(-3.2, 0.5, (n_t, 3)).astype(np.float32)
+    sm = rng.uniform(-1.6, 1.6, (n_s, 3)).astype(np.float32)
+    sm[:300] = tm[:300] + rng.normal(0, 0.01, (300, 3)).astype(np.float32)  # duplicates
+    vms, intr = [], []
+    for k in range(2):
+        c = np.array([2.2 * np.cos(1.3 * k + 0.4), 0.1 * k, 2.2 * np.sin(1.3 * k + 0.4)])
+        vms.append(look_at(c, (0.0, 0.0, 0.0), 0.0))
+        intr.append(pinhole(40, 30, 20.0))
+    depth = (0.8 + 2.5 * rng.random((2, 30, 40))).astype(np.float32)
+    depth[0, :3, :5] = 0.0  # holes carve nothing
+    return tm, tls, sm, np.array(vms, np.float32), np.array(intr, np.float32), depth
+
+
+def test_dedup_matches_oracle():
+    announce("dedup")
+    import torch
+    from paper_2605_10760_amd import dedup as gpu_dedup
+    tm, tls, sm, vms, intr, depth = _case(3)
+    v, k = 0.05, 1.0
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    keep, nvox = gpu_dedup(t(sm), t(tm), t(tls), t(depth), t(vms), t(intr), v, k)
+    ref, n_amb = dedup(sm, tm, tls, depth, vms, intr, v, k)
+    assert n_amb == 0
+    # no box bound sits within 1e-9 of a voxel plane (where FP64 exp may differ
+    # by an ulp between libraries), so every decision is exact
+    s = np.exp(tls.astype(np.float64))
+    for x in ((tm - k * s) / v, (tm + k * s) / v, sm.astype(np.float64) / v):
+        assert np.min(np.abs(x - np.round(x))) > 1e-9
+    np.testing.assert_array_equal(keep.cpu().numpy().astype(bool), ref)
+    occ = occupied(tm, tls, v, k)
+    fr, _ = free(depth, vms, intr, v)
+    assert nvox == len(occ | fr)
+    assert 0 < ref.sum() < ref.shape[0] and not ref[:300].any()
+
+
+def test_dedup_overflow_reported():
+    """A hash set too small for the target's voxels reports GSR_E_OVERFLOW."""
+    announce("dedup overflow")
+    import torch
+    from paper_2605_10760_amd import GsrError, dedup as gpu_dedup
+    tm, tls, sm, _, _, _ = _case(4)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    with pytest.raises(GsrError):
+        gpu_dedup(t(sm), t(tm), t(tls), None, None, None, 0.05, 1.0, table_slots=1 << 10)
