@@ -51,13 +51,25 @@ __device__ __forceinline__ unsigned long long dd_mix(unsigned long long k) {
   return k;
 }
 
+// A slot's key only ever goes from empty to its final value, so a plain
+// read that already shows the key (or the flag) settles the insert without
+// an atomic: many rays of one keyframe share the voxels near its camera, and
+// their CASes would otherwise queue on the same slot.  A stale read of an
+// empty slot falls through to the CAS, which decides.
 __device__ void dd_insert(const DedupTable& T, unsigned long long key, unsigned int flag) {
   unsigned long long h = dd_mix(key) & T.mask;
   for (int probe = 0; probe < DD_MAX_PROBE && probe <= (long long)T.mask; ++probe) {
-    const unsigned long long prev = atomicCAS(&T.keys[h], DD_EMPTY, key);
-    if (prev == DD_EMPTY || prev == key) {
-      if (prev == DD_EMPTY) atomicAdd(&T.counters[1], 1u);
-      atomicOr(&T.flags[h], flag);
+    unsigned long long cur = T.keys[h];
+    if (cur == DD_EMPTY) {
+      cur = atomicCAS(&T.keys[h], DD_EMPTY, key);
+      if (cur == DD_EMPTY) {
+        atomicAdd(&T.counters[1], 1u);
+        atomicOr(&T.flags[h], flag);
+        return;
+      }
+    }
+    if (cur == key) {
+      if ((T.flags[h] & flag) == 0u) atomicOr(&T.flags[h], flag);
       return;
     }
     h = (h + 1) & T.mask;
