@@ -18,6 +18,7 @@ Contents (each module cites the passage it follows):
   refine     exposure-compensated L1 gradient, opacity pruning
   ssim       SSIM term of the refinement loss and its gradient
   dedup      occupancy-aware deduplication of borrowed Gaussians
+  mapping    isotropy and depth-normal terms of the mapping loss, seeding
 
 Parity status: every function is pinned by tests under tests/ (closed
 forms, invariants, brute force, library routines, finite differences).
