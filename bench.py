@@ -233,7 +233,8 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, reps=10):
     call from torch events on the stream they launch on, algorithmic bytes,
     and the fraction of the 8 TB/s HBM peak."""
     import numpy as np
-    from paper_2605_10760_amd import l1_loss_grad, prune, sim3_gaussians, sim3_views, ssim_grad
+    from paper_2605_10760_amd import (iso_grad, l1_loss_grad, normal_loss_grad, prune, seed,
+                                      sim3_gaussians, sim3_views, ssim_grad)
     V, _, H, W = out_color.shape
     N = sc.n
     rng = np.random.default_rng(0)
@@ -249,6 +250,9 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, reps=10):
               d_exposure=torch.empty((V, 2), device="cuda"))
     ws = ssim_grad(out_color, tc, gl["d_color"], expo, gl["d_exposure"])
     px = V * H * W
+    prior = torch.zeros_like(out_color)
+    prior[:, 2] = -1.0
+    g_ls = torch.zeros_like(sc.log_scales)
     calls = {
         # 40 B read + 40 B written per Gaussian
         "sim3_gaussians": (lambda: sim3_gaussians(sc.means, sc.log_scales, sc.quats,
@@ -260,6 +264,11 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, reps=10):
         # per pixel and channel: read I^ and I, read-modify-write dI^
         "ssim_grad": (lambda: ssim_grad(out_color, tc, gl["d_color"], expo, gl["d_exposure"],
                                         workspace=ws), 16 * 3 * px),
+        # read the log-scales, read-modify-write their gradient
+        "iso_grad": (lambda: iso_grad(sc.log_scales, g_ls, 10.0), 36 * N),
+        # read depth and the 3-channel prior, read-modify-write dD
+        "normal_loss_grad": (lambda: normal_loss_grad(out_depth, prior, vw.intrinsics,
+                                                      gl["d_depth"], 1e-2), 24 * px),
     }
     res = {}
     for name, (fn, nbytes) in calls.items():
@@ -293,6 +302,14 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, reps=10):
     res["dedup"] = dict(ms=round(ms, 3), target=tb - ta, borrowed=sb - sa,
                         kept=int(keep.sum().item()), rays=len(kfs) * H * W, voxels=nvox,
                         note="voxel 0.05, k 1; includes the host synchronisation")
+    # seeding one keyframe synchronises (host count): wall time of one call
+    seed(out_depth[0], out_color[0], vw.viewmats[0], vw.intrinsics[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sd = seed(out_depth[0], out_color[0], vw.viewmats[0], vw.intrinsics[0])
+    ms = (time.perf_counter() - t0) * 1e3
+    res["seed"] = dict(ms=round(ms, 4), seeded=int(sd["means"].shape[0]), pixels=H * W,
+                       note="one keyframe, stride 1; includes the host synchronisation")
     # pruning synchronises (host offsets): wall time of one call
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -337,6 +337,53 @@ gsr_status gsr_prune(const gsr_scene* scene, float min_opacity, float* means_out
                      float* log_scales_out, float* quats_out, float* opacity_out,
                      float* colors_out, int64_t* set_offsets_out, void* stream);
 
+/* Isotropy term of the mapping loss (Sec. III-A, Eq. (map_loss)):
+ * L_iso = sum_i sum_c |s_ic - mean_c s_ic| with s = exp(log_scales) (the
+ * paper weights it by lambda_s = 10).  ADDS weight * dL_iso/d log_scales into
+ * d_log_scales [n,3] (the subgradient of |.| at 0 is 0).  log_scales,
+ * d_log_scales: device arrays.  One kernel on `stream`, no allocation or
+ * synchronisation (graph-capturable).  GSR_E_INVALID_ARG for n < 0 or null
+ * pointers with n > 0. */
+gsr_status gsr_iso_grad(const float* log_scales, int64_t n, float weight, float* d_log_scales,
+                        void* stream);
+
+/* Depth-normal term of the mapping loss (Sec. III-A, Eq. (map_loss), weight
+ * lambda_n = 1e-2 in the paper): for camera points P(i, j) = D(i, j)
+ * ((i + 0.5 - cx)/fx, (j + 0.5 - cy)/fy, 1), the normal at an interior pixel
+ * is N = normalize((P(i, j+1) - P(i, j-1)) x (P(i+1, j) - P(i-1, j))), which
+ * faces the camera; L = sum over interior pixels with the four neighbour
+ * depths > 0 and a non-zero cross product of (1 - N . prior), divided by
+ * V (H-2) (W-2).  ADDS weight * dL/dD into d_depth [V,H,W].  depth [V,H,W]
+ * (rendered depth), normal_prior [V,3,H,W] (channel planes, not required to
+ * be unit length), intrinsics [V,4] (fx, fy, cx, cy): device arrays.  One
+ * kernel on `stream`, no allocation or synchronisation (graph-capturable);
+ * images narrower or lower than 3 pixels have no interior and leave d_depth
+ * unchanged.  GSR_E_INVALID_ARG for null pointers or bad sizes. */
+gsr_status gsr_normal_loss_grad(const float* depth, const float* normal_prior,
+                                const float* intrinsics, int32_t n_views, int32_t width,
+                                int32_t height, float weight, float* d_depth, void* stream);
+
+/* Seeding of a new keyframe's Gaussians (Sec. III-A: means back-projected
+ * through the keyframe's pose, mu = T^-1 pi^-1(u, d)).  One Gaussian per
+ * pixel (stride*gi, stride*gj) of the stride grid with depth > 0, in
+ * row-major grid order: mean = R^T (p - t) for the camera point p of the
+ * pixel centre at its depth; isotropic log-scale = log of the mean distance
+ * from p to the points of its up to four grid neighbours (at +-stride) with
+ * depth > 0, or log(d stride / fx) without one; quaternion (1, 0, 0, 0);
+ * opacity logit = opacity_logit; colour = the pixel's RGB.  depth [H,W],
+ * color [3,H,W] (channel planes), viewmat [3,4] world->camera, intrinsics
+ * [4]: device arrays.  Outputs (device, capacity max_out rows): means_out,
+ * log_scales_out, colors_out [max_out,3], quats_out [max_out,4],
+ * opacity_out [max_out].  Allocates a small temporary and synchronises
+ * `stream`; *n_out (HOST) gets the number of seeded Gaussians.
+ * GSR_E_OVERFLOW when that exceeds max_out (the first max_out rows are
+ * written); GSR_E_INVALID_ARG for null pointers or bad sizes. */
+gsr_status gsr_seed(const float* depth, const float* color, const float* viewmat,
+                    const float* intrinsics, int32_t width, int32_t height, int32_t stride,
+                    float opacity_logit, int64_t max_out, float* means_out,
+                    float* log_scales_out, float* quats_out, float* opacity_out,
+                    float* colors_out, int64_t* n_out, void* stream);
+
 /* Time forward+backward of the given call for each candidate tile shape and
  * report the fastest (tile_w, tile_h) in `best` (other fields copied from
  * `base`).  Synchronises; allocates its own temporary context. */

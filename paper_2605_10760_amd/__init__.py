@@ -5,5 +5,5 @@ this package only marshals PyTorch tensors into those calls.
 """
 from ._lib import GsrError, load  # noqa: F401
 from .rasterizer import (Rasterizer, SceneTensors, ViewTensors, apply_pose_delta,  # noqa: F401
-                         autotune, dedup, l1_loss_grad, pairs_of, prune, rasterize, sim3_gaussians,
-                         sim3_views, ssim_grad)
+                         autotune, dedup, iso_grad, l1_loss_grad, normal_loss_grad, pairs_of,
+                         prune, rasterize, seed, sim3_gaussians, sim3_views, ssim_grad)

@@ -21,7 +21,8 @@ EXPORTED = ("gsr_create", "gsr_destroy", "gsr_plan", "gsr_state_bytes", "gsr_for
             "gsr_autotune", "gsr_profile_enable", "gsr_profile_read", "gsr_status_string",
             "gsr_last_error", "gsr_sim3_gaussians", "gsr_sim3_views", "gsr_l1_loss_grad",
             "gsr_prune", "gsr_ssim_workspace_bytes", "gsr_ssim_grad",
-            "gsr_dedup_workspace_bytes", "gsr_dedup")
+            "gsr_dedup_workspace_bytes", "gsr_dedup", "gsr_iso_grad", "gsr_normal_loss_grad",
+            "gsr_seed")
 
 STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "render_bwd",
           "project_bwd")
@@ -140,6 +141,14 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gsr_dedup.restype = C.c_int
     lib.gsr_prune.argtypes = [P(Scene), C.c_float, vp, vp, vp, vp, vp, P(C.c_int64), vp]
     lib.gsr_prune.restype = C.c_int
+    lib.gsr_iso_grad.argtypes = [vp, C.c_int64, C.c_float, vp, vp]
+    lib.gsr_iso_grad.restype = C.c_int
+    lib.gsr_normal_loss_grad.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float,
+                                         vp, vp]
+    lib.gsr_normal_loss_grad.restype = C.c_int
+    lib.gsr_seed.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float,
+                             C.c_int64, vp, vp, vp, vp, vp, P(C.c_int64), vp]
+    lib.gsr_seed.restype = C.c_int
     lib.gsr_status_string.argtypes = [C.c_int]
     lib.gsr_status_string.restype = C.c_char_p
     lib.gsr_last_error.argtypes = [vp]

@@ -764,6 +764,64 @@ gsr_status gsr_prune(const gsr_scene* sc, float min_opacity, float* means_out,
   return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
 }
 
+gsr_status gsr_iso_grad(const float* log_scales, int64_t n, float weight, float* d_log_scales,
+                        void* stream) {
+  if (n < 0 || (n > 0 && (!log_scales || !d_log_scales))) return GSR_E_INVALID_ARG;
+  if (n > 0x7FFFFFFFL * 64L) return GSR_E_INVALID_ARG;
+  hipError_t e = launch_iso_grad((long)n, log_scales, weight, d_log_scales, (hipStream_t)stream);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
+gsr_status gsr_normal_loss_grad(const float* depth, const float* normal_prior,
+                                const float* intrinsics, int32_t n_views, int32_t width,
+                                int32_t height, float weight, float* d_depth, void* stream) {
+  if (!depth || !normal_prior || !intrinsics || !d_depth || n_views < 1 || width < 1 ||
+      height < 1)
+    return GSR_E_INVALID_ARG;
+  const double tiles = (double)n_views * ((width + 15) / 16) * ((height + 15) / 16);
+  if (tiles > 2147483647.0 || (double)n_views * width * height * 3 > 9.0e15)
+    return GSR_E_INVALID_ARG;
+  if (width < 3 || height < 3) return GSR_OK;  // no interior pixel: the loss is empty
+  // the loss is a mean over the interior pixels of the batch
+  const float w =
+      (float)((double)weight / ((double)n_views * (double)(height - 2) * (double)(width - 2)));
+  hipError_t e = launch_normal_grad(n_views, width, height, depth, normal_prior, intrinsics, w,
+                                    d_depth, (hipStream_t)stream);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
+gsr_status gsr_seed(const float* depth, const float* color, const float* viewmat,
+                    const float* intrinsics, int32_t width, int32_t height, int32_t stride,
+                    float opacity_logit, int64_t max_out, float* means_out,
+                    float* log_scales_out, float* quats_out, float* opacity_out,
+                    float* colors_out, int64_t* n_out, void* stream) {
+  if (!depth || !color || !viewmat || !intrinsics || !n_out || width < 1 || height < 1 ||
+      stride < 1 || max_out < 0)
+    return GSR_E_INVALID_ARG;
+  if (max_out > 0 && (!means_out || !log_scales_out || !quats_out || !opacity_out || !colors_out))
+    return GSR_E_INVALID_ARG;
+  const long gm = (long)((width + stride - 1) / stride) * ((height + stride - 1) / stride);
+  if ((double)width * height * 3 > 2147483647.0 || gm > 0x7FFFFFFFL) return GSR_E_INVALID_ARG;
+  const size_t nb = (size_t)((gm + 255) / 256);
+  void* tmp = nullptr;
+  if (hipMalloc(&tmp, 4 * (nb + 1)) != hipSuccess) {
+    (void)hipGetLastError();
+    return GSR_E_OOM;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* blk = (uint32_t*)tmp;
+  uint32_t total = 0;
+  hipError_t e = launch_seed(width, height, stride, depth, color, viewmat, intrinsics,
+                             opacity_logit, (long)max_out, blk, means_out, log_scales_out,
+                             quats_out, opacity_out, colors_out, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, blk + nb, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return GSR_E_DEVICE;
+  *n_out = (int64_t)total;
+  return (int64_t)total > max_out ? GSR_E_OVERFLOW : GSR_OK;
+}
+
 gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* sc,
                         const gsr_views* vw, const gsr_settings* set, gsr_plan_desc* best,
                         float* best_ms, void* stream) {

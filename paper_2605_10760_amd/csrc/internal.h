@@ -175,5 +175,14 @@ hipError_t launch_ssim(int nv, int W, int H, float weight, const float* color,
 hipError_t launch_prune(long n, const SceneDev& in, int color_stride, float thr,
                         const SimSetTab& sets, uint32_t* blk, long long* bounds, float* m,
                         float* ls, float* q, float* o, float* col, hipStream_t s);
+// exclusive scan of nb block counts in place, total at blk[nb] (one workgroup)
+hipError_t launch_block_scan(int nb, uint32_t* blk, hipStream_t s);
+hipError_t launch_iso_grad(long n, const float* ls, float w, float* g, hipStream_t s);
+hipError_t launch_normal_grad(int nv, int W, int H, const float* depth, const float* prior,
+                              const float* intr, float w, float* g_dep, hipStream_t s);
+hipError_t launch_seed(int W, int H, int stride, const float* depth, const float* color,
+                       const float* vm, const float* intr, float opac_logit, long max_out,
+                       uint32_t* blk, float* m, float* ls, float* q, float* o, float* c,
+                       hipStream_t s);
 
 }  // namespace gsr

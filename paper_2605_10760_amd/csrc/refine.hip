@@ -100,6 +100,11 @@ __global__ __launch_bounds__(1024) void k_prune_scan(int nb, uint32_t* blk) {
   if (threadIdx.x == 0) blk[nb] = (uint32_t)carry;
 }
 
+hipError_t launch_block_scan(int nb, uint32_t* blk, hipStream_t s) {
+  hipLaunchKernelGGL(k_prune_scan, dim3(1), dim3(1024), 0, s, nb, blk);
+  return hipGetLastError();
+}
+
 // Kept count before each set boundary (one thread per boundary).
 __global__ void k_prune_bounds(SimSetTab tab, const float* opac, float thr, const uint32_t* blk,
                                long long* out) {

@@ -433,6 +433,57 @@ def prune(scene: SceneTensors, min_opacity: float = 0.005, stream=None) -> Scene
     return SceneTensors(*(x[:n] for x in new), offs, scene.sh_degree)
 
 
+def iso_grad(log_scales: torch.Tensor, d_log_scales: torch.Tensor, weight: float = 10.0,
+             stream=None) -> torch.Tensor:
+    """Adds weight * d/d log_scales of sum_i sum_c |s_ic - mean_c s_ic|
+    (s = exp(log_scales) [n,3]) into d_log_scales on the device."""
+    lib = L.load()
+    st = lib.gsr_iso_grad(_ptr(log_scales.contiguous()), int(log_scales.shape[0]), float(weight),
+                          _ptr(d_log_scales), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_iso_grad failed")
+    return d_log_scales
+
+
+def normal_loss_grad(depth: torch.Tensor, normal_prior: torch.Tensor, intrinsics: torch.Tensor,
+                     d_depth: torch.Tensor, weight: float = 1e-2, stream=None) -> torch.Tensor:
+    """Adds weight * dL_normal/dD into d_depth [V,H,W] on the device;
+    L_normal is the mean over interior pixels of 1 - N(D) . prior with the
+    depth-induced normal N (prior [V,3,H,W])."""
+    lib = L.load()
+    V, H, W = depth.shape
+    st = lib.gsr_normal_loss_grad(_ptr(depth.contiguous()), _ptr(normal_prior.contiguous()),
+                                  _ptr(intrinsics.contiguous()), int(V), int(W), int(H),
+                                  float(weight), _ptr(d_depth), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_normal_loss_grad failed")
+    return d_depth
+
+
+def seed(depth: torch.Tensor, color: torch.Tensor, viewmat: torch.Tensor,
+         intrinsics: torch.Tensor, stride: int = 1, opacity_logit: float = 0.0,
+         stream=None) -> dict:
+    """Gaussians seeded from one keyframe (depth [H,W], color [3,H,W],
+    viewmat [3,4], intrinsics [4]) on the device: dict of means, log_scales,
+    quats, opacity_logits, colors (synchronises)."""
+    lib = L.load()
+    H, W = depth.shape
+    cap = ((W + stride - 1) // stride) * ((H + stride - 1) // stride)
+    dev = depth.device
+    out = dict(means=torch.empty((cap, 3), device=dev), log_scales=torch.empty((cap, 3), device=dev),
+               quats=torch.empty((cap, 4), device=dev), opacity_logits=torch.empty(cap, device=dev),
+               colors=torch.empty((cap, 3), device=dev))
+    n = C.c_int64()
+    st = lib.gsr_seed(_ptr(depth.contiguous()), _ptr(color.contiguous()),
+                      _ptr(viewmat.contiguous()), _ptr(intrinsics.contiguous()), int(W), int(H),
+                      int(stride), float(opacity_logit), int(cap), _ptr(out["means"]),
+                      _ptr(out["log_scales"]), _ptr(out["quats"]), _ptr(out["opacity_logits"]),
+                      _ptr(out["colors"]), C.byref(n), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_seed failed")
+    return {k: v[:int(n.value)] for k, v in out.items()}
+
+
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_delta, viewmats,

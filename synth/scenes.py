@@ -319,3 +319,37 @@ WORKLOADS = {
     3: multi_agent,
     4: fused_map,
 }
+
+
+# --------------------------------------------------------------------------
+# depth maps for the mapping-loss extras and seeding
+# --------------------------------------------------------------------------
+
+def slanted_depth(rng: np.random.Generator, n_views: int, width: int, height: int,
+                  f: float = 600.0, hole_frac: float = 0.01, noise: float = 2e-3):
+    """Piecewise-planar camera depth maps [V,H,W] standing in for rendered
+    room depth: per view, the nearest of three random planes
+    z = z0 / (1 - gx x - gy y) in normalised image coordinates, z0 in
+    U[1.5, 4], gradients N(0, 0.3), plus N(0, noise) jitter and a fraction
+    of zero-depth holes; and unit normal priors [V,3,H,W] that face the
+    camera, (N(0, 0.3), N(0, 0.3), -1) normalised.  Intrinsics [V,4] use
+    focal f and the image centre."""
+    intr = np.array([pinhole(width, height, f)] * n_views)
+    x = (np.arange(width) + 0.5 - width / 2.0) / f
+    y = (np.arange(height) + 0.5 - height / 2.0) / f
+    depth = np.empty((n_views, height, width))
+    for v in range(n_views):
+        best = np.full((height, width), np.inf)
+        for _ in range(3):
+            z0 = rng.uniform(1.5, 4.0)
+            gx, gy = rng.normal(0, 0.3, 2)
+            den = 1.0 - gx * x[None, :] - gy * y[:, None]
+            z = np.where(den > 0.2, z0 / np.maximum(den, 0.2), np.inf)
+            best = np.minimum(best, z)
+        best = np.where(np.isfinite(best), best, 5.0)
+        depth[v] = best + rng.normal(0, noise, best.shape)
+    depth[rng.random(depth.shape) < hole_frac] = 0.0
+    pr = np.stack([rng.normal(0, 0.3, depth.shape), rng.normal(0, 0.3, depth.shape),
+                   -np.ones(depth.shape)], axis=1)
+    pr /= np.linalg.norm(pr, axis=1, keepdims=True)
+    return depth.astype(F32), pr.astype(F32), intr.astype(F32)

@@ -152,3 +152,23 @@ def test_dedup_argument_validation():
     # misaligned workspace
     assert lib.gsr_dedup(C.byref(ok), f, f, 10, None, None, None, 0, 0, 0, f, 10, f,
                          C.c_void_p(0x1008), C.byref(n), None) == E
+
+
+def test_mapping_argument_validation():
+    from paper_2605_10760_amd import _lib
+    lib = _lib.load()
+    E = _lib.GSR_E_INVALID_ARG
+    f = C.c_void_p(0x1000)
+    assert lib.gsr_iso_grad(f, -1, 10.0, f, None) == E
+    assert lib.gsr_iso_grad(None, 5, 10.0, f, None) == E
+    assert lib.gsr_iso_grad(f, 5, 10.0, None, None) == E
+    assert lib.gsr_normal_loss_grad(None, f, f, 1, 8, 8, 1.0, f, None) == E
+    assert lib.gsr_normal_loss_grad(f, f, f, 0, 8, 8, 1.0, f, None) == E
+    # no interior pixel: nothing to do, no device work
+    assert lib.gsr_normal_loss_grad(f, f, f, 1, 2, 8, 1.0, f, None) == _lib.GSR_OK
+    n = C.c_int64()
+    args = [f, f, f, f, 8, 8, 1, 0.0, 64, f, f, f, f, f, C.byref(n), None]
+    for k, bad in ((6, 0), (8, -1), (9, None), (14, None), (4, 0)):
+        a = list(args)
+        a[k] = bad
+        assert lib.gsr_seed(*a) == E, k
