@@ -12,14 +12,15 @@
 //                per chunk takes its pairs 64 at a time and appends
 //                (pair id, x0, x1) to every row the rect spans, ranked inside
 //                each row by a wave ballot (lane order = depth order).
-//   Both scatters keep their per-bucket cursors in registers (bucket k in
-//   lane k % 64 of register k / 64), read and advanced with readlane.
+//   The row scatter keeps its per-row cursors in registers (row k in lane
+//   k % 64 of register k / 64), read and advanced with readlane.
 //   tile level : each row list (still in depth order) is cut into segments
 //                of SEG entries; per segment the number of entries covering
 //                each tile of the row, an exclusive scan down each tile's
 //                segments, a scan over all tiles (the tile ranges), and a
-//                scatter where one wave per segment ranks each entry inside
-//                every tile it covers by a wave ballot.
+//                scatter where one wave per segment holds the segment in
+//                registers and, column by column, ranks the entries covering
+//                the column by a wave ballot per 64 entries.
 #include "common.h"
 
 namespace gsr {
@@ -324,62 +325,108 @@ __global__ __launch_bounds__(256) void k_seg_colscan(int nrows, int TX, const ui
   tile_cnt[g] = run;
 }
 
-// One wave per segment (grid-stride over the device-side segment count),
-// 64 entries per step (lane order = list order).  For every tile column a
-// ballot gives the lanes whose entry covers it; lane l stores its pair at
-// the column's cursor plus the number of lower lanes in the mask.  The
-// cursor of column x lives in lane x % 64 of register cur[x / 64]: no LDS,
-// no barriers.  Consecutive covering lanes store consecutive words of one
-// tile's list, and a column's runs of consecutive steps are adjacent.
+// One wave per segment (grid-stride over the device-side segment count).
+// The segment's SEG entries are loaded into registers at once, 64 per step in
+// list order; the cursors of the columns it covers go to the wave's row of
+// LDS.  Column by column, a ballot per step gives the lanes whose entry
+// covers the column; lane l stores its pair at the column's cursor plus the
+// number of lower lanes in the mask, and the cursor advances by the mask's
+// count.  A column's stores of the whole segment are issued back to back and
+// land on consecutive words, so its cache lines are filled before the next
+// column starts (walking step-major instead interleaves every column's short
+// runs, and partly filled lines reach HBM about twice over).  The step loop
+// is unrolled so that the entries are addressed statically.
 constexpr int TS_WAVES = 4;
+constexpr int TS_STEPS = SEG / 64;
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
+  return x;
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, 64));
+  return x;
+}
+// Lanes whose entry covers column x store their pair at c plus their rank
+// among the covering lanes; c advances by the number of covering lanes.
+__device__ __forceinline__ void scatter_step(int x, int x0, int span, uint32_t pid, uint32_t& c,
+                                             uint32_t* inst) {
+  const bool cov = (unsigned)(x - x0) < (unsigned)span;
+  const unsigned long long m = __ballot(cov);
+  if (cov) {
+    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    inst[c + rank] = pid;
+  }
+  c += (uint32_t)__popcll(m);
+}
+
 __global__ __launch_bounds__(64 * TS_WAVES) void k_tile_scatter(BinTab t, StateDev st,
                                                                 const uint32_t* seg_off,
                                                                 const uint32_t* seg_row,
                                                                 const uint32_t* seg_cnt,
                                                                 const uint2* row_rg,
                                                                 const uint2* rows) {
-  constexpr int NG = MAX_COLS / 64;
+  __shared__ uint32_t curs[TS_WAVES][MAX_COLS];
   if (st.hdr->overflow) return;
   const int nrows = t.nv * t.TY;
   const uint32_t nseg = seg_off[nrows];
   const int lane = threadIdx.x & 63, TX = t.TX;
   const uint32_t nw = gridDim.x * TS_WAVES;
-  const unsigned long long lt = (1ull << lane) - 1ull;
   const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint32_t* cw = curs[wave];
   for (uint32_t s = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * TS_WAVES + wave; s < nseg;
        s += nw) {
     int r;
     uint32_t lo, hi;
     seg_range(seg_off, seg_row, row_rg, s, r, lo, hi);
-    uint32_t cur[NG];
+    const int nsteps = (int)((hi - lo + 63) / 64);
+    uint32_t pid[TS_STEPS];
+    int x0[TS_STEPS], span[TS_STEPS];
+    int xmin = TX, xmax = 0;
+    // unconditional loads (clamped into the segment) so that all of them are
+    // in flight together
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      const int x = g * 64 + lane;
-      cur[g] = x < TX ? st.ranges[(size_t)r * TX + x].x + seg_cnt[(size_t)s * TX + x] : 0u;
-    }
-    for (uint32_t base = lo; base < hi; base += 64) {
-      const uint32_t i = base + lane;
+    for (int k = 0; k < TS_STEPS; ++k) {
+      const uint32_t i = lo + (uint32_t)(k * 64 + lane);
+      const uint2 e = rows[min(i, hi - 1u)];
       const bool valid = i < hi;
-      const uint2 e = valid ? rows[i] : make_uint2(0u, 0u);
-      const int x0 = (int)(e.y & 0xFFFF), x1 = valid ? (int)(e.y >> 16) : 0;
-#pragma unroll
-      for (int g = 0; g < NG; ++g) {
-        if (g * 64 >= TX) break;
-        const int xe = min(64, TX - g * 64);
-        for (int xi = 0; xi < xe; ++xi) {
-          const int x = g * 64 + xi;
-          const bool cov = x0 <= x && x < x1;
-          const unsigned long long m = __ballot(cov);
-          if (m == 0ull) continue;
-          const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)cur[g], xi);
-          if (cov) {
-            const uint32_t pos = c0 + (uint32_t)__popcll(m & lt);
-            if (pos < st.cap) st.inst[pos] = e.x;
-          }
-          if (lane == xi) cur[g] = c0 + (uint32_t)__popcll(m);
-        }
+      pid[k] = e.x;
+      x0[k] = (int)(e.y & 0xFFFF);
+      span[k] = valid ? (int)(e.y >> 16) - x0[k] : 0;
+      if (valid) {
+        xmin = min(xmin, x0[k]);
+        xmax = max(xmax, (int)(e.y >> 16));
       }
     }
+    xmin = __builtin_amdgcn_readfirstlane(wave_min_i(xmin));
+    xmax = __builtin_amdgcn_readfirstlane(wave_max_i(xmax));
+    // the cursors of the covered columns go to this wave's LDS row
+    for (int x = xmin + lane; x < xmax; x += 64)
+      cw[x] = st.ranges[(size_t)r * TX + x].x + seg_cnt[(size_t)s * TX + x];
+    __builtin_amdgcn_wave_barrier();
+    // Stores stay inside the tile's range: the column's cursor plus the
+    // covering entries of this segment end at the next segment's cursor
+    // (the counts used the same x0 <= x < x1 rule), and the ranges fit the
+    // capacity (checked above through the overflow flag).
+    if (nsteps == TS_STEPS) {
+#pragma unroll 1
+      for (int x = xmin; x < xmax; ++x) {
+        uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cw[x]);
+#pragma unroll
+        for (int k = 0; k < TS_STEPS; ++k) scatter_step(x, x0[k], span[k], pid[k], c, st.inst);
+      }
+    } else {
+#pragma unroll 1
+      for (int x = xmin; x < xmax; ++x) {
+        uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cw[x]);
+#pragma unroll
+        for (int k = 0; k < TS_STEPS; ++k)
+          if (k < nsteps) scatter_step(x, x0[k], span[k], pid[k], c, st.inst);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
