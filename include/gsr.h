@@ -91,7 +91,8 @@ typedef struct gsr_plan_desc {
   int32_t height;
   int32_t tile_w;        /* tile shape: 8, 16 or 32 each, tile_w*tile_h in [64, 512] */
   int32_t tile_h;
-  int32_t chunk;         /* depth-sorted pairs per binning chunk (0 = automatic) */
+  int32_t chunk;         /* depth-sorted pairs per binning chunk, at most 256
+                            (0 = automatic) */
 } gsr_plan_desc;
 
 /* Gaussians, concatenated over sets; set s owns [set_offsets[s], set_offsets[s+1]). */

@@ -142,7 +142,8 @@ gsr_status check_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   if (TX > MAX_COLS || TY > MAX_ROWS)
     return fail(c, GSR_E_INVALID_ARG, "too many tiles per view (%ld x %ld, at most %d x %d)", TX,
                 TY, MAX_COLS, MAX_ROWS);
-  if (p->chunk < 0) return fail(c, GSR_E_INVALID_ARG, "chunk must be >= 0");
+  if (p->chunk < 0 || p->chunk > MAX_CHUNK)
+    return fail(c, GSR_E_INVALID_ARG, "chunk must be in [0, %d]", MAX_CHUNK);
   return GSR_OK;
 }
 

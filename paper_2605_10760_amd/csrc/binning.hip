@@ -12,8 +12,8 @@
 //                per chunk takes its pairs 64 at a time and appends
 //                (pair id, x0, x1) to every row the rect spans, ranked inside
 //                each row by a wave ballot (lane order = depth order).
-//   The row scatter keeps its per-row cursors in registers (row k in lane
-//   k % 64 of register k / 64), read and advanced with readlane.
+//   Both scatters hold their chunk / segment in registers and walk it
+//   bucket by bucket, so each bucket's stores are issued back to back.
 //   tile level : each row list (still in depth order) is cut into segments
 //                of SEG entries; per segment the number of entries covering
 //                each tile of the row, an exclusive scan down each tile's
@@ -169,54 +169,84 @@ __global__ __launch_bounds__(1024) void k_range_scan(int n, const uint32_t* cnt,
   }
 }
 
+// Wave-wide minimum / maximum (every lane active), returned in every lane.
+__device__ __forceinline__ int wave_min_i(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
+  return x;
+}
+__device__ __forceinline__ int wave_max_i(int x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, 64));
+  return x;
+}
+
 // One wave per chunk: append every pair, in order, to each row it spans.
-// Row entries are (pair id, x0 | x1 << 16).  Each step takes 64 consecutive
-// pairs (lane order = depth order); for every row, a ballot gives the mask
-// of lanes spanning it, so lane l's slot in that row is the row cursor plus
-// the number of lower lanes in the mask.  The cursor of row y lives in lane
-// y % 64 of register cur[y / 64]: no LDS, no barriers.
+// Row entries are (pair id, x0 | x1 << 16).  The chunk's pairs sit in
+// registers, 64 per step (lane order = depth order); for every row the chunk
+// spans, a ballot per step gives the lanes spanning it, so lane l's slot in
+// that row is the row cursor plus the number of lower lanes in the mask.
+// The row cursors sit in the wave's row of LDS (no barriers: one wave).
 __global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, const uint32_t* counts,
                                                      const uint2* row_rg, uint2* rows,
-                                                     unsigned long long row_cap,
                                                      const unsigned int* row_flag) {
-  constexpr int NG = MAX_ROWS / 64;
+  constexpr int STEPS = MAX_CHUNK / 64;
+  __shared__ uint32_t curs[4][MAX_ROWS];
   const int nc = t.cblk_off[t.nv];
-  const int b = xcd_remap(blockIdx.x, (nc + 3) / 4) * 4 +
-                __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int b = xcd_remap(blockIdx.x, (nc + 3) / 4) * 4 + wave;
   if (b < 0 || b >= nc) return;
   int v, lo, hi;
   chunk_range(t, st.hdr, b, v, lo, hi);
   if (lo >= hi || *row_flag) return;
   const int lane = threadIdx.x & 63, TY = t.TY;
-  uint32_t cur[NG];
+  const int nsteps = (hi - lo + 63) / 64;
+  // the chunk's pairs and rects, every load issued before the first use
+  uint32_t pid[STEPS];
 #pragma unroll
-  for (int g = 0; g < NG; ++g) {
-    const int y = g * 64 + lane;
-    cur[g] = y < TY ? row_rg[(size_t)v * TY + y].x + counts[(size_t)b * TY + y] : 0u;
+  for (int k = 0; k < STEPS; ++k) pid[k] = st.order[min(lo + k * 64 + lane, hi - 1)];
+  uint2 rc[STEPS];
+#pragma unroll
+  for (int k = 0; k < STEPS; ++k) rc[k] = st.rect[pid[k]];
+  int y0[STEPS], span[STEPS];
+  uint32_t xs[STEPS];
+  int ymin = TY, ymax = 0;
+#pragma unroll
+  for (int k = 0; k < STEPS; ++k) {
+    const bool valid = lo + k * 64 + lane < hi;
+    y0[k] = (int)(rc[k].x >> 16);
+    const int y1 = (int)(rc[k].y >> 16);
+    span[k] = valid ? y1 - y0[k] : 0;
+    xs[k] = (rc[k].x & 0xFFFF) | (rc[k].y << 16);
+    if (valid && y1 > y0[k]) {
+      ymin = min(ymin, y0[k]);
+      ymax = max(ymax, y1);
+    }
   }
-  const unsigned long long lt = (1ull << lane) - 1ull;
-  for (int base = lo; base < hi; base += 64) {
-    const int i = base + lane;
-    const bool valid = i < hi;
-    const uint32_t pair = valid ? st.order[i] : 0u;
-    const uint2 r = valid ? st.rect[pair] : make_uint2(0u, 0u);
-    const int y0 = (int)(r.x >> 16), y1 = valid ? (int)(r.y >> 16) : 0;
-    const uint2 ent = make_uint2(pair, (r.x & 0xFFFF) | (r.y << 16));
+  ymin = __builtin_amdgcn_readfirstlane(wave_min_i(ymin));
+  ymax = __builtin_amdgcn_readfirstlane(wave_max_i(ymax));
+  uint32_t* cw = curs[wave];
+  for (int y = ymin + lane; y < ymax; y += 64)
+    cw[y] = row_rg[(size_t)v * TY + y].x + counts[(size_t)b * TY + y];
+  __builtin_amdgcn_wave_barrier();
+  // row by row: a ballot per 64 pairs; the row's stores of the chunk are
+  // issued back to back onto consecutive entries.  They stay inside the row's
+  // range: the counts used the same y0 <= y < y1 rule, and an overflowing
+  // row level returned above.
+#pragma unroll 1
+  for (int y = ymin; y < ymax; ++y) {
+    uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cw[y]);
 #pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      if (g * 64 >= TY) break;
-      const int ye = min(64, TY - g * 64);
-      for (int yi = 0; yi < ye; ++yi) {
-        const int y = g * 64 + yi;
-        const bool cov = y0 <= y && y < y1;
+    for (int k = 0; k < STEPS; ++k) {
+      if (k < nsteps) {
+        const bool cov = (unsigned)(y - y0[k]) < (unsigned)span[k];
         const unsigned long long m = __ballot(cov);
-        if (m == 0ull) continue;
-        const uint32_t c0 = (uint32_t)__builtin_amdgcn_readlane((int)cur[g], yi);
         if (cov) {
-          const uint32_t pos = c0 + (uint32_t)__popcll(m & lt);
-          if (pos < row_cap) rows[pos] = ent;
+          const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          rows[c + rank] = make_uint2(pid[k], xs[k]);
         }
-        if (lane == yi) cur[g] = c0 + (uint32_t)__popcll(m);
+        c += (uint32_t)__popcll(m);
       }
     }
   }
@@ -338,16 +368,6 @@ __global__ __launch_bounds__(256) void k_seg_colscan(int nrows, int TX, const ui
 // is unrolled so that the entries are addressed statically.
 constexpr int TS_WAVES = 4;
 constexpr int TS_STEPS = SEG / 64;
-__device__ __forceinline__ int wave_min_i(int x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = min(x, __shfl_xor(x, d, 64));
-  return x;
-}
-__device__ __forceinline__ int wave_max_i(int x) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) x = max(x, __shfl_xor(x, d, 64));
-  return x;
-}
 // Lanes whose entry covers column x store their pair at c plus their rank
 // among the covering lanes; c advances by the number of covering lanes.
 __device__ __forceinline__ void scatter_step(int x, int x0, int span, uint32_t pid, uint32_t& c,
@@ -443,7 +463,7 @@ hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStr
                      (const unsigned long long*)nullptr);
   if (nc > 0)
     hipLaunchKernelGGL(k_row_scatter, dim3(xcd_grid((nc + 3) / 4)), dim3(256), 0, s, t, st,
-                       w.counts, w.row_rg, w.rows, w.row_cap, w.row_flag);
+                       w.counts, w.row_rg, w.rows, w.row_flag);
   // level 2: tiles, per row segment
   hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, s, nrows, w.row_rg, w.seg_off,
                      w.seg_row, w.row_flag);

@@ -24,6 +24,7 @@ constexpr int GRAD2D = 10;        // u, v, A, B, C, sigma, r, g, b, z
 constexpr uint32_t CULLED = 0xFFFFFFFFu;
 constexpr int MAX_ROWS = 512;     // tile rows per view (binning LDS arrays)
 constexpr int MAX_COLS = 512;     // tile columns per view
+constexpr int MAX_CHUNK = 256;   // depth-sorted pairs per row-binning chunk
 constexpr int SEG = 1024;         // row-list entries per tile-binning segment
 
 // Pair p of view v is Gaussian (set_goff[view_set[v]] + p - pair_off[v]).
