@@ -389,31 +389,40 @@ def dedup(src_means: torch.Tensor, tgt_means: torch.Tensor, tgt_log_scales: torc
           table_slots: int | None = None, stream=None):
     """Occupancy-aware deduplication on the device: returns (keep uint8
     [n_src], distinct voxels).  depth [K,H,W] (camera depth of the target's
-    keyframes) may be None (no free-space carving).  Synchronises."""
+    keyframes) may be None (no free-space carving).  With table_slots None
+    the hash set starts at twice the number of boxes and rays (rays of one
+    keyframe share most of their voxels) and grows fourfold when it
+    overflows.  Synchronises."""
     lib = L.load()
     n_tgt, n_src = int(tgt_means.shape[0]), int(src_means.shape[0])
     K = 0 if depth is None else int(depth.shape[0])
     H = 0 if depth is None else int(depth.shape[1])
     W = 0 if depth is None else int(depth.shape[2])
-    if table_slots is None:
-        est = 27 * n_tgt + 64 * K * H * W + 1024
-        table_slots = 1 << max(10, int(2 * est - 1).bit_length())
-    nb = C.c_size_t()
-    st = lib.gsr_dedup_workspace_bytes(int(table_slots), C.byref(nb))
-    if st != L.GSR_OK:
-        raise L.GsrError(st, "gsr_dedup_workspace_bytes failed")
-    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=src_means.device)
+    grow = table_slots is None
+    if grow:
+        est = 2 * (n_tgt + K * H * W) + 1024
+        table_slots = 1 << max(10, int(est - 1).bit_length())
     keep = torch.empty(n_src, dtype=torch.uint8, device=src_means.device)
     nvox = C.c_int64()
     c = lambda t: None if t is None else t.contiguous()
-    prm = L.DedupParams(float(voxel), float(k_env), int(table_slots))
-    st = lib.gsr_dedup(C.byref(prm), _ptr(c(tgt_means)), _ptr(c(tgt_log_scales)), n_tgt,
-                       _ptr(c(depth)), _ptr(c(viewmats)), _ptr(c(intrinsics)), K, W, H,
-                       _ptr(c(src_means)), n_src, _ptr(keep), _ptr(ws), C.byref(nvox),
-                       _stream(stream))
-    if st != L.GSR_OK:
-        raise L.GsrError(st, "gsr_dedup failed")
-    return keep, int(nvox.value)
+    while True:
+        nb = C.c_size_t()
+        st = lib.gsr_dedup_workspace_bytes(int(table_slots), C.byref(nb))
+        if st != L.GSR_OK:
+            raise L.GsrError(st, "gsr_dedup_workspace_bytes failed")
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device=src_means.device)
+        prm = L.DedupParams(float(voxel), float(k_env), int(table_slots))
+        st = lib.gsr_dedup(C.byref(prm), _ptr(c(tgt_means)), _ptr(c(tgt_log_scales)), n_tgt,
+                           _ptr(c(depth)), _ptr(c(viewmats)), _ptr(c(intrinsics)), K, W, H,
+                           _ptr(c(src_means)), n_src, _ptr(keep), _ptr(ws), C.byref(nvox),
+                           _stream(stream))
+        if st == L.GSR_E_OVERFLOW and grow and table_slots < (1 << 30):
+            del ws
+            table_slots *= 4
+            continue
+        if st != L.GSR_OK:
+            raise L.GsrError(st, "gsr_dedup failed")
+        return keep, int(nvox.value)
 
 
 def prune(scene: SceneTensors, min_opacity: float = 0.005, stream=None) -> SceneTensors:

@@ -58,3 +58,22 @@ def test_dedup_overflow_reported():
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     with pytest.raises(GsrError):
         gpu_dedup(t(sm), t(tm), t(tls), None, None, None, 0.05, 1.0, table_slots=1 << 10)
+
+
+def test_dedup_table_grows_on_overflow():
+    """The binding's default hash set starts from the input counts; one large
+    box (about 21^3 voxels) overflows it, and the call grows the set and
+    still matches the oracle."""
+    announce("dedup table growth")
+    import torch
+    from paper_2605_10760_amd import dedup as gpu_dedup
+    rng = np.random.default_rng(9)
+    tm = np.array([[0.013, -0.021, 0.007]], np.float32)
+    tls = np.full((1, 3), np.log(0.5), np.float32)
+    sm = rng.uniform(-0.7, 0.7, (3000, 3)).astype(np.float32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    keep, nvox = gpu_dedup(t(sm), t(tm), t(tls), None, None, None, 0.05, 1.0)
+    occ = occupied(tm, tls, 0.05, 1.0)
+    assert nvox == len(occ) > 4096
+    ref = np.array([tuple(q) not in occ for q in voxel_of(sm, 0.05)])
+    np.testing.assert_array_equal(keep.cpu().numpy().astype(bool), ref)
