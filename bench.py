@@ -481,7 +481,8 @@ def main():
     npx = V * H * W
     chunk_T = rast.desc.chunk or 0
     alg_bytes = {
-        "project": 12 * P + 4 * P + (par - 12 + 48 + 8) * nv_pairs,
+        # parameters once per Gaussian, a key per pair, rect + record per visible pair
+        "project": par * sc_np.n + 4 * P + (48 + 8) * nv_pairs,
         "compact": 4 * P + 8 * nv_pairs,
         "depth_sort": 4 * 24 * nv_pairs,
         "binning": 2 * 12 * nv_pairs + 4 * I,

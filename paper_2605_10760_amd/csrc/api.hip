@@ -219,6 +219,24 @@ gsr_status build_tabs(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw, Call
   t.P = (int)P;
   if ((size_t)blk > c->max_blocks || (size_t)sblk > c->max_sblocks || (size_t)cblk > c->max_chunks)
     return fail(c, GSR_E_CAPACITY, "block tables exceed the plan");
+  // sets, for the projection: every view, blocks only for rendered sets
+  {
+    ProjTab& pt = t.pt;
+    pt.ns = sc->n_sets;
+    int gb = 0, nvs = 0;
+    for (int s = 0; s < sc->n_sets; ++s) {
+      pt.set_goff[s] = (int)sc->set_offsets[s];
+      pt.set_gblk[s] = gb;
+      pt.set_voff[s] = nvs;
+      for (int v = 0; v < nv; ++v)
+        if (vw->view_set[v] == s) pt.vset[nvs++] = v;
+      if (nvs > pt.set_voff[s])
+        gb += ceil_div(sc->set_offsets[s + 1] - sc->set_offsets[s], PROJ_BLOCK);
+    }
+    pt.set_goff[sc->n_sets] = (int)sc->set_offsets[sc->n_sets];
+    pt.set_gblk[sc->n_sets] = gb;
+    pt.set_voff[sc->n_sets] = nvs;
+  }
   // sets, for the projection backward
   SetTab& st = t.set;
   st.ns = sc->n_sets;

@@ -35,6 +35,11 @@ struct ProjTab {
   int pair_off[MAXV + 1];
   int blk_off[MAXV + 1];      // PROJ_BLOCK-pair blocks per view, prefix
   int g_off[MAXV];            // first global Gaussian of the view's set
+  int ns;                     // sets
+  int set_goff[MAXS + 1];     // Gaussian offsets of the sets
+  int set_gblk[MAXS + 1];     // PROJ_BLOCK-Gaussian blocks of the rendered sets, prefix
+  int set_voff[MAXS + 1];     // views of each set in vset
+  int vset[MAXV];             // view ids grouped by set (every view)
 };
 
 struct SortTab {

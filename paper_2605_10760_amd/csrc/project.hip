@@ -1,15 +1,15 @@
 // Projection of (view, Gaussian) pairs, visible-pair compaction and the
 // pose-delta update.
 //
-// One thread per pair.  Each thread evaluates the key path in FP32 with no
-// fused multiply-add and a fixed operation order (it decides culling, the
-// tile rectangle and the depth key and must match an FP32 re-evaluation bit
-// for bit), then, for visible pairs, the screen-space record in FP64 rounded
-// once to FP32 (the 2D conic of an elongated splat loses digits to
-// cancellation in FP32).  Reads are coalesced AoS rows of the FP32 parameter
-// arrays; writes are one 48-byte record, one 8-byte rect and one 4-byte key
-// per pair, and one visible count per 256-pair block for the ordered
-// compaction that follows.
+// One thread per Gaussian, looping over the views of its set.  Each pair
+// evaluates the key path in FP32 with no fused multiply-add and a fixed
+// operation order (it decides culling, the tile rectangle and the depth key
+// and must match an FP32 re-evaluation bit for bit), then, for visible
+// pairs, the screen-space record in FP64 rounded once to FP32 (the 2D conic
+// of an elongated splat loses digits to cancellation in FP32).  The
+// parameters are read once per Gaussian (coalesced AoS rows); writes are one
+// 48-byte record, one 8-byte rect and one 4-byte key per pair, and one
+// visible count per 256-pair block for the ordered compaction that follows.
 #include "common.h"
 
 namespace gsr {
@@ -63,21 +63,22 @@ struct KeyResult {
 
 // The FP32 key path.  Every +, -, *, / and sqrt is one IEEE FP32 operation
 // in the order written (contraction disabled); exp and log run in FP64 on
-// the FP32 inputs and are rounded once.  Returns false when culled.
-__device__ __forceinline__ bool key_path(const float* m, const float* ls, const float* q, float o,
-                                      const float* Rc, const float* tc, float fx, float fy,
-                                      float cx, float cy, int W, int H, int TW, int TH,
-                                      int TX, int TY, float z_near, KeyResult& kr) {
+// the FP32 inputs and are rounded once.  The part that depends on the
+// Gaussian alone (3D covariance, opacity threshold) is evaluated once per
+// Gaussian; the part that depends on the view once per pair.
+struct KeyGauss {
+  float S00, S01, S02, S11, S12, S22;  // 3D covariance
+  float k2;                            // 2 ln(255 sigma)
+  bool ok;                             // unit quaternion defined, 255 sigma > 1
+};
+
+__device__ __forceinline__ KeyGauss key_gauss(const float* ls, const float* q, float o) {
 #pragma clang fp contract(off)
-  const float p0 = ((Rc[0] * m[0] + Rc[1] * m[1]) + Rc[2] * m[2]) + tc[0];
-  const float p1 = ((Rc[3] * m[0] + Rc[4] * m[1]) + Rc[5] * m[2]) + tc[1];
-  const float p2 = cam_depth32(m, Rc, tc);
-  if (!(p2 > z_near)) return false;
+  KeyGauss g;
   const float s0 = (float)exp((double)ls[0]);
   const float s1 = (float)exp((double)ls[1]);
   const float s2 = (float)exp((double)ls[2]);
   const float qn = sqrtf(((q[0] * q[0] + q[1] * q[1]) + q[2] * q[2]) + q[3] * q[3]);
-  if (!(qn > 0.f)) return false;
   const float w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
   const float xx = x * x, yy = y * y, zz = z * z;
   const float xy = x * y, xz = x * z, yz = y * z;
@@ -88,14 +89,30 @@ __device__ __forceinline__ bool key_path(const float* m, const float* ls, const 
   const float M00 = R00 * s0, M01 = R01 * s1, M02 = R02 * s2;
   const float M10 = R10 * s0, M11 = R11 * s1, M12 = R12 * s2;
   const float M20 = R20 * s0, M21 = R21 * s1, M22 = R22 * s2;
-  float S[3][3];
-  S[0][0] = (M00 * M00 + M01 * M01) + M02 * M02;
-  S[0][1] = (M00 * M10 + M01 * M11) + M02 * M12;
-  S[0][2] = (M00 * M20 + M01 * M21) + M02 * M22;
-  S[1][1] = (M10 * M10 + M11 * M11) + M12 * M12;
-  S[1][2] = (M10 * M20 + M11 * M21) + M12 * M22;
-  S[2][2] = (M20 * M20 + M21 * M21) + M22 * M22;
-  S[1][0] = S[0][1]; S[2][0] = S[0][2]; S[2][1] = S[1][2];
+  g.S00 = (M00 * M00 + M01 * M01) + M02 * M02;
+  g.S01 = (M00 * M10 + M01 * M11) + M02 * M12;
+  g.S02 = (M00 * M20 + M01 * M21) + M02 * M22;
+  g.S11 = (M10 * M10 + M11 * M11) + M12 * M12;
+  g.S12 = (M10 * M20 + M11 * M21) + M12 * M22;
+  g.S22 = (M20 * M20 + M21 * M21) + M22 * M22;
+  const float sigma = (float)(1.0 / (1.0 + exp(-(double)o)));
+  const double t = 255.0 * (double)sigma;
+  g.ok = qn > 0.f && t > 1.0;
+  g.k2 = g.ok ? (float)(2.0 * log(t)) : 0.f;
+  return g;
+}
+
+// Returns false when the pair is culled.
+__device__ __forceinline__ bool key_view(const float* m, const KeyGauss& g, const float* Rc,
+                                         const float* tc, float fx, float fy, float cx, float cy,
+                                         int W, int H, int TW, int TH, int TX, int TY,
+                                         float z_near, KeyResult& kr) {
+#pragma clang fp contract(off)
+  const float p0 = ((Rc[0] * m[0] + Rc[1] * m[1]) + Rc[2] * m[2]) + tc[0];
+  const float p1 = ((Rc[3] * m[0] + Rc[4] * m[1]) + Rc[5] * m[2]) + tc[1];
+  const float p2 = cam_depth32(m, Rc, tc);
+  if (!(p2 > z_near) || !g.ok) return false;
+  const float S[3][3] = {{g.S00, g.S01, g.S02}, {g.S01, g.S11, g.S12}, {g.S02, g.S12, g.S22}};
   float Wm[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -127,12 +144,8 @@ __device__ __forceinline__ bool key_path(const float* m, const float* ls, const 
   const float c = (T11 * j11 + T12 * j12) + 0.3f;
   const float det = a * c - b * b;
   if (!(det > 0.f)) return false;
-  const float sigma = (float)(1.0 / (1.0 + exp(-(double)o)));
-  const double t = 255.0 * (double)sigma;
-  if (!(t > 1.0)) return false;
-  const float k2 = (float)(2.0 * log(t));
-  const float ex = sqrtf(k2 * a);
-  const float ey = sqrtf(k2 * c);
+  const float ex = sqrtf(g.k2 * a);
+  const float ey = sqrtf(g.k2 * c);
   if (!(isfinite(u) && isfinite(v) && isfinite(ex) && isfinite(ey))) return false;
   const float itw = 1.0f / (float)TW, ith = 1.0f / (float)TH;
   const float fX = (float)TX, fY = (float)TY;
@@ -151,61 +164,85 @@ __device__ __forceinline__ bool key_path(const float* m, const float* ls, const 
   return true;
 }
 
+// One thread per Gaussian of a rendered set; it projects its Gaussian into
+// every view of the set in turn (views are uniform across the workgroup,
+// whose Gaussians all belong to one set).  The parameters are read once and
+// the view-independent work (3D covariance, opacity threshold, colour for
+// degree 0) is done once, instead of once per view.  Pair p of view v is
+// Gaussian p - pair_off[v] of the set, so the workgroup's 256 Gaussians are
+// the 256-pair block (blk_off[v] + its block index in the set) of each view.
 template <int SHD>
 __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, CamDev cam,
                                                         StateDev st, uint32_t* blk_cnt) {
-  const int b = xcd_remap(blockIdx.x, t.blk_off[t.nv]);
+  const int b = xcd_remap(blockIdx.x, t.set_gblk[t.ns]);
   if (b < 0) return;
-  const int v = find_seg(t.blk_off, t.nv, b);
-  const int local = (b - t.blk_off[v]) * PROJ_BLOCK + (int)threadIdx.x;
-  const int n = t.pair_off[v + 1] - t.pair_off[v];
-  bool vis = false;
-  if (local < n) {
+  const int s = find_seg(t.set_gblk, t.ns, b);
+  const int lb = b - t.set_gblk[s];
+  const int local = lb * PROJ_BLOCK + (int)threadIdx.x;
+  const bool valid = local < t.set_goff[s + 1] - t.set_goff[s];
+  const long gi = (long)t.set_goff[s] + (valid ? local : 0);
+  float m[3] = {0.f, 0.f, 0.f}, ls[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, o = 0.f;
+  if (valid) {
+    m[0] = sc.means[3 * gi]; m[1] = sc.means[3 * gi + 1]; m[2] = sc.means[3 * gi + 2];
+    ls[0] = sc.log_scales[3 * gi]; ls[1] = sc.log_scales[3 * gi + 1];
+    ls[2] = sc.log_scales[3 * gi + 2];
+    const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
+    q[0] = q4.x; q[1] = q4.y; q[2] = q4.z; q[3] = q4.w;
+    o = sc.opac[gi];
+  }
+  KeyGauss kg = key_gauss(ls, q, o);
+  kg.ok = kg.ok && valid;
+  // ---- view-independent part of the FP64 record.  Scales, rotation and
+  // opacity are formed in FP32 first: their rounding perturbs the parameters
+  // by ~1e-7 relative, while the products below, where elongated splats
+  // cancel, run in FP64.
+  double Sd[3][3];
+  float sigf = 0.f, k2f = 0.f;
+  float col[3] = {0.f, 0.f, 0.f};
+  {
+    const float sv[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+    const float qi = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    const float qw = q[0] * qi, qx = q[1] * qi, qy = q[2] * qi, qz = q[3] * qi;
+    const float R[3][3] = {{1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy)},
+                           {2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx)},
+                           {2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
+    double M[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M[i][j] = (double)R[i][j] * (double)sv[j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j) {
+        Sd[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
+        Sd[j][i] = Sd[i][j];
+      }
+    sigf = 1.f / (1.f + expf(-o));
+    // half-extents of the alpha >= 1/255 ellipse use k2f, widened by a
+    // margin far above FP32 rounding: every pixel outside that box has
+    // alpha < 1/255, so the compositing kernels may skip the splat there
+    // without changing any result
+    const float t255 = 255.f * sigf;
+    k2f = t255 > 1.f ? 2.f * logf(t255) : 0.f;
+    if (SHD == 0 && valid) {
+      col[0] = sc.colors[3 * gi]; col[1] = sc.colors[3 * gi + 1]; col[2] = sc.colors[3 * gi + 2];
+    }
+  }
+  for (int vi = t.set_voff[s]; vi < t.set_voff[s + 1]; ++vi) {
+    const int v = t.vset[vi];
     const int pair = t.pair_off[v] + local;
-    const long gi = (long)t.g_off[v] + local;
     const float* vm = cam.viewmats + 12 * v;
     const float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
     const float tc[3] = {vm[3], vm[7], vm[11]};
     const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
-    const float m[3] = {sc.means[3 * gi], sc.means[3 * gi + 1], sc.means[3 * gi + 2]};
-    // the other parameters are read only for Gaussians in front of the camera
-    float ls[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, o = 0.f;
     KeyResult kr;
-    if (cam_depth32(m, Rc, tc) > cam.z_near) {
-      ls[0] = sc.log_scales[3 * gi];
-      ls[1] = sc.log_scales[3 * gi + 1];
-      ls[2] = sc.log_scales[3 * gi + 2];
-      const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
-      q[0] = q4.x; q[1] = q4.y; q[2] = q4.z; q[3] = q4.w;
-      o = sc.opac[gi];
-      vis = key_path(m, ls, q, o, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX,
-                     t.TY, cam.z_near, kr);
-    }
-    st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
+    const bool vis = key_view(m, kg, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX,
+                              t.TY, cam.z_near, kr);
+    if (valid) st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
     if (vis) {
       st.rect[pair] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
-      // ---- screen-space record in FP64.  Scales, rotation and opacity are
-      // formed in FP32 first: their rounding perturbs the parameters by ~1e-7
-      // relative, while the products below, where elongated splats cancel,
-      // run in FP64.
-      const float sv[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
-      const float qi = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-      const float qw = q[0] * qi, qx = q[1] * qi, qy = q[2] * qi, qz = q[3] * qi;
-      const float R[3][3] = {{1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy)},
-                             {2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx)},
-                             {2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
-      double M[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) M[i][j] = (double)R[i][j] * (double)sv[j];
-      double S[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          S[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
       double Wd[3][3], V[3][3];
       for (int i = 0; i < 3; ++i)
         for (int k = 0; k < 3; ++k)
-          Wd[i][k] = (double)Rc[3 * i] * S[0][k] + (double)Rc[3 * i + 1] * S[1][k] +
-                     (double)Rc[3 * i + 2] * S[2][k];
+          Wd[i][k] = (double)Rc[3 * i] * Sd[0][k] + (double)Rc[3 * i + 1] * Sd[1][k] +
+                     (double)Rc[3 * i + 2] * Sd[2][k];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
           V[i][j] = Wd[i][0] * Rc[3 * j] + Wd[i][1] * Rc[3 * j + 1] + Wd[i][2] * Rc[3 * j + 2];
@@ -228,11 +265,8 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
       const double c = T11 * j11 + T12 * j12 + 0.3;
       const double det = a * c - bb * bb;
       const double u = fx * rx + (double)in.z, vv = fy * ry + (double)in.w;
-      const float sigf = 1.f / (1.f + expf(-o));
-      float col[3];
-      if (SHD == 0) {
-        col[0] = sc.colors[3 * gi]; col[1] = sc.colors[3 * gi + 1]; col[2] = sc.colors[3 * gi + 2];
-      } else {
+      float cv[3] = {col[0], col[1], col[2]};
+      if (SHD > 0) {
         // camera centre o_cam = -Rc^T tc; direction d = (mu - o_cam)/|mu - o_cam|
         const float ox = -(Rc[0] * tc[0] + Rc[3] * tc[1] + Rc[6] * tc[2]);
         const float oy = -(Rc[1] * tc[0] + Rc[4] * tc[1] + Rc[7] * tc[2]);
@@ -249,16 +283,10 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
         for (int i = 0; i < NB; ++i) {
           r += Y[i] * k[3 * i]; g += Y[i] * k[3 * i + 1]; bl += Y[i] * k[3 * i + 2];
         }
-        col[0] = fmaxf(r, 0.f); col[1] = fmaxf(g, 0.f); col[2] = fmaxf(bl, 0.f);
+        cv[0] = fmaxf(r, 0.f); cv[1] = fmaxf(g, 0.f); cv[2] = fmaxf(bl, 0.f);
       }
-      // half-extents of the alpha >= 1/255 ellipse, widened by a margin far
-      // above FP32 rounding: every pixel outside this box has alpha < 1/255,
-      // so the compositing kernels may skip the splat there without changing
-      // any result
-      const float t255 = 255.f * sigf;
-      const float k2 = t255 > 1.f ? 2.f * logf(t255) : 0.f;
-      const float exr = sqrtf(k2 * (float)a) * (1.f + 1e-4f) + 1e-2f;
-      const float eyr = sqrtf(k2 * (float)c) * (1.f + 1e-4f) + 1e-2f;
+      const float exr = sqrtf(k2f * (float)a) * (1.f + 1e-4f) + 1e-2f;
+      const float eyr = sqrtf(k2f * (float)c) * (1.f + 1e-4f) + 1e-2f;
       float4* rp = st.rec + 3 * (long)pair;
       // conic (A, B, C) = (c, -b, a)/det, stored pre-scaled so that the
       // exponent in base 2 is A' dx^2 + B' dx dy + C' dy^2:
@@ -267,11 +295,11 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
       const double h = L2E / det;
       rp[0] = make_float4((float)u, (float)vv, (float)(-0.5 * h * c), (float)(h * bb));
       rp[1] = make_float4((float)(-0.5 * h * a), sigf, (float)p[2], exr);
-      rp[2] = make_float4(col[0], col[1], col[2], eyr);
+      rp[2] = make_float4(cv[0], cv[1], cv[2], eyr);
     }
+    const int cnt = __syncthreads_count(vis);
+    if (threadIdx.x == 0) blk_cnt[t.blk_off[v] + lb] = (uint32_t)cnt;
   }
-  const int cnt = __syncthreads_count(vis);
-  if (threadIdx.x == 0) blk_cnt[b] = (uint32_t)cnt;
 }
 
 // Exclusive scan of the per-block visible counts (one workgroup) and the
@@ -382,7 +410,7 @@ __global__ void k_pose_delta(const float* vin, const float* delta, float* vout, 
 
 hipError_t launch_project(const ProjTab& t, const SceneDev& sc, const CamDev& cam, StateDev st,
                           uint32_t* blk_cnt, hipStream_t s) {
-  const int nb = t.blk_off[t.nv];
+  const int nb = t.set_gblk[t.ns];
   if (nb == 0) return hipSuccess;
   switch (sc.sh_degree) {
     case 0: hipLaunchKernelGGL(k_project<0>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
