@@ -53,18 +53,20 @@ __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcp
 // dy of the ellipse's leftmost / rightmost points (the right boundary
 // x(dy) = u + (-b dy + sqrt(4ac - b^2) sqrt(ey^2 - dy^2)) / 2a is concave,
 // the left one convex), and the comparison carries a further margin for
-// the FP32 arithmetic.  NaN inputs give true.
+// the FP32 arithmetic.  Square roots and reciprocals are the hardware
+// approximations (about 1 ulp, no correctly-rounded expansion): their error
+// is orders of magnitude inside that margin.  NaN inputs give true.
 __device__ __forceinline__ bool reaches(const float4& r0, float Cs, float ex, float ey, float x0,
                                         float x1, float y0, float y1) {
   const float a = -r0.z, b = -r0.w, c = -Cs;
   const float lo = fmaxf(y0 - r0.y, -ey), hi = fminf(y1 - r0.y, ey);
   if (lo > hi) return false;
-  const float sd = sqrtf(fmaxf(4.f * a * c - b * b, 0.f));
-  const float ys = b * ey / (2.f * sqrtf(a * c));
+  const float sd = __builtin_amdgcn_sqrtf(fmaxf(4.f * a * c - b * b, 0.f));
+  const float ys = 0.5f * b * ey * __builtin_amdgcn_rsqf(a * c);
   const float yr = fminf(fmaxf(-ys, lo), hi), yl = fminf(fmaxf(ys, lo), hi);
-  const float wr = sd * sqrtf(fmaxf((ey - yr) * (ey + yr), 0.f));
-  const float wl = sd * sqrtf(fmaxf((ey - yl) * (ey + yl), 0.f));
-  const float h = 0.5f / a;
+  const float wr = sd * __builtin_amdgcn_sqrtf(fmaxf((ey - yr) * (ey + yr), 0.f));
+  const float wl = sd * __builtin_amdgcn_sqrtf(fmaxf((ey - yl) * (ey + yl), 0.f));
+  const float h = 0.5f * __builtin_amdgcn_rcpf(a);
   const float xr = r0.x + (wr - b * yr) * h, xl = r0.x - (wl + b * yl) * h;
   const float m = 0.05f + 1e-3f * ex;
   return !(xr + m < x0 || xl - m > x1);
@@ -83,7 +85,12 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
   const int v = g / T, tl = g - v * T;
   const int ty = tl / TX, tx = tl - ty * TX;
   const int tid = threadIdx.x;
-  const int px = tx * TW + (tid % TW), py = ty * TH + (tid / TW);
+  // 16x16 tiles: wave w shades the 8x8 quadrant (w & 1, w >> 1), whose
+  // reach box is tighter around round footprints than a 16x4 strip's; other
+  // shapes: wave w shades tile rows [w RW, (w + 1) RW)
+  constexpr bool QUAD = TW == 16 && TH == 16;
+  const int px = QUAD ? tx * TW + ((tid >> 6) & 1) * 8 + (tid & 7) : tx * TW + (tid % TW);
+  const int py = QUAD ? ty * TH + (tid >> 7) * 8 + ((tid >> 3) & 7) : ty * TH + (tid / TW);
   const bool inside = px < W && py < H;
   uint2 rg = st.ranges[g];
   if (st.hdr->overflow) rg = make_uint2(0u, 0u);
@@ -91,7 +98,7 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
   float Tc = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dz = 0.f;
   uint32_t last = 0, stopn = 0;
   bool done = !inside;
-  // wave w shades tile rows [w RW, (w + 1) RW); pixel-centre box of the tile
+  // pixel-centre box of the tile; rows per wave for the strip layout
   constexpr int NWV = NT / 64, RW = 64 / TW;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const float x0c = (float)(tx * TW) + 0.5f, x1c = x0c + (float)(TW - 1);
@@ -106,9 +113,15 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
       uint32_t m = 0;
 #pragma unroll
       for (int w = 0; w < NWV; ++w)
-        m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c, x1c, y0c + (float)(w * RW),
-                               y0c + (float)(w * RW + RW - 1))
-             << w;
+        if (QUAD)
+          m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c + (float)((w & 1) * 8),
+                                 x0c + (float)((w & 1) * 8 + 7), y0c + (float)((w >> 1) * 8),
+                                 y0c + (float)((w >> 1) * 8 + 7))
+               << w;
+        else
+          m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c, x1c, y0c + (float)(w * RW),
+                                 y0c + (float)(w * RW + RW - 1))
+               << w;
       s0[tid] = r0;
       s1[tid] = r1;
       s2[tid] = r2;
