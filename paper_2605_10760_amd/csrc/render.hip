@@ -40,8 +40,9 @@ __device__ __forceinline__ float splat_power(const float4& a, const float4& b, f
 __device__ __forceinline__ float exp2_fast(float p) { return __builtin_amdgcn_exp2f(p); }
 
 // 1/x by the hardware reciprocal (about 1 ulp); the backward's transmittance
-// recovery T_j = T_{j+1} / (1 - alpha_j) uses it instead of an IEEE division
-// (1 - alpha_j >= 0.01, so x is far from denormal).
+// recovery T_j = T_{j+1} / (1 - alpha_j) and its opacity gradient (a division
+// by sigma > 1/255) use it instead of an IEEE division (x is far from
+// denormal in both).
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Whether the splat's alpha >= 1/255 region can reach a pixel centre of the
@@ -410,7 +411,8 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
           out = idx == 1 ? LN2 * (a.w * m0 + 2.f * b.x * m1) : out;
           out = (idx == 2 || idx == 4) ? -0.5f * tot : out;
           out = idx == 3 ? -tot : out;
-          out = idx == 5 ? tot / b.y : out;
+          // dL/dsigma = (sum of gp) / sigma, by the hardware reciprocal
+          out = idx == 5 ? tot * rcp_fast(b.y) : out;
           if (idx >= 0 && out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
         }
       }

@@ -70,13 +70,14 @@ def test_prune_matches_oracle():
     assert 0 < idx.shape[0] < o.shape[0]
 
 
-def test_ssim_grad_matches_oracle():
-    announce("refine ssim")
+@pytest.mark.parametrize("V,H,W", [(2, 37, 45), (2, 150, 70)])
+def test_ssim_grad_matches_oracle(V, H, W):
+    """Ragged tiles in both directions (16 x 64 output tiles, 5-pixel halo)."""
+    announce(f"refine ssim {V}x{H}x{W}")
     import torch
     from oracle.ssim import ssim, ssim_term_grad
     from paper_2605_10760_amd import ssim_grad
     rng = np.random.default_rng(9)
-    V, H, W = 2, 37, 45  # ragged tiles
     c = rng.random((V, 3, H, W)).astype(np.float32)
     tgt = np.clip(c + 0.1 * rng.normal(size=c.shape), 0, 1).astype(np.float32)
     ex = np.array([[0.15, 0.02], [-0.1, -0.03]], np.float32)
