@@ -134,3 +134,36 @@ def test_seed_full_size_sampled():
         np.testing.assert_allclose(g["means"][q], r["means"][k], rtol=0, atol=1e-5)
         np.testing.assert_allclose(g["log_scales"][q], r["log_scales"][k], rtol=0, atol=2e-5)
         np.testing.assert_array_equal(g["colors"][q], col[:, j, i])
+
+
+def test_seed_degenerate_inputs():
+    """No valid depth seeds nothing; a stride beyond the image keeps only
+    pixel (0, 0); a capacity below the count reports an overflow."""
+    announce("mapping seed degenerate")
+    import ctypes as C
+    import torch
+    from paper_2605_10760_amd import _lib, seed as gpu_seed
+    H, W = 9, 11
+    col = np.zeros((3, H, W), np.float32)
+    vm = np.concatenate([np.eye(3), np.zeros((3, 1))], 1).astype(np.float32)
+    intr = np.array([10.0, 10.0, 5.5, 4.5], np.float32)
+    got = gpu_seed(_t(np.zeros((H, W), np.float32)), _t(col), _t(vm), _t(intr))
+    assert got["means"].shape[0] == 0
+    d = np.full((H, W), 2.0, np.float32)
+    got = gpu_seed(_t(d), _t(col), _t(vm), _t(intr), stride=50)
+    ref = seed(d, col, vm, intr, stride=50)
+    assert got["means"].shape[0] == ref["means"].shape[0] == 1
+    np.testing.assert_allclose(got["log_scales"].cpu().numpy(), ref["log_scales"], atol=2e-6)
+    lib = _lib.load()
+    dt, ct, vt, it = _t(d), _t(col), _t(vm), _t(intr)
+    out = [torch.empty((4, k), device="cuda") for k in (3, 3, 4)]
+    op, cl = torch.empty(4, device="cuda"), torch.empty((4, 3), device="cuda")
+    n = C.c_int64()
+    st = lib.gsr_seed(dt.data_ptr(), ct.data_ptr(), vt.data_ptr(), it.data_ptr(), W, H, 1, 0.0, 4,
+                      out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), op.data_ptr(),
+                      cl.data_ptr(), C.byref(n), None)
+    torch.cuda.synchronize()
+    assert st == _lib.GSR_E_OVERFLOW and n.value == H * W
+    # the first four rows are still written
+    ref = seed(d, col, vm, intr)
+    np.testing.assert_allclose(out[0].cpu().numpy(), ref["means"][:4], atol=1e-6)
