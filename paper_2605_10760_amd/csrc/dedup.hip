@@ -8,7 +8,8 @@
 //                box [mu - k s, mu + k s];
 //   k_dd_free    one thread per keyframe pixel walks the voxels of the
 //                segment from the camera centre to the back-projected depth
-//                (t in [0, 1)) and inserts them;
+//                (t in [0, 1)) and inserts them, through a workgroup-local
+//                LDS set that drops the repeats of neighbouring rays;
 //   k_dd_probe   one thread per borrowed Gaussian looks up the voxel of its
 //                mean: kept only when absent.
 // Voxel indices are floor(x / v) in FP64 from the FP32 inputs; segment
@@ -77,6 +78,32 @@ __device__ void dd_insert(const DedupTable& T, unsigned long long key, unsigned 
   atomicOr(&T.counters[0], 1u);
 }
 
+// Workgroup-local filter in front of dd_insert: the rays of one workgroup
+// (neighbouring pixels of one keyframe) cross mostly the same voxels, so a
+// key goes to the global set only from the thread that first places it in
+// this LDS set (bounded probing; a key that finds no LDS slot goes straight
+// to the global set).  Every key still reaches the global set, once per
+// workgroup at most.
+constexpr int DD_LSLOTS = 4096;
+constexpr int DD_LPROBE = 8;
+__device__ void dd_insert_local(const DedupTable& T, unsigned long long* lk,
+                                unsigned long long key, unsigned int flag) {
+  unsigned int h = (unsigned int)(dd_mix(key) >> 40) & (DD_LSLOTS - 1);
+  for (int probe = 0; probe < DD_LPROBE; ++probe) {
+    unsigned long long cur = lk[h];
+    if (cur == DD_EMPTY) {
+      cur = atomicCAS(&lk[h], DD_EMPTY, key);
+      if (cur == DD_EMPTY) {
+        dd_insert(T, key, flag);
+        return;
+      }
+    }
+    if (cur == key) return;
+    h = (h + 1) & (DD_LSLOTS - 1);
+  }
+  dd_insert(T, key, flag);
+}
+
 __global__ __launch_bounds__(256) void k_dd_clear(DedupTable T) {
   const unsigned long long i = (unsigned long long)blockIdx.x * 256 + threadIdx.x;
   if (i <= T.mask) {
@@ -120,6 +147,9 @@ __global__ __launch_bounds__(256) void k_dd_free(DedupTable T, const float* dept
                                                  const float* viewmats, const float* intr,
                                                  int W, int H, long long npix, double v) {
 #pragma clang fp contract(off)
+  __shared__ unsigned long long lk[DD_LSLOTS];
+  for (int k = threadIdx.x; k < DD_LSLOTS; k += 256) lk[k] = DD_EMPTY;
+  __syncthreads();  // the only barrier: threads may leave after it
   const long long g = (long long)blockIdx.x * 256 + threadIdx.x;
   if (g >= npix) return;
   const int kf = (int)(g / ((long long)W * H));
@@ -158,7 +188,7 @@ __global__ __launch_bounds__(256) void k_dd_free(DedupTable T, const float* dept
     atomicOr(&T.counters[0], 2u);
     return;
   }
-  dd_insert(T, dd_pack(cur[0], cur[1], cur[2]), 2u);
+  dd_insert_local(T, lk, dd_pack(cur[0], cur[1], cur[2]), 2u);
   // next plane index per axis (the walk stops at the end voxel's planes)
   long long nxt[3];
   int step[3];
@@ -181,7 +211,7 @@ __global__ __launch_bounds__(256) void k_dd_free(DedupTable T, const float* dept
     if (best < 0) break;
     cur[best] += step[best];
     nxt[best] += step[best];
-    dd_insert(T, dd_pack(cur[0], cur[1], cur[2]), 2u);
+    dd_insert_local(T, lk, dd_pack(cur[0], cur[1], cur[2]), 2u);
   }
 }
 
