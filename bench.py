@@ -227,7 +227,7 @@ def time_cpu_baseline(wl, seconds):
                        f"({time.perf_counter() - t_start:.1f} s of CPU work, FP64 NumPy, 1 thread)")
 
 
-def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, reps=10):
+def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, rast=None, reps=10):
     """HBM-bound kernels beyond the rasterizer (Sim(3) correction, pose lift,
     refinement loss gradients, pruning) on the same batch: average time per
     call from torch events on the stream they launch on, algorithmic bytes,
@@ -321,6 +321,25 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, reps=10):
     res["prune"] = dict(ms=round(ms, 4), kept=kept, of=N,
                         algorithmic_GBps=round(nbytes / (ms * 1e-3) / 1e9, 1),
                         note="includes the host synchronisation for the pruned set offsets")
+    if rast is not None:
+        # one iteration of the joint refinement (Eq. (refine_loss)) of every
+        # view: forward, L1 + SSIM + normal gradients on the exposure-
+        # compensated render, backward, Adam over Gaussians, pose deltas and
+        # exposure (eager; it moves the scene, so it runs last)
+        from paper_2605_10760_amd import REFINE_WEIGHTS, Optimizer, Rates
+        opt = Optimizer(rast, sc, vw, tc, td, prior, REFINE_WEIGHTS, Rates().scaled(0.5),
+                        pose=True, exposure=True)
+        opt.step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            opt.step()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res["refine_step"] = dict(ms=round(ms, 3), views=V, views_per_s=round(V / (ms * 1e-3), 1),
+                                  note="eager, one refinement iteration of all views")
     return res
 
 
@@ -524,7 +543,7 @@ def main():
         roof["algorithmic_bytes"] = int(alg_bytes.get(dom, 0))
     step_bytes = sum(alg_bytes.values())
 
-    extras = measure_extras(torch, sc, vw, step.out[0], step.out[1], tc, td)
+    extras = measure_extras(torch, sc, vw, step.out[0], step.out[1], tc, td, rast=rast)
 
     cpu = None
     if not args.no_cpu:
