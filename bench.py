@@ -103,6 +103,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=WORKLOADS, default="multi-agent")
     ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the tile shape and binning chunk with gsr_autotune first")
     ap.add_argument("--no-graph", action="store_true", help="time the batched step eagerly")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -380,7 +382,13 @@ def main():
                           else np.zeros((V, H, W), np.float32)).cuda()
     so = sc_np.set_offsets
     P = int(sum(so[s + 1] - so[s] for s in vw_np.view_set))
-    rast = Rasterizer(W, H, P, V, tile=tile)
+    chunk, tuned = 0, None
+    if args.autotune:
+        from paper_2605_10760_amd import autotune
+        tile, tune_ms, chunk = autotune(sc, vw)
+        tuned = dict(ms=round(tune_ms, 3), tile=f"{tile[0]}x{tile[1]}", chunk=chunk)
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
+    rast = Rasterizer(W, H, P, V, tile=tile, chunk=chunk)
     rast.fit_capacity(sc, vw)
 
     # ---- counts for the metric (untimed forward)
@@ -567,6 +575,7 @@ def main():
         "config": {"workload": wl.name, "views": V, "fwd_bwd_views": n_bwd, "width": W, "height": H,
                    "gaussians": int(sc_np.n), "sets": int(sc_np.n_sets),
                    "sh_degree": int(sc_np.sh_degree), "tile": f"{tile[0]}x{tile[1]}",
+                   "binning_chunk": int(rast.desc.chunk), "autotuned": tuned is not None,
                    "form": "batched, hip graph replay" if graph is not None else "batched, eager"},
         "evals_per_s": round((evals_fwd + evals_bwd) / dt, 1),
         "evals": {"forward": evals_fwd, "backward": evals_bwd},

@@ -385,9 +385,12 @@ gsr_status gsr_seed(const float* depth, const float* color, const float* viewmat
                     float* log_scales_out, float* quats_out, float* opacity_out,
                     float* colors_out, int64_t* n_out, void* stream);
 
-/* Time forward+backward of the given call for each candidate tile shape and
- * report the fastest (tile_w, tile_h) in `best` (other fields copied from
- * `base`).  Synchronises; allocates its own temporary context. */
+/* Time forward+backward of the given call for each candidate tile shape
+ * (with the automatic binning chunk), then for the fastest shape each
+ * binning chunk of 64, 128 and 256 pairs, and report the fastest plan in
+ * `best` (tile_w, tile_h, chunk; other fields copied from `base`, the
+ * instance capacity raised if a candidate overflowed).  Synchronises;
+ * allocates its own temporary contexts and buffers. */
 gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* scene,
                         const gsr_views* views, const gsr_settings* settings,
                         gsr_plan_desc* best, float* best_ms, void* stream);

@@ -846,7 +846,11 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
                         float* best_ms, void* stream) {
   if (!base || !sc || !vw || !best || !best_ms) return GSR_E_INVALID_ARG;
   if (check_plan(nullptr, base) != GSR_OK) return GSR_E_INVALID_ARG;
-  static const int cand[][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {32, 8}, {32, 16}, {16, 32}};
+  // first every tile shape (binning chunk automatic), then the binning chunk
+  // (depth-sorted pairs per wave of the row binning) for the best shape
+  static const int tiles[][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {32, 8}, {32, 16}, {16, 32}};
+  static const int chunks[] = {64, 128, 256};
+  constexpr int NT_ = sizeof(tiles) / sizeof(tiles[0]), NC_ = sizeof(chunks) / sizeof(chunks[0]);
   hipStream_t st = (hipStream_t)stream;
   DeviceGuard g(device);
   const int V = vw->n_views, W = vw->width, H = vw->height;
@@ -875,10 +879,17 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  for (auto& c : cand) {
+  for (int ci = 0; ci < NT_ + NC_; ++ci) {
     gsr_plan_desc p = *base;
-    p.tile_w = c[0];
-    p.tile_h = c[1];
+    if (ci < NT_) {
+      p.tile_w = tiles[ci][0];
+      p.tile_h = tiles[ci][1];
+      p.chunk = 0;
+    } else {
+      if (result != GSR_OK) break;  // no tile shape ran
+      p = best_p;
+      p.chunk = chunks[ci - NT_];
+    }
     if (check_plan(nullptr, &p) != GSR_OK) continue;
     gsr_ctx* ctx = nullptr;
     if (gsr_create(&ctx, device) != GSR_OK) { result = GSR_E_DEVICE; break; }

@@ -268,8 +268,9 @@ class Rasterizer:
 def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = None,
              max_instances: int | None = None, z_near=0.2, device: int | None = None,
              stream=None):
-    """Time forward+backward of this call for every supported tile shape
-    (native, in libgsr) and return (best (tile_w, tile_h), its ms)."""
+    """Time forward+backward of this call for every supported tile shape,
+    then the binning chunk for the best shape (native, in libgsr), and
+    return (best (tile_w, tile_h), its ms, best chunk)."""
     lib = L.load()
     dev = torch.cuda.current_device() if device is None else int(device)
     P = pairs_of(scene, views) if max_pairs is None else int(max_pairs)
@@ -284,7 +285,7 @@ def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = No
                               C.byref(best), C.byref(ms), _stream(stream))
     if status != L.GSR_OK:
         raise L.GsrError(status, "gsr_autotune failed")
-    return (best.tile_w, best.tile_h), float(ms.value)
+    return (best.tile_w, best.tile_h), float(ms.value), int(best.chunk)
 
 
 def apply_pose_delta(viewmats: torch.Tensor, delta: torch.Tensor, out: torch.Tensor | None = None,

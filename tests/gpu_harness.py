@@ -35,12 +35,12 @@ def make_rasterizer(scene, views, tile=(16, 16), max_instances=None, chunk=0):
 
 
 def gpu_forward(scene, views, tile=(16, 16), z_near=0.2, bg=(0.0, 0.0, 0.0), export=True,
-                rast=None):
+                rast=None, chunk=0):
     """Forward on the GPU; returns dict of numpy outputs (+ binning export)."""
     import torch
     st_, vt = to_gpu(scene, views)
     if rast is None:
-        rast, P = make_rasterizer(scene, views, tile)
+        rast, P = make_rasterizer(scene, views, tile, chunk=chunk)
     else:
         P = int(sum(scene.set_offsets[s + 1] - scene.set_offsets[s] for s in views.view_set))
     c, d, a, state, ne = rast.forward(st_, vt, z_near=z_near, bg=bg, n_eval=True)

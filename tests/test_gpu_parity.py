@@ -507,10 +507,10 @@ def test_profile_stages_and_autotune():
     ms = r.stage_ms()
     r.profile(False)
     assert all(v > 0 for v in ms.values()), ms
-    tile, t_ms = autotune(g["scene_t"], g["views_t"])
+    tile, t_ms, chunk = autotune(g["scene_t"], g["views_t"])
     assert tile in [(16, 16), (16, 8), (8, 16), (8, 8), (32, 8), (32, 16), (16, 32)]
-    assert t_ms > 0
-    g2 = gpu_forward(scene, views, tile=tile, export=False)
+    assert t_ms > 0 and chunk in (0, 64, 128, 256)
+    g2 = gpu_forward(scene, views, tile=tile, chunk=chunk, export=False)
     np.testing.assert_array_equal(g2["color"], g["color"])
 
 
