@@ -221,7 +221,7 @@ gsr_status gsr_debug_export(gsr_ctx* ctx, const void* state, int32_t n_views,
 gsr_status gsr_apply_pose_delta(const float* viewmats_in, const float* delta,
                                 float* viewmats_out, int32_t n_views, void* stream);
 
-/* Sim(3) correction of Gaussian sets (Sec. III-D, Eq. (gauss_update)).  The
+/* Sim(3) correction of Gaussian sets (Sec. III-C, Eq. (gauss_update)).  The
  * Gaussians [set_offsets[k], set_offsets[k+1]) of set k move by
  * sims[k] = (s, qw, qx, qy, qz, tx, ty, tz) (s > 0; the quaternion is
  * normalised here): means -> s R means + t, log_scales -> log_scales + ln s,
@@ -248,7 +248,7 @@ gsr_status gsr_sim3_gaussians(const float* means_in, const float* log_scales_in,
 gsr_status gsr_sim3_views(const float* viewmats_in, const float* sims, const int32_t* view_set,
                           int32_t n_views, int32_t n_sets, float* viewmats_out, void* stream);
 
-/* Gradient of the L1 terms of the refinement loss (Sec. III-D, Eq.
+/* Gradient of the L1 terms of the refinement loss (Sec. III-C, Eq.
  * (refine_loss)) on the exposure-compensated render I~ = exp(a_v) I^ + b_v:
  *   L = w_color mean|I~ - I| + w_depth mean|D^ - D|
  * (means over every channel and pixel of the n_views views; the subgradient
@@ -270,7 +270,7 @@ gsr_status gsr_l1_loss_grad(const float* color, const float* depth, const float*
 gsr_status gsr_ssim_workspace_bytes(int32_t n_views, int32_t width, int32_t height,
                                     size_t* out_bytes);
 
-/* SSIM term of the refinement loss (Sec. III-D, Eq. (refine_loss)),
+/* SSIM term of the refinement loss (Sec. III-C, Eq. (refine_loss)),
  * L = weight (1 - mean SSIM(I~, I)) with I~ = exp(a_v) I^ + b_v (weight = 0.2
  * in the paper).  SSIM per colour channel under an 11 x 11 Gaussian window
  * (sigma 1.5, zero outside the image), C1 = 0.01^2, C2 = 0.03^2, the mean
@@ -289,7 +289,7 @@ gsr_status gsr_ssim_grad(const float* color, const float* target_color, const fl
                          void* workspace, float* d_color, float* d_exposure, float* ssim_out,
                          void* stream);
 
-/* Occupancy-aware deduplication of borrowed Gaussians (Sec. III-D, Eqs.
+/* Occupancy-aware deduplication of borrowed Gaussians (Sec. III-C, Eqs.
  * (envelope), (free_carve), (dedup)).  With voxel index floor(x / voxel)
  * per axis (FP64 from the FP32 inputs): occupied voxels are every voxel
  * meeting a target Gaussian's box [mu - k_env s, mu + k_env s],
@@ -323,7 +323,7 @@ gsr_status gsr_dedup(const gsr_dedup_params* params, const float* tgt_means,
                      int32_t width, int32_t height, const float* src_means, int64_t n_src,
                      uint8_t* keep, void* workspace, int64_t* n_voxels, void* stream);
 
-/* Opacity pruning of the refinement (Sec. III-D): keeps the Gaussians with
+/* Opacity pruning of the refinement (Sec. III-C): keeps the Gaussians with
  * sigmoid(opacity_logit) >= min_opacity (0.005 in the paper), in their
  * order, set by set.  `scene` gives the device input arrays and the HOST
  * set_offsets (n = set_offsets[n_sets] Gaussians; colors rows of 3 floats,

@@ -1,7 +1,7 @@
 """Occupancy-aware deduplication of borrowed Gaussians (test infrastructure
 only).
 
-Sec. III-D: with voxel index kappa(x) = floor(x / v) (per axis, voxel size
+Sec. III-C: with voxel index kappa(x) = floor(x / v) (per axis, voxel size
 v), the target map's occupied voxels are every voxel that meets the box
 [mu_i - k s_i, mu_i + k s_i] of a target Gaussian, Eq. (envelope); the free
 voxels are every voxel met by the segment from keyframe k's camera centre c_k

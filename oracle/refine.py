@@ -2,7 +2,7 @@
 exposure-compensated render, the gradient of the L1 terms of the refinement
 loss, and opacity pruning.
 
-Sec. III-D: every keyframe k carries a log-gain and a bias (a_k, b_k), and
+Sec. III-C: every keyframe k carries a log-gain and a bias (a_k, b_k), and
 the refinement compares the exposure-compensated render
 I~ = exp(a_k) I^ + b_k (the same scalars on every colour channel) with the
 image, Eq. (refine_loss):  alpha' L1(I~, I) + lambda (1 - SSIM(I~, I))

@@ -1,8 +1,8 @@
 """Sim(3) correction of a Gaussian submap and the lift of its keyframe poses
 into the global frame (test infrastructure only).
 
-After pose-graph convergence each submap carries a similarity C = (s, R, t)
-(Sec. III-D).  Eq. (gauss_update) gives its action on a Gaussian: the mean
+Once the pose graph has converged, every submap has a similarity correction
+C = (s, R, t) (Sec. III-C).  Eq. (gauss_update) gives its action on a Gaussian: the mean
 maps to s R mu + t, the covariance to s^2 R Sigma R^T and the scale vector to
 s times itself, with opacity and colour unchanged.  With the factorisation
 Sigma = Rg diag(sg)^2 Rg^T this is: log-scales + ln s, and the Gaussian's

@@ -1,7 +1,7 @@
 """Structural-similarity term of the refinement loss and its gradient (test
 infrastructure only).
 
-Sec. III-D, Eq. (refine_loss) adds lambda (1 - SSIM(I~, I)), lambda = 0.2, on
+Sec. III-C, Eq. (refine_loss) adds lambda (1 - SSIM(I~, I)), lambda = 0.2, on
 the exposure-compensated render I~ = exp(a_k) I^ + b_k.  The paper does not
 spell SSIM out; the reading here is the usual one (Wang et al. 2004, as used
 by 3DGS): per colour channel, local statistics under an 11 x 11 Gaussian

@@ -1,4 +1,4 @@
-// Occupancy-aware deduplication of borrowed Gaussians (Sec. III-D, Eqs.
+// Occupancy-aware deduplication of borrowed Gaussians (Sec. III-C, Eqs.
 // (envelope), (free_carve), (dedup)).
 //
 // One open-addressing hash set of 64-bit voxel keys (21 bits per axis,

@@ -1,4 +1,4 @@
-// Refinement extras of the fused map (Sec. III-D, Eq. (refine_loss)): the
+// Refinement extras of the fused map (Sec. III-C, Eq. (refine_loss)): the
 // gradient of the L1 terms on the exposure-compensated render
 // I~ = exp(a_k) I^ + b_k, and opacity pruning.
 //

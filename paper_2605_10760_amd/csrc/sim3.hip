@@ -1,5 +1,5 @@
 // Sim(3) correction of Gaussian sets and the lift of keyframe poses into the
-// global frame (Sec. III-D, Eq. (gauss_update) and Eq. (mapgba_lift)).
+// global frame (Sec. III-C, Eq. (gauss_update); Sec. III-B, Eq. (mapgba_lift)).
 //
 // A similarity is stored as 8 floats (s, qw, qx, qy, qz, tx, ty, tz).  Each
 // Gaussian of set k moves by sims[k]: mean -> s R mean + t, log-scales +

@@ -1,4 +1,4 @@
-// SSIM term of the refinement loss (Sec. III-D, Eq. (refine_loss)) on the
+// SSIM term of the refinement loss (Sec. III-C, Eq. (refine_loss)) on the
 // exposure-compensated render I~ = exp(a_v) I^ + b_v, and its gradient.
 //
 // Statistics under an 11 x 11 Gaussian window (sigma 1.5, zero outside the

@@ -5,7 +5,7 @@ torch supplies memory, streams and the fused Adam update):
 * mapping (Sec. III-A, Eq. (map_loss)):
   alpha L1(I^, I) + beta L1(D^, D) + lambda_n L_normal + lambda_s L_iso,
   alpha = 0.95, beta = 0.25, lambda_n = 1e-2, lambda_s = 10;
-* joint photometric refinement of the fused map (Sec. III-D,
+* joint photometric refinement of the fused map (Sec. III-C,
   Eq. (refine_loss)): alpha' L1(I~, I) + lambda (1 - SSIM(I~, I))
   + beta L1(D^, D-bar) + lambda_n' L_normal on the exposure-compensated
   render I~ = exp(a_k) I^ + b_k, with each keyframe's pose delta and
@@ -161,7 +161,7 @@ def refine(rast: Rasterizer, scene: SceneTensors, views: ViewTensors,
            target_color: torch.Tensor, target_depth: torch.Tensor | None = None,
            normal_prior: torch.Tensor | None = None, iters: int = 2000,
            rates: Rates = Rates(), min_opacity: float = 0.005):
-    """Joint photometric refinement of a fused map (Sec. III-D): `iters`
+    """Joint photometric refinement of a fused map (Sec. III-C): `iters`
     steps of Eq. (refine_loss) at half the mapping rates over the Gaussians,
     the pose deltas and the exposure, then opacity pruning.  Returns (pruned
     scene, refined view matrices, exposure [V,2])."""

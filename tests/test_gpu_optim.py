@@ -1,5 +1,5 @@
 """GPU checks of the optimisation drivers (Sec. III-A Eq. (map_loss),
-Sec. III-D Eq. (refine_loss)): one step's gradients against the oracle's
+Sec. III-C Eq. (refine_loss)): one step's gradients against the oracle's
 chain (render, loss-term gradients, render backward), and convergence of the
 exposure and pose parameters on targets rendered at known values."""
 import numpy as np

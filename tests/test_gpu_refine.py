@@ -1,4 +1,4 @@
-"""GPU parity of the refinement extras (Sec. III-D, Eq. (refine_loss)):
+"""GPU parity of the refinement extras (Sec. III-C, Eq. (refine_loss)):
 exposure-compensated L1 gradient and opacity pruning, through the C ABI,
 against the oracle."""
 import numpy as np

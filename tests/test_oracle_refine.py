@@ -1,4 +1,4 @@
-"""Pins of the oracle's refinement extras (Sec. III-D, Eq. (refine_loss)):
+"""Pins of the oracle's refinement extras (Sec. III-C, Eq. (refine_loss)):
 finite differences of the exposure-compensated L1 loss, the reduction to the
 plain L1 gradient, and opacity pruning against a direct recount."""
 import numpy as np
