@@ -101,3 +101,89 @@ def pixel_grid(x0, y0, x1, y1):
     yy, xx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
     xx, yy = xx.ravel(), yy.ravel()
     return xx, yy, xx + 0.5, yy + 0.5
+
+
+def composite_branches(x, y, rec, order, bg, band_alpha=AMBIG_ALPHA, band_t=AMBIG_T,
+                       max_branches=64):
+    """Every outcome of one pixel (sample point x, y) that an evaluation in
+    another precision could legitimately reach.
+
+    The walk is the one of composite(), entry by entry.  A decision whose FP64
+    operand lies within the relative band of its threshold (the clamp at
+    0.99, the skip at 1/255, the stop at 1e-4) is taken both ways, and each
+    choice continues as its own branch.  Returns a list of dicts (color [3],
+    depth, alpha, T_final, last, n_eval), one per branch; with no decision in
+    a band it holds exactly composite()'s result for that pixel.
+    """
+    order = np.asarray(order, np.int64)
+    bg = np.asarray(bg, float)
+    L = order.shape[0]
+    if L == 0:
+        return [dict(color=bg.copy(), depth=0.0, alpha=0.0, T_final=1.0, last=0, n_eval=0)]
+    # per-entry quantities with the same array expressions as composite()
+    u, v = rec["u"][order], rec["v"][order]
+    A, B, C = rec["A"][order], rec["B"][order], rec["C"][order]
+    sig, z, col = rec["sigma"][order], rec["z"][order], rec["color"][order]
+    dx = u[None, :] - np.array([[float(x)]])
+    dy = v[None, :] - np.array([[float(y)]])
+    power = (-0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy)[0]
+    raw = (sig * np.exp(np.minimum(power, 0.0))[None, :])[0]
+    out = []
+
+    def finish(T, c, d, last, n_eval):
+        out.append(dict(color=c + T * bg, depth=d, alpha=1.0 - T, T_final=T, last=last,
+                        n_eval=n_eval))
+
+    # explicit stack of partial walks: (position, T, colour, depth, last)
+    stack = [(0, 1.0, np.zeros(3), 0.0, 0)]
+    while stack:
+        if len(out) + len(stack) > max_branches:
+            raise RuntimeError("too many ambiguous decisions on one pixel")
+        j, T, c, d, last = stack.pop()
+        while True:
+            if j == L:
+                finish(T, c, d, last, L)
+                break
+            if power[j] > 0:
+                j += 1
+                continue
+            # clamp: alpha = min(0.99, raw), both ways inside the band
+            alphas = [min(A_MAX, raw[j])]
+            if abs(raw[j] - A_MAX) <= band_alpha * A_MAX:
+                alphas = [A_MAX, raw[j]]
+            # skip: alpha < 1/255, both ways inside the band
+            opts = []
+            for a in alphas:
+                if abs(raw[j] - A_MIN) <= band_alpha * A_MIN:
+                    opts += [None, a]
+                elif a < A_MIN:
+                    opts.append(None)
+                else:
+                    opts.append(a)
+            walks = []
+            for a in opts:
+                if a is None:
+                    walks.append((j + 1, T, c, d, last, False))
+                    continue
+                Tn = T * (1.0 - a)
+                stops = [Tn < T_MIN]
+                if abs(Tn - T_MIN) <= band_t * T_MIN:
+                    stops = [True, False]
+                for s in stops:
+                    if s:
+                        walks.append((j, T, c, d, last, True))
+                    else:
+                        w = a * T
+                        walks.append((j + 1, Tn, c + w * col[j], d + w * z[j], j + 1, False))
+            # first option continues here, the others are pushed as branches
+            for jj, TT, cc, dd, ll, stopped in walks[1:]:
+                if stopped:
+                    finish(TT, cc, dd, ll, jj + 1)
+                else:
+                    stack.append((jj, TT, cc, dd, ll))
+            jj, TT, cc, dd, ll, stopped = walks[0]
+            if stopped:
+                finish(TT, cc, dd, ll, jj + 1)
+                break
+            j, T, c, d, last = jj, TT, cc, dd, ll
+    return out

@@ -253,3 +253,94 @@ def test_p13_culling():
     for key in ("d_means", "d_log_scales", "d_quats", "d_colors"):
         assert np.all(g[key][:5] == 0) and np.any(g[key][5] != 0)
     assert np.all(g["d_opacity"][:5] == 0)
+
+
+# ---------------------------------------------------------------- ambiguous branches
+def _tile_pixels(r, st, W, H):
+    """(pixel x, pixel y, list order) of every pixel of a rendered view."""
+    su = r["setup"]
+    TX = su["kp"]["TX"]
+    for t in range(TX * su["kp"]["TY"]):
+        tx, ty = t % TX, t // TX
+        lo, hi = r["ranges"][t]
+        order = su["local"][r["vals"][lo:hi] - su["g0"]]
+        for y in range(ty * st.tile_h, min((ty + 1) * st.tile_h, H)):
+            for x in range(tx * st.tile_w, min((tx + 1) * st.tile_w, W)):
+                yield x, y, order
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_branches_reduce_to_composite(seed):
+    """With no decision inside the ambiguity band the branch walk has one
+    branch, equal to composite() exactly; with one, composite()'s outcome is
+    among the branches."""
+    from oracle.composite import composite_branches
+    sc, vw = tiny_scene(seed, n=40, width=32, height=24, pose_noise=0.1 * (seed % 2))
+    st = Settings()
+    r = render_view(sc, vw, 0, st)
+    rec = r["setup"]["rec"]
+    for x, y, order in _tile_pixels(r, st, vw.width, vw.height):
+        br = composite_branches(x + 0.5, y + 0.5, rec, order, np.zeros(3))
+        want = (r["color"][:, y, x], r["depth"][y, x], r["alpha"][y, x], r["last"][y, x],
+                r["n_eval"][y, x])
+        hits = [b for b in br if np.all(b["color"] == want[0]) and b["depth"] == want[1]
+                and b["alpha"] == want[2] and b["last"] == want[3] and b["n_eval"] == want[4]]
+        if r["ambiguous"][y, x]:
+            assert len(br) >= 2 and hits
+        else:
+            assert len(br) == 1 and len(hits) == 1
+
+
+def test_branches_at_skip_and_stop_thresholds():
+    """A pixel whose sigma*G sits 1e-6 (relative) above 1/255 yields the
+    blended and the skipped outcome; a pixel whose transmittance after a
+    blend sits 1e-6 above 1e-4 yields the stopped and the continued one."""
+    from oracle.composite import composite_branches
+    rec = dict(u=np.array([0.0]), v=np.array([0.0]), A=np.array([0.5]), B=np.array([0.0]),
+               C=np.array([0.5]), sigma=np.array([0.5]), z=np.array([2.0]),
+               color=np.array([[1.0, 0.5, 0.25]]))
+    # sigma exp(-x^2/4) = (1/255)(1 + 1e-6) at sample point (x, 0)
+    x = math.sqrt(-4.0 * math.log(A_MIN * (1 + 1e-6) / 0.5))
+    br = composite_branches(x, 0.0, rec, [0], np.zeros(3))
+    assert sorted(b["last"] for b in br) == [0, 1]
+    a = [b["alpha"] for b in br if b["last"] == 1][0]
+    assert a == pytest.approx(A_MIN * (1 + 1e-6), rel=1e-12)
+    assert all(b["alpha"] == 0.0 for b in br if b["last"] == 0)
+    # stop: T after the third blend equals 1e-4 (1 + 1e-6); no alpha near 0.99
+    a1 = 0.95
+    a3 = 1.0 - T_MIN * (1 + 1e-6) / (1.0 - a1) ** 2
+    rec2 = dict(u=np.zeros(4), v=np.zeros(4), A=np.full(4, 1.0), B=np.zeros(4),
+                C=np.full(4, 1.0), sigma=np.array([a1, a1, a3, 0.5]),
+                z=np.array([1.0, 2.0, 3.0, 4.0]), color=np.eye(4)[:, :3])
+    br = composite_branches(0.0, 0.0, rec2, [0, 1, 2, 3], np.zeros(3))
+    got = sorted((b["last"], b["n_eval"]) for b in br)
+    # continuing past the third entry, the fourth stops either way:
+    # 1e-4 (1 + 1e-6) (1 - 0.5) < 1e-4
+    assert got == [(2, 3), (3, 4)]
+    cont = [b for b in br if b["last"] == 3][0]
+    assert cont["T_final"] == pytest.approx(T_MIN * (1 + 1e-6), rel=1e-9)
+    stop = [b for b in br if b["last"] == 2][0]
+    assert stop["T_final"] == pytest.approx((1.0 - a1) ** 2, rel=1e-12)
+
+
+def test_branches_cover_ambiguous_pixels_of_small_workload():
+    """On the 2,000-Gaussian workload every pixel flagged ambiguous has two
+    or more branches, one of them composite()'s own outcome; a sample of the
+    other pixels has exactly that one."""
+    from oracle.composite import composite_branches
+    wl = small_plain(0)
+    st = Settings()
+    r = render_view(wl.scene, wl.views, 0, st)
+    rec = r["setup"]["rec"]
+    rng = np.random.default_rng(0)
+    n_amb = 0
+    for x, y, order in _tile_pixels(r, st, wl.views.width, wl.views.height):
+        amb = r["ambiguous"][y, x]
+        if not amb and rng.random() > 0.02:
+            continue
+        br = composite_branches(x + 0.5, y + 0.5, rec, order, np.zeros(3))
+        hit = [b for b in br if np.all(b["color"] == r["color"][:, y, x])
+               and b["alpha"] == r["alpha"][y, x] and b["n_eval"] == r["n_eval"][y, x]]
+        assert hit and (len(br) >= 2 if amb else len(br) == 1)
+        n_amb += int(amb)
+    assert n_amb == int(r["ambiguous"].sum()) > 0
