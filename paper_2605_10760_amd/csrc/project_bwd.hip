@@ -279,8 +279,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
                                  (gq[2] - qh[2] * dq) / qn, (gq[3] - qh[3] * dq) / qn);
   *reinterpret_cast<float4*>(out.d_quats + 4 * gi) = gq4;
   for (int k = 0; k < 3; ++k) out.d_means[3 * gi + k] = gm[k];
-  const float sg = 1.f / (1.f + expf(-sc.opac[gi]));
-  out.d_opacity_logits[gi] = gsig * sg * (1.f - sg);
+  // d sigmoid(o)/do = e/(1 + e)^2 with e = exp(-|o|) <= 1: accurate for
+  // every logit (sigma (1 - sigma) in FP32 is exactly 0 once sigma rounds
+  // to 1, at o above about 16.6)
+  const float eo = expf(-fabsf(sc.opac[gi]));
+  const float ro = 1.f / (1.f + eo);
+  out.d_opacity_logits[gi] = gsig * (eo * ro * ro);
   if (SHD == 0) {
     for (int c = 0; c < 3; ++c) out.d_colors[3 * gi + c] = gk[0][c];
   } else {

@@ -6,6 +6,14 @@ import sys
 
 import numpy as np
 
+IMG_TOL = 1e-5
+GRAD_TOL = 1e-3
+# Two runs of the same backward: each pair's screen-space gradient is summed
+# with float atomics from many tiles, in an order that differs between runs,
+# so the parameter gradients agree to rounding of those sums (measured up to
+# 2.3e-5 of a tensor's max-norm), not bit for bit.
+RERUN_TOL = 1e-4
+
 
 def announce(msg: str):
     """Name the GPU case about to run (flushed, so a crash still shows it)."""
@@ -74,3 +82,145 @@ def grad_rel_err(got, ref):
     n2 = np.linalg.norm(ref)
     return (np.abs(d).max() / ninf if ninf > 0 else np.abs(d).max(),
             np.linalg.norm(d) / n2 if n2 > 0 else np.linalg.norm(d))
+
+
+# ---------------------------------------------------------------- oracle comparisons
+from oracle.composite import composite_branches  # noqa: E402
+from oracle.render import Settings, render_view  # noqa: E402
+
+
+def _oracle_views(scene, views, st=Settings(), keep=False):
+    return [render_view(scene, views, k, st, keep=keep) for k in range(views.n)]
+
+
+def _check_keys(scene, views, g, orc, st=Settings()):
+    dbg = g["dbg"]
+    vid, gid = pair_to_gauss(scene, views)
+    so = scene.set_offsets
+    T = dbg["TX"] * dbg["TY"]
+    off = 0
+    straddle = set()
+    for k, r in enumerate(orc):
+        kp = r["setup"]["kp"]
+        n = kp["visible"].shape[0]
+        zk = dbg["zkeys"][off:off + n]
+        vis = zk != 0xFFFFFFFF
+        s0 = so[views.view_set[k]]
+        straddle |= set((s0 + np.nonzero(kp["straddle"])[0]).tolist())
+        ok = ~kp["straddle"]
+        np.testing.assert_array_equal(vis[ok], kp["visible"][ok], err_msg=f"culling, view {k}")
+        both = vis & kp["visible"] & ok
+        np.testing.assert_array_equal(zk[both], kp["zbits"][both], err_msg=f"depth bits, view {k}")
+        np.testing.assert_array_equal(dbg["rects"][off:off + n][both].astype(np.int64),
+                                      kp["rect"][both], err_msg=f"rects, view {k}")
+        off += n
+    # sorted instances: (global tile, depth bits, Gaussian) per instance
+    inst = dbg["inst"].astype(np.int64)
+    tile_of = np.zeros(inst.shape[0], np.int64)
+    for t in range(views.n * T):
+        lo, hi = dbg["ranges"][t]
+        tile_of[lo:hi] = t
+    g_keys = (tile_of.astype(np.uint64) << np.uint64(32)) | dbg["zkeys"][inst].astype(np.uint64)
+    g_vals = gid[inst]
+    o_keys = np.concatenate([r["keys"] for r in orc])
+    o_vals = np.concatenate([r["vals"] for r in orc])
+    if straddle:
+        sel_g = ~np.isin(g_vals, list(straddle))
+        sel_o = ~np.isin(o_vals, list(straddle))
+        g_keys, g_vals, o_keys, o_vals = g_keys[sel_g], g_vals[sel_g], o_keys[sel_o], o_vals[sel_o]
+    else:
+        assert g["counts"]["instances"] == o_keys.shape[0]
+        # the oracle's ranges are per view; shift to global positions
+        base = np.cumsum([0] + [r["keys"].shape[0] for r in orc])
+        o_rng = np.concatenate([np.where(r["ranges"][:, 1:2] > r["ranges"][:, :1],
+                                         r["ranges"] + base[k], 0) for k, r in enumerate(orc)])
+        np.testing.assert_array_equal(dbg["ranges"].astype(np.int64), o_rng, err_msg="tile ranges")
+    np.testing.assert_array_equal(g_keys, o_keys, err_msg="sorted keys")
+    np.testing.assert_array_equal(g_vals, o_vals, err_msg="sorted values")
+
+
+def _check_images(views, g, orc, st=Settings()):
+    for k, r in enumerate(orc):
+        ok = ~r["ambiguous"]
+        zmax = max(1.0, float(np.max(r["setup"]["pr"]["z"], initial=0.0)))
+        dc = np.abs(g["color"][k] - r["color"])[:, ok].max(initial=0.0)
+        da = np.abs(g["alpha"][k] - r["alpha"])[ok].max(initial=0.0)
+        dd = np.abs(g["depth"][k] - r["depth"])[ok].max(initial=0.0)
+        assert dc <= IMG_TOL, f"colour err {dc} view {k}"
+        assert da <= IMG_TOL, f"alpha err {da} view {k}"
+        assert dd <= IMG_TOL * zmax, f"depth err {dd} view {k}"
+        np.testing.assert_array_equal(g["n_eval"][k][ok], r["n_eval"][ok])
+        assert r["ambiguous"].mean() <= 1e-3
+        check_ambiguous_pixels(g, k, r, views, st, zmax)
+
+
+def check_ambiguous_pixels(g, k, r, views, st, zmax):
+    """A pixel with a decision inside the ambiguity band must equal one of
+    the oracle's outcomes of that decision (both ways, every such decision)."""
+    ys, xs = np.nonzero(r["ambiguous"])
+    if ys.size == 0:
+        return 0
+    su = r["setup"]
+    TX = su["kp"]["TX"]
+    for y, x in zip(ys, xs):
+        t = (y // st.tile_h) * TX + x // st.tile_w
+        lo, hi = r["ranges"][t]
+        order = su["local"][r["vals"][lo:hi] - su["g0"]]
+        br = composite_branches(x + 0.5, y + 0.5, su["rec"], order, np.asarray(st.bg, float))
+        assert len(br) >= 2
+        hit = any(np.abs(g["color"][k][:, y, x] - b["color"]).max() <= IMG_TOL
+                  and abs(g["alpha"][k][y, x] - b["alpha"]) <= IMG_TOL
+                  and abs(g["depth"][k][y, x] - b["depth"]) <= IMG_TOL * zmax
+                  and g["n_eval"][k][y, x] == b["n_eval"] for b in br)
+        assert hit, f"ambiguous pixel ({x}, {y}) of view {k} matches none of {len(br)} branches"
+    return ys.size
+
+
+def _upstream(views, seed, orc):
+    rng = np.random.default_rng(seed)
+    V, H, W = views.n, views.height, views.width
+    gc = rng.normal(size=(V, 3, H, W)).astype(np.float32)
+    gd = (0.3 * rng.normal(size=(V, H, W))).astype(np.float32)
+    ga = rng.normal(size=(V, H, W)).astype(np.float32)
+    for k, r in enumerate(orc):
+        amb = r["ambiguous"]
+        gc[k][:, amb] = 0
+        gd[k][amb] = 0
+        ga[k][amb] = 0
+    return gc, gd, ga
+
+
+def _gpu_backward(g, gc, gd, ga):
+    import torch
+    t = lambda a: torch.from_numpy(a).cuda()
+    out = g["rast"].backward(g["scene_t"], g["views_t"], g["state"], t(gc), t(gd), t(ga))
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+GMAP = dict(d_means="d_means", d_log_scales="d_log_scales", d_quats="d_quats",
+            d_opacity_logits="d_opacity", d_colors="d_colors", d_pose="d_pose")
+
+
+
+
+def check_ambiguous_samples(g, k, scene, views, px, py, ro, zmax, st=Settings()):
+    """Sampled pixels (render_pixels output `ro`) with a decision inside the
+    ambiguity band must equal one of the oracle's branches, walked over every
+    visible Gaussian of the view in (depth bits, index) order."""
+    from oracle.render import setup_view
+    amb = np.nonzero(ro["ambiguous"])[0]
+    if amb.size == 0:
+        return 0
+    su = setup_view(scene, views, k, st)
+    vis = su["vis"]
+    order = np.lexsort((vis, su["kp"]["zbits"][vis]))
+    for i in amb:
+        x, y = int(px[i]), int(py[i])
+        br = composite_branches(x + 0.5, y + 0.5, su["rec"], order, np.asarray(st.bg, float))
+        hit = any(np.abs(g["color"][k][:, y, x] - b["color"]).max() <= IMG_TOL
+                  and abs(g["alpha"][k][y, x] - b["alpha"]) <= IMG_TOL
+                  and abs(g["depth"][k][y, x] - b["depth"]) <= 10 * IMG_TOL * zmax
+                  for b in br)
+        assert hit, f"ambiguous sample ({x}, {y}) of view {k} matches none of {len(br)} branches"
+    return amb.size

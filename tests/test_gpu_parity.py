@@ -9,24 +9,15 @@ pixels."""
 import numpy as np
 import pytest
 
-from gpu_harness import announce, gpu_forward, grad_rel_err, pair_to_gauss, to_gpu
+from gpu_harness import (GMAP, GRAD_TOL, IMG_TOL, RERUN_TOL, _check_images, _check_keys,
+                         _gpu_backward, _oracle_views, _upstream, announce, check_ambiguous_samples,
+                         gpu_forward,
+                         grad_rel_err, pair_to_gauss, to_gpu)
 from oracle.render import Settings, render_backward, render_pixels, render_view
 from oracle.keypath32 import keypath
 from synth.scenes import fused_map, multi_agent, room_plain, small_plain, tiny_scene
 
 pytestmark = pytest.mark.gpu
-
-IMG_TOL = 1e-5
-# Two runs of the same backward: each pair's screen-space gradient is summed
-# with float atomics from many tiles, in an order that differs between runs,
-# so the parameter gradients agree to rounding of those sums (measured up to
-# 2.3e-5 of a tensor's max-norm), not bit for bit.
-RERUN_TOL = 1e-4
-GRAD_TOL = 1e-3
-
-
-def _oracle_views(scene, views, st=Settings(), keep=False):
-    return [render_view(scene, views, k, st, keep=keep) for k in range(views.n)]
 
 
 def _scene_case(name):
@@ -47,52 +38,6 @@ def _scene_case(name):
 CASES = ["small-plain", "tiny-0", "tiny-1", "tiny-2", "multi-agent-small", "sh3"]
 
 
-def _check_keys(scene, views, g, orc, st=Settings()):
-    dbg = g["dbg"]
-    vid, gid = pair_to_gauss(scene, views)
-    so = scene.set_offsets
-    T = dbg["TX"] * dbg["TY"]
-    off = 0
-    straddle = set()
-    for k, r in enumerate(orc):
-        kp = r["setup"]["kp"]
-        n = kp["visible"].shape[0]
-        zk = dbg["zkeys"][off:off + n]
-        vis = zk != 0xFFFFFFFF
-        s0 = so[views.view_set[k]]
-        straddle |= set((s0 + np.nonzero(kp["straddle"])[0]).tolist())
-        ok = ~kp["straddle"]
-        np.testing.assert_array_equal(vis[ok], kp["visible"][ok], err_msg=f"culling, view {k}")
-        both = vis & kp["visible"] & ok
-        np.testing.assert_array_equal(zk[both], kp["zbits"][both], err_msg=f"depth bits, view {k}")
-        np.testing.assert_array_equal(dbg["rects"][off:off + n][both].astype(np.int64),
-                                      kp["rect"][both], err_msg=f"rects, view {k}")
-        off += n
-    # sorted instances: (global tile, depth bits, Gaussian) per instance
-    inst = dbg["inst"].astype(np.int64)
-    tile_of = np.zeros(inst.shape[0], np.int64)
-    for t in range(views.n * T):
-        lo, hi = dbg["ranges"][t]
-        tile_of[lo:hi] = t
-    g_keys = (tile_of.astype(np.uint64) << np.uint64(32)) | dbg["zkeys"][inst].astype(np.uint64)
-    g_vals = gid[inst]
-    o_keys = np.concatenate([r["keys"] for r in orc])
-    o_vals = np.concatenate([r["vals"] for r in orc])
-    if straddle:
-        sel_g = ~np.isin(g_vals, list(straddle))
-        sel_o = ~np.isin(o_vals, list(straddle))
-        g_keys, g_vals, o_keys, o_vals = g_keys[sel_g], g_vals[sel_g], o_keys[sel_o], o_vals[sel_o]
-    else:
-        assert g["counts"]["instances"] == o_keys.shape[0]
-        # the oracle's ranges are per view; shift to global positions
-        base = np.cumsum([0] + [r["keys"].shape[0] for r in orc])
-        o_rng = np.concatenate([np.where(r["ranges"][:, 1:2] > r["ranges"][:, :1],
-                                         r["ranges"] + base[k], 0) for k, r in enumerate(orc)])
-        np.testing.assert_array_equal(dbg["ranges"].astype(np.int64), o_rng, err_msg="tile ranges")
-    np.testing.assert_array_equal(g_keys, o_keys, err_msg="sorted keys")
-    np.testing.assert_array_equal(g_vals, o_vals, err_msg="sorted values")
-
-
 @pytest.mark.parametrize("case", CASES)
 def test_binning_bit_exact(case):
     announce(f"binning {case}")
@@ -100,20 +45,6 @@ def test_binning_bit_exact(case):
     g = gpu_forward(scene, views)
     orc = _oracle_views(scene, views)
     _check_keys(scene, views, g, orc)
-
-
-def _check_images(views, g, orc):
-    for k, r in enumerate(orc):
-        ok = ~r["ambiguous"]
-        zmax = max(1.0, float(np.max(r["setup"]["pr"]["z"], initial=0.0)))
-        dc = np.abs(g["color"][k] - r["color"])[:, ok].max(initial=0.0)
-        da = np.abs(g["alpha"][k] - r["alpha"])[ok].max(initial=0.0)
-        dd = np.abs(g["depth"][k] - r["depth"])[ok].max(initial=0.0)
-        assert dc <= IMG_TOL, f"colour err {dc} view {k}"
-        assert da <= IMG_TOL, f"alpha err {da} view {k}"
-        assert dd <= IMG_TOL * zmax, f"depth err {dd} view {k}"
-        np.testing.assert_array_equal(g["n_eval"][k][ok], r["n_eval"][ok])
-        assert r["ambiguous"].mean() <= 1e-3
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -131,32 +62,6 @@ def test_forward_images(case):
         # a pixel's list would change it by a factor (1 - alpha) <= 254/255
         tf, to = dbg["t_final"][k][ok].astype(np.float64), r["T_final"][ok]
         assert np.all(np.abs(tf - to) <= 1e-4 * to + 1e-9), f"T_final view {k}"
-
-
-def _upstream(views, seed, orc):
-    rng = np.random.default_rng(seed)
-    V, H, W = views.n, views.height, views.width
-    gc = rng.normal(size=(V, 3, H, W)).astype(np.float32)
-    gd = (0.3 * rng.normal(size=(V, H, W))).astype(np.float32)
-    ga = rng.normal(size=(V, H, W)).astype(np.float32)
-    for k, r in enumerate(orc):
-        amb = r["ambiguous"]
-        gc[k][:, amb] = 0
-        gd[k][amb] = 0
-        ga[k][amb] = 0
-    return gc, gd, ga
-
-
-def _gpu_backward(g, gc, gd, ga):
-    import torch
-    t = lambda a: torch.from_numpy(a).cuda()
-    out = g["rast"].backward(g["scene_t"], g["views_t"], g["state"], t(gc), t(gd), t(ga))
-    torch.cuda.synchronize()
-    return {k: v.cpu().numpy() for k, v in out.items()}
-
-
-GMAP = dict(d_means="d_means", d_log_scales="d_log_scales", d_quats="d_quats",
-            d_opacity_logits="d_opacity", d_colors="d_colors", d_pose="d_pose")
 
 
 @pytest.mark.parametrize("case", CASES)
@@ -338,6 +243,7 @@ def _sampled_full_size_checks(scene, views, view_ids, n_gauss=3000, n_pix=192, s
         da = np.abs(g["alpha"][k][py, px] - ro["alpha"])[ok].max()
         dd = np.abs(g["depth"][k][py, px] - ro["depth"])[ok].max()
         assert dc <= IMG_TOL and da <= IMG_TOL and dd <= IMG_TOL * 10 * zmax, (k, dc, da, dd)
+        check_ambiguous_samples(g, k, scene, views, px, py, ro, zmax)
     return g
 
 
@@ -580,3 +486,62 @@ def test_backward_repeatable_and_needs_grad_mask():
     for k_gpu, k_ref in GMAP.items():
         e_inf, e_2 = grad_rel_err(a[k_gpu], ref[k_ref])
         assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+
+
+@pytest.mark.slow
+def test_multi_agent_full_size_backward_windows():
+    """The benched batch at its own size (6 submaps of 50k..600k Gaussians x
+    8 keyframes at 640x480): per-tile sorted lists of 48 sampled tiles in 4
+    views against an independent construction from the oracle's key path;
+    then upstream gradients on 24x40 windows of two keyframes of the largest
+    submap and one keyframe of every other submap, and every parameter
+    gradient plus all 48 pose rows against the oracle's (views without a
+    window must get exactly zero pose gradient)."""
+    announce("multi-agent 1.67M x 8 640x480 full-size backward windows")
+    wl = multi_agent()
+    scene, views = wl.scene, wl.views
+    g = gpu_forward(scene, views)
+    dbg = g["dbg"]
+    TX, TY = dbg["TX"], dbg["TY"]
+    T = TX * TY
+    so = scene.set_offsets
+    pair_off = np.concatenate([[0], np.cumsum([so[s + 1] - so[s] for s in views.view_set])])
+    rng = np.random.default_rng(41)
+    for k in (2, 13, 30, 45):
+        s = views.view_set[k]
+        sl = slice(so[s], so[s + 1])
+        kp = keypath(scene.means[sl], scene.log_scales[sl], scene.quats[sl],
+                     scene.opacity_logits[sl], views.viewmats[k], views.intrinsics[k],
+                     views.width, views.height)
+        vis, rect = kp["visible"], kp["rect"]
+        for t in rng.choice(T, size=12, replace=False):
+            ty, tx = divmod(int(t), TX)
+            cov = vis & (rect[:, 0] <= tx) & (tx < rect[:, 2]) & (rect[:, 1] <= ty) & (ty < rect[:, 3])
+            ids = np.nonzero(cov)[0]
+            if kp["straddle"][ids].any():
+                continue
+            want = ids[np.lexsort((ids, kp["zbits"][ids]))]
+            lo, hi = dbg["ranges"][k * T + t]
+            got = dbg["inst"][lo:hi].astype(np.int64) - pair_off[k]
+            np.testing.assert_array_equal(got, want, err_msg=f"view {k} tile {t}")
+    # windows: keyframes 40 and 43 of the 600k submap, one of every other
+    win_views = [40, 43, 0, 9, 18, 27, 36]
+    V, H, W = views.n, views.height, views.width
+    gc = np.zeros((V, 3, H, W), np.float32)
+    gd = np.zeros((V, H, W), np.float32)
+    ga = np.zeros((V, H, W), np.float32)
+    for i, k in enumerate(win_views):
+        y0 = int(rng.integers(0, H - 24))
+        x0 = int(rng.integers(0, W - 40))
+        a, b, c = _window_upstream(scene, views, k, y0, x0, 24, 40, seed=50 + i)
+        gc[k], gd[k], ga[k] = a[k], b[k], c[k]
+    got = _gpu_backward(g, gc, gd, ga)
+    ref = render_backward(scene, views, gc, gd, ga, view_ids=win_views)
+    for k_gpu, k_ref in GMAP.items():
+        e_inf, e_2 = grad_rel_err(got[k_gpu], ref[k_ref])
+        assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+    others = np.setdiff1d(np.arange(V), win_views)
+    assert np.all(got["d_pose"][others] == 0)
+    for k in win_views:
+        e_inf, _ = grad_rel_err(got["d_pose"][k], ref["d_pose"][k])
+        assert e_inf <= GRAD_TOL, (k, e_inf)
