@@ -108,6 +108,8 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="time the batched step eagerly")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the kernels beyond the rasterizer step (profiling runs)")
     ap.add_argument("--plain-steps", type=int, default=None)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--digest", action="store_true",
@@ -371,6 +373,15 @@ def main():
             torch.neg(src, out=dst)
         torch.cuda.synchronize()
         del src, dst
+        # a gather of 48-byte rows in random order (the record reads of the
+        # compositing kernels): 1 GiB gathered + 1 GiB written per launch
+        rows = torch.empty((1 << 30) // 48, 12, dtype=torch.float32, device="cuda").fill_(1.0)
+        perm = torch.randperm(rows.shape[0], device="cuda", dtype=torch.int64)
+        gat = torch.empty_like(rows)
+        for _ in range(3):
+            torch.index_select(rows, 0, perm, out=gat)
+        torch.cuda.synchronize()
+        del rows, perm, gat
     tile = tuple(int(x) for x in args.tile.split("x"))
     wl = make_workload(args.workload)
     sc_np, vw_np = wl.scene, wl.views
@@ -551,7 +562,9 @@ def main():
         roof["algorithmic_bytes"] = int(alg_bytes.get(dom, 0))
     step_bytes = sum(alg_bytes.values())
 
-    extras = measure_extras(torch, sc, vw, step.out[0], step.out[1], tc, td, rast=rast)
+    extras = None
+    if not args.no_extras:
+        extras = measure_extras(torch, sc, vw, step.out[0], step.out[1], tc, td, rast=rast)
 
     cpu = None
     if not args.no_cpu:
