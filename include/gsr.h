@@ -68,6 +68,9 @@ extern "C" {
 
 #define GSR_MAX_VIEWS 64 /* views per forward/backward call */
 #define GSR_MAX_SETS 64  /* Gaussian sets (submaps) per call */
+/* grid points (ceil(W / stride) x ceil(H / stride)) of one gsr_seed_noalloc
+ * call: its library-held block counts take 4 B per 256 points (256 KiB) */
+#define GSR_SEED_NOALLOC_MAX_POINTS (1 << 24)
 
 typedef enum gsr_status {
   GSR_OK = 0,
@@ -384,6 +387,27 @@ gsr_status gsr_seed(const float* depth, const float* color, const float* viewmat
                     float opacity_logit, int64_t max_out, float* means_out,
                     float* log_scales_out, float* quats_out, float* opacity_out,
                     float* colors_out, int64_t* n_out, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): gsr_seed
+ * with its per-block counts in a buffer the library holds (a file-scope
+ * device array, one per GPU, kept until the process ends) instead of a
+ * temporary allocation.  Same inputs, outputs and kernels as gsr_seed,
+ * except that the number of seeded Gaussians goes to *n_out_dev, a DEVICE
+ * int64 written on `stream` (no host synchronisation; the caller compares
+ * it with max_out: only the first max_out rows are written).  At most
+ * GSR_SEED_NOALLOC_MAX_POINTS grid points per call (GSR_E_CAPACITY above).
+ * Calls no allocating routine.  Every call on a GPU shares that GPU's
+ * buffer: calls that overlap on one GPU (other streams or host threads)
+ * race and must be serialised by the caller.  GSR_E_INVALID_ARG for null
+ * pointers or bad sizes; GSR_E_DEVICE for a HIP error (including a current
+ * device beyond the library's device table). */
+gsr_status gsr_seed_noalloc(const float* depth, const float* color, const float* viewmat,
+                            const float* intrinsics, int32_t width, int32_t height,
+                            int32_t stride, float opacity_logit, int64_t max_out,
+                            float* means_out, float* log_scales_out, float* quats_out,
+                            float* opacity_out, float* colors_out, int64_t* n_out_dev,
+                            void* stream);
 
 /* Time forward+backward of the given call for each candidate tile shape
  * (with the automatic binning chunk), then for the fastest shape each

@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libgsr.so")
 
 GSR_MAX_VIEWS = 64
 GSR_MAX_SETS = 64
+GSR_SEED_NOALLOC_MAX_POINTS = 1 << 24
 
 STATUS = {0: "GSR_OK", 1: "GSR_E_INVALID_ARG", 2: "GSR_E_NOT_PLANNED", 3: "GSR_E_CAPACITY",
           4: "GSR_E_OVERFLOW", 5: "GSR_E_DEVICE", 6: "GSR_E_OOM", 7: "GSR_E_UNIMPLEMENTED"}
@@ -22,7 +23,7 @@ EXPORTED = ("gsr_create", "gsr_destroy", "gsr_plan", "gsr_state_bytes", "gsr_for
             "gsr_last_error", "gsr_sim3_gaussians", "gsr_sim3_views", "gsr_l1_loss_grad",
             "gsr_prune", "gsr_ssim_workspace_bytes", "gsr_ssim_grad",
             "gsr_dedup_workspace_bytes", "gsr_dedup", "gsr_iso_grad", "gsr_normal_loss_grad",
-            "gsr_seed")
+            "gsr_seed", "gsr_seed_noalloc")
 
 STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "render_bwd",
           "project_bwd")
@@ -149,6 +150,9 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gsr_seed.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float,
                              C.c_int64, vp, vp, vp, vp, vp, P(C.c_int64), vp]
     lib.gsr_seed.restype = C.c_int
+    lib.gsr_seed_noalloc.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float,
+                                     C.c_int64, vp, vp, vp, vp, vp, vp, vp]
+    lib.gsr_seed_noalloc.restype = C.c_int
     lib.gsr_status_string.argtypes = [C.c_int]
     lib.gsr_status_string.restype = C.c_char_p
     lib.gsr_last_error.argtypes = [vp]

@@ -841,6 +841,35 @@ gsr_status gsr_seed(const float* depth, const float* color, const float* viewmat
   return (int64_t)total > max_out ? GSR_E_OVERFLOW : GSR_OK;
 }
 
+gsr_status gsr_seed_noalloc(const float* depth, const float* color, const float* viewmat,
+                            const float* intrinsics, int32_t width, int32_t height,
+                            int32_t stride, float opacity_logit, int64_t max_out,
+                            float* means_out, float* log_scales_out, float* quats_out,
+                            float* opacity_out, float* colors_out, int64_t* n_out_dev,
+                            void* stream) {
+  if (!depth || !color || !viewmat || !intrinsics || !n_out_dev || width < 1 || height < 1 ||
+      stride < 1 || max_out < 0)
+    return GSR_E_INVALID_ARG;
+  if (max_out > 0 && (!means_out || !log_scales_out || !quats_out || !opacity_out || !colors_out))
+    return GSR_E_INVALID_ARG;
+  if ((double)width * height * 3 > 2147483647.0) return GSR_E_INVALID_ARG;
+  const long gm = (long)((width + stride - 1) / stride) * ((height + stride - 1) / stride);
+  if (gm > SEED_NOALLOC_MAX_POINTS) return GSR_E_CAPACITY;
+  const int nb = (int)((gm + 255) / 256);
+  uint32_t* blk = nullptr;
+  hipError_t e = seed_scratch(&blk);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return GSR_E_DEVICE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  e = launch_seed(width, height, stride, depth, color, viewmat, intrinsics, opacity_logit,
+                  (long)max_out, blk, means_out, log_scales_out, quats_out, opacity_out,
+                  colors_out, st);
+  if (e == hipSuccess) e = launch_seed_total(blk, nb, n_out_dev, st);
+  return e == hipSuccess ? GSR_OK : GSR_E_DEVICE;
+}
+
 gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* sc,
                         const gsr_views* vw, const gsr_settings* set, gsr_plan_desc* best,
                         float* best_ms, void* stream) {

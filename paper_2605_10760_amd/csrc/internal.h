@@ -26,6 +26,8 @@ constexpr int MAX_ROWS = 512;     // tile rows per view (binning LDS arrays)
 constexpr int MAX_COLS = 512;     // tile columns per view
 constexpr int MAX_CHUNK = 256;   // depth-sorted pairs per row-binning chunk
 constexpr int SEG = 1024;         // row-list entries per tile-binning segment
+constexpr int GSR_MAX_DEVICES = 64;  // devices with a looked-up library-held buffer
+constexpr long SEED_NOALLOC_MAX_POINTS = GSR_SEED_NOALLOC_MAX_POINTS;
 
 // Pair p of view v is Gaussian (set_goff[view_set[v]] + p - pair_off[v]).
 struct ProjTab {
@@ -190,5 +192,7 @@ hipError_t launch_seed(int W, int H, int stride, const float* depth, const float
                        const float* vm, const float* intr, float opac_logit, long max_out,
                        uint32_t* blk, float* m, float* ls, float* q, float* o, float* c,
                        hipStream_t s);
+hipError_t seed_scratch(uint32_t** out);
+hipError_t launch_seed_total(const uint32_t* blk, int nb, int64_t* n_out, hipStream_t s);
 
 }  // namespace gsr

@@ -16,6 +16,10 @@
 // k_seed_*: ordered compaction (per-block counts, one-workgroup scan,
 // wave-ballot ranks) of the pixels with positive depth on a stride grid,
 // each writing one isotropic Gaussian at its back-projected point.
+// The allocation-free seeding variant keeps the per-block counts in a
+// file-scope device array instead of a temporary allocation.
+#include <mutex>
+
 #include "common.h"
 
 namespace gsr {
@@ -206,6 +210,46 @@ __global__ __launch_bounds__(256) void k_seed_write(SeedGrid sgd, const float* d
   c[3 * pos] = col[px];
   c[3 * pos + 1] = col[HW + px];
   c[3 * pos + 2] = col[2 * HW + px];
+}
+
+// ------------------------------------------------- allocation-free seeding
+// Block counts of gsr_seed_noalloc: one word per 256 grid points plus the
+// total, at most SEED_NOALLOC_MAX_POINTS points.  Every GPU the library runs
+// on holds its own copy until the process ends; every call on a GPU shares
+// it, so calls that overlap on one GPU race.  Nothing in it needs clearing:
+// the count kernel writes every word the scan reads.
+static __device__ __align__(256) uint32_t scratch[SEED_NOALLOC_MAX_POINTS / 256 + 64];
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current (the array's name is a host-side stand-in
+// in host code and must never reach a kernel).
+hipError_t seed_scratch(uint32_t** out) {
+  static std::mutex mu;
+  static uint32_t* addr[GSR_MAX_DEVICES] = {};
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= GSR_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = (uint32_t*)p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
+}
+
+// The grid total (blk[nb] after the scan) as a device int64.
+__global__ void k_seed_total(const uint32_t* blk, int nb, int64_t* n_out) {
+  if (threadIdx.x == 0) n_out[0] = (int64_t)blk[nb];
+}
+
+hipError_t launch_seed_total(const uint32_t* blk, int nb, int64_t* n_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_seed_total, dim3(1), dim3(64), 0, s, blk, nb, n_out);
+  return hipGetLastError();
 }
 
 hipError_t launch_seed(int W, int H, int stride, const float* depth, const float* color,

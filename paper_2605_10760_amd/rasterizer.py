@@ -494,6 +494,27 @@ def seed(depth: torch.Tensor, color: torch.Tensor, viewmat: torch.Tensor,
     return {k: v[:int(n.value)] for k, v in out.items()}
 
 
+def seed_noalloc(depth: torch.Tensor, color: torch.Tensor, viewmat: torch.Tensor,
+                 intrinsics: torch.Tensor, out: dict, n_out: torch.Tensor, stride: int = 1,
+                 opacity_logit: float = 0.0, stream=None) -> None:
+    """gsr_seed_noalloc: seeding into caller-allocated rows `out` (means,
+    log_scales, quats, opacity_logits, colors, capacity = their row count)
+    with the seeded count written to the device int64 tensor `n_out` [1];
+    the library allocates nothing and does not synchronise."""
+    lib = L.load()
+    H, W = depth.shape
+    cap = int(out["means"].shape[0])
+    if not (n_out.dtype == torch.int64 and n_out.numel() == 1 and n_out.is_cuda):
+        raise ValueError("n_out must be a one-element int64 CUDA tensor")
+    st = lib.gsr_seed_noalloc(_ptr(depth), _ptr(color), _ptr(viewmat), _ptr(intrinsics),
+                              int(W), int(H), int(stride), float(opacity_logit), cap,
+                              _ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
+                              _ptr(out["opacity_logits"]), _ptr(out["colors"]),
+                              C.c_void_p(n_out.data_ptr()), _stream(stream))
+    if st != L.GSR_OK:
+        raise L.GsrError(st, "gsr_seed_noalloc failed")
+
+
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_delta, viewmats,
