@@ -96,6 +96,15 @@ typedef struct gsr_plan_desc {
   int32_t tile_h;
   int32_t chunk;         /* depth-sorted pairs per binning chunk, at most 256
                             (0 = automatic) */
+  int32_t fwd_batch;     /* list entries staged per thread per round in the
+                            forward compositing: 1 or 2 (0 = 1) */
+  int32_t bwd_batch;     /* list entries staged per lane per round in the
+                            backward compositing: 1, 2 or 4 (0 = 2) */
+  int32_t persistent;    /* 1: compositing kernels run a grid of resident
+                            workgroups that take tiles from a queue ordered by
+                            decreasing list length; 0: one workgroup (forward)
+                            or wave (backward) per tile */
+  int32_t reserved;
 } gsr_plan_desc;
 
 /* Gaussians, concatenated over sets; set s owns [set_offsets[s], set_offsets[s+1]). */
@@ -202,6 +211,8 @@ gsr_status gsr_poll(gsr_ctx* ctx, const void* state, gsr_counts* out, void* stre
  *   inst    uint32 [I]  pair id of every tile instance, tile-major, depth order
  *   ranges  uint32 [V*TX*TY,2] [first, last+1) per tile, (0,0) when empty
  *   t_final float [V,H,W], last uint32 [V,H,W] (last blended list position + 1)
+ *   n_blend int32 [V,H,W] list entries blended per pixel (counted by a debug
+ *                       kernel with the forward's skip arithmetic)
  * P is the call's pair count (sum of set sizes over views); I from gsr_poll. */
 typedef struct gsr_debug {
   uint32_t* zkeys;
@@ -212,6 +223,7 @@ typedef struct gsr_debug {
   uint32_t* ranges;
   float* t_final;
   uint32_t* last;
+  int32_t* n_blend;
   int64_t n_pairs;     /* in: capacity of zkeys/rects/order (elements) */
   int64_t n_inst;      /* in: capacity of inst (elements) */
 } gsr_debug;
@@ -409,10 +421,14 @@ gsr_status gsr_seed_noalloc(const float* depth, const float* color, const float*
                             float* opacity_out, float* colors_out, int64_t* n_out_dev,
                             void* stream);
 
-/* Time forward+backward of the given call for each candidate tile shape
- * (with the automatic binning chunk), then for the fastest shape each
- * binning chunk of 64, 128 and 256 pairs, and report the fastest plan in
- * `best` (tile_w, tile_h, chunk; other fields copied from `base`, the
+/* Time forward+backward of the given call for each candidate plan and
+ * report the fastest in `best`, by coordinate search: every tile shape
+ * (binning chunk automatic, one entry per thread in the forward, two per
+ * lane in the backward, grid launch), then for the fastest plan so far each
+ * binning chunk of 64, 128 and 256 pairs, the forward's 1 or 2 entries per
+ * thread, the backward's 1, 2 or 4 entries per lane, and the grid or
+ * persistent tile queue.  `best` holds tile_w, tile_h, chunk, fwd_batch,
+ * bwd_batch and persistent; other fields are copied from `base` (the
  * instance capacity raised if a candidate overflowed).  Synchronises;
  * allocates its own temporary contexts and buffers. */
 gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* scene,

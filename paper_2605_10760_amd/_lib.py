@@ -32,7 +32,9 @@ STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "
 class PlanDesc(C.Structure):
     _fields_ = [("max_pairs", C.c_int64), ("max_instances", C.c_int64),
                 ("max_views", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
-                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("chunk", C.c_int32)]
+                ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("chunk", C.c_int32),
+                ("fwd_batch", C.c_int32), ("bwd_batch", C.c_int32), ("persistent", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Scene(C.Structure):
@@ -80,7 +82,8 @@ class DedupParams(C.Structure):
 class Debug(C.Structure):
     _fields_ = [("zkeys", C.c_void_p), ("rects", C.c_void_p), ("order", C.c_void_p),
                 ("vis_off", C.c_void_p), ("inst", C.c_void_p), ("ranges", C.c_void_p),
-                ("t_final", C.c_void_p), ("last", C.c_void_p), ("n_pairs", C.c_int64),
+                ("t_final", C.c_void_p), ("last", C.c_void_p), ("n_blend", C.c_void_p),
+                ("n_pairs", C.c_int64),
                 ("n_inst", C.c_int64)]
 
 

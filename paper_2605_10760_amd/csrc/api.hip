@@ -27,6 +27,8 @@ struct gsr_ctx {
   uint32_t* hist = nullptr;
   BinWork bw{};
   float* grad2d = nullptr;
+  unsigned int* sched = nullptr;  // tile cursors of the persistent compositing
+  RenderCfg rc{1, 2, false};
   size_t max_blocks = 0, max_sblocks = 0, max_chunks = 0;
   bool prof = false;
   hipEvent_t ev[GSR_NUM_STAGES][2] = {};
@@ -95,6 +97,7 @@ StateLayout state_layout(const gsr_plan_desc& p) {
   L.rec = o; o = align256(o + P * 48);
   L.order = o; o = align256(o + P * 4);
   L.ranges = o; o = align256(o + V * (size_t)TX * TY * 8);
+  L.torder = o; o = align256(o + V * (size_t)TX * TY * 4);
   L.inst = o; o = align256(o + (size_t)p.max_instances * 4);
   L.tfinal = o; o = align256(o + px * 4);
   L.last = o; o = align256(o + px * 4);
@@ -112,6 +115,7 @@ StateDev state_ptrs(void* base, const gsr_plan_desc& p) {
   s.rec = (float4*)(b + L.rec);
   s.order = (uint32_t*)(b + L.order);
   s.ranges = (uint2*)(b + L.ranges);
+  s.torder = (uint32_t*)(b + L.torder);
   s.inst = (uint32_t*)(b + L.inst);
   s.tfinal = (float*)(b + L.tfinal);
   s.last = (uint32_t*)(b + L.last);
@@ -144,6 +148,12 @@ gsr_status check_plan(gsr_ctx* c, const gsr_plan_desc* p) {
                 TY, MAX_COLS, MAX_ROWS);
   if (p->chunk < 0 || p->chunk > MAX_CHUNK)
     return fail(c, GSR_E_INVALID_ARG, "chunk must be in [0, %d]", MAX_CHUNK);
+  if (p->fwd_batch < 0 || p->fwd_batch > 2)
+    return fail(c, GSR_E_INVALID_ARG, "fwd_batch must be 0, 1 or 2");
+  if (!(p->bwd_batch == 0 || p->bwd_batch == 1 || p->bwd_batch == 2 || p->bwd_batch == 4))
+    return fail(c, GSR_E_INVALID_ARG, "bwd_batch must be 0, 1, 2 or 4");
+  if (p->persistent != 0 && p->persistent != 1)
+    return fail(c, GSR_E_INVALID_ARG, "persistent must be 0 or 1");
   return GSR_OK;
 }
 
@@ -397,6 +407,7 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   const size_t o_sr = o; o = align256(o + seg_cap * 4);
   const size_t o_sc = o; o = align256(o + seg_cap * (size_t)c->TX * 4);
   const size_t o_g2 = o; o = align256(o + P * GRAD2D * 4);
+  const size_t o_sch = o; o = align256(o + SCHED_WORDS * 4);
   void* ws = nullptr;
   hipError_t e = hipMalloc(&ws, o);
   if (e != hipSuccess) {
@@ -427,6 +438,10 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   // workgroups per CU (256 CUs) keep every CU busy
   c->bw.seg_grid = (int)std::min<size_t>(2048, 8 * ((seg_cap + 7) / 8));
   c->grad2d = (float*)(b + o_g2);
+  c->sched = (unsigned int*)(b + o_sch);
+  c->rc.fwd_batch = p->fwd_batch == 2 ? 2 : 1;
+  c->rc.bwd_batch = p->bwd_batch == 0 ? 2 : p->bwd_batch;
+  c->rc.persistent = p->persistent == 1;
   // The per-pair screen-space gradient rows start at zero and every
   // backward leaves them at zero (the projection backward clears what it
   // reads), so no clearing pass is needed per call.
@@ -476,9 +491,12 @@ gsr_status gsr_forward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   }
   {
     StageMark m(c, GSR_STAGE_RENDER_FWD, st);
+    if (c->rc.persistent &&
+        (e = launch_tile_order(vw->n_views * c->T, sd, c->sched, st)) != hipSuccess)
+      return hip_fail(c, e, "tile order");
     if ((e = launch_render_fwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
-                               c->plan.tile_h, c->TX, c->TY, cam, sd, out->color, out->depth,
-                               out->alpha, out->n_eval, st)) != hipSuccess)
+                               c->plan.tile_h, c->TX, c->TY, c->rc, cam, sd, c->sched,
+                               out->color, out->depth, out->alpha, out->n_eval, st)) != hipSuccess)
       return hip_fail(c, e, "render forward");
   }
   return GSR_OK;
@@ -507,14 +525,14 @@ gsr_status gsr_backward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   hipError_t e;
   {
     StageMark m(c, GSR_STAGE_ZERO, st);
-    if ((e = launch_zero_pose(out->d_pose, vw->n_views, st)) != hipSuccess)
+    if ((e = launch_zero_pose(out->d_pose, vw->n_views, c->sched + 1, st)) != hipSuccess)
       return hip_fail(c, e, "zero");
   }
   {
     StageMark m(c, GSR_STAGE_RENDER_BWD, st);
     if ((e = launch_render_bwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
-                               c->plan.tile_h, c->TX, c->TY, t.grad_mask, cam, sd, gc, gd, ga,
-                               c->grad2d, st)) != hipSuccess)
+                               c->plan.tile_h, c->TX, c->TY, c->rc, t.grad_mask, cam, sd,
+                               c->sched, gc, gd, ga, c->grad2d, st)) != hipSuccess)
       return hip_fail(c, e, "render backward");
   }
   {
@@ -566,6 +584,17 @@ gsr_status gsr_debug_export(gsr_ctx* c, const void* state, int32_t n_views, gsr_
     const size_t ni = (size_t)std::min<unsigned long long>(
         std::min<unsigned long long>(h.inst_total, sd.cap), (unsigned long long)std::max<int64_t>(0, d->n_inst));
     cps.push_back({d->inst, sd.inst, ni * 4});
+  }
+  if (d->n_blend) {
+    // blended entries per pixel, counted by a debug kernel into a temporary
+    int32_t* tmp = nullptr;
+    if ((e = hipMalloc(&tmp, std::max<size_t>(px, 1) * 4)) != hipSuccess) return hip_fail(c, e, "debug alloc");
+    e = launch_count_blend(n_views, c->plan.width, c->plan.height, c->plan.tile_w, c->plan.tile_h,
+                           c->TX, c->TY, sd, tmp, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess) e = hipMemcpy(d->n_blend, tmp, px * 4, hipMemcpyDeviceToHost);
+    (void)hipFree(tmp);
+    if (e != hipSuccess) return hip_fail(c, e, "debug blend count");
   }
   if (d->t_final) cps.push_back({d->t_final, sd.tfinal, px * 4});
   if (d->last) cps.push_back({d->last, sd.last, px * 4});
@@ -875,11 +904,17 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
                         float* best_ms, void* stream) {
   if (!base || !sc || !vw || !best || !best_ms) return GSR_E_INVALID_ARG;
   if (check_plan(nullptr, base) != GSR_OK) return GSR_E_INVALID_ARG;
-  // first every tile shape (binning chunk automatic), then the binning chunk
-  // (depth-sorted pairs per wave of the row binning) for the best shape
+  // Coordinate search: every tile shape (other options at their defaults),
+  // then for the best plan so far the binning chunk (depth-sorted pairs per
+  // wave of the row binning), the forward's entries per thread, the
+  // backward's entries per lane, and the persistent tile queue.
   static const int tiles[][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {32, 8}, {32, 16}, {16, 32}};
   static const int chunks[] = {64, 128, 256};
+  static const int fbs[] = {1, 2};
+  static const int bbs[] = {1, 2, 4};
+  static const int pers[] = {0, 1};
   constexpr int NT_ = sizeof(tiles) / sizeof(tiles[0]), NC_ = sizeof(chunks) / sizeof(chunks[0]);
+  constexpr int NF_ = 2, NB_ = 3, NP_ = 2;
   hipStream_t st = (hipStream_t)stream;
   DeviceGuard g(device);
   const int V = vw->n_views, W = vw->width, H = vw->height;
@@ -908,16 +943,28 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  for (int ci = 0; ci < NT_ + NC_; ++ci) {
+  for (int ci = 0; ci < NT_ + NC_ + NF_ + NB_ + NP_; ++ci) {
     gsr_plan_desc p = *base;
     if (ci < NT_) {
       p.tile_w = tiles[ci][0];
       p.tile_h = tiles[ci][1];
       p.chunk = 0;
+      p.fwd_batch = 1;
+      p.bwd_batch = 2;
+      p.persistent = 0;
     } else {
       if (result != GSR_OK) break;  // no tile shape ran
       p = best_p;
-      p.chunk = chunks[ci - NT_];
+      int k = ci - NT_;
+      if (k < NC_) {
+        p.chunk = chunks[k];
+      } else if ((k -= NC_) < NF_) {
+        p.fwd_batch = fbs[k];
+      } else if ((k -= NF_) < NB_) {
+        p.bwd_batch = bbs[k];
+      } else {
+        p.persistent = pers[k - NB_];
+      }
     }
     if (check_plan(nullptr, &p) != GSR_OK) continue;
     gsr_ctx* ctx = nullptr;

@@ -26,6 +26,7 @@ constexpr int MAX_ROWS = 512;     // tile rows per view (binning LDS arrays)
 constexpr int MAX_COLS = 512;     // tile columns per view
 constexpr int MAX_CHUNK = 256;   // depth-sorted pairs per row-binning chunk
 constexpr int SEG = 1024;         // row-list entries per tile-binning segment
+constexpr int SCHED_WORDS = 2 + 2 * 33;  // tile cursors + length-bucket counts (render.hip)
 constexpr int GSR_MAX_DEVICES = 64;  // devices with a looked-up library-held buffer
 constexpr long SEED_NOALLOC_MAX_POINTS = GSR_SEED_NOALLOC_MAX_POINTS;
 
@@ -96,7 +97,7 @@ static_assert(sizeof(StateHeader) <= STATE_HEADER_BYTES, "header");
 
 // Byte offsets of the arrays inside a saved-state buffer (all 256-aligned).
 struct StateLayout {
-  size_t hdr, zkey, rect, rec, order, ranges, inst, tfinal, last, total;
+  size_t hdr, zkey, rect, rec, order, ranges, torder, inst, tfinal, last, total;
 };
 
 // Pointers into a saved-state buffer.
@@ -107,6 +108,7 @@ struct StateDev {
   float4* rec;        // [P][3]: (u, v, A', B'), (C', sigma, z, ex), (r, g, b, ey)
   uint32_t* order;    // [P] pair ids in (view, depth, id) order
   uint2* ranges;      // [V*T]
+  uint32_t* torder;   // [V*T] tiles by decreasing list length (persistent render)
   uint32_t* inst;     // [cap]
   float* tfinal;      // [V*H*W]
   uint32_t* last;     // [V*H*W]
@@ -150,14 +152,28 @@ hipError_t launch_compact(const ProjTab& t, StateDev st, uint32_t* blk_cnt,
 hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
                              uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s);
 hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStream_t s);
+// Compositing launch options (from the plan): list entries staged per
+// thread in the forward (1 or 2), per lane in the backward (1, 2 or 4), and
+// the persistent length-ordered tile queue instead of one workgroup/wave per
+// tile.
+struct RenderCfg {
+  int fwd_batch;
+  int bwd_batch;
+  bool persistent;
+};
+hipError_t launch_tile_order(int ntiles, StateDev st, unsigned int* sched, hipStream_t s);
 hipError_t launch_render_fwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
-                             const CamDev& cam, StateDev st, float* color, float* depth,
-                             float* alpha, int32_t* n_eval, hipStream_t s);
+                             const RenderCfg& rc, const CamDev& cam, StateDev st,
+                             unsigned int* sched, float* color, float* depth, float* alpha,
+                             int32_t* n_eval, hipStream_t s);
 hipError_t launch_render_bwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
-                             unsigned long long grad_mask, const CamDev& cam, StateDev st,
+                             const RenderCfg& rc, unsigned long long grad_mask,
+                             const CamDev& cam, StateDev st, unsigned int* sched,
                              const float* g_color, const float* g_depth, const float* g_alpha,
                              float* grad2d, hipStream_t s);
-hipError_t launch_zero_pose(float* d_pose, int nv, hipStream_t s);
+hipError_t launch_count_blend(int nv, int W, int H, int TW, int TH, int TX, int TY, StateDev st,
+                              int32_t* n_blend, hipStream_t s);
+hipError_t launch_zero_pose(float* d_pose, int nv, unsigned int* bwd_next, hipStream_t s);
 hipError_t launch_project_bwd(const SetTab& t, const SceneDev& sc, const CamDev& cam,
                               StateDev st, float* grad2d, const gsr_grads& g,
                               int n_total, hipStream_t s);

@@ -13,6 +13,8 @@
 // (T_j = T_{j+1} / (1 - alpha_j)) instead of storing per-pixel lists, the
 // ten splat gradients of an entry are summed over the wave with DPP row
 // operations, and ten lanes issue one global atomic each per (tile, entry).
+#include <algorithm>
+
 #include "common.h"
 
 namespace gsr {
@@ -73,16 +75,15 @@ __device__ __forceinline__ bool reaches(const float4& r0, float Cs, float ex, fl
   return !(xr + m < x0 || xl - m > x1);
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H, int TX, int TY, CamDev cam,
-                                                       StateDev st, float* color, float* depth,
-                                                       float* alpha, int32_t* n_eval) {
-  constexpr int NT = TW * TH;
-  __shared__ float4 s0[NT], s1[NT], s2[NT];
-  __shared__ uint32_t smask[NT];
+// One tile of the forward: FB * TW * TH list entries are staged per round
+// (FB per thread).
+template <int TW, int TH, int FB>
+__device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, const CamDev& cam,
+                                         const StateDev& st, float* color, float* depth,
+                                         float* alpha, int32_t* n_eval, float4* s0, float4* s1,
+                                         float4* s2, uint32_t* smask) {
+  constexpr int NT = TW * TH, NS = FB * NT;
   const int T = TX * TY;
-  const int g = xcd_remap(blockIdx.x, ntiles);
-  if (g < 0) return;
   const int v = g / T, tl = g - v * T;
   const int ty = tl / TX, tx = tl - ty * TX;
   const int tid = threadIdx.x;
@@ -104,32 +105,35 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const float x0c = (float)(tx * TW) + 0.5f, x1c = x0c + (float)(TW - 1);
   const float y0c = (float)(ty * TH) + 0.5f;
-  for (uint32_t base = rg.x; base < rg.y; base += NT) {
+  for (uint32_t base = rg.x; base < rg.y; base += NS) {
     if (__syncthreads_count(!done) == 0) break;
-    const uint32_t idx = base + tid;
-    if (idx < rg.y) {
-      const float4* r = st.rec + 3 * (size_t)st.inst[idx];
-      const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-      // bit w: the entry can reach a pixel of wave w's rows
-      uint32_t m = 0;
 #pragma unroll
-      for (int w = 0; w < NWV; ++w)
-        if (QUAD)
-          m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c + (float)((w & 1) * 8),
-                                 x0c + (float)((w & 1) * 8 + 7), y0c + (float)((w >> 1) * 8),
-                                 y0c + (float)((w >> 1) * 8 + 7))
-               << w;
-        else
-          m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c, x1c, y0c + (float)(w * RW),
-                                 y0c + (float)(w * RW + RW - 1))
-               << w;
-      s0[tid] = r0;
-      s1[tid] = r1;
-      s2[tid] = r2;
-      smask[tid] = m;
+    for (int k = 0; k < FB; ++k) {
+      const uint32_t idx = base + tid + k * NT;
+      if (idx < rg.y) {
+        const float4* r = st.rec + 3 * (size_t)st.inst[idx];
+        const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+        // bit w: the entry can reach a pixel of wave w's rows
+        uint32_t m = 0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w)
+          if (QUAD)
+            m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c + (float)((w & 1) * 8),
+                                   x0c + (float)((w & 1) * 8 + 7), y0c + (float)((w >> 1) * 8),
+                                   y0c + (float)((w >> 1) * 8 + 7))
+                 << w;
+          else
+            m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c, x1c, y0c + (float)(w * RW),
+                                   y0c + (float)(w * RW + RW - 1))
+                 << w;
+        s0[tid + k * NT] = r0;
+        s1[tid + k * NT] = r1;
+        s2[tid + k * NT] = r2;
+        smask[tid + k * NT] = m;
+      }
     }
     __syncthreads();
-    const int n = (int)min((uint32_t)NT, rg.y - base);
+    const int n = (int)min((uint32_t)NS, rg.y - base);
     // Branch-free per pixel: every lane evaluates every entry and a finished
     // or skipped pixel takes a zero weight (adding an exact zero leaves the
     // sums unchanged), so the loop carries no divergent control flow; a wave
@@ -207,6 +211,38 @@ __global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H,
   }
 }
 
+// Grid form: one workgroup per (view, tile), XCD-aware order.  Persistent
+// form: a grid sized to the resident workgroups, each taking tiles from the
+// forward's length-ordered queue (longest lists first) until it is empty.
+template <int TW, int TH, int FB, bool PERSIST>
+__global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H, int TX, int TY,
+                                                       CamDev cam, StateDev st,
+                                                       unsigned int* next, float* color,
+                                                       float* depth, float* alpha,
+                                                       int32_t* n_eval) {
+  constexpr int NS = FB * TW * TH;
+  __shared__ float4 s0[NS], s1[NS], s2[NS];
+  __shared__ uint32_t smask[NS];
+  __shared__ int s_tile;
+  if (!PERSIST) {
+    const int g = xcd_remap(blockIdx.x, ntiles);
+    if (g < 0) return;
+    fwd_tile<TW, TH, FB>(g, W, H, TX, TY, cam, st, color, depth, alpha, n_eval, s0, s1, s2,
+                         smask);
+    return;
+  }
+  for (;;) {
+    // the barrier also ends every read of the previous tile's staged entries
+    if (threadIdx.x == 0) s_tile = (int)atomicAdd(next, 1u);
+    __syncthreads();
+    const int q = s_tile;
+    __syncthreads();
+    if (q >= ntiles) return;
+    fwd_tile<TW, TH, FB>((int)st.torder[q], W, H, TX, TY, cam, st, color, depth, alpha, n_eval,
+                         s0, s1, s2, smask);
+  }
+}
+
 // Wave sums of ten values at once, by a transposing butterfly: at each
 // exchange a lane keeps half of its values and hands the other half to its
 // partner, so the number of values per lane halves as the partial sums
@@ -258,28 +294,17 @@ __device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane) {
   return z;
 }
 
-// One wave per tile.  Lane l shades pixel (l % 8, l / 8) of each of the
-// tile's PPL 8x8 blocks; a record staged in LDS is read once per lane and
-// used for its PPL pixels.
-template <int TW, int TH, int B, int TPW>
-__global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, int H, int TX, int TY,
-                                                           unsigned long long grad_mask, CamDev cam,
-                                                           StateDev st, const float* gcol,
-                                                           const float* gdep, const float* galp,
-                                                           float* grad2d) {
+// One tile of the backward on one wave.  Lane l shades pixel (l % 8, l / 8)
+// of each of the tile's PPL 8x8 blocks; a record staged in the wave's LDS
+// slice (B entries) is read once per lane and used for its PPL pixels.
+template <int TW, int TH, int B>
+__device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
+                                         unsigned long long grad_mask, const CamDev& cam,
+                                         const StateDev& st, const float* gcol, const float* gdep,
+                                         const float* galp, float* grad2d, float4* s0, float4* s1,
+                                         float4* s2, uint32_t* sp) {
   constexpr int PPL = TW * TH / 64;
-  __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
-  __shared__ uint32_t LP[TPW][B];
   const int T = TX * TY;
-  const int wv = threadIdx.x >> 6;
-  const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
-  if (blk < 0) return;
-  const int g = blk * TPW + wv;
-  if (g >= ntiles) return;
-  float4* s0 = L0[wv];
-  float4* s1 = L1[wv];
-  float4* s2 = L2[wv];
-  uint32_t* sp = LP[wv];
   const int v = g / T, tl = g - v * T;
   if (!((grad_mask >> v) & 1ull)) return;
   if (st.hdr->overflow) return;
@@ -420,64 +445,263 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
   }
 }
 
+// TPW waves per workgroup, each with a private LDS slice and no workgroup
+// barrier.  Grid form: wave w of workgroup b takes tile b TPW + w (XCD-aware
+// order).  Persistent form: a grid sized to the resident waves, each wave
+// taking tiles from the forward's length-ordered queue until it is empty.
+template <int TW, int TH, int B, int TPW, bool PERSIST>
+__global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, int H, int TX, int TY,
+                                                           unsigned long long grad_mask, CamDev cam,
+                                                           StateDev st, unsigned int* next,
+                                                           const float* gcol, const float* gdep,
+                                                           const float* galp, float* grad2d) {
+  __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
+  __shared__ uint32_t LP[TPW][B];
+  const int wv = threadIdx.x >> 6;
+  if (!PERSIST) {
+    const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
+    if (blk < 0) return;
+    const int g = blk * TPW + wv;
+    if (g >= ntiles) return;
+    bwd_tile<TW, TH, B>(g, W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp, grad2d, L0[wv],
+                        L1[wv], L2[wv], LP[wv]);
+    return;
+  }
+  for (;;) {
+    uint32_t q = 0;
+    if ((threadIdx.x & 63) == 0) q = atomicAdd(next, 1u);
+    q = (uint32_t)__builtin_amdgcn_readfirstlane((int)q);
+    if (q >= (uint32_t)ntiles) return;
+    bwd_tile<TW, TH, B>((int)st.torder[q], W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp,
+                        grad2d, L0[wv], L1[wv], L2[wv], LP[wv]);
+    // the next tile's staging overwrites this wave's LDS slice: every lane
+    // has finished reading it
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 // Clears the pose gradients (the per-pair screen-space gradient rows are
 // kept at zero between backward calls: the projection backward clears the
 // rows it consumes).
-__global__ __launch_bounds__(256) void k_zero_pose(float* d_pose, int nv) {
+__global__ __launch_bounds__(256) void k_zero_pose(float* d_pose, int nv, unsigned int* bwd_next) {
   for (int k = threadIdx.x; k < 6 * nv; k += 256) d_pose[k] = 0.f;
+  // the persistent backward's tile cursor starts every call at 0
+  if (threadIdx.x == 0 && bwd_next) *bwd_next = 0u;
 }
 
-template <int TW, int TH>
-static void fwd_t(int nv, int W, int H, int TX, int TY, const CamDev& cam, StateDev st,
-                  float* color, float* depth, float* alpha, int32_t* n_eval, hipStream_t s) {
-  hipLaunchKernelGGL((k_render_fwd<TW, TH>), dim3(xcd_grid(nv * TX * TY)), dim3(TW * TH), 0, s,
-                     nv * TX * TY, W, H, TX,
-                     TY, cam, st, color, depth, alpha, n_eval);
+// ------------------------------------------------------ tile scheduling
+// The persistent forms take tiles in decreasing order of list length
+// (longest first, so that the last tiles to start are short ones): a bucket
+// sort by the position of the length's leading bit (bucket clz(len), empty
+// tiles last), per-workgroup bucket counts reserved with one global atomic
+// per bucket and workgroup.  Order within a bucket is arbitrary.
+// sched: [0] forward tile cursor, [1] backward tile cursor,
+// [2, 2 + NLB) bucket totals, [2 + NLB, 2 + 2 NLB) bucket fill cursors.
+constexpr int NLB = 33;
+__device__ __forceinline__ int len_bucket(uint2 r) {
+  const uint32_t n = r.y - r.x;
+  return n ? __clz((int)n) : 32;
 }
 
-constexpr int BWD_BATCH = 128;  // entries staged per wave
-constexpr int BWD_TPW = 4;      // tiles (waves) per workgroup
+__global__ __launch_bounds__(64) void k_order_reset(unsigned int* sched) {
+  for (int i = threadIdx.x; i < SCHED_WORDS; i += 64) sched[i] = 0u;
+}
 
-template <int TW, int TH>
-static void bwd_t(int nv, int W, int H, int TX, int TY, unsigned long long mask,
-                  const CamDev& cam, StateDev st, const float* gc, const float* gd,
-                  const float* ga, float* grad2d, hipStream_t s) {
+__global__ __launch_bounds__(1024) void k_len_hist(int ntiles, const uint2* ranges,
+                                                   unsigned int* sched) {
+  __shared__ unsigned int h[NLB];
+  if (threadIdx.x < NLB) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int t = blockIdx.x * 1024 + (int)threadIdx.x;
+  if (t < ntiles) atomicAdd(&h[len_bucket(ranges[t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < NLB && h[threadIdx.x]) atomicAdd(&sched[2 + threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ __launch_bounds__(1024) void k_len_scatter(int ntiles, const uint2* ranges,
+                                                      unsigned int* sched, uint32_t* torder) {
+  __shared__ unsigned int h[NLB], off[NLB], fill[NLB];
+  if (threadIdx.x < NLB) {
+    h[threadIdx.x] = 0u;
+    fill[threadIdx.x] = 0u;
+  }
+  __syncthreads();
+  const int t = blockIdx.x * 1024 + (int)threadIdx.x;
+  const int b = t < ntiles ? len_bucket(ranges[t]) : 0;
+  if (t < ntiles) atomicAdd(&h[b], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned int run = 0;
+    for (int k = 0; k < NLB; ++k) {
+      off[k] = run;
+      run += sched[2 + k];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < NLB && h[threadIdx.x])
+    off[threadIdx.x] += atomicAdd(&sched[2 + NLB + threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  if (t < ntiles) torder[off[b] + atomicAdd(&fill[b], 1u)] = (uint32_t)t;
+}
+
+hipError_t launch_tile_order(int ntiles, StateDev st, unsigned int* sched, hipStream_t s) {
+  hipLaunchKernelGGL(k_order_reset, dim3(1), dim3(64), 0, s, sched);
+  const int nb = (ntiles + 1023) / 1024;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_len_hist, dim3(nb), dim3(1024), 0, s, ntiles, st.ranges, sched);
+    hipLaunchKernelGGL(k_len_scatter, dim3(nb), dim3(1024), 0, s, ntiles, st.ranges, sched,
+                       st.torder);
+  }
+  return hipGetLastError();
+}
+
+// Workgroups of `kernel` (block threads) resident on the whole device at
+// once: the persistent grid.
+static int resident_blocks(const void* kernel, int threads) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return 1024;
+  }
+  return std::max(1, cus) * std::max(1, per);
+}
+
+template <int TW, int TH, int FB>
+static void fwd_fb(int nv, int W, int H, int TX, int TY, bool persist, const CamDev& cam,
+                   StateDev st, unsigned int* sched, float* color, float* depth, float* alpha,
+                   int32_t* n_eval, hipStream_t s) {
   const int ntiles = nv * TX * TY;
-  hipLaunchKernelGGL((k_render_bwd_w<TW, TH, BWD_BATCH, BWD_TPW>),
-                     dim3(xcd_grid((ntiles + BWD_TPW - 1) / BWD_TPW)), dim3(64 * BWD_TPW), 0, s,
-                     ntiles, W, H, TX, TY, mask, cam, st, gc, gd, ga, grad2d);
+  if (persist) {
+    const auto k = k_render_fwd<TW, TH, FB, true>;
+    const int grid = std::min(ntiles, resident_blocks((const void*)k, TW * TH));
+    hipLaunchKernelGGL(k, dim3(std::max(1, grid)), dim3(TW * TH), 0, s, ntiles, W, H, TX, TY, cam,
+                       st, sched, color, depth, alpha, n_eval);
+  } else {
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, FB, false>), dim3(xcd_grid(ntiles)), dim3(TW * TH),
+                       0, s, ntiles, W, H, TX, TY, cam, st, sched, color, depth, alpha, n_eval);
+  }
 }
 
-#define GSR_TILE_SWITCH(F, ...)                                  \
-  do {                                                           \
-    if (TW == 16 && TH == 16) F<16, 16>(__VA_ARGS__);            \
-    else if (TW == 8 && TH == 8) F<8, 8>(__VA_ARGS__);           \
-    else if (TW == 16 && TH == 8) F<16, 8>(__VA_ARGS__);         \
-    else if (TW == 8 && TH == 16) F<8, 16>(__VA_ARGS__);         \
-    else if (TW == 32 && TH == 8) F<32, 8>(__VA_ARGS__);         \
-    else if (TW == 32 && TH == 16) F<32, 16>(__VA_ARGS__);       \
-    else if (TW == 16 && TH == 32) F<16, 32>(__VA_ARGS__);       \
-    else return hipErrorInvalidValue;                            \
+template <int TW, int TH>
+static hipError_t fwd_t(int nv, int W, int H, int TX, int TY, const RenderCfg& rc,
+                        const CamDev& cam, StateDev st, unsigned int* sched, float* color,
+                        float* depth, float* alpha, int32_t* n_eval, hipStream_t s) {
+  if (rc.fwd_batch == 2)
+    fwd_fb<TW, TH, 2>(nv, W, H, TX, TY, rc.persistent, cam, st, sched, color, depth, alpha,
+                      n_eval, s);
+  else
+    fwd_fb<TW, TH, 1>(nv, W, H, TX, TY, rc.persistent, cam, st, sched, color, depth, alpha,
+                      n_eval, s);
+  return hipGetLastError();
+}
+
+constexpr int BWD_TPW = 4;  // tiles (waves) per workgroup
+
+template <int TW, int TH, int B>
+static void bwd_b(int nv, int W, int H, int TX, int TY, bool persist, unsigned long long mask,
+                  const CamDev& cam, StateDev st, unsigned int* sched, const float* gc,
+                  const float* gd, const float* ga, float* grad2d, hipStream_t s) {
+  const int ntiles = nv * TX * TY;
+  if (persist) {
+    const auto k = k_render_bwd_w<TW, TH, B, BWD_TPW, true>;
+    const int need = (ntiles + BWD_TPW - 1) / BWD_TPW;
+    const int grid = std::min(need, resident_blocks((const void*)k, 64 * BWD_TPW));
+    hipLaunchKernelGGL(k, dim3(std::max(1, grid)), dim3(64 * BWD_TPW), 0, s, ntiles, W, H, TX, TY,
+                       mask, cam, st, sched + 1, gc, gd, ga, grad2d);
+  } else {
+    hipLaunchKernelGGL((k_render_bwd_w<TW, TH, B, BWD_TPW, false>),
+                       dim3(xcd_grid((ntiles + BWD_TPW - 1) / BWD_TPW)), dim3(64 * BWD_TPW), 0, s,
+                       ntiles, W, H, TX, TY, mask, cam, st, sched + 1, gc, gd, ga, grad2d);
+  }
+}
+
+template <int TW, int TH>
+static hipError_t bwd_t(int nv, int W, int H, int TX, int TY, const RenderCfg& rc,
+                        unsigned long long mask, const CamDev& cam, StateDev st,
+                        unsigned int* sched, const float* gc, const float* gd, const float* ga,
+                        float* grad2d, hipStream_t s) {
+  if (rc.bwd_batch == 1)
+    bwd_b<TW, TH, 64>(nv, W, H, TX, TY, rc.persistent, mask, cam, st, sched, gc, gd, ga, grad2d, s);
+  else if (rc.bwd_batch == 4)
+    bwd_b<TW, TH, 256>(nv, W, H, TX, TY, rc.persistent, mask, cam, st, sched, gc, gd, ga, grad2d,
+                       s);
+  else
+    bwd_b<TW, TH, 128>(nv, W, H, TX, TY, rc.persistent, mask, cam, st, sched, gc, gd, ga, grad2d,
+                       s);
+  return hipGetLastError();
+}
+
+#define GSR_TILE_SWITCH(F, ...)                                         \
+  do {                                                                  \
+    if (TW == 16 && TH == 16) return F<16, 16>(__VA_ARGS__);            \
+    else if (TW == 8 && TH == 8) return F<8, 8>(__VA_ARGS__);           \
+    else if (TW == 16 && TH == 8) return F<16, 8>(__VA_ARGS__);         \
+    else if (TW == 8 && TH == 16) return F<8, 16>(__VA_ARGS__);         \
+    else if (TW == 32 && TH == 8) return F<32, 8>(__VA_ARGS__);         \
+    else if (TW == 32 && TH == 16) return F<32, 16>(__VA_ARGS__);       \
+    else if (TW == 16 && TH == 32) return F<16, 32>(__VA_ARGS__);       \
+    else return hipErrorInvalidValue;                                   \
   } while (0)
 
 hipError_t launch_render_fwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
-                             const CamDev& cam, StateDev st, float* color, float* depth,
-                             float* alpha, int32_t* n_eval, hipStream_t s) {
-  GSR_TILE_SWITCH(fwd_t, nv, W, H, TX, TY, cam, st, color, depth, alpha, n_eval, s);
-  return hipGetLastError();
+                             const RenderCfg& rc, const CamDev& cam, StateDev st,
+                             unsigned int* sched, float* color, float* depth, float* alpha,
+                             int32_t* n_eval, hipStream_t s) {
+  GSR_TILE_SWITCH(fwd_t, nv, W, H, TX, TY, rc, cam, st, sched, color, depth, alpha, n_eval, s);
 }
 
 hipError_t launch_render_bwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
-                             unsigned long long grad_mask, const CamDev& cam, StateDev st,
+                             const RenderCfg& rc, unsigned long long grad_mask,
+                             const CamDev& cam, StateDev st, unsigned int* sched,
                              const float* g_color, const float* g_depth, const float* g_alpha,
                              float* grad2d, hipStream_t s) {
-  GSR_TILE_SWITCH(bwd_t, nv, W, H, TX, TY, grad_mask, cam, st, g_color, g_depth, g_alpha, grad2d,
-                  s);
+  GSR_TILE_SWITCH(bwd_t, nv, W, H, TX, TY, rc, grad_mask, cam, st, sched, g_color, g_depth,
+                  g_alpha, grad2d, s);
+}
+
+// ------------------------------------------------------ debug counter
+// Entries blended per pixel (alpha >= 1/255 and before the stop): the
+// non-skipped entries before the pixel's last contributor, with the
+// forward's own skip arithmetic.  One workgroup per tile, one thread per
+// pixel, records read straight from the state (set-up and tests only).
+__global__ __launch_bounds__(512) void k_count_blend(int ntiles, int W, int H, int TW, int TX,
+                                                     int TY, StateDev st, int32_t* n_blend) {
+  const int g = blockIdx.x;
+  if (g >= ntiles) return;
+  const int T = TX * TY, v = g / T, tl = g - v * T;
+  const int ty = tl / TX, tx = tl - ty * TX;
+  const int px = tx * TW + (int)threadIdx.x % TW, py = ty * (int)(blockDim.x / TW) +
+                                                        (int)threadIdx.x / TW;
+  if (px >= W || py >= H) return;
+  const size_t HW = (size_t)W * H, q = v * HW + (size_t)py * W + px;
+  const uint2 rg = st.ranges[g];
+  const uint32_t last = st.hdr->overflow ? 0u : st.last[q];
+  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
+  int cnt = 0;
+  for (uint32_t i = 0; i < last; ++i) {
+    const float4* r = st.rec + 3 * (size_t)st.inst[rg.x + i];
+    const float4 a = r[0], b = r[1];
+    float dx, dy;
+    const float p = splat_power(a, b, fx, fy, dx, dy);
+    const float al = fminf(ALPHA_MAX, b.y * exp2_fast(p));
+    cnt += (p > 0.f || al < ALPHA_MIN) ? 0 : 1;
+  }
+  n_blend[q] = cnt;
+}
+
+hipError_t launch_count_blend(int nv, int W, int H, int TW, int TH, int TX, int TY, StateDev st,
+                              int32_t* n_blend, hipStream_t s) {
+  const int ntiles = nv * TX * TY;
+  if (ntiles > 0)
+    hipLaunchKernelGGL(k_count_blend, dim3(ntiles), dim3(TW * TH), 0, s, ntiles, W, H, TW, TX, TY,
+                       st, n_blend);
   return hipGetLastError();
 }
 
-hipError_t launch_zero_pose(float* d_pose, int nv, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_pose, dim3(1), dim3(256), 0, s, d_pose, nv);
+hipError_t launch_zero_pose(float* d_pose, int nv, unsigned int* bwd_next, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_pose, dim3(1), dim3(256), 0, s, d_pose, nv, bwd_next);
   return hipGetLastError();
 }
 

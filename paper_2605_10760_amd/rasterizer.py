@@ -97,7 +97,7 @@ class Rasterizer:
 
     def __init__(self, width: int, height: int, max_pairs: int, max_views: int = 1,
                  max_instances: int | None = None, tile=(16, 16), device: int | None = None,
-                 chunk: int = 0):
+                 chunk: int = 0, fwd_batch: int = 1, bwd_batch: int = 2, persistent: bool = False):
         self.lib = L.load()
         self.device = torch.cuda.current_device() if device is None else int(device)
         h = C.c_void_p()
@@ -108,7 +108,8 @@ class Rasterizer:
         if max_instances is None:
             max_instances = max(1 << 20, 24 * int(max_pairs))
         self.desc = L.PlanDesc(int(max_pairs), int(max_instances), int(max_views), int(width),
-                               int(height), int(tile[0]), int(tile[1]), int(chunk))
+                               int(height), int(tile[0]), int(tile[1]), int(chunk),
+                               int(fwd_batch), int(bwd_batch), int(bool(persistent)), 0)
         self._plan()
 
     def _plan(self):
@@ -244,7 +245,7 @@ class Rasterizer:
         return {name: float(buf[i]) for i, name in enumerate(L.STAGES)}
 
     def debug_export(self, state: torch.Tensor, n_views: int, n_pairs: int, n_inst: int,
-                     stream=None) -> dict:
+                     stream=None, n_blend: bool = False) -> dict:
         TX = -(-self.desc.width // self.desc.tile_w)
         TY = -(-self.desc.height // self.desc.tile_h)
         H, W = self.desc.height, self.desc.width
@@ -257,25 +258,31 @@ class Rasterizer:
         tf = np.zeros((n_views, H, W), np.float32)
         last = np.zeros((n_views, H, W), np.uint32)
         vp = lambda a: C.c_void_p(a.ctypes.data)
+        nb = np.zeros((n_views, H, W), np.int32) if n_blend else None
         d = L.Debug(vp(z), vp(rects), vp(order), vp(vis_off), vp(inst), vp(ranges), vp(tf),
-                    vp(last), int(n_pairs), int(n_inst))
+                    vp(last), vp(nb) if n_blend else None, int(n_pairs), int(n_inst))
         self._check(self.lib.gsr_debug_export(self.ctx, C.c_void_p(state.data_ptr()),
                                               int(n_views), C.byref(d), _stream(stream)))
-        return dict(zkeys=z, rects=rects, order=order[:int(vis_off[-1])], vis_off=vis_off,
-                    inst=inst[:n_inst], ranges=ranges, t_final=tf, last=last, TX=TX, TY=TY)
+        out = dict(zkeys=z, rects=rects, order=order[:int(vis_off[-1])], vis_off=vis_off,
+                   inst=inst[:n_inst], ranges=ranges, t_final=tf, last=last, TX=TX, TY=TY)
+        if n_blend:
+            out["n_blend"] = nb
+        return out
 
 
 def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = None,
              max_instances: int | None = None, z_near=0.2, device: int | None = None,
              stream=None):
-    """Time forward+backward of this call for every supported tile shape,
-    then the binning chunk for the best shape (native, in libgsr), and
-    return (best (tile_w, tile_h), its ms, best chunk)."""
+    """Native coordinate search (gsr_autotune) over the tile shape, binning
+    chunk, forward entries per thread, backward entries per lane and the
+    persistent tile queue for this call.  Returns a dict: tile (tile_w,
+    tile_h), ms (its forward+backward time), chunk, fwd_batch, bwd_batch,
+    persistent — the keyword arguments of Rasterizer besides the sizes."""
     lib = L.load()
     dev = torch.cuda.current_device() if device is None else int(device)
     P = pairs_of(scene, views) if max_pairs is None else int(max_pairs)
     base = L.PlanDesc(P, int(max_instances or max(1 << 20, 24 * P)), views.n, views.width,
-                      views.height, 16, 16, 0)
+                      views.height, 16, 16, 0, 1, 2, 0, 0)
     sc, keep1 = Rasterizer._scene(scene)
     vw, keep2 = Rasterizer._views(views)
     st = Rasterizer._settings(z_near)
@@ -285,7 +292,9 @@ def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = No
                               C.byref(best), C.byref(ms), _stream(stream))
     if status != L.GSR_OK:
         raise L.GsrError(status, "gsr_autotune failed")
-    return (best.tile_w, best.tile_h), float(ms.value), int(best.chunk)
+    return dict(tile=(best.tile_w, best.tile_h), ms=float(ms.value), chunk=int(best.chunk),
+                fwd_batch=int(best.fwd_batch) or 1, bwd_batch=int(best.bwd_batch) or 2,
+                persistent=bool(best.persistent))
 
 
 def apply_pose_delta(viewmats: torch.Tensor, delta: torch.Tensor, out: torch.Tensor | None = None,

@@ -34,21 +34,23 @@ def to_gpu(scene, views):
     return SceneTensors.from_numpy(scene), ViewTensors.from_numpy(views)
 
 
-def make_rasterizer(scene, views, tile=(16, 16), max_instances=None, chunk=0):
+def make_rasterizer(scene, views, tile=(16, 16), max_instances=None, chunk=0, **opts):
+    """A Rasterizer planned for this call; `opts` are the compositing options
+    (fwd_batch, bwd_batch, persistent)."""
     from paper_2605_10760_amd import Rasterizer
     so = scene.set_offsets
     P = int(sum(so[s + 1] - so[s] for s in views.view_set))
     return Rasterizer(views.width, views.height, max(P, 1), views.n,
-                      max_instances=max_instances, tile=tile, chunk=chunk), P
+                      max_instances=max_instances, tile=tile, chunk=chunk, **opts), P
 
 
 def gpu_forward(scene, views, tile=(16, 16), z_near=0.2, bg=(0.0, 0.0, 0.0), export=True,
-                rast=None, chunk=0):
+                rast=None, chunk=0, n_blend=False, **opts):
     """Forward on the GPU; returns dict of numpy outputs (+ binning export)."""
     import torch
     st_, vt = to_gpu(scene, views)
     if rast is None:
-        rast, P = make_rasterizer(scene, views, tile, chunk=chunk)
+        rast, P = make_rasterizer(scene, views, tile, chunk=chunk, **opts)
     else:
         P = int(sum(scene.set_offsets[s + 1] - scene.set_offsets[s] for s in views.view_set))
     c, d, a, state, ne = rast.forward(st_, vt, z_near=z_near, bg=bg, n_eval=True)
@@ -57,8 +59,19 @@ def gpu_forward(scene, views, tile=(16, 16), z_near=0.2, bg=(0.0, 0.0, 0.0), exp
                n_eval=ne.cpu().numpy(), counts=counts, state=state, rast=rast, scene_t=st_,
                views_t=vt, P=P)
     if export:
-        out["dbg"] = rast.debug_export(state, views.n, P, int(counts["instances"]))
+        out["dbg"] = rast.debug_export(state, views.n, P, int(counts["instances"]),
+                                       n_blend=n_blend)
     torch.cuda.synchronize()
+    return out
+
+
+def oracle_blend_count(views, orc_keep):
+    """Entries blended per pixel [V,H,W] from oracle renders made with
+    keep=True (a blended entry has a positive weight)."""
+    out = np.zeros((views.n, views.height, views.width), np.int64)
+    for k, r in enumerate(orc_keep):
+        for xx, yy, piece in r["pieces"]:
+            out[k, yy, xx] = (piece["w"] > 0).sum(axis=1)
     return out
 
 

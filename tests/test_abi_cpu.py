@@ -48,10 +48,11 @@ def test_create_without_device_reports_device_error():
 def _desc(**kw):
     from paper_2605_10760_amd import _lib
     d = dict(max_pairs=1000, max_instances=10000, max_views=2, width=128, height=96,
-             tile_w=16, tile_h=16, chunk=0)
+             tile_w=16, tile_h=16, chunk=0, fwd_batch=0, bwd_batch=0, persistent=0)
     d.update(kw)
     return _lib.PlanDesc(*[d[k] for k in ("max_pairs", "max_instances", "max_views", "width",
-                                          "height", "tile_w", "tile_h", "chunk")])
+                                          "height", "tile_w", "tile_h", "chunk", "fwd_batch",
+                                          "bwd_batch", "persistent")])
 
 
 def test_state_bytes_host_only_and_validation():
@@ -59,11 +60,14 @@ def test_state_bytes_host_only_and_validation():
     lib = _lib.load()
     n = C.c_size_t()
     assert lib.gsr_state_bytes(C.byref(_desc()), C.byref(n)) == _lib.GSR_OK
-    # header + keys + rects + records + order + ranges + instances + 2 per-pixel planes
-    assert n.value >= 512 + 1000 * (4 + 8 + 48 + 4) + 2 * 48 * 8 + 10000 * 4 + 2 * 2 * 128 * 96 * 4
+    # header + keys + rects + records + order + ranges + tile order + instances + 2 per-pixel
+    # planes
+    assert n.value >= (512 + 1000 * (4 + 8 + 48 + 4) + 2 * 48 * (8 + 4) + 10000 * 4
+                       + 2 * 2 * 128 * 96 * 4)
     assert n.value % 256 == 0
     for bad in (dict(max_pairs=0), dict(max_views=65), dict(tile_w=12), dict(tile_w=32, tile_h=32),
-                dict(width=0), dict(max_instances=0), dict(chunk=-1)):
+                dict(width=0), dict(max_instances=0), dict(chunk=-1), dict(fwd_batch=3),
+                dict(bwd_batch=3), dict(bwd_batch=8), dict(persistent=2)):
         assert lib.gsr_state_bytes(C.byref(_desc(**bad)), C.byref(n)) == _lib.GSR_E_INVALID_ARG, bad
     assert lib.gsr_state_bytes(None, C.byref(n)) == _lib.GSR_E_INVALID_ARG
 

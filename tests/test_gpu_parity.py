@@ -11,8 +11,8 @@ import pytest
 
 from gpu_harness import (GMAP, GRAD_TOL, IMG_TOL, RERUN_TOL, _check_images, _check_keys,
                          _gpu_backward, _oracle_views, _upstream, announce, check_ambiguous_samples,
-                         gpu_forward,
-                         grad_rel_err, pair_to_gauss, to_gpu)
+                         gpu_forward, grad_rel_err, oracle_blend_count, pair_to_gauss,
+                         to_gpu)
 from oracle.render import Settings, render_backward, render_pixels, render_view
 from oracle.keypath32 import keypath
 from synth.scenes import fused_map, multi_agent, room_plain, small_plain, tiny_scene
@@ -413,11 +413,63 @@ def test_profile_stages_and_autotune():
     ms = r.stage_ms()
     r.profile(False)
     assert all(v > 0 for v in ms.values()), ms
-    tile, t_ms, chunk = autotune(g["scene_t"], g["views_t"])
-    assert tile in [(16, 16), (16, 8), (8, 16), (8, 8), (32, 8), (32, 16), (16, 32)]
-    assert t_ms > 0 and chunk in (0, 64, 128, 256)
-    g2 = gpu_forward(scene, views, tile=tile, chunk=chunk, export=False)
+    best = autotune(g["scene_t"], g["views_t"])
+    assert best["tile"] in [(16, 16), (16, 8), (8, 16), (8, 8), (32, 8), (32, 16), (16, 32)]
+    assert best["ms"] > 0 and best["chunk"] in (0, 64, 128, 256)
+    assert best["fwd_batch"] in (1, 2) and best["bwd_batch"] in (1, 2, 4)
+    g2 = gpu_forward(scene, views, tile=best["tile"], chunk=best["chunk"], export=False,
+                     fwd_batch=best["fwd_batch"], bwd_batch=best["bwd_batch"],
+                     persistent=best["persistent"])
     np.testing.assert_array_equal(g2["color"], g["color"])
+
+
+# (entries per thread in the forward, per lane in the backward, persistent queue)
+RENDER_OPTS = [(2, 2, False), (1, 1, True), (2, 4, True), (1, 4, False)]
+
+
+@pytest.mark.parametrize("case", ["multi-agent-small", "sh3"])
+@pytest.mark.parametrize("opts", RENDER_OPTS)
+def test_render_options(case, opts):
+    """Every compositing batch size and the persistent tile queue: forward
+    outputs bit-identical to the default launch (the per-pixel arithmetic
+    and its order do not change), gradients against the oracle."""
+    fb, bb, pers = opts
+    announce(f"render options fb={fb} bb={bb} persistent={pers} {case}")
+    scene, views = _scene_case(case)
+    g0 = gpu_forward(scene, views)
+    g1 = gpu_forward(scene, views, fwd_batch=fb, bwd_batch=bb, persistent=pers)
+    for key in ("color", "depth", "alpha", "n_eval"):
+        np.testing.assert_array_equal(g0[key], g1[key], err_msg=key)
+    for key in ("t_final", "last"):
+        np.testing.assert_array_equal(g0["dbg"][key], g1["dbg"][key], err_msg=key)
+    orc = _oracle_views(scene, views)
+    gc, gd, ga = _upstream(views, 11, orc)
+    got = _gpu_backward(g1, gc, gd, ga)
+    ref = render_backward(scene, views, gc, gd, ga)
+    for k_gpu, k_ref in GMAP.items():
+        e_inf, e_2 = grad_rel_err(got[k_gpu], ref[k_ref])
+        assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+    # a second backward on the same saved state (the persistent queue's
+    # cursor restarts every call)
+    got2 = _gpu_backward(g1, gc, gd, ga)
+    for k_gpu, k_ref in GMAP.items():
+        e_inf, e_2 = grad_rel_err(got2[k_gpu], ref[k_ref])
+        assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+
+
+@pytest.mark.parametrize("case", ["small-plain", "multi-agent-small", "sh3"])
+def test_blend_count_matches_oracle(case):
+    """The debug count of blended entries per pixel (the unit of the
+    compositing arithmetic) equals the oracle's on unambiguous pixels."""
+    announce(f"blend count {case}")
+    scene, views = _scene_case(case)
+    g = gpu_forward(scene, views, n_blend=True)
+    orc = _oracle_views(scene, views, keep=True)
+    want = oracle_blend_count(views, orc)
+    for k, r in enumerate(orc):
+        ok = ~r["ambiguous"]
+        np.testing.assert_array_equal(g["dbg"]["n_blend"][k][ok], want[k][ok])
+        assert np.all(g["dbg"]["n_blend"][k] <= g["dbg"]["last"][k])
 
 
 def test_graph_replay_matches_eager():
