@@ -32,20 +32,28 @@ if ROOT not in sys.path:
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP32_VECTOR_PEAK_TFLOPS = 157.3        # packed / dual-issue FP32
+FP32_NONPACKED_PEAK_TFLOPS = 78.6      # one FMA per lane per cycle
+# VALU instruction issue of the whole chip at one wave64 instruction per SIMD
+# per 4 cycles: 256 CUs x 4 SIMDs x 2.4 GHz / 4
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4
 
-# Arithmetic per list entry examined, counted from the compositing
-# definition (one op per +, -, *, min, compare, exp): offset (2), quadratic
-# form (9), exp (1), opacity and clamp (2), skip test (1), transmittance
-# update and stop test (3); for a blended entry the weight (1) and four
-# multiply-adds into colour and depth (8).
-OPS_FWD_EXAMINED = 18
+# Floating-point operations per unit of compositing work, counted from the
+# definition (one per +, -, *, /, min, compare, exp).
+# Forward, per list entry examined by a pixel: offsets (2), the quadratic
+# form -(A dx^2 + C dy^2)/2 - B dx dy (9), exp (1), sigma G (1), clamp (1),
+# the two skip tests (2), T (1 - alpha) (2), the stop test (1).
+OPS_FWD_EXAMINED = 19
+# Forward, per blended entry: weight alpha T (1), colour and depth
+# accumulation (8).
 OPS_FWD_BLENDED = 9
-# Backward per blended entry walked: the forward's 18 to recover alpha, the
-# transmittance division (2), dL/dalpha over three colours, depth and alpha
-# (16), suffix-sum updates (8), colour/depth gradients (4), the unclamped
-# branch (14) and the ten wave reductions amortised per lane (10).
-OPS_BWD_BLENDED = 72
+# Backward, per entry walked back from the pixel's last contributor: alpha
+# recomputed up to the skip tests (16), T_j = T_(j+1) / (1 - alpha) (2).
+OPS_BWD_WALKED = 18
+# Backward, per blended entry: c . dL/dC + z dL/dD (7), dL/dalpha (3), the
+# running sum with its weight (3), colour and depth gradients (8), sigma
+# gradient (2), dL/dpower (1), conic gradients (9), mean gradients (10).
+OPS_BWD_BLENDED = 43
 
 WORKLOADS = ("multi-agent", "room", "room-1m", "fused", "small")
 LR_SCALE = 1e-3
@@ -57,7 +65,7 @@ STAGE_KERNEL = {"project": "k_project", "render_fwd": "k_render_fwd",
 
 def source_digest():
     """SHA-256 over the library's kernel sources and the ABI header: a
-    recorded HBM-traffic figure holds only for the sources it was taken on."""
+    recorded counter figure holds only for the sources it was taken on."""
     import hashlib
     h = hashlib.sha256()
     for d in (os.path.join(ROOT, "paper_2605_10760_amd", "csrc"), os.path.join(ROOT, "include")):
@@ -69,22 +77,22 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel, workload, tile):
-    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
-    summary under profiles/ (a line `traffic-json: {...}` giving FETCH_SIZE
-    and WRITE_SIZE per dispatch, each already scaled by the factor a plain
-    copy kernel of known size reads on the same counter), or None when no
-    summary matches this kernel, workload, tile shape and source digest."""
+def recorded(tag, kernel, workload, tile):
+    """A record from a committed rocprofv3 counter summary under profiles/
+    (a line `<tag>-json: {...}`) for this kernel, workload, tile shape and
+    source digest, or None.  Tags: `traffic` (FETCH_SIZE and WRITE_SIZE per
+    dispatch, each scaled by what the counter reads for a plain copy of known
+    size) and `valu` (VALU instructions, busy and dual-issue quad-cycles)."""
     d = os.path.join(ROOT, "profiles")
     if not os.path.isdir(d):
         return None
     want = source_digest()
     for f in sorted(os.listdir(d)):
-        if not f.endswith(".txt"):
+        if not f.endswith((".txt", ".md")):
             continue
         with open(os.path.join(d, f)) as fh:
             for ln in fh:
-                if not ln.startswith("traffic-json:"):
+                if not ln.startswith(f"{tag}-json:"):
                     continue
                 try:
                     r = json.loads(ln.split(":", 1)[1])
@@ -92,7 +100,7 @@ def recorded_traffic(kernel, workload, tile):
                     continue
                 if (r.get("kernel") == kernel and r.get("workload") == workload
                         and r.get("tile") == tile and r.get("source_digest") == want):
-                    return int(r["fetch_bytes"] + r["write_bytes"])
+                    return r
     return None
 
 
@@ -102,18 +110,24 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=WORKLOADS, default="multi-agent")
-    ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--autotune", action="store_true",
-                    help="pick the tile shape and binning chunk with gsr_autotune first")
+    ap.add_argument("--tile", default="16x16", help="tile shape when not autotuning")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip gsr_autotune and use --tile with the default compositing options")
+    ap.add_argument("--persistent", type=int, choices=(0, 1), default=None,
+                    help="force the persistent tile queue off/on (after autotuning)")
     ap.add_argument("--no-graph", action="store_true", help="time the batched step eagerly")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the kernels beyond the rasterizer step (profiling runs)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (small, room, room-1m autograd, fused map)")
+    ap.add_argument("--config-steps", type=int, default=5)
     ap.add_argument("--plain-steps", type=int, default=None)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU oracle budget per run (one core, then every core)")
     ap.add_argument("--digest", action="store_true",
-                    help="print the kernel-source digest that traffic records are keyed on")
+                    help="print the kernel-source digest that counter records are keyed on")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM counters)")
     return ap.parse_args()
@@ -131,6 +145,14 @@ def make_workload(name):
         # 16 forward-only novel views + 32 fwd+bwd keyframes in one batch
         return scenes.fused_map()
     return scenes.small_plain(0)
+
+
+def plan_options(tuned):
+    """Rasterizer keyword arguments of an autotune result (or defaults)."""
+    if tuned is None:
+        return dict(chunk=0, fwd_batch=1, bwd_batch=2, persistent=False)
+    return dict(chunk=tuned["chunk"], fwd_batch=tuned["fwd_batch"],
+                bwd_batch=tuned["bwd_batch"], persistent=tuned["persistent"])
 
 
 class Step:
@@ -172,18 +194,55 @@ class Step:
         self.opt.step()
 
 
-def time_cpu_baseline(wl, seconds):
-    """The CPU oracle (FP64 NumPy, one thread) on a bounded sample of the
-    same workload: one keyframe of the largest submap with its full
-    projection, binning, sort and projection backward, and compositing
-    forward+backward on an evenly spaced sample of its tiles; the per-view
-    time is extrapolated to all tiles."""
+_CPU = {}
+
+
+def _cpu_tiles(tiles):
+    """Compositing forward + backward of some tiles of the CPU baseline's
+    keyframe (a worker of the all-core run; the keyframe's set-up is
+    inherited from the parent process)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle.composite import composite, pixel_grid
+    from oracle.render import splat_grads
+    su, vals, rng_t, TX, W, H = (_CPU[k] for k in ("su", "vals", "rng_t", "TX", "W", "H"))
+    nv = su["vis"].shape[0]
+    acc = {key: np.zeros(nv) for key in ("u", "v", "A", "B", "C", "sigma", "z")}
+    acc["color"] = np.zeros((nv, 3))
+    if len(tiles) == 0:
+        return acc
+    rng = np.random.default_rng(int(tiles[0]))
+    with threadpool_limits(limits=1):
+        for t in tiles:
+            ty, tx = divmod(int(t), TX)
+            xx, yy, sx, sy = pixel_grid(tx * 16, ty * 16, min(tx * 16 + 16, W), min(ty * 16 + 16, H))
+            lo, hi = rng_t[t]
+            lst = su["local"][vals[lo:hi] - su["g0"]]
+            r = composite(sx, sy, su["rec"], lst, np.zeros(3), keep=True)
+            g = splat_grads(r, rng.normal(size=(sx.shape[0], 3)), rng.normal(size=sx.shape[0]),
+                            np.zeros(sx.shape[0]))
+            for key in acc:
+                np.add.at(acc[key], r["order"], g[key])
+    return acc
+
+
+def time_cpu_baseline(wl, seconds):
+    """The CPU oracle (FP64 NumPy) on a bounded sample of the same workload:
+    one keyframe of the largest submap with its full projection, binning,
+    sort and projection backward, and compositing forward+backward on an
+    evenly spread sample of its tiles, extrapolated to all tiles.  Timed on
+    one core, then with the compositing spread over every host core (a
+    process pool over tiles; set-up and projection backward stay on one
+    core)."""
+    import multiprocessing as mp
+    import platform
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
     from oracle.project64 import project_backward
-    from oracle.render import Settings, bin_view, setup_view, splat_grads
+    from oracle.render import Settings, bin_view, setup_view
     sc, vw = wl.scene, wl.views
     sizes = np.diff(sc.set_offsets)
     k = int(np.nonzero(vw.view_set == int(np.argmax(sizes)))[0][0])
@@ -191,44 +250,288 @@ def time_cpu_baseline(wl, seconds):
     H, W = one.height, one.width
     st = Settings()
     TX, TY = -(-W // 16), -(-H // 16)
-    rng = np.random.default_rng(0)
+    order = np.argsort((np.arange(TX * TY) * 0.6180339887) % 1.0)
     t_start = time.perf_counter()
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         su = setup_view(sc, one, 0, st)
         keys, vals, rng_t = bin_view(su, 0, st, W, H)
         t_setup = time.perf_counter() - t0
-        nv = su["vis"].shape[0]
-        acc = {key: np.zeros(nv) for key in ("u", "v", "A", "B", "C", "sigma", "z")}
-        acc["color"] = np.zeros((nv, 3))
-        order = np.argsort((np.arange(TX * TY) * 0.6180339887) % 1.0)
-        n_done, t_tiles = 0, 0.0
-        budget = max(2.0, seconds - 1.5 * t_setup)
-        while n_done < TX * TY and t_tiles < budget:
-            t = int(order[n_done])
-            ty, tx = divmod(t, TX)
-            xx, yy, sx, sy = pixel_grid(tx * 16, ty * 16, min(tx * 16 + 16, W), min(ty * 16 + 16, H))
-            lo, hi = rng_t[t]
-            lst = su["local"][vals[lo:hi] - su["g0"]]
-            t1 = time.perf_counter()
-            r = composite(sx, sy, su["rec"], lst, np.zeros(3), keep=True)
-            g = splat_grads(r, rng.normal(size=(sx.shape[0], 3)), rng.normal(size=sx.shape[0]),
-                            np.zeros(sx.shape[0]))
-            for key in acc:
-                np.add.at(acc[key], r["order"], g[key])
-            t_tiles += time.perf_counter() - t1
-            n_done += 1
+    _CPU.update(su=su, vals=vals, rng_t=rng_t, TX=TX, W=W, H=H)
+    _cpu_tiles(order[:0])  # imports outside the timed region
+    # one core: tiles one by one until the budget is spent
+    budget = max(2.0, seconds - 1.5 * t_setup)
+    n_done, t_tiles, acc = 0, 0.0, None
+    while n_done < TX * TY and t_tiles < budget:
+        t1 = time.perf_counter()
+        a = _cpu_tiles(order[n_done:n_done + 4])
+        t_tiles += time.perf_counter() - t1
+        n_done += len(order[n_done:n_done + 4])
+        acc = a if acc is None else {key: acc[key] + a[key] for key in acc}
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         sl = su["g0"] + su["vis"]
         project_backward(su["pr"], acc["u"], acc["v"], np.stack([acc["A"], acc["B"], acc["C"]], 1),
                          acc["sigma"], acc["color"], acc["z"], sc.colors[sl], sc.sh_degree)
         t_pb = time.perf_counter() - t0
-    per_view = t_setup + t_pb + t_tiles / n_done * TX * TY
-    return dict(value=1.0 / per_view, unit="views/s", cores=1, kind="oracle",
-                sample=f"one {W}x{H} keyframe of the {int(sizes.max())}-Gaussian submap: full "
-                       f"projection, binning, sort and projection backward, compositing fwd+bwd "
-                       f"on {n_done} of {TX * TY} tiles, extrapolated to the whole view "
-                       f"({time.perf_counter() - t_start:.1f} s of CPU work, FP64 NumPy, 1 thread)")
+    per_view_1 = t_setup + t_pb + t_tiles / n_done * TX * TY
+    # every core: the same per-tile work over a process pool
+    # worker processes: the host cores, at most 16 (the CPU share of one GPU)
+    ncpu = max(1, min(16, os.cpu_count() or 1))
+    n_all = min(TX * TY, max(n_done, 1) * ncpu)
+    chunks = [order[i:n_all:ncpu * 4] for i in range(0, ncpu * 4)]
+    chunks = [c for c in chunks if len(c)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(ncpu) as pool:
+        t1 = time.perf_counter()
+        parts = pool.map(_cpu_tiles, chunks)
+        t_pool = time.perf_counter() - t1
+    del parts
+    per_view_n = t_setup + t_pb + t_pool / n_all * TX * TY
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        model = platform.processor()
+    desc = (f"one {W}x{H} keyframe of the {int(sizes.max())}-Gaussian submap: projection, "
+            f"binning, sort and projection backward in full, compositing fwd+bwd on a sample "
+            f"of its {TX * TY} tiles extrapolated to the whole view; FP64 NumPy")
+    return dict(value=round(1.0 / per_view_1, 6), unit="views/s", cores=1, kind="oracle",
+                sample=f"{desc}; {n_done} tiles on 1 core",
+                all_cores=dict(value=round(1.0 / per_view_n, 6), unit="views/s", cores=ncpu,
+                               sample=f"{n_all} tiles over a pool of {ncpu} processes "
+                                      f"(set-up and projection backward on one core)"),
+                cpu_model=model, host_cpus=ncpu,
+                seconds=round(time.perf_counter() - t_start, 1))
+
+
+def work_counts(np, rast, sc, vw, V, H, W, tile):
+    """Measured work of one untimed forward: pairs, instances, entries
+    examined (forward) and walked (backward) per pixel, blended entries, and
+    the per-tile maxima that bound the compositing list reads."""
+    c, d, a, state, ne = rast.forward(sc, vw, n_eval=True)
+    counts = rast.poll(state)
+    P = int(sum(int(sc.set_offsets[s + 1] - sc.set_offsets[s]) for s in vw.view_set))
+    dbg = rast.debug_export(state, V, P, 0, n_blend=True)
+    n_eval = ne.cpu().numpy().astype(np.int64)
+    last = dbg["last"].astype(np.int64)
+    TX, TY = dbg["TX"], dbg["TY"]
+
+    def tile_max(x):
+        pad = np.zeros((V, TY * tile[1], TX * tile[0]), np.int64)
+        pad[:, :H, :W] = x
+        return pad.reshape(V, TY, tile[1], TX, tile[0]).max(axis=(2, 4))
+
+    out = dict(pairs=P, visible_pairs=int(counts["visible_pairs"]),
+               instances=int(counts["instances"]), examined=int(n_eval.sum()),
+               walked=int(last.sum()), blended=int(dbg["n_blend"].astype(np.int64).sum()),
+               E_fwd=int(tile_max(n_eval).sum()), E_bwd=int(tile_max(last).sum()))
+    del state, c, d, a, ne
+    return out
+
+
+def algorithmic(cnt, sc_np, V, H, W, sh_stride, fwd_only_views=0):
+    """Algorithmic bytes per stage (the minimum each stage must move, from
+    the measured counts) and operations of the compositing kernels."""
+    P, Pv, I = cnt["pairs"], cnt["visible_pairs"], cnt["instances"]
+    rgb = sc_np.sh_degree == 0
+    par = 56 if rgb else 4 * (3 + 3 + 4 + 1 + 3 * sh_stride)
+    npx = V * H * W
+    byt = {
+        # parameters once per Gaussian, a key per pair, rect + record per visible pair
+        "project": par * sc_np.n + 4 * P + (48 + 8) * Pv,
+        "compact": 4 * P + 8 * Pv,
+        "depth_sort": 4 * 24 * Pv,
+        "binning": 2 * 12 * Pv + 4 * I,
+        "render_fwd": 52 * cnt["E_fwd"] + 28 * npx,
+        "render_bwd": 52 * cnt["E_bwd"] + 80 * cnt["E_bwd"] + 28 * npx,
+        "project_bwd": (40 + 32 + 4) * Pv + 2 * par * sc_np.n,
+    }
+    ops = {
+        "render_fwd": OPS_FWD_EXAMINED * cnt["examined"] + OPS_FWD_BLENDED * cnt["blended"],
+        "render_bwd": OPS_BWD_WALKED * cnt["walked"] + OPS_BWD_BLENDED * cnt["blended"],
+    }
+    return byt, ops
+
+
+def time_steps(torch, run, steps):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def run_plain(torch, np, wl, sc, vw, tc, td, step, tile, opts, steps):
+    """The per-view loop: each view with its own projection, sort,
+    compositing and backward, eagerly; gradients summed, then Adam."""
+    from paper_2605_10760_amd import Rasterizer, l1_loss_grad
+    sc_np, vw_np = wl.scene, wl.views
+    V, H, W = vw_np.n, vw_np.height, vw_np.width
+    so = sc_np.set_offsets
+    per_view = [vw.select([k]) for k in range(V)]
+    max_set = int(max(so[s_ + 1] - so[s_] for s_ in vw_np.view_set))
+    r1 = Rasterizer(W, H, max_set, 1, tile=tile, max_instances=1 << 20, **opts)
+    for k in range(V):
+        r1.fit_capacity(sc, per_view[k])
+    st1 = r1.new_state()
+    o1 = (torch.empty((1, 3, H, W), device="cuda"), torch.empty((1, H, W), device="cuda"),
+          torch.empty((1, H, W), device="cuda"))
+    g1 = {k_: torch.empty_like(v_) for k_, v_ in step.grads.items()}
+    g1["d_pose"] = torch.empty((1, 6), device="cuda")
+    gcv = torch.empty((1, 3, H, W), device="cuda")
+    gdv = torch.empty((1, H, W), device="cuda")
+    lgv = dict(d_color=gcv, d_depth=gdv, d_exposure=None)
+    tot = step.grads
+
+    def plain_step():
+        for g_ in tot.values():
+            g_.zero_()
+        for k in range(V):
+            c1, d1, _, _ = r1.forward(sc, per_view[k], state=st1, out=o1)
+            if vw_np.needs_grad is not None and not vw_np.needs_grad[k]:
+                continue
+            # the batch's loss is a mean over all V views: scale by 1/V
+            l1_loss_grad(c1, tc[k:k + 1], d1, td[k:k + 1], None, 0.95 / V, 0.25 / V, out=lgv)
+            r1.backward(sc, per_view[k], st1, gcv, gdv, None, out=g1)
+            for key in ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors"):
+                tot[key].add_(g1[key])
+            tot["d_pose"][k].copy_(g1["d_pose"][0])
+        step.opt.step()
+
+    plain_step()
+    return time_steps(torch, plain_step, steps)
+
+
+def run_workload(torch, np, wl, args, steps, warmup, tuned=None, tile=(16, 16), stages=True,
+                 plain_steps=2):
+    """Batched step (graph replay) and plain loop on one workload: rates,
+    measured work, per-stage times and algorithmic bytes/ops."""
+    from paper_2605_10760_amd import Rasterizer, SceneTensors, ViewTensors
+    sc_np, vw_np = wl.scene, wl.views
+    V, H, W = vw_np.n, vw_np.height, vw_np.width
+    sc = SceneTensors.from_numpy(sc_np)
+    vw = ViewTensors.from_numpy(vw_np)
+    tc = torch.from_numpy(wl.target_color).cuda()
+    td = torch.from_numpy(wl.target_depth if wl.target_depth is not None
+                          else np.zeros((V, H, W), np.float32)).cuda()
+    so = sc_np.set_offsets
+    P = int(sum(so[s + 1] - so[s] for s in vw_np.view_set))
+    if tuned is not None:
+        tile = tuned["tile"]
+    opts = plan_options(tuned)
+    if args.persistent is not None:
+        opts["persistent"] = bool(args.persistent)
+    rast = Rasterizer(W, H, P, V, tile=tile, **opts)
+    rast.fit_capacity(sc, vw)
+    cnt = work_counts(np, rast, sc, vw, V, H, W, tile)
+
+    # The Adam update runs in full every step, with the learning rates
+    # scaled by LR_SCALE: against random targets the full rates move every
+    # opacity logit by ~0.05 per step, so the scene (and the work per step)
+    # would drift away from the one the counts were taken on.
+    step = Step(torch, rast, sc, vw, tc, td, lr_scale=LR_SCALE)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(max(1, warmup)):
+            step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(2):
+            graph.replay()
+    dt = time_steps(torch, graph.replay if graph is not None else step, steps)
+    post = rast.poll(step.state, raise_on_overflow=False)
+    if post["overflow"]:
+        raise RuntimeError(f"{wl.name}: instance capacity overflow during the timed steps")
+
+    stage_acc = {}
+    if stages:
+        # per-stage times: eager steps with HIP events on the launching stream
+        rast.profile(True)
+        n_prof = max(3, min(steps, 10))
+        for _ in range(n_prof):
+            step()
+            for k_, v_ in rast.stage_ms().items():
+                stage_acc[k_] = stage_acc.get(k_, 0.0) + v_ / n_prof
+        rast.profile(False)
+        torch.cuda.synchronize()
+
+    n_bwd = int(np.sum(vw_np.needs_grad)) if vw_np.needs_grad is not None else V
+    plain = None
+    if plain_steps:
+        pdt = run_plain(torch, np, wl, sc, vw, tc, td, step, tile, opts, plain_steps)
+        plain = dict(views_per_s=round(n_bwd / pdt, 2),
+                     evals_per_s=round((cnt["examined"] + cnt["walked"]) / pdt, 1),
+                     ms_per_step=round(pdt * 1e3, 3), steps=plain_steps)
+    byt, ops = algorithmic(cnt, sc_np, V, H, W, sc.sh_stride)
+    res = dict(name=wl.name, V=V, H=H, W=W, n_bwd=n_bwd, dt=dt, cnt=cnt, bytes=byt, ops=ops,
+               stage_ms=stage_acc, plain=plain, tile=tile, opts=opts, rast=rast, step=step,
+               sc=sc, vw=vw, tc=tc, td=td, graph=graph is not None,
+               step_bytes=sum(byt.values()))
+    return res
+
+
+def summary(res):
+    """Compact record of a workload's batched rate, plain rate and work."""
+    dt, cnt = res["dt"], res["cnt"]
+    return dict(workload=res["name"], fwd_bwd_views=res["n_bwd"], views=res["V"],
+                views_per_s=round(res["n_bwd"] / dt, 2), ms_per_step=round(dt * 1e3, 4),
+                evals_per_s=round((cnt["examined"] + cnt["walked"]) / dt, 1),
+                evals={"forward": cnt["examined"], "backward": cnt["walked"],
+                       "blended": cnt["blended"]},
+                counts={k: cnt[k] for k in ("pairs", "visible_pairs", "instances")},
+                step_algorithmic_GB=round(res["step_bytes"] / 1e9, 3),
+                step_hbm_roofline_frac=round(res["step_bytes"] / (dt * HBM_PEAK_GBS * 1e9), 4),
+                tile=f"{res['tile'][0]}x{res['tile'][1]}", options=res["opts"],
+                form="batched, hip graph replay" if res["graph"] else "batched, eager",
+                plain=res["plain"])
+
+
+def run_autograd(torch, np, wl, steps, warmup):
+    """The autograd form: rasterize() as a torch.autograd.Function with a
+    pose delta, the mapping loss in torch, loss.backward(), Adam (eager)."""
+    from paper_2605_10760_amd import Rasterizer, rasterize
+    sc_np, vw_np = wl.scene, wl.views
+    V, H, W = vw_np.n, vw_np.height, vw_np.width
+    P = int(sum(sc_np.set_offsets[s + 1] - sc_np.set_offsets[s] for s in vw_np.view_set))
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda().requires_grad_(True)
+    params = [f(sc_np.means), f(sc_np.log_scales), f(sc_np.quats), f(sc_np.opacity_logits),
+              f(sc_np.colors)]
+    pose = torch.zeros((V, 6), device="cuda", requires_grad=True)
+    vm = torch.from_numpy(vw_np.viewmats).cuda()
+    intr = torch.from_numpy(vw_np.intrinsics).cuda()
+    tc = torch.from_numpy(wl.target_color).cuda()
+    td = torch.from_numpy(wl.target_depth).cuda()
+    rast = Rasterizer(W, H, P, V)
+    lrs = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1e-3)
+    opt = torch.optim.Adam([{"params": [p], "lr": lr * LR_SCALE}
+                            for p, lr in zip(params + [pose], lrs)], fused=True)
+
+    def one():
+        opt.zero_grad(set_to_none=False)
+        c, d, _ = rasterize(rast, *params, vm, intr, sc_np.set_offsets, vw_np.view_set, W, H,
+                            pose_delta=pose, sh_degree=int(sc_np.sh_degree))
+        loss = 0.95 * (c - tc).abs().mean() + 0.25 * (d - td).abs().mean()
+        loss.backward()
+        opt.step()
+
+    for _ in range(max(1, warmup)):
+        one()
+    dt = time_steps(torch, one, steps)
+    return dict(workload=wl.name + "-autograd", views=V, fwd_bwd_views=V,
+                views_per_s=round(V / dt, 2), ms_per_step=round(dt * 1e3, 4),
+                form="torch.autograd.Function, eager, with pose delta")
 
 
 def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, rast=None, reps=10):
@@ -288,24 +591,30 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, rast=None, reps=
         gbs = nbytes / (ms * 1e-3) / 1e9
         res[name] = dict(ms=round(ms, 4), algorithmic_GBps=round(gbs, 1),
                          hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
-    # deduplication: the largest submap's Gaussians and keyframe depths as the
-    # target, the next largest submap as the borrowed set (synchronises)
+    # deduplication: the target is the largest submap's Gaussians in the part
+    # of the room with x < 0.5 m, with that submap's keyframe depths; the
+    # borrowed set is the next largest submap (uniform in the room), so the
+    # borrowed Gaussians beyond the target's coverage survive (synchronises)
     from paper_2605_10760_amd import dedup
     so = sc.set_offsets
     tgt, src = len(so) - 2, len(so) - 3
     kfs = [k for k in range(V) if vw.view_set[k] == tgt]
     ta, tb = int(so[tgt]), int(so[tgt + 1])
     sa, sb = int(so[src]), int(so[src + 1])
+    part = sc.means[ta:tb, 0] < 0.5
+    t_means = sc.means[ta:tb][part].contiguous()
+    t_ls = sc.log_scales[ta:tb][part].contiguous()
     dep = out_depth[kfs].contiguous()
     vm_k, in_k = vw.viewmats[kfs].contiguous(), vw.intrinsics[kfs].contiguous()
-    dedup(sc.means[sa:sb], sc.means[ta:tb], sc.log_scales[ta:tb], dep, vm_k, in_k)
+    dedup(sc.means[sa:sb], t_means, t_ls, dep, vm_k, in_k)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    keep, nvox = dedup(sc.means[sa:sb], sc.means[ta:tb], sc.log_scales[ta:tb], dep, vm_k, in_k)
+    keep, nvox = dedup(sc.means[sa:sb], t_means, t_ls, dep, vm_k, in_k)
     ms = (time.perf_counter() - t0) * 1e3
-    res["dedup"] = dict(ms=round(ms, 3), target=tb - ta, borrowed=sb - sa,
+    res["dedup"] = dict(ms=round(ms, 3), target=int(t_means.shape[0]), borrowed=sb - sa,
                         kept=int(keep.sum().item()), rays=len(kfs) * H * W, voxels=nvox,
-                        note="voxel 0.05, k 1; includes the host synchronisation")
+                        note="voxel 0.05, k 1; target: the largest submap's Gaussians with "
+                             "x < 0.5 m; includes the host synchronisation")
     # seeding one keyframe synchronises (host count): wall time of one call
     seed(out_depth[0], out_color[0], vw.viewmats[0], vw.intrinsics[0])
     torch.cuda.synchronize()
@@ -347,6 +656,46 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, rast=None, reps=
     return res
 
 
+def roofline_of(res, kernel_stage, workload_name):
+    """Roofline record of one compositing (VALU-bound) or HBM-bound stage:
+    algorithmic rate over the measured average launch time, with the HBM
+    traffic and VALU issue figures of the committed counter summaries when
+    they were taken on these sources."""
+    ms = res["stage_ms"].get(kernel_stage, 0.0)
+    if ms <= 0:
+        return None
+    kern = STAGE_KERNEL.get(kernel_stage, kernel_stage)
+    tile = f"{res['tile'][0]}x{res['tile'][1]}"
+    byt = res["bytes"].get(kernel_stage, 0)
+    hbm = byt / (ms * 1e-3) / 1e9
+    tr = recorded("traffic", kern, workload_name, tile)
+    va = recorded("valu", kern, workload_name, tile)
+    if kernel_stage in res["ops"]:
+        ach = res["ops"][kernel_stage] / (ms * 1e-3) / 1e12
+        r = dict(bound="alu", kernel=kern, achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
+                 unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4),
+                 frac_of_nonpacked=round(ach / FP32_NONPACKED_PEAK_TFLOPS, 4))
+    else:
+        r = dict(bound="hbm", kernel=kern, achieved=round(hbm, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                 frac=round(hbm / HBM_PEAK_GBS, 4))
+    r["traffic"] = None if tr is None else int(tr["fetch_bytes"] + tr["write_bytes"])
+    if tr is not None:
+        r["traffic_unit"] = "bytes per launch"
+    r["algorithmic_bytes"] = int(byt)
+    r["hbm_algorithmic_GBps"] = round(hbm, 1)
+    r["hbm_frac"] = round(hbm / HBM_PEAK_GBS, 4)
+    if va is not None:
+        # counter-based: VALU instructions over the issue capacity at one
+        # wave64 instruction per SIMD per 4 cycles (2.4 GHz), and the share
+        # of quad-cycles with a VALU instruction issued
+        r["valu_issue_frac"] = round(va["valu_insts"] / (ms * 1e-3 * VALU_ISSUE_PEAK), 4)
+        r["valu_busy_frac"] = va.get("valu_busy_frac")
+        r["valu_dual_issue_frac"] = va.get("valu_dual_frac")
+        r["clock_GHz"] = va.get("clock_GHz")
+    r["ms"] = round(ms, 4)
+    return r
+
+
 def main():
     args = parse()
     if args.digest:
@@ -359,9 +708,19 @@ def main():
               "built; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
+
+    wl = make_workload(args.workload)
+    # the CPU oracle first: its process pool forks before anything touches the GPU
+    cpu = None
+    if not args.no_cpu:
+        cpu = time_cpu_baseline(wl, args.cpu_seconds)
+        print(f"[bench] cpu baseline: {cpu['value']:.4g} views/s on 1 core, "
+              f"{cpu['all_cores']['value']:.4g} on {cpu['all_cores']['cores']}",
+              file=sys.stderr, flush=True)
+
     import torch
 
-    from paper_2605_10760_amd import Rasterizer, SceneTensors, ViewTensors, l1_loss_grad
+    from paper_2605_10760_amd import SceneTensors, ViewTensors
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if args.copy_calibration:
@@ -382,222 +741,99 @@ def main():
             torch.index_select(rows, 0, perm, out=gat)
         torch.cuda.synchronize()
         del rows, perm, gat
+
+    tuned = None
     tile = tuple(int(x) for x in args.tile.split("x"))
-    wl = make_workload(args.workload)
-    sc_np, vw_np = wl.scene, wl.views
-    V, H, W = vw_np.n, vw_np.height, vw_np.width
-    sc = SceneTensors.from_numpy(sc_np)
-    vw = ViewTensors.from_numpy(vw_np)
-    tc = torch.from_numpy(wl.target_color).cuda()
-    td = torch.from_numpy(wl.target_depth if wl.target_depth is not None
-                          else np.zeros((V, H, W), np.float32)).cuda()
-    so = sc_np.set_offsets
-    P = int(sum(so[s + 1] - so[s] for s in vw_np.view_set))
-    chunk, tuned = 0, None
-    if args.autotune:
+    if not args.no_autotune:
         from paper_2605_10760_amd import autotune
-        tile, tune_ms, chunk = autotune(sc, vw)
-        tuned = dict(ms=round(tune_ms, 3), tile=f"{tile[0]}x{tile[1]}", chunk=chunk)
-        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
-    rast = Rasterizer(W, H, P, V, tile=tile, chunk=chunk)
-    rast.fit_capacity(sc, vw)
-
-    # ---- counts for the metric (untimed forward)
-    c, d, a, state, ne = rast.forward(sc, vw, n_eval=True)
-    counts = rast.poll(state)
-    dbg = rast.debug_export(state, V, P, 0)
-    n_eval = ne.cpu().numpy().astype(np.int64)
-    last = dbg["last"].astype(np.int64)
-    evals_fwd = int(n_eval.sum())
-    evals_bwd = int(last.sum())
-    TX, TY = dbg["TX"], dbg["TY"]
-
-    def tile_max(x):
-        pad = np.zeros((V, TY * tile[1], TX * tile[0]), np.int64)
-        pad[:, :H, :W] = x
-        return pad.reshape(V, TY, tile[1], TX, tile[0]).max(axis=(2, 4))
-
-    E_fwd = int(tile_max(n_eval).sum())      # list entries staged per tile, forward
-    E_bwd = int(tile_max(last).sum())        # list entries walked per tile, backward
-    del state, c, d, a, ne
-
-    # ---- batched step: warmup, graph capture, timed replays
-    # The Adam update runs in full every step, with the learning rates scaled
-    # by LR_SCALE: against random targets the full rates move every opacity
-    # logit by ~0.05 per step, so the scene (and the work per step) would
-    # drift away from the one the evaluation counts were taken on.
-    step = Step(torch, rast, sc, vw, tc, td, lr_scale=LR_SCALE)
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        for _ in range(max(1, args.warmup)):
-            step()
-    torch.cuda.current_stream().wait_stream(s)
-    torch.cuda.synchronize()
-    graph = None
-    if not args.no_graph:
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            step()
-        for _ in range(2):
-            graph.replay()
-    run = graph.replay if graph is not None else step
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    post = rast.poll(step.state, raise_on_overflow=False)
-    if post["overflow"]:
-        print(json.dumps({"error": "instance capacity overflow during the timed steps"}))
-        sys.exit(3)
-
-    # ---- per-stage times (eager steps with HIP events on the same stream)
-    rast.profile(True)
-    stage_acc = {}
-    n_prof = max(3, min(args.steps, 10))
-    for _ in range(n_prof):
-        step()
-        for k_, v_ in rast.stage_ms().items():
-            stage_acc[k_] = stage_acc.get(k_, 0.0) + v_ / n_prof
-    rast.profile(False)
-    torch.cuda.synchronize()
-
-    # ---- plain per-view loop
-    plain = None
-    n_bwd_views = int(np.sum(vw_np.needs_grad)) if vw_np.needs_grad is not None else V
-    if not args.no_plain:
-        per_view = [vw.select([k]) for k in range(V)]
-        max_set = int(max(so[s_ + 1] - so[s_] for s_ in vw_np.view_set))
-        r1 = Rasterizer(W, H, max_set, 1, tile=tile,
-                        max_instances=max(rast.desc.max_instances // max(1, V) * 4, 1 << 20))
-        for k in range(V):
-            r1.fit_capacity(sc, per_view[k])
-        st1 = r1.new_state()
-        o1 = (torch.empty((1, 3, H, W), device="cuda"), torch.empty((1, H, W), device="cuda"),
-              torch.empty((1, H, W), device="cuda"))
-        g1 = {k_: torch.empty_like(v_) for k_, v_ in step.grads.items()}
-        g1["d_pose"] = torch.empty((1, 6), device="cuda")
-        gcv = torch.empty((1, 3, H, W), device="cuda")
-        gdv = torch.empty((1, H, W), device="cuda")
-        lgv = dict(d_color=gcv, d_depth=gdv, d_exposure=None)
-        tot = step.grads
-
-        def plain_step():
-            for g_ in tot.values():
-                g_.zero_()
-            for k in range(V):
-                c1, d1, _, _ = r1.forward(sc, per_view[k], state=st1, out=o1)
-                if vw_np.needs_grad is not None and not vw_np.needs_grad[k]:
-                    continue
-                # the batch's loss is a mean over all V views: scale by 1/V
-                l1_loss_grad(c1, tc[k:k + 1], d1, td[k:k + 1], None, 0.95 / V, 0.25 / V,
-                             out=lgv)
-                r1.backward(sc, per_view[k], st1, gcv, gdv, None, out=g1)
-                for key in ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors"):
-                    tot[key].add_(g1[key])
-                tot["d_pose"][k].copy_(g1["d_pose"][0])
-            step.opt.step()
-
-        plain_step()
-        torch.cuda.synchronize()
-        ps = args.plain_steps if args.plain_steps is not None else max(2, args.steps // 4)
         t0 = time.perf_counter()
-        for _ in range(ps):
-            plain_step()
-        torch.cuda.synchronize()
-        pdt = (time.perf_counter() - t0) / ps
-        plain = dict(views_per_s=n_bwd_views / pdt, evals_per_s=(evals_fwd + evals_bwd) / pdt,
-                     ms_per_step=pdt * 1e3, steps=ps)
+        tuned = autotune(SceneTensors.from_numpy(wl.scene), ViewTensors.from_numpy(wl.views))
+        tuned["seconds"] = round(time.perf_counter() - t0, 1)
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    ps = args.plain_steps if args.plain_steps is not None else max(2, args.steps // 4)
+    res = run_workload(torch, np, wl, args, args.steps, args.warmup, tuned=tuned, tile=tile,
+                       plain_steps=0 if args.no_plain else ps)
+    print(f"[bench] {wl.name}: {res['dt'] * 1e3:.3f} ms per step", file=sys.stderr, flush=True)
 
-    # ---- algorithmic work per stage (measured counts)
-    nv_pairs = counts["visible_pairs"]
-    I = counts["instances"]
-    rgb = sc_np.sh_degree == 0
-    par = 56 if rgb else 4 * (3 + 3 + 4 + 1 + 3 * sc.sh_stride)
-    npx = V * H * W
-    chunk_T = rast.desc.chunk or 0
-    alg_bytes = {
-        # parameters once per Gaussian, a key per pair, rect + record per visible pair
-        "project": par * sc_np.n + 4 * P + (48 + 8) * nv_pairs,
-        "compact": 4 * P + 8 * nv_pairs,
-        "depth_sort": 4 * 24 * nv_pairs,
-        "binning": 2 * 12 * nv_pairs + 4 * I,
-        "render_fwd": 52 * E_fwd + 28 * npx,
-        "render_bwd": 52 * E_bwd + 80 * E_bwd + 28 * npx,
-        "project_bwd": (40 + 32 + 4) * nv_pairs + 2 * par * sc_np.n,
-    }
-    blended = evals_bwd
-    alg_ops = {
-        "render_fwd": OPS_FWD_EXAMINED * evals_fwd + OPS_FWD_BLENDED * blended,
-        "render_bwd": OPS_BWD_BLENDED * evals_bwd,
-    }
     stages = {}
-    for name, ms in stage_acc.items():
+    for name, ms in res["stage_ms"].items():
         if ms <= 0:
             continue
         e = dict(ms=round(ms, 4))
-        if name in alg_bytes:
-            e["algorithmic_GBps"] = round(alg_bytes[name] / (ms * 1e-3) / 1e9, 1)
-        if name in alg_ops:
-            e["algorithmic_TOPs"] = round(alg_ops[name] / (ms * 1e-3) / 1e12, 2)
+        if name in res["bytes"]:
+            e["algorithmic_GBps"] = round(res["bytes"][name] / (ms * 1e-3) / 1e9, 1)
+        if name in res["ops"]:
+            e["algorithmic_TFLOPs"] = round(res["ops"][name] / (ms * 1e-3) / 1e12, 2)
         stages[name] = e
-    dom = max(stage_acc, key=lambda k_: stage_acc[k_])
-    dms = stage_acc[dom]
-    kern = STAGE_KERNEL.get(dom, dom)
-    traffic = recorded_traffic(kern, wl.name, args.tile)
-    if dom in alg_ops:
-        ach = alg_ops[dom] / (dms * 1e-3) / 1e12
-        roof = dict(bound="alu", kernel=kern, achieved=round(ach, 3), peak=FP32_VECTOR_PEAK_TFLOPS,
-                    unit="TFLOP/s", frac=round(ach / FP32_VECTOR_PEAK_TFLOPS, 4), traffic=traffic,
-                    ms=round(dms, 4))
-    else:
-        ach = alg_bytes.get(dom, 0) / (dms * 1e-3) / 1e9
-        roof = dict(bound="hbm", kernel=kern, achieved=round(ach, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic,
-                    ms=round(dms, 4))
-    if traffic is not None:
-        roof["traffic_unit"] = "bytes per launch"
-        roof["algorithmic_bytes"] = int(alg_bytes.get(dom, 0))
-    step_bytes = sum(alg_bytes.values())
+    dom = max(res["stage_ms"], key=lambda k_: res["stage_ms"][k_])
+    roof = roofline_of(res, dom, wl.name)
+    roof_fwd = roofline_of(res, "render_fwd", wl.name) if dom != "render_fwd" else None
 
     extras = None
     if not args.no_extras:
-        extras = measure_extras(torch, sc, vw, step.out[0], step.out[1], tc, td, rast=rast)
+        extras = measure_extras(torch, res["sc"], res["vw"], res["step"].out[0],
+                                res["step"].out[1], res["tc"], res["td"], rast=res["rast"])
+    main_sum = summary(res)
+    for k_ in ("rast", "step", "sc", "vw", "tc", "td"):
+        res.pop(k_, None)
+    torch.cuda.empty_cache()
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = time_cpu_baseline(wl, args.cpu_seconds)
+    configs = None
+    if not args.no_configs:
+        # the other workloads at their own sizes: small plain, room 300k plain,
+        # room 1M through the autograd form, the fused SH3 map (batched vs
+        # plain, its own roofline)
+        configs = {}
+        cs = max(2, args.config_steps)
+        for name in ("small", "room", "fused"):
+            w2 = make_workload(name)
+            r2 = run_workload(torch, np, w2, args, cs, 2, tuned=None, tile=(16, 16),
+                              plain_steps=2 if name != "small" else cs)
+            d2 = summary(r2)
+            d2["roofline"] = roofline_of(r2, max(r2["stage_ms"], key=lambda k_: r2["stage_ms"][k_]),
+                                         w2.name)
+            d2["stages_ms"] = {k_: round(v_, 4) for k_, v_ in r2["stage_ms"].items() if v_ > 0}
+            configs[name] = d2
+            print(f"[bench] {w2.name}: {r2['dt'] * 1e3:.3f} ms per step", file=sys.stderr,
+                  flush=True)
+            del r2, w2
+            torch.cuda.empty_cache()
+        configs["room-1m-autograd"] = run_autograd(torch, np, make_workload("room-1m"), cs, 2)
+        torch.cuda.empty_cache()
 
-    n_bwd = int(np.sum(vw_np.needs_grad)) if vw_np.needs_grad is not None else V
-    views_per_s = n_bwd / dt
     line = {
         "metric": "fwd+bwd views/sec and Gaussian-pixel evals/sec, batched vs plain, 1 MI355X",
-        "value": round(views_per_s, 2),
+        "value": main_sum["views_per_s"],
         "unit": "views/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt * 1e3, 4),
+        "ms_per_step": main_sum["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "views": V, "fwd_bwd_views": n_bwd, "width": W, "height": H,
-                   "gaussians": int(sc_np.n), "sets": int(sc_np.n_sets),
-                   "sh_degree": int(sc_np.sh_degree), "tile": f"{tile[0]}x{tile[1]}",
-                   "binning_chunk": int(rast.desc.chunk), "autotuned": tuned is not None,
-                   "form": "batched, hip graph replay" if graph is not None else "batched, eager"},
-        "evals_per_s": round((evals_fwd + evals_bwd) / dt, 1),
-        "evals": {"forward": evals_fwd, "backward": evals_bwd},
-        "counts": {"pairs": P, "visible_pairs": int(nv_pairs), "instances": int(I)},
-        "step_algorithmic_GB": round(step_bytes / 1e9, 3),
-        "step_hbm_roofline_frac": round(step_bytes / (dt * HBM_PEAK_GBS * 1e9), 4),
-        "plain": plain,
+        "config": {"workload": wl.name, "views": res["V"], "fwd_bwd_views": res["n_bwd"],
+                   "width": res["W"], "height": res["H"], "gaussians": int(wl.scene.n),
+                   "sets": int(wl.scene.n_sets), "sh_degree": int(wl.scene.sh_degree),
+                   "tile": main_sum["tile"], "binning_chunk": int(res["opts"]["chunk"]),
+                   "fwd_batch": int(res["opts"]["fwd_batch"]),
+                   "bwd_batch": int(res["opts"]["bwd_batch"]),
+                   "persistent": bool(res["opts"]["persistent"]),
+                   "autotuned": tuned is not None, "form": main_sum["form"]},
+        "evals_per_s": main_sum["evals_per_s"],
+        "evals": main_sum["evals"],
+        "counts": main_sum["counts"],
+        "step_algorithmic_GB": main_sum["step_algorithmic_GB"],
+        "step_hbm_roofline_frac": main_sum["step_hbm_roofline_frac"],
+        "plain": main_sum["plain"],
         "stages_ms": stages,
         "roofline": roof,
+        "roofline_render_fwd": roof_fwd,
+        "autotune": tuned,
+        "configs": configs,
         "extras": extras,
         "cpu_baseline": cpu,
     }
