@@ -84,6 +84,25 @@ def segment_voxels(c, r, v=VOXEL, tie_eps=1e-12):
     return out, amb
 
 
+def ray_ends(depth_k, viewmat, intr):
+    """Segments of one keyframe: camera centre c [3] and the back-projected
+    end point r [H,W,3] of every pixel (pixels with depth <= 0 carve nothing:
+    mask [H,W] of the others).  The R^T products are written out in a fixed
+    order (left to right, no fused multiply-add), so that the camera centre
+    and the end points are reproducible bit for bit."""
+    dep = np.asarray(depth_k, np.float64)
+    H, W = dep.shape
+    vm = np.asarray(viewmat, np.float64).reshape(3, 4)
+    R, tt = vm[:, :3], vm[:, 3]
+    fx, fy, cx, cy = (float(x) for x in intr)
+    c = np.array([-((R[0, a] * tt[0] + R[1, a] * tt[1]) + R[2, a] * tt[2]) for a in range(3)])
+    ii, jj = np.meshgrid(np.arange(W, dtype=np.float64), np.arange(H, dtype=np.float64))
+    rx, ry = (ii + 0.5 - cx) / fx, (jj + 0.5 - cy) / fy
+    r = np.stack([c[a] + dep * ((R[0, a] * rx + R[1, a] * ry) + R[2, a] * 1.0)
+                  for a in range(3)], axis=-1)
+    return c, r, dep > 0.0
+
+
 def free(depth, viewmats, intrinsics, v=VOXEL):
     """Eq. (free_carve) over keyframe depth maps depth [K,H,W]: (set,
     number of ambiguous segments)."""
@@ -92,22 +111,12 @@ def free(depth, viewmats, intrinsics, v=VOXEL):
     n_amb = 0
     K, H, W = dep.shape
     for kf in range(K):
-        vm = np.asarray(viewmats[kf], np.float64).reshape(3, 4)
-        R, tt = vm[:, :3], vm[:, 3]
-        fx, fy, cx, cy = (float(x) for x in intrinsics[kf])
-        # R^T products written out in a fixed order (left to right, no fused
-        # multiply-add), so that the camera centre and the end point are
-        # reproducible bit for bit
-        c = np.array([-((R[0, a] * tt[0] + R[1, a] * tt[1]) + R[2, a] * tt[2]) for a in range(3)])
+        c, r, ok = ray_ends(dep[kf], viewmats[kf], intrinsics[kf])
         for j in range(H):
             for i in range(W):
-                dd = dep[kf, j, i]
-                if not dd > 0.0:
+                if not ok[j, i]:
                     continue
-                ray = ((i + 0.5 - cx) / fx, (j + 0.5 - cy) / fy, 1.0)
-                rpt = np.array([c[a] + dd * ((R[0, a] * ray[0] + R[1, a] * ray[1]) + R[2, a] * ray[2])
-                                for a in range(3)])
-                vox, amb = segment_voxels(c, rpt, v)
+                vox, amb = segment_voxels(c, r[j, i], v)
                 out |= vox
                 n_amb += int(amb)
     return out, n_amb

@@ -77,3 +77,76 @@ def test_dedup_table_grows_on_overflow():
     assert nvox == len(occ) > 4096
     ref = np.array([tuple(q) not in occ for q in voxel_of(sm, 0.05)])
     np.testing.assert_array_equal(keep.cpu().numpy().astype(bool), ref)
+
+
+def _slab_hits(c, r, lo, hi, margin):
+    """Segments c + t (r - c), t in [0, 1], that pass within `margin` of the
+    box [lo, hi] (a conservative prefilter: the oracle's walk decides)."""
+    d = r - c
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t0 = (lo - margin - c) / d
+        t1 = (hi + margin - c) / d
+    tmin = np.where(d == 0, -np.inf, np.minimum(t0, t1))
+    tmax = np.where(d == 0, np.inf, np.maximum(t0, t1))
+    inside = np.all((d != 0) | ((c >= lo - margin) & (c <= hi + margin)), axis=-1)
+    a = np.max(tmin, axis=-1)
+    b = np.min(tmax, axis=-1)
+    return inside & (a <= b) & (b >= -1e-9) & (a <= 1.0 + 1e-9)
+
+
+def test_dedup_full_size_sampled():
+    """A keyframe-sized case: 300k target Gaussians in the part of the room
+    with x < 0.5 m, 200k borrowed Gaussians uniform in the room, eight
+    640 x 480 keyframe depth maps (slanted planes, holes) from cameras on a
+    circle around the room.  Sampled borrowed Gaussians, kept and dropped,
+    against the oracle's definition: the target boxes and keyframe segments
+    that could meet the Gaussian's voxel are preselected with a margin, and
+    the oracle's box rule and segment walk decide."""
+    announce("dedup full size 300k / 200k / 8 x 640x480")
+    import torch
+    from oracle.dedup import occupied, ray_ends, segment_voxels
+    from paper_2605_10760_amd import dedup as gpu_dedup
+    from synth.scenes import slanted_depth
+    rng = np.random.default_rng(21)
+    v, k = 0.05, 1.0
+    lo_room, hi_room = np.array([-3.0, -1.5, -2.0]), np.array([3.0, 1.5, 2.0])
+    tm = rng.uniform(lo_room, [0.5, 1.5, 2.0], (300_000, 3)).astype(np.float32)
+    tls = rng.normal(-3.6, 0.4, (300_000, 3)).astype(np.float32)
+    sm = rng.uniform(lo_room, hi_room, (200_000, 3)).astype(np.float32)
+    K, H, W = 8, 480, 640
+    depth, _, intr = slanted_depth(rng, K, W, H, f=320.0, hole_frac=0.02)
+    depth = (0.6 * depth).astype(np.float32)
+    vms = []
+    for kf in range(K):
+        th = 2 * np.pi * kf / K + 0.3
+        c = np.array([2.6 * np.cos(th), 0.2 * np.sin(3 * th), 1.8 * np.sin(th)])
+        vms.append(look_at(c, (0.0, 0.0, 0.0), 0.1 * np.sin(kf)))
+    vms = np.array(vms, np.float32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    keep, nvox = gpu_dedup(t(sm), t(tm), t(tls), t(depth), t(vms), t(intr.astype(np.float32)), v, k)
+    keep = keep.cpu().numpy().astype(bool)
+    assert 0.05 * keep.size < keep.sum() < 0.95 * keep.size
+    ends = [ray_ends(depth[kf], vms[kf], intr[kf]) for kf in range(K)]
+    s_t = np.exp(tls.astype(np.float64))
+    m_t = tm.astype(np.float64)
+    pick = np.concatenate([rng.choice(np.nonzero(keep)[0], 40, replace=False),
+                           rng.choice(np.nonzero(~keep)[0], 40, replace=False)])
+    for i in pick:
+        q = np.floor(sm[i].astype(np.float64) / v).astype(np.int64)
+        lo, hi = q * v, (q + 1) * v
+        # target Gaussians whose box may reach the voxel
+        near = np.all((m_t + k * s_t >= lo - 1e-6) & (m_t - k * s_t <= hi + 1e-6), axis=1)
+        in_occ = tuple(q) in occupied(tm[near], tls[near], v, k) if near.any() else False
+        in_free = False
+        if not in_occ:
+            for c, r, ok in ends:
+                cand = np.nonzero(ok & _slab_hits(c, r, lo, hi, 1e-6))
+                for j, ii in zip(*cand):
+                    vox, amb = segment_voxels(c, r[j, ii], v)
+                    assert not amb
+                    if tuple(q) in vox:
+                        in_free = True
+                        break
+                if in_free:
+                    break
+        assert keep[i] == (not in_occ and not in_free), (int(i), in_occ, in_free)

@@ -11,12 +11,14 @@ from synth.scenes import multi_agent
 pytestmark = pytest.mark.gpu
 
 
-def test_l1_loss_grad_matches_oracle():
-    announce("refine l1 grad")
+@pytest.mark.parametrize("H,W", [(37, 53), (40, 52)])
+def test_l1_loss_grad_matches_oracle(H, W):
+    """37 x 53: ragged, one pixel at a time; 40 x 52: four pixels per load."""
+    announce(f"refine l1 grad {H}x{W}")
     import torch
     from paper_2605_10760_amd import l1_loss_grad as gpu_grad
     rng = np.random.default_rng(7)
-    V, H, W = 3, 37, 53  # ragged: not a multiple of the 256-pixel blocks
+    V = 3
     c = rng.random((V, 3, H, W)).astype(np.float32)
     d = (0.5 + 3 * rng.random((V, H, W))).astype(np.float32)
     tc = rng.random((V, 3, H, W)).astype(np.float32)
@@ -99,3 +101,46 @@ def test_ssim_grad_matches_oracle(V, H, W):
     sa = np.abs(ref["d_a"]).max()
     np.testing.assert_allclose(ge[:, 0], ref["d_a"], atol=1e-3 * sa)
     np.testing.assert_allclose(ge[:, 1], ref["d_b"], atol=1e-3 * np.abs(ref["d_b"]).max())
+
+
+def test_ssim_grad_full_size_sampled():
+    """The refinement batch's size, 48 views x 3 x 480 x 640: the gradient and
+    exposure gradients of three sampled views against the oracle (the window
+    stays inside a view, so a view's gradient is the one-view oracle's scaled
+    by 1/48), and the batch's mean SSIM against the mean of the 48 one-view
+    means the kernel reports."""
+    V, H, W = 48, 480, 640
+    announce(f"refine ssim full size {V}x3x{H}x{W}")
+    import torch
+    from oracle.ssim import ssim, ssim_term_grad
+    from paper_2605_10760_amd import ssim_grad
+    rng = np.random.default_rng(12)
+    c = rng.random((V, 3, H, W), dtype=np.float32)
+    tgt = np.clip(c + 0.08 * rng.standard_normal(c.shape, dtype=np.float32), 0, 1)
+    ex = np.stack([rng.normal(0, 0.1, V), rng.normal(0, 0.02, V)], 1).astype(np.float32)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    d_color = torch.zeros((V, 3, H, W), device="cuda")
+    d_exp = torch.zeros((V, 2), device="cuda")
+    out = torch.zeros(1, device="cuda")
+    ct, tt, et = t(c), t(tgt), t(ex)
+    ssim_grad(ct, tt, d_color, et, d_exp, 0.2, ssim_out=out)
+    torch.cuda.synchronize()
+    per_view = []
+    one = torch.zeros(1, device="cuda")
+    for v in range(V):
+        ssim_grad(ct[v:v + 1], tt[v:v + 1], torch.zeros((1, 3, H, W), device="cuda"), et[v:v + 1],
+                  None, 0.2, ssim_out=one)
+        per_view.append(one.item())
+    assert abs(out.item() - float(np.mean(per_view))) <= 1e-5
+    g = d_color.cpu().numpy()
+    ge = d_exp.cpu().numpy()
+    for v in (0, 23, 47):
+        ref = ssim_term_grad(c[v:v + 1], tgt[v:v + 1], ex[v:v + 1, 0], ex[v:v + 1, 1], 0.2)
+        xt = np.exp(ex[v, 0]) * c[v:v + 1].astype(np.float64) + ex[v, 1]
+        assert abs(per_view[v] - ssim(xt, tgt[v:v + 1])) <= 2e-5
+        want = ref["d_color"][0] / V
+        assert np.abs(g[v] - want).max() <= 1e-3 * np.abs(want).max(), v
+        np.testing.assert_allclose(ge[v, 0], ref["d_a"][0] / V, rtol=1e-3,
+                                   atol=1e-4 * abs(ref["d_a"][0] / V))
+        np.testing.assert_allclose(ge[v, 1], ref["d_b"][0] / V, rtol=1e-3,
+                                   atol=1e-4 * abs(ref["d_b"][0] / V))
