@@ -180,10 +180,10 @@ class Step:
         for p, k in zip(params, ("d_means", "d_log_scales", "d_quats", "d_opacity_logits", "d_colors")):
             p.grad = self.grads[k]
         lrs = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3)
-        # fused=True: one multi-tensor kernel per step (graph-capturable); the
-        # foreach form runs a dozen elementwise passes over the parameters
-        self.opt = torch.optim.Adam([{"params": [p], "lr": lr * lr_scale} for p, lr in zip(params, lrs)],
-                                    fused=True, capturable=True)
+        # the library's Adam: one launch over the five parameter arrays
+        # (graph-capturable, device step count)
+        from paper_2605_10760_amd import Adam
+        self.opt = Adam([(p, lr * lr_scale) for p, lr in zip(params, lrs)], eps=1e-15)
 
     def __call__(self):
         t = self.t
@@ -515,11 +515,13 @@ def run_autograd(torch, np, wl, steps, warmup):
     td = torch.from_numpy(wl.target_depth).cuda()
     rast = Rasterizer(W, H, P, V)
     lrs = (1.6e-4, 5e-3, 1e-3, 5e-2, 2.5e-3, 1e-3)
-    opt = torch.optim.Adam([{"params": [p], "lr": lr * LR_SCALE}
-                            for p, lr in zip(params + [pose], lrs)], fused=True)
+    from paper_2605_10760_amd import Adam
+    opt = Adam([(p, lr * LR_SCALE) for p, lr in zip(params + [pose], lrs)], eps=1e-15)
 
     def one():
-        opt.zero_grad(set_to_none=False)
+        for p in params + [pose]:
+            if p.grad is not None:
+                p.grad.zero_()
         c, d, _ = rasterize(rast, *params, vm, intr, sc_np.set_offsets, vw_np.view_set, W, H,
                             pose_delta=pose, sh_degree=int(sc_np.sh_degree))
         loss = 0.95 * (c - tc).abs().mean() + 0.25 * (d - td).abs().mean()

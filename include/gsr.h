@@ -38,11 +38,20 @@
  *
  * Memory.  Every float pointer in gsr_scene, gsr_views, gsr_images,
  * gsr_grads and the state buffer is DEVICE memory of the context's GPU,
- * caller-owned, FP32, C-contiguous.  set_offsets and view_set (structure,
- * not values) are HOST arrays read during the call.  The context owns its
- * workspace (allocated by gsr_plan).  Each forward writes its saved state
- * into a caller-owned device buffer of gsr_state_bytes() bytes, which the
- * matching backward reads; several forwards may be alive at once.
+ * caller-owned, FP32, C-contiguous.  set_offsets, view_set and needs_grad
+ * (the call's structure, not its values) are HOST arrays read during the
+ * call and turned into kernel arguments: changing a set's size or a view's
+ * set therefore needs a new call (and a new capture of a graph that holds
+ * the old one), while the Gaussians' values and the cameras may change in
+ * place between replays.  The context owns its workspace (allocated by
+ * gsr_plan).  Each forward writes its saved state into a caller-owned
+ * device buffer of gsr_state_bytes() bytes, which the matching backward
+ * reads; several forwards may be alive at once.
+ *
+ * Limits.  One call renders at most GSR_MAX_VIEWS (64) views of at most
+ * GSR_MAX_SETS (64) Gaussian sets: the per-view tables travel as kernel
+ * arguments and the backward's view mask is one 64-bit word.  Larger batches
+ * are split into several calls (the gradients of the calls add).
  *
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
  * stream).  gsr_forward and gsr_backward only enqueue work: they do not
@@ -399,6 +408,34 @@ gsr_status gsr_seed(const float* depth, const float* color, const float* viewmat
                     float opacity_logit, int64_t max_out, float* means_out,
                     float* log_scales_out, float* quats_out, float* opacity_out,
                     float* colors_out, int64_t* n_out, void* stream);
+
+/* One Adam step (Kingma & Ba 2015) over up to GSR_ADAM_MAX_GROUPS arrays
+ * in one launch: the optimiser of the mapping loss (Sec. III-A, Eq.
+ * (map_loss)) and of the refinement (Sec. III-C, Eq. (refine_loss)), which
+ * the paper minimises by gradient steps with per-parameter learning rates.
+ * With t = *step + 1 and per element
+ *   m <- beta1 m + (1 - beta1) g,   v <- beta2 v + (1 - beta2) g^2,
+ *   p <- p - lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps),
+ * then *step <- t.  All arrays are device FP32 of length n (param, exp_avg
+ * and exp_avg_sq updated in place; exp_avg and exp_avg_sq start at zero and
+ * *step at 0); `step` is a device int32.  The betas are FP64 so that
+ * 1 - beta and the bias corrections 1 - beta^t (which cancel) keep their
+ * digits; the moment updates run in FP32.  Enqueues two kernels on `stream`
+ * (no allocation, no synchronisation: graph-capturable).  GSR_E_INVALID_ARG
+ * for null pointers, n < 0, betas outside [0, 1), eps < 0, n_groups outside
+ * 1..GSR_ADAM_MAX_GROUPS or more than 2^31 - 8 chunks of 1024 elements. */
+#define GSR_ADAM_MAX_GROUPS 8
+typedef struct gsr_adam_group {
+  float* param;
+  const float* grad;
+  float* exp_avg;
+  float* exp_avg_sq;
+  int64_t n;
+  float lr;
+  int32_t reserved;
+} gsr_adam_group;
+gsr_status gsr_adam(const gsr_adam_group* groups, int32_t n_groups, double beta1, double beta2,
+                    double eps, int32_t* step, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): gsr_seed

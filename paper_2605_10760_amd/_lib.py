@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libgsr.so")
 GSR_MAX_VIEWS = 64
 GSR_MAX_SETS = 64
 GSR_SEED_NOALLOC_MAX_POINTS = 1 << 24
+GSR_ADAM_MAX_GROUPS = 8
 
 STATUS = {0: "GSR_OK", 1: "GSR_E_INVALID_ARG", 2: "GSR_E_NOT_PLANNED", 3: "GSR_E_CAPACITY",
           4: "GSR_E_OVERFLOW", 5: "GSR_E_DEVICE", 6: "GSR_E_OOM", 7: "GSR_E_UNIMPLEMENTED"}
@@ -23,7 +24,7 @@ EXPORTED = ("gsr_create", "gsr_destroy", "gsr_plan", "gsr_state_bytes", "gsr_for
             "gsr_last_error", "gsr_sim3_gaussians", "gsr_sim3_views", "gsr_l1_loss_grad",
             "gsr_prune", "gsr_ssim_workspace_bytes", "gsr_ssim_grad",
             "gsr_dedup_workspace_bytes", "gsr_dedup", "gsr_iso_grad", "gsr_normal_loss_grad",
-            "gsr_seed", "gsr_seed_noalloc")
+            "gsr_seed", "gsr_seed_noalloc", "gsr_adam")
 
 STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "render_bwd",
           "project_bwd")
@@ -77,6 +78,12 @@ class Counts(C.Structure):
 
 class DedupParams(C.Structure):
     _fields_ = [("voxel", C.c_double), ("k_env", C.c_double), ("table_slots", C.c_int64)]
+
+
+class AdamGroup(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("exp_avg", C.c_void_p),
+                ("exp_avg_sq", C.c_void_p), ("n", C.c_int64), ("lr", C.c_float),
+                ("reserved", C.c_int32)]
 
 
 class Debug(C.Structure):
@@ -156,6 +163,8 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     lib.gsr_seed_noalloc.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_float,
                                      C.c_int64, vp, vp, vp, vp, vp, vp, vp]
     lib.gsr_seed_noalloc.restype = C.c_int
+    lib.gsr_adam.argtypes = [P(AdamGroup), C.c_int32, C.c_double, C.c_double, C.c_double, vp, vp]
+    lib.gsr_adam.restype = C.c_int
     lib.gsr_status_string.argtypes = [C.c_int]
     lib.gsr_status_string.restype = C.c_char_p
     lib.gsr_last_error.argtypes = [vp]

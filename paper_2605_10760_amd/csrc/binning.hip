@@ -21,6 +21,8 @@
 //                scatter where one wave per segment holds the segment in
 //                registers and, column by column, ranks the entries covering
 //                the column by a wave ballot per 64 entries.
+#include <algorithm>
+
 #include "common.h"
 
 namespace gsr {
@@ -40,30 +42,50 @@ __device__ __forceinline__ void unpack_rect(uint2 r, int& x0, int& y0, int& x1, 
   y1 = r.y >> 16;
 }
 
-// Per chunk: pairs spanning each row (rows[y] for y < TY).
+// Per chunk: pairs spanning each row (rows[y] for y < TY).  A workgroup
+// takes RC_SUB chunks: their rects are loaded together, counted into one 1D
+// difference array per chunk in LDS, and wave k scans chunk k's array.
+constexpr int RC_SUB = 4;
 __global__ __launch_bounds__(256) void k_row_count(BinTab t, StateDev st, uint32_t* counts) {
-  __shared__ int dif[MAX_ROWS + 1];
-  const int b = xcd_remap(blockIdx.x, t.cblk_off[t.nv]);
-  if (b < 0) return;
-  int v, lo, hi;
-  chunk_range(t, st.hdr, b, v, lo, hi);
-  if (lo >= hi) return;
+  __shared__ int dif[RC_SUB][MAX_ROWS + 1];
+  const int nc = t.cblk_off[t.nv];
+  const int g = xcd_remap(blockIdx.x, (nc + RC_SUB - 1) / RC_SUB);
+  if (g < 0) return;
   const int TY = t.TY;
-  for (int i = threadIdx.x; i <= TY; i += 256) dif[i] = 0;
+  int lo[RC_SUB], hi[RC_SUB];
+  uint2 rc[RC_SUB];
+#pragma unroll
+  for (int k = 0; k < RC_SUB; ++k) {
+    const int b = g * RC_SUB + k;
+    lo[k] = hi[k] = 0;
+    if (b < nc) {
+      int v;
+      chunk_range(t, st.hdr, b, v, lo[k], hi[k]);
+    }
+    // a chunk holds at most 256 pairs: one per thread
+    const int i = lo[k] + (int)threadIdx.x;
+    rc[k] = i < hi[k] ? st.rect[st.order[i]] : make_uint2(0u, 0u);
+  }
+  for (int i = threadIdx.x; i < RC_SUB * (MAX_ROWS + 1); i += 256) (&dif[0][0])[i] = 0;
   __syncthreads();
-  for (int i = lo + (int)threadIdx.x; i < hi; i += 256) {
-    int x0, y0, x1, y1;
-    unpack_rect(st.rect[st.order[i]], x0, y0, x1, y1);
-    atomicAdd(&dif[y0], 1);
-    atomicSub(&dif[y1], 1);
+#pragma unroll
+  for (int k = 0; k < RC_SUB; ++k) {
+    if (lo[k] + (int)threadIdx.x < hi[k]) {
+      int x0, y0, x1, y1;
+      unpack_rect(rc[k], x0, y0, x1, y1);
+      atomicAdd(&dif[k][y0], 1);
+      atomicSub(&dif[k][y1], 1);
+    }
   }
   __syncthreads();
-  if (threadIdx.x < 64) {
-    // wave-wide inclusive scan of the difference array, 64 rows at a time
+  // wave k: inclusive scan of chunk k's difference array, 64 rows at a time
+  const int k = threadIdx.x >> 6;
+  const int b = g * RC_SUB + k;
+  if (b < nc && lo[k] < hi[k]) {
     int carry = 0;
     for (int base = 0; base < TY; base += 64) {
-      const int y = base + (int)threadIdx.x;
-      const int x = y < TY ? dif[y] : 0;
+      const int y = base + lane_id();
+      const int x = y < TY ? dif[k][y] : 0;
       const int inc = (int)wave_incl_scan((uint32_t)x) + carry;
       if (y < TY) counts[(size_t)b * TY + y] = (uint32_t)inc;
       carry = __shfl(inc, 63, 64);
@@ -126,9 +148,12 @@ __global__ __launch_bounds__(CS_COLS* CS_SEGS) void k_colscan(BinTab t, const St
   }
 }
 
-// One workgroup: exclusive scan of n bucket totals into [first, last+1)
-// ranges ((0, 0) when empty), the grand total into *total (if given) and the
-// capacity flag into *flag (set when the total exceeds cap).
+// Exclusive scan of n bucket totals into [first, last+1) ranges ((0, 0)
+// when empty), over ceil(n / RS_TILE) workgroups: workgroup b scans tile b
+// after summing every total before it; the last workgroup writes the grand
+// total into *total (if given) and the capacity flag into *flag (set when
+// the total exceeds cap).
+constexpr int RS_TILE = 4096;  // 1024 threads x 4 totals
 __global__ __launch_bounds__(1024) void k_range_scan(int n, const uint32_t* cnt, uint2* ranges,
                                                     unsigned long long cap,
                                                     unsigned long long* total,
@@ -136,37 +161,45 @@ __global__ __launch_bounds__(1024) void k_range_scan(int n, const uint32_t* cnt,
                                                     const unsigned int* prior_flag,
                                                     const unsigned long long* prior_total) {
   __shared__ unsigned long long sh[17];
-  unsigned long long carry = 0;
-  for (int base = 0; base < n; base += 4096) {
-    const int i0 = base + 4 * (int)threadIdx.x;
-    uint32_t x[4];
-    unsigned long long s = 0;
+  const int base = (int)blockIdx.x * RS_TILE;
+  const unsigned long long carry = wg_sum_before<1024>(cnt, base, sh);
+  const int i0 = base + 4 * (int)threadIdx.x;
+  uint32_t x[4];
+  unsigned long long s = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      x[k] = (i0 + k < n) ? cnt[i0 + k] : 0u;
-      s += x[k];
-    }
-    unsigned long long tot;
-    unsigned long long pre = wg_excl_scan<1024>(s, sh, &tot) + carry;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i0 + k < n) {
-        const uint32_t a = (uint32_t)min(pre, 0xFFFFFFFFull);
-        const uint32_t e = (uint32_t)min(pre + x[k], 0xFFFFFFFFull);
-        ranges[i0 + k] = x[k] ? make_uint2(a, e) : make_uint2(0u, 0u);
-      }
-      pre += x[k];
-    }
-    carry += tot;
+  for (int k = 0; k < 4; ++k) {
+    x[k] = (i0 + k < n) ? cnt[i0 + k] : 0u;
+    s += x[k];
   }
-  if (threadIdx.x == 0) {
+  unsigned long long tot;
+  unsigned long long pre = wg_excl_scan<1024>(s, sh, &tot) + carry;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < n) {
+      const uint32_t a = (uint32_t)min(pre, 0xFFFFFFFFull);
+      const uint32_t e = (uint32_t)min(pre + x[k], 0xFFFFFFFFull);
+      ranges[i0 + k] = x[k] ? make_uint2(a, e) : make_uint2(0u, 0u);
+    }
+    pre += x[k];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    unsigned long long all = carry + tot;
     // an earlier level that overflowed leaves this level's counts empty: keep
     // the flag and report the earlier level's total as a lower bound
     const bool prior = prior_flag && *prior_flag;
-    if (prior && prior_total && *prior_total > carry) carry = *prior_total;
-    if (total) *total = carry;
-    *flag = (prior || carry > cap) ? 1u : 0u;
+    if (prior && prior_total && *prior_total > all) all = *prior_total;
+    if (total) *total = all;
+    *flag = (prior || all > cap) ? 1u : 0u;
   }
+}
+
+static void range_scan(int n, const uint32_t* cnt, uint2* ranges, unsigned long long cap,
+                       unsigned long long* total, unsigned int* flag,
+                       const unsigned int* prior_flag, const unsigned long long* prior_total,
+                       hipStream_t s) {
+  const int nb = std::max(1, (n + RS_TILE - 1) / RS_TILE);
+  hipLaunchKernelGGL(k_range_scan, dim3(nb), dim3(1024), 0, s, n, cnt, ranges, cap, total, flag,
+                     prior_flag, prior_total);
 }
 
 // Wave-wide minimum / maximum (every lane active), returned in every lane.
@@ -256,10 +289,9 @@ __global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, cons
 // long row is spread over many workgroups; segment s of row r covers
 // entries [row_rg[r].x + (s - seg_off[r]) * SEG, ...) of that row.
 
-// One workgroup: segment offsets of the row lists and the row of every
-// segment (zero segments when the row level overflowed).
+// One workgroup: segment offsets of the row lists (zero segments when the
+// row level overflowed).
 __global__ __launch_bounds__(1024) void k_seg_scan(int n, const uint2* row_rg, uint32_t* seg_off,
-                                                  uint32_t* seg_row,
                                                   const unsigned int* row_flag) {
   __shared__ unsigned long long sh[17];
   const bool off = *row_flag != 0u;
@@ -273,13 +305,17 @@ __global__ __launch_bounds__(1024) void k_seg_scan(int n, const uint2* row_rg, u
     }
     unsigned long long tot;
     const unsigned long long pre = wg_excl_scan<1024>(ns, sh, &tot) + carry;
-    if (r < n) {
-      seg_off[r] = (uint32_t)pre;
-      for (uint32_t k = 0; k < ns; ++k) seg_row[pre + k] = (uint32_t)r;
-    }
+    if (r < n) seg_off[r] = (uint32_t)pre;
     carry += tot;
   }
   if (threadIdx.x == 0) seg_off[n] = (uint32_t)carry;
+}
+
+// One workgroup per row list: the row of each of its segments.
+__global__ __launch_bounds__(256) void k_seg_rows(const uint32_t* seg_off, uint32_t* seg_row) {
+  const int r = blockIdx.x;
+  const uint32_t s0 = seg_off[r], s1 = seg_off[r + 1];
+  for (uint32_t k = s0 + threadIdx.x; k < s1; k += 256) seg_row[k] = (uint32_t)r;
 }
 
 // Row r and entry range [lo, hi) of segment s.
@@ -455,25 +491,26 @@ hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStr
   const int nrows = t.nv * t.TY;
   // level 1: rows
   if (nc > 0)
-    hipLaunchKernelGGL(k_row_count, dim3(xcd_grid(nc)), dim3(256), 0, s, t, st, w.counts);
+    hipLaunchKernelGGL(k_row_count, dim3(xcd_grid((nc + RC_SUB - 1) / RC_SUB)), dim3(256), 0, s,
+                       t, st, w.counts);
   hipLaunchKernelGGL(k_colscan, dim3((nrows + CS_COLS - 1) / CS_COLS), dim3(CS_COLS * CS_SEGS),
                      0, s, t, st.hdr, t.TY, w.counts, w.row_tot);
-  hipLaunchKernelGGL(k_range_scan, dim3(1), dim3(1024), 0, s, nrows, w.row_tot, w.row_rg,
-                     w.row_cap, &st.hdr->row_total, w.row_flag, (const unsigned int*)nullptr,
-                     (const unsigned long long*)nullptr);
+  range_scan(nrows, w.row_tot, w.row_rg, w.row_cap, &st.hdr->row_total, w.row_flag,
+             (const unsigned int*)nullptr, (const unsigned long long*)nullptr, s);
   if (nc > 0)
     hipLaunchKernelGGL(k_row_scatter, dim3(xcd_grid((nc + 3) / 4)), dim3(256), 0, s, t, st,
                        w.counts, w.row_rg, w.rows, w.row_flag);
   // level 2: tiles, per row segment
   hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, s, nrows, w.row_rg, w.seg_off,
-                     w.seg_row, w.row_flag);
+                     w.row_flag);
+  if (nrows > 0)
+    hipLaunchKernelGGL(k_seg_rows, dim3(nrows), dim3(256), 0, s, w.seg_off, w.seg_row);
   hipLaunchKernelGGL(k_tile_count, dim3(w.seg_grid), dim3(256), 0, s, nrows, t.TX, w.seg_off,
                      w.seg_row, w.row_rg, w.rows, w.seg_cnt);
   hipLaunchKernelGGL(k_seg_colscan, dim3((nrows * t.TX + 255) / 256), dim3(256), 0, s, nrows,
                      t.TX, w.seg_off, w.seg_cnt, w.tile_cnt);
-  hipLaunchKernelGGL(k_range_scan, dim3(1), dim3(1024), 0, s, t.nv * t.T, w.tile_cnt, st.ranges,
-                     st.cap, &st.hdr->inst_total, &st.hdr->overflow, w.row_flag,
-                     &st.hdr->row_total);
+  range_scan(t.nv * t.T, w.tile_cnt, st.ranges, st.cap, &st.hdr->inst_total, &st.hdr->overflow,
+             w.row_flag, &st.hdr->row_total, s);
   hipLaunchKernelGGL(k_tile_scatter, dim3(w.seg_grid), dim3(64 * TS_WAVES), 0, s, t, st,
                      w.seg_off, w.seg_row, w.seg_cnt, w.row_rg, w.rows);
   return hipGetLastError();

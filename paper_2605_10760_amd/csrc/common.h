@@ -100,4 +100,85 @@ __device__ __forceinline__ unsigned long long wg_excl_scan(unsigned long long x,
   return r;
 }
 
+// FP64 3D covariance Sigma = M M^T, M = R diag(s), of a Gaussian from its
+// FP32 log-scales and (unnormalised) quaternion (w, x, y, z).  The scales,
+// the normalised quaternion and the rotation are formed in FP32 (a ~1e-7
+// relative perturbation of the parameters); the products, where elongated
+// splats cancel, run in FP64.  The projection and its backward share this
+// code, so the backward maps gradients through the very conic the forward
+// rendered with.
+__device__ __forceinline__ void cov3_fp64(const float* ls, const float* q, double Sd[3][3]) {
+  const float sv[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
+  const float qi = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const float qw = q[0] * qi, qx = q[1] * qi, qy = q[2] * qi, qz = q[3] * qi;
+  const float R[3][3] = {{1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy)},
+                         {2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx)},
+                         {2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
+  double M[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[i][j] = (double)R[i][j] * (double)sv[j];
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      Sd[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
+      Sd[j][i] = Sd[i][j];
+    }
+}
+
+// FP64 camera-space mean p, its guard-clamped-free ratios (p_x/p_z, p_y/p_z)
+// and the dilated 2D covariance [[a, b], [b, c]] = J (Rc Sigma Rc^T) J^T +
+// 0.3 I of a Gaussian in one view (J at the guard-clamped ratios).
+struct ScreenCov {
+  double p[3];
+  double rx, ry;
+  double a, b, c;
+};
+__device__ __forceinline__ ScreenCov screen_cov_fp64(const double Sd[3][3], const float* Rc,
+                                                     const float* tc, const float* m, float fxf,
+                                                     float fyf, int W, int H) {
+  ScreenCov o;
+  double Wd[3][3], V[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k)
+      Wd[i][k] = (double)Rc[3 * i] * Sd[0][k] + (double)Rc[3 * i + 1] * Sd[1][k] +
+                 (double)Rc[3 * i + 2] * Sd[2][k];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      V[i][j] = Wd[i][0] * Rc[3 * j] + Wd[i][1] * Rc[3 * j + 1] + Wd[i][2] * Rc[3 * j + 2];
+  for (int i = 0; i < 3; ++i)
+    o.p[i] = (double)Rc[3 * i] * m[0] + (double)Rc[3 * i + 1] * m[1] +
+             (double)Rc[3 * i + 2] * m[2] + (double)tc[i];
+  const double fx = fxf, fy = fyf;
+  const double ip2 = 1.0 / o.p[2];
+  o.rx = o.p[0] * ip2;
+  o.ry = o.p[1] * ip2;
+  const double limx = 1.3 * (0.5 * W) / fx, limy = 1.3 * (0.5 * H) / fy;
+  const double rxc = fmin(fmax(o.rx, -limx), limx), ryc = fmin(fmax(o.ry, -limy), limy);
+  const double j00 = fx * ip2, j02 = -fx * rxc * ip2;
+  const double j11 = fy * ip2, j12 = -fy * ryc * ip2;
+  const double T00 = j00 * V[0][0] + j02 * V[2][0], T01 = j00 * V[0][1] + j02 * V[2][1];
+  const double T02 = j00 * V[0][2] + j02 * V[2][2];
+  const double T11 = j11 * V[1][1] + j12 * V[2][1], T12 = j11 * V[1][2] + j12 * V[2][2];
+  o.a = T00 * j00 + T02 * j02 + 0.3;
+  o.b = T01 * j11 + T02 * j12;
+  o.c = T11 * j11 + T12 * j12 + 0.3;
+  return o;
+}
+
+// Sum of x[0, n) (n a multiple of 4) over a workgroup of NT threads,
+// returned in every thread: the carry of a multi-workgroup scan whose
+// workgroup reads every element before its own tile (the tiles are few, so
+// the redundant reads stay in L2).  Contains __syncthreads().
+template <int NT>
+__device__ __forceinline__ unsigned long long wg_sum_before(const uint32_t* x, int n,
+                                                            unsigned long long* sh) {
+  unsigned long long part = 0;
+  for (int i = 4 * (int)threadIdx.x; i < n; i += 4 * NT) {
+    const uint4 q = *reinterpret_cast<const uint4*>(x + i);
+    part += (unsigned long long)q.x + q.y + q.z + q.w;
+  }
+  unsigned long long tot;
+  (void)wg_excl_scan<NT>(part, sh, &tot);
+  return tot;
+}
+
 }  // namespace gsr

@@ -97,13 +97,14 @@ static_assert(sizeof(StateHeader) <= STATE_HEADER_BYTES, "header");
 
 // Byte offsets of the arrays inside a saved-state buffer (all 256-aligned).
 struct StateLayout {
-  size_t hdr, zkey, rect, rec, order, ranges, torder, inst, tfinal, last, total;
+  size_t hdr, zkey, vidx, rect, rec, order, ranges, torder, inst, tfinal, last, total;
 };
 
 // Pointers into a saved-state buffer.
 struct StateDev {
   StateHeader* hdr;
   uint32_t* zkey;     // [P]
+  uint32_t* vidx;     // [P] position in the compacted visible list, CULLED if culled
   uint2* rect;        // [P] packed (x0 | y0 << 16, x1 | y1 << 16)
   float4* rec;        // [P][3]: (u, v, A', B'), (C', sigma, z, ex), (r, g, b, ey)
   uint32_t* order;    // [P] pair ids in (view, depth, id) order
@@ -147,8 +148,8 @@ StateDev state_ptrs(void* base, const gsr_plan_desc& p);
 // ------------------------------------------------------------------ launches
 hipError_t launch_project(const ProjTab& t, const SceneDev& sc, const CamDev& cam,
                           StateDev st, uint32_t* blk_cnt, hipStream_t s);
-hipError_t launch_compact(const ProjTab& t, StateDev st, uint32_t* blk_cnt,
-                          uint32_t* keys_out, uint32_t* vals_out, hipStream_t s);
+hipError_t launch_compact(const ProjTab& t, StateDev st, const uint32_t* blk_cnt,
+                          uint32_t* blk_scan, uint32_t* kout, uint32_t* vout, hipStream_t s);
 hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
                              uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s);
 hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStream_t s);
@@ -208,6 +209,8 @@ hipError_t launch_seed(int W, int H, int stride, const float* depth, const float
                        const float* vm, const float* intr, float opac_logit, long max_out,
                        uint32_t* blk, float* m, float* ls, float* q, float* o, float* c,
                        hipStream_t s);
+hipError_t launch_adam(const gsr_adam_group* gr, int ng, double b1, double b2, double eps,
+                       int32_t* step, hipStream_t s);
 hipError_t seed_scratch(uint32_t** out);
 hipError_t launch_seed_total(const uint32_t* blk, int nb, int64_t* n_out, hipStream_t s);
 

@@ -10,6 +10,8 @@
 // parameters are read once per Gaussian (coalesced AoS rows); writes are one
 // 48-byte record, one 8-byte rect and one 4-byte key per pair, and one
 // visible count per 256-pair block for the ordered compaction that follows.
+#include <algorithm>
+
 #include "common.h"
 
 namespace gsr {
@@ -200,20 +202,7 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
   float sigf = 0.f, k2f = 0.f;
   float col[3] = {0.f, 0.f, 0.f};
   {
-    const float sv[3] = {expf(ls[0]), expf(ls[1]), expf(ls[2])};
-    const float qi = 1.f / sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
-    const float qw = q[0] * qi, qx = q[1] * qi, qy = q[2] * qi, qz = q[3] * qi;
-    const float R[3][3] = {{1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy)},
-                           {2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx)},
-                           {2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
-    double M[3][3];
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) M[i][j] = (double)R[i][j] * (double)sv[j];
-    for (int i = 0; i < 3; ++i)
-      for (int j = i; j < 3; ++j) {
-        Sd[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
-        Sd[j][i] = Sd[i][j];
-      }
+    cov3_fp64(ls, q, Sd);
     sigf = 1.f / (1.f + expf(-o));
     // half-extents of the alpha >= 1/255 ellipse use k2f, widened by a
     // margin far above FP32 rounding: every pixel outside that box has
@@ -238,31 +227,11 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
     if (valid) st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
     if (vis) {
       st.rect[pair] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
-      double Wd[3][3], V[3][3];
-      for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k)
-          Wd[i][k] = (double)Rc[3 * i] * Sd[0][k] + (double)Rc[3 * i + 1] * Sd[1][k] +
-                     (double)Rc[3 * i + 2] * Sd[2][k];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          V[i][j] = Wd[i][0] * Rc[3 * j] + Wd[i][1] * Rc[3 * j + 1] + Wd[i][2] * Rc[3 * j + 2];
-      double p[3];
-      for (int i = 0; i < 3; ++i)
-        p[i] = (double)Rc[3 * i] * m[0] + (double)Rc[3 * i + 1] * m[1] +
-               (double)Rc[3 * i + 2] * m[2] + (double)tc[i];
+      ScreenCov sc2 = screen_cov_fp64(Sd, Rc, tc, m, in.x, in.y, t.W, t.H);
       const double fx = in.x, fy = in.y;
-      const double ip2 = 1.0 / p[2];
-      const double rx = p[0] * ip2, ry = p[1] * ip2;
-      const double limx = 1.3 * (0.5 * t.W) / fx, limy = 1.3 * (0.5 * t.H) / fy;
-      const double rxc = fmin(fmax(rx, -limx), limx), ryc = fmin(fmax(ry, -limy), limy);
-      const double j00 = fx * ip2, j02 = -fx * rxc * ip2;
-      const double j11 = fy * ip2, j12 = -fy * ryc * ip2;
-      const double T00 = j00 * V[0][0] + j02 * V[2][0], T01 = j00 * V[0][1] + j02 * V[2][1];
-      const double T02 = j00 * V[0][2] + j02 * V[2][2];
-      const double T11 = j11 * V[1][1] + j12 * V[2][1], T12 = j11 * V[1][2] + j12 * V[2][2];
-      const double a = T00 * j00 + T02 * j02 + 0.3;
-      const double bb = T01 * j11 + T02 * j12;
-      const double c = T11 * j11 + T12 * j12 + 0.3;
+      const double* p = sc2.p;
+      const double rx = sc2.rx, ry = sc2.ry;
+      const double a = sc2.a, bb = sc2.b, c = sc2.c;
       const double det = a * c - bb * bb;
       const double u = fx * rx + (double)in.z, vv = fy * ry + (double)in.w;
       float cv[3] = {col[0], col[1], col[2]};
@@ -302,66 +271,100 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
   }
 }
 
-// Exclusive scan of the per-block visible counts (one workgroup) and the
-// per-view offsets of the compacted, view-major visible-pair list.
-__global__ __launch_bounds__(1024) void k_scan_blocks(ProjTab t, uint32_t* blk, StateHeader* hdr) {
+// Exclusive scan of the per-block visible counts and the per-view offsets
+// of the compacted, view-major visible-pair list, over ceil(nb / 4096)
+// workgroups: workgroup b scans tile b after summing every count before it,
+// writes the offset of each view whose first block falls in its tile, and
+// the last workgroup writes the total.
+constexpr int SB_TILE = 4096;  // 1024 threads x 4 counts
+__global__ __launch_bounds__(1024) void k_scan_blocks(ProjTab t, const uint32_t* blk,
+                                                     uint32_t* scan, StateHeader* hdr) {
   __shared__ unsigned long long sh[17];
   const int nb = t.blk_off[t.nv];
-  unsigned long long carry = 0;
-  for (int base = 0; base < nb; base += 1024 * 4) {
-    const int i0 = base + 4 * (int)threadIdx.x;
-    uint32_t x[4];
-    unsigned long long s = 0;
+  const int base = (int)blockIdx.x * SB_TILE;
+  const unsigned long long carry = wg_sum_before<1024>(blk, base, sh);
+  const int i0 = base + 4 * (int)threadIdx.x;
+  uint32_t x[4];
+  unsigned long long s = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      x[k] = (i0 + k < nb) ? blk[i0 + k] : 0u;
-      s += x[k];
-    }
-    unsigned long long tot;
-    unsigned long long pre = wg_excl_scan<1024>(s, sh, &tot) + carry;
+  for (int k = 0; k < 4; ++k) {
+    x[k] = (i0 + k < nb) ? blk[i0 + k] : 0u;
+    s += x[k];
+  }
+  unsigned long long tot;
+  unsigned long long pre = wg_excl_scan<1024>(s, sh, &tot) + carry;
+  // the prefix goes to its own array: later workgroups still read the counts
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      if (i0 + k < nb) blk[i0 + k] = (uint32_t)pre;
-      pre += x[k];
-    }
-    carry += tot;
+  for (int k = 0; k < 4; ++k) {
+    if (i0 + k < nb) scan[i0 + k] = (uint32_t)pre;
+    pre += x[k];
+  }
+  const bool last = blockIdx.x == gridDim.x - 1;
+  const unsigned long long all = carry + tot;
+  if (last && threadIdx.x == 0) {
+    hdr->vis_total = (uint32_t)all;
+    hdr->vis_off[t.nv] = (uint32_t)all;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    hdr->vis_total = (uint32_t)carry;
-    hdr->vis_off[t.nv] = (uint32_t)carry;
+  // view offsets: the scanned value of the view's first block, or the total
+  // for views whose blocks start at nb (empty views at the end)
+  for (int v = threadIdx.x; v < t.nv; v += 1024) {
+    const int f = t.blk_off[v];
+    if (f >= base && f < base + SB_TILE && f < nb) hdr->vis_off[v] = scan[f];
+    else if (f >= nb && last) hdr->vis_off[v] = (uint32_t)all;
   }
-  for (int v = threadIdx.x; v < t.nv; v += 1024)
-    hdr->vis_off[v] = (t.blk_off[v] < nb) ? blk[t.blk_off[v]] : (uint32_t)carry;
 }
 
-// Ordered compaction: visible pairs keep their (view-major, id) order.
+// Ordered compaction: visible pairs keep their (view-major, id) order.  A
+// workgroup takes CP_SUB consecutive 256-pair blocks (their keys loaded
+// together, then compacted block by block).
+constexpr int CP_SUB = 4;
 __global__ __launch_bounds__(PROJ_BLOCK) void k_compact(ProjTab t, StateDev st,
                                                         const uint32_t* blk_scan,
                                                         uint32_t* kout, uint32_t* vout) {
-  const int b = xcd_remap(blockIdx.x, t.blk_off[t.nv]);
-  if (b < 0) return;
-  const int v = find_seg(t.blk_off, t.nv, b);
-  const int local = (b - t.blk_off[v]) * PROJ_BLOCK + (int)threadIdx.x;
-  const int n = t.pair_off[v + 1] - t.pair_off[v];
-  bool vis = false;
-  uint32_t key = CULLED;
-  const int pair = t.pair_off[v] + local;
-  if (local < n) {
-    key = st.zkey[pair];
-    vis = key != CULLED;
-  }
-  const unsigned long long m = __ballot(vis);
+  const int nb = t.blk_off[t.nv];
+  const int g = xcd_remap(blockIdx.x, (nb + CP_SUB - 1) / CP_SUB);
+  if (g < 0) return;
+  __shared__ int wc[CP_SUB][PROJ_BLOCK / 64];
   const int lane = lane_id(), w = threadIdx.x >> 6;
-  const int rank = __popcll(m & ((1ull << lane) - 1ull));
-  __shared__ int wc[PROJ_BLOCK / 64];
-  if (lane == 0) wc[w] = __popcll(m);
+  uint32_t key[CP_SUB];
+  int pair[CP_SUB];
+  bool in[CP_SUB];
+#pragma unroll
+  for (int k = 0; k < CP_SUB; ++k) {
+    const int b = g * CP_SUB + k;
+    in[k] = false;
+    key[k] = CULLED;
+    pair[k] = 0;
+    if (b < nb) {
+      const int v = find_seg(t.blk_off, t.nv, b);
+      const int local = (b - t.blk_off[v]) * PROJ_BLOCK + (int)threadIdx.x;
+      pair[k] = t.pair_off[v] + local;
+      in[k] = local < t.pair_off[v + 1] - t.pair_off[v];
+      if (in[k]) key[k] = st.zkey[pair[k]];
+    }
+  }
+  unsigned long long m[CP_SUB];
+#pragma unroll
+  for (int k = 0; k < CP_SUB; ++k) {
+    m[k] = __ballot(key[k] != CULLED);
+    if (lane == 0) wc[k][w] = __popcll(m[k]);
+  }
   __syncthreads();
-  if (vis) {
-    uint32_t pos = blk_scan[b] + rank;
-    for (int i = 0; i < w; ++i) pos += wc[i];
-    kout[pos] = key;
-    vout[pos] = (uint32_t)pair;
+#pragma unroll
+  for (int k = 0; k < CP_SUB; ++k) {
+    const int b = g * CP_SUB + k;
+    if (b >= nb) break;
+    uint32_t pos = CULLED;
+    if (key[k] != CULLED) {
+      pos = blk_scan[b] + (uint32_t)__popcll(m[k] & ((1ull << lane) - 1ull));
+      for (int i = 0; i < w; ++i) pos += wc[k][i];
+      kout[pos] = key[k];
+      vout[pos] = (uint32_t)pair[k];
+    }
+    // position of the pair in the compacted visible list (the row of its
+    // screen-space gradient), CULLED for culled pairs
+    if (in[k]) st.vidx[pair[k]] = pos;
   }
 }
 
@@ -421,12 +424,14 @@ hipError_t launch_project(const ProjTab& t, const SceneDev& sc, const CamDev& ca
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const ProjTab& t, StateDev st, uint32_t* blk_cnt, uint32_t* kout,
-                          uint32_t* vout, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, t, blk_cnt, st.hdr);
+hipError_t launch_compact(const ProjTab& t, StateDev st, const uint32_t* blk_cnt,
+                          uint32_t* blk_scan, uint32_t* kout, uint32_t* vout, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan_blocks, dim3(std::max(1, (t.blk_off[t.nv] + SB_TILE - 1) / SB_TILE)),
+                     dim3(1024), 0, s, t, blk_cnt, blk_scan, st.hdr);
   const int nb = t.blk_off[t.nv];
   if (nb > 0)
-    hipLaunchKernelGGL(k_compact, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, st, blk_cnt, kout, vout);
+    hipLaunchKernelGGL(k_compact, dim3(xcd_grid((nb + CP_SUB - 1) / CP_SUB)), dim3(PROJ_BLOCK), 0,
+                       s, t, st, blk_scan, kout, vout);
   return hipGetLastError();
 }
 

@@ -77,12 +77,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
 
   float m[3] = {0.f, 0.f, 0.f}, sv[3] = {1.f, 1.f, 1.f}, qh[4] = {1.f, 0.f, 0.f, 0.f};
   float qn = 1.f, R[3][3], M[3][3], S3[3][3];
+  float lsv[3] = {0.f, 0.f, 0.f}, q4v[4] = {1.f, 0.f, 0.f, 0.f};
   if (valid) {
     for (int k = 0; k < 3; ++k) {
       m[k] = sc.means[3 * gi + k];
-      sv[k] = expf(sc.log_scales[3 * gi + k]);
+      lsv[k] = sc.log_scales[3 * gi + k];
+      sv[k] = expf(lsv[k]);
     }
     const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
+    q4v[0] = q4.x; q4v[1] = q4.y; q4v[2] = q4.z; q4v[3] = q4.w;
     qn = sqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
     qh[0] = q4.x / qn; qh[1] = q4.y / qn; qh[2] = q4.z / qn; qh[3] = q4.w / qn;
   }
@@ -96,6 +99,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
     for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sv[j];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) S3[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
+  // the forward's FP64 covariance (the conic is recomputed per view from it
+  // rather than read back from the screen-space record)
+  double Sd[3][3];
+  cov3_fp64(lsv, q4v, Sd);
 
   float gm[3] = {0.f, 0.f, 0.f};
   float GS3[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
@@ -108,13 +115,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
     const int v = t.view_by_set[vi];
     float pose[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     const int pair = t.pair_off[v] + local;
-    if (valid && st.zkey[pair] != CULLED) {
+    // row of the pair's screen-space gradient: its visible-list position
+    const uint32_t row = valid ? st.vidx[pair] : CULLED;
+    if (row != CULLED) {
       const float* vm = cam.viewmats + 12 * v;
       const float Rc[3][3] = {{vm[0], vm[1], vm[2]}, {vm[4], vm[5], vm[6]}, {vm[8], vm[9], vm[10]}};
       const float tc[3] = {vm[3], vm[7], vm[11]};
       const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
       const float fx = in.x, fy = in.y;
-      float2* g10 = reinterpret_cast<float2*>(grad2d + (size_t)GRAD2D * pair);
+      float2* g10 = reinterpret_cast<float2*>(grad2d + (size_t)GRAD2D * row);
       const float2 q0 = g10[0], q1 = g10[1], q2 = g10[2], q3 = g10[3], q4 = g10[4];
       // consume and clear the row: rows are zero between backward calls
 #pragma unroll
@@ -122,10 +131,18 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
       const float gu = q0.x, gv = q0.y, gA = q1.x, gB = q1.y, gC = q2.x;
       const float gs = q2.y, gz = q4.y;
       float gc[3] = {q3.x, q3.y, q4.x};
-      const float4 r0 = st.rec[3 * (size_t)pair], r1 = st.rec[3 * (size_t)pair + 1];
-      // unscale the stored conic (see the projection's record)
-      constexpr float LN2 = 0.6931471805599453f;
-      const float A = -2.f * LN2 * r0.z, B = -LN2 * r0.w, C = -2.f * LN2 * r1.x;
+      // the conic (A, B, C) = (c, -b, a) / det of the forward's FP64 2D
+      // covariance, recomputed (no read of the record)
+      float A, B, C;
+      {
+        const float Rf[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
+        const float tf[3] = {vm[3], vm[7], vm[11]};
+        const ScreenCov s2 = screen_cov_fp64(Sd, Rf, tf, m, fx, fy, t.W, t.H);
+        const double idet = 1.0 / (s2.a * s2.c - s2.b * s2.b);
+        A = (float)(s2.c * idet);
+        B = (float)(-s2.b * idet);
+        C = (float)(s2.a * idet);
+      }
 
       float p[3];
       for (int i = 0; i < 3; ++i) p[i] = Rc[i][0] * m[0] + Rc[i][1] * m[1] + Rc[i][2] * m[2] + tc[i];

@@ -21,7 +21,14 @@ __global__ __launch_bounds__(256) void k_zero_f32(float* p, int n) {
 }
 
 // A view's pixels are spread over blocks_per_view blocks that stride through
-// them, so the exposure sums take few atomics per view.
+// them, so the exposure sums take few atomics per view.  Pixels go four at a
+// time (16-byte loads and stores) when the plane size and every pointer
+// allow it, one at a time otherwise.
+__device__ __forceinline__ float l1_sign(float e, float w) {
+  return e > 0.f ? w : (e < 0.f ? -w : 0.f);
+}
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_l1_grad(int HW, int blocks_per_view, const float* color,
                                                  const float* depth, const float* tcol,
                                                  const float* tdep, const float* expo,
@@ -33,21 +40,47 @@ __global__ __launch_bounds__(256) void k_l1_grad(int HW, int blocks_per_view, co
   const float a = expo ? expo[2 * v] : 0.f, b = expo ? expo[2 * v + 1] : 0.f;
   const float ea = expf(a);
   float sa = 0.f, sb = 0.f;
-  for (int p = b0 * 256 + (int)threadIdx.x; p < HW; p += blocks_per_view * 256) {
-    const size_t base = (size_t)v * 3 * HW + p;
+  if (VEC) {
+    const int n4 = HW / 4;
+    for (int p = b0 * 256 + (int)threadIdx.x; p < n4; p += blocks_per_view * 256) {
+      const size_t base = (size_t)v * 3 * HW + 4 * (size_t)p;
 #pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-      const float c = color[base + (size_t)ch * HW];
-      const float e = ea * c + b - tcol[base + (size_t)ch * HW];
-      const float g = e > 0.f ? w_col : (e < 0.f ? -w_col : 0.f);
-      g_col[base + (size_t)ch * HW] = ea * g;
-      sa += c * g;
-      sb += g;
+      for (int ch = 0; ch < 3; ++ch) {
+        const float4 c = *reinterpret_cast<const float4*>(color + base + (size_t)ch * HW);
+        const float4 t = *reinterpret_cast<const float4*>(tcol + base + (size_t)ch * HW);
+        const float4 g = make_float4(l1_sign(ea * c.x + b - t.x, w_col),
+                                     l1_sign(ea * c.y + b - t.y, w_col),
+                                     l1_sign(ea * c.z + b - t.z, w_col),
+                                     l1_sign(ea * c.w + b - t.w, w_col));
+        *reinterpret_cast<float4*>(g_col + base + (size_t)ch * HW) =
+            make_float4(ea * g.x, ea * g.y, ea * g.z, ea * g.w);
+        sa += c.x * g.x + c.y * g.y + c.z * g.z + c.w * g.w;
+        sb += g.x + g.y + g.z + g.w;
+      }
+      if (g_dep) {
+        const size_t q = (size_t)v * HW + 4 * (size_t)p;
+        const float4 d = *reinterpret_cast<const float4*>(depth + q);
+        const float4 t = *reinterpret_cast<const float4*>(tdep + q);
+        *reinterpret_cast<float4*>(g_dep + q) =
+            make_float4(l1_sign(d.x - t.x, w_dep), l1_sign(d.y - t.y, w_dep),
+                        l1_sign(d.z - t.z, w_dep), l1_sign(d.w - t.w, w_dep));
+      }
     }
-    if (g_dep) {
-      const size_t q = (size_t)v * HW + p;
-      const float e = depth[q] - tdep[q];
-      g_dep[q] = e > 0.f ? w_dep : (e < 0.f ? -w_dep : 0.f);
+  } else {
+    for (int p = b0 * 256 + (int)threadIdx.x; p < HW; p += blocks_per_view * 256) {
+      const size_t base = (size_t)v * 3 * HW + p;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        const float c = color[base + (size_t)ch * HW];
+        const float g = l1_sign(ea * c + b - tcol[base + (size_t)ch * HW], w_col);
+        g_col[base + (size_t)ch * HW] = ea * g;
+        sa += c * g;
+        sb += g;
+      }
+      if (g_dep) {
+        const size_t q = (size_t)v * HW + p;
+        g_dep[q] = l1_sign(depth[q] - tdep[q], w_dep);
+      }
     }
   }
   if (!g_expo) return;  // uniform
@@ -69,10 +102,18 @@ hipError_t launch_l1_grad(int nv, int HW, const float* color, const float* depth
                           const float* tcol, const float* tdep, const float* expo, float w_col,
                           float w_dep, float* g_col, float* g_dep, float* g_expo, hipStream_t s) {
   if (g_expo) hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(256), 0, s, g_expo, 2 * nv);
+  const uintptr_t al = (uintptr_t)color | (uintptr_t)tcol | (uintptr_t)g_col |
+                       (g_dep ? ((uintptr_t)depth | (uintptr_t)tdep | (uintptr_t)g_dep) : 0);
+  const bool vec = HW % 4 == 0 && (al & 15) == 0;
   // enough blocks to fill the chip, few enough per view for its atomics
-  const int bpv = std::min((HW + 255) / 256, std::max(64, 2048 / nv));
-  hipLaunchKernelGGL(k_l1_grad, dim3(nv * bpv), dim3(256), 0, s, HW, bpv, color, depth, tcol,
-                     tdep, expo, w_col, w_dep, g_col, g_dep, g_expo);
+  const int per = vec ? HW / 4 : HW;
+  const int bpv = std::min((per + 255) / 256, std::max(64, 2048 / nv));
+  if (vec)
+    hipLaunchKernelGGL(k_l1_grad<true>, dim3(nv * bpv), dim3(256), 0, s, HW, bpv, color, depth,
+                       tcol, tdep, expo, w_col, w_dep, g_col, g_dep, g_expo);
+  else
+    hipLaunchKernelGGL(k_l1_grad<false>, dim3(nv * bpv), dim3(256), 0, s, HW, bpv, color, depth,
+                       tcol, tdep, expo, w_col, w_dep, g_col, g_dep, g_expo);
   return hipGetLastError();
 }
 

@@ -87,12 +87,13 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
   const int v = g / T, tl = g - v * T;
   const int ty = tl / TX, tx = tl - ty * TX;
   const int tid = threadIdx.x;
-  // 16x16 tiles: wave w shades the 8x8 quadrant (w & 1, w >> 1), whose
-  // reach box is tighter around round footprints than a 16x4 strip's; other
-  // shapes: wave w shades tile rows [w RW, (w + 1) RW)
-  constexpr bool QUAD = TW == 16 && TH == 16;
-  const int px = QUAD ? tx * TW + ((tid >> 6) & 1) * 8 + (tid & 7) : tx * TW + (tid % TW);
-  const int py = QUAD ? ty * TH + (tid >> 7) * 8 + ((tid >> 3) & 7) : ty * TH + (tid / TW);
+  // wave w shades the 8x8 block (w % BX, w / BX) of the tile (BX blocks per
+  // tile row), whose reach box is tighter around round footprints than a
+  // strip of whole tile rows
+  constexpr int BX = TW / 8;
+  static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 blocks");
+  const int px = tx * TW + ((tid >> 6) % BX) * 8 + (tid & 7);
+  const int py = ty * TH + ((tid >> 6) / BX) * 8 + ((tid >> 3) & 7);
   const bool inside = px < W && py < H;
   uint2 rg = st.ranges[g];
   if (st.hdr->overflow) rg = make_uint2(0u, 0u);
@@ -100,10 +101,10 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
   float Tc = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dz = 0.f;
   uint32_t last = 0, stopn = 0;
   bool done = !inside;
-  // pixel-centre box of the tile; rows per wave for the strip layout
-  constexpr int NWV = NT / 64, RW = 64 / TW;
+  // pixel-centre corner of the tile
+  constexpr int NWV = NT / 64;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-  const float x0c = (float)(tx * TW) + 0.5f, x1c = x0c + (float)(TW - 1);
+  const float x0c = (float)(tx * TW) + 0.5f;
   const float y0c = (float)(ty * TH) + 0.5f;
   for (uint32_t base = rg.x; base < rg.y; base += NS) {
     if (__syncthreads_count(!done) == 0) break;
@@ -113,19 +114,14 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
       if (idx < rg.y) {
         const float4* r = st.rec + 3 * (size_t)st.inst[idx];
         const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-        // bit w: the entry can reach a pixel of wave w's rows
+        // bit w: the entry can reach a pixel of wave w's block
         uint32_t m = 0;
 #pragma unroll
         for (int w = 0; w < NWV; ++w)
-          if (QUAD)
-            m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c + (float)((w & 1) * 8),
-                                   x0c + (float)((w & 1) * 8 + 7), y0c + (float)((w >> 1) * 8),
-                                   y0c + (float)((w >> 1) * 8 + 7))
-                 << w;
-          else
-            m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c, x1c, y0c + (float)(w * RW),
-                                   y0c + (float)(w * RW + RW - 1))
-                 << w;
+          m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c + (float)((w % BX) * 8),
+                                 x0c + (float)((w % BX) * 8 + 7), y0c + (float)((w / BX) * 8),
+                                 y0c + (float)((w / BX) * 8 + 7))
+               << w;
         s0[tid + k * NT] = r0;
         s1[tid + k * NT] = r1;
         s2[tid + k * NT] = r2;
@@ -366,7 +362,8 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
         s0[lane + 64 * r] = r0;
         s1[lane + 64 * r] = r1;
         s2[lane + 64 * r] = r2;
-        sp[lane + 64 * r] = pr;
+        // the entry's screen-space gradient row: its visible-list position
+        sp[lane + 64 * r] = st.vidx[pr];
         mr[r] = m;
       }
     }

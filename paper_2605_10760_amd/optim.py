@@ -1,6 +1,6 @@
 """The two optimisation loops that drive the rasterizer, as thin drivers
-over the library's entry points (every arithmetic step runs in its kernels;
-torch supplies memory, streams and the fused Adam update):
+over the library's entry points (every arithmetic step, the Adam update
+included, runs in its kernels; torch supplies memory and streams):
 
 * mapping (Sec. III-A, Eq. (map_loss)):
   alpha L1(I^, I) + beta L1(D^, D) + lambda_n L_normal + lambda_s L_iso,
@@ -30,8 +30,8 @@ from dataclasses import astuple, dataclass
 import torch
 
 from . import _lib as L
-from .rasterizer import (Rasterizer, SceneTensors, ViewTensors, apply_pose_delta, iso_grad,
-                         l1_loss_grad, normal_loss_grad, prune, ssim_grad)
+from .rasterizer import (Adam, Rasterizer, SceneTensors, ViewTensors, apply_pose_delta,
+                         iso_grad, l1_loss_grad, normal_loss_grad, prune, ssim_grad)
 
 
 @dataclass(frozen=True)
@@ -84,14 +84,15 @@ class Optimizer:
         self.params = [scene.means, scene.log_scales, scene.quats, scene.opacity_logits,
                        scene.colors]
         lrs = [rates.means, rates.log_scales, rates.quats, rates.opacity, rates.colors]
-        groups = [{"params": [p], "lr": lr} for p, lr in zip(self.params, lrs)]
+        groups = list(zip(self.params, lrs))
         self.pose = torch.zeros((V, 6), device=dev) if pose else None
         self.exposure = torch.zeros((V, 2), device=dev) if exposure else None
         if pose:
-            groups.append({"params": [self.pose], "lr": rates.pose})
+            groups.append((self.pose, rates.pose))
         if exposure:
-            groups.append({"params": [self.exposure], "lr": rates.exposure})
-        self.adam = torch.optim.Adam(groups, eps=1e-15, fused=True, capturable=True)
+            groups.append((self.exposure, rates.exposure))
+        # one gsr_adam launch updates every array (device step count, moments)
+        self.adam = Adam(groups, eps=1e-15)
         self.state = rast.new_state()
         self.img = (torch.empty((V, 3, H, W), device=dev), torch.empty((V, H, W), device=dev),
                     torch.empty((V, H, W), device=dev))

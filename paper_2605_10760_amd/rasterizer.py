@@ -524,6 +524,40 @@ def seed_noalloc(depth: torch.Tensor, color: torch.Tensor, viewmat: torch.Tensor
         raise L.GsrError(st, "gsr_seed_noalloc failed")
 
 
+class Adam:
+    """Adam over a list of (parameter, learning rate) on the device: one
+    gsr_adam launch per step updates every parameter from its `.grad` (the
+    tensor itself is read at each step, so gradients may be written in place
+    between steps).  Moments and the step count are device buffers, so
+    `step()` allocates nothing and can be captured in a graph."""
+
+    def __init__(self, params_lrs, betas=(0.9, 0.999), eps=1e-15):
+        self.lib = L.load()
+        self.params = [p for p, _ in params_lrs]
+        self.lrs = [float(lr) for _, lr in params_lrs]
+        if not 1 <= len(self.params) <= L.GSR_ADAM_MAX_GROUPS:
+            raise ValueError(f"1..{L.GSR_ADAM_MAX_GROUPS} parameter arrays")
+        for p in self.params:
+            if not (p.is_cuda and p.dtype == torch.float32 and p.is_contiguous()):
+                raise ValueError("parameters must be contiguous CUDA float32 tensors")
+        self.m = [torch.zeros_like(p) for p in self.params]
+        self.v = [torch.zeros_like(p) for p in self.params]
+        self.t = torch.zeros(1, dtype=torch.int32, device=self.params[0].device)
+        self.betas, self.eps = (float(betas[0]), float(betas[1])), float(eps)
+
+    def step(self, stream=None):
+        groups = (L.AdamGroup * len(self.params))()
+        for k, p in enumerate(self.params):
+            if p.grad is None or not p.grad.is_contiguous():
+                raise ValueError("every parameter needs a contiguous .grad")
+            groups[k] = L.AdamGroup(p.data_ptr(), p.grad.data_ptr(), self.m[k].data_ptr(),
+                                    self.v[k].data_ptr(), p.numel(), self.lrs[k], 0)
+        st = self.lib.gsr_adam(groups, len(self.params), self.betas[0], self.betas[1], self.eps,
+                               _ptr(self.t), _stream(stream))
+        if st != L.GSR_OK:
+            raise L.GsrError(st, "gsr_adam failed")
+
+
 class _RasterizeFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, means, log_scales, quats, opacity_logits, colors, pose_delta, viewmats,
