@@ -409,7 +409,7 @@ def run_plain(torch, np, wl, sc, vw, tc, td, step, tile, opts, steps):
 
 
 def run_workload(torch, np, wl, args, steps, warmup, tuned=None, tile=(16, 16), stages=True,
-                 plain_steps=2):
+                 plain_steps=2, ab_steps=0):
     """Batched step (graph replay) and plain loop on one workload: rates,
     measured work, per-stage times and algorithmic bytes/ops."""
     from paper_2605_10760_amd import Rasterizer, SceneTensors, ViewTensors
@@ -467,6 +467,27 @@ def run_workload(torch, np, wl, args, steps, warmup, tuned=None, tile=(16, 16), 
         rast.profile(False)
         torch.cuda.synchronize()
 
+    ab = None
+    if ab_steps:
+        # A/B of the compositing options on this workload: eager steps with
+        # one option changed from the plan in use (same state buffer)
+        base = dict(fwd_batch=rast.desc.fwd_batch or 1, bwd_batch=rast.desc.bwd_batch or 2,
+                    persistent=rast.desc.persistent)
+        variants = [("plan", {})]
+        variants.append(("persistent" if not base["persistent"] else "grid",
+                         dict(persistent=1 - base["persistent"])))
+        variants.append((f"fwd_batch={3 - base['fwd_batch']}", dict(fwd_batch=3 - base["fwd_batch"])))
+        for bb in (1, 2, 4):
+            if bb != base["bwd_batch"]:
+                variants.append((f"bwd_batch={bb}", dict(bwd_batch=bb)))
+        ab = {}
+        for name, change in variants:
+            rast.replan(**{**base, **change})
+            step()
+            ab[name] = round(time_steps(torch, step, ab_steps) * 1e3, 4)
+        rast.replan(**base)
+        torch.cuda.synchronize()
+
     n_bwd = int(np.sum(vw_np.needs_grad)) if vw_np.needs_grad is not None else V
     plain = None
     if plain_steps:
@@ -476,7 +497,7 @@ def run_workload(torch, np, wl, args, steps, warmup, tuned=None, tile=(16, 16), 
                      ms_per_step=round(pdt * 1e3, 3), steps=plain_steps)
     byt, ops = algorithmic(cnt, sc_np, V, H, W, sc.sh_stride)
     res = dict(name=wl.name, V=V, H=H, W=W, n_bwd=n_bwd, dt=dt, cnt=cnt, bytes=byt, ops=ops,
-               stage_ms=stage_acc, plain=plain, tile=tile, opts=opts, rast=rast, step=step,
+               stage_ms=stage_acc, plain=plain, tile=tile, opts=opts, rast=rast, step=step, ab=ab,
                sc=sc, vw=vw, tc=tc, td=td, graph=graph is not None,
                step_bytes=sum(byt.values()))
     return res
@@ -494,6 +515,7 @@ def summary(res):
                 step_algorithmic_GB=round(res["step_bytes"] / 1e9, 3),
                 step_hbm_roofline_frac=round(res["step_bytes"] / (dt * HBM_PEAK_GBS * 1e9), 4),
                 tile=f"{res['tile'][0]}x{res['tile'][1]}", options=res["opts"],
+                option_ab_ms_per_step=res.get("ab"),
                 form="batched, hip graph replay" if res["graph"] else "batched, eager",
                 plain=res["plain"])
 
@@ -755,7 +777,8 @@ def main():
         torch.cuda.empty_cache()
     ps = args.plain_steps if args.plain_steps is not None else max(2, args.steps // 4)
     res = run_workload(torch, np, wl, args, args.steps, args.warmup, tuned=tuned, tile=tile,
-                       plain_steps=0 if args.no_plain else ps)
+                       plain_steps=0 if args.no_plain else ps,
+                       ab_steps=0 if args.no_extras else 5)
     print(f"[bench] {wl.name}: {res['dt'] * 1e3:.3f} ms per step", file=sys.stderr, flush=True)
 
     stages = {}
@@ -790,12 +813,23 @@ def main():
         cs = max(2, args.config_steps)
         for name in ("small", "room", "fused"):
             w2 = make_workload(name)
-            r2 = run_workload(torch, np, w2, args, cs, 2, tuned=None, tile=(16, 16),
-                              plain_steps=2 if name != "small" else cs)
+            tuned2 = None
+            if name == "fused" and not args.no_autotune:
+                # the fused map's batch of uneven views: tile shape, batches
+                # and the persistent queue tuned for it
+                from paper_2605_10760_amd import autotune
+                t0 = time.perf_counter()
+                tuned2 = autotune(SceneTensors.from_numpy(w2.scene), ViewTensors.from_numpy(w2.views))
+                tuned2["seconds"] = round(time.perf_counter() - t0, 1)
+                torch.cuda.empty_cache()
+            r2 = run_workload(torch, np, w2, args, cs, 2, tuned=tuned2, tile=(16, 16),
+                              plain_steps=2 if name != "small" else cs,
+                              ab_steps=3 if name == "fused" else 0)
             d2 = summary(r2)
             d2["roofline"] = roofline_of(r2, max(r2["stage_ms"], key=lambda k_: r2["stage_ms"][k_]),
                                          w2.name)
             d2["stages_ms"] = {k_: round(v_, 4) for k_, v_ in r2["stage_ms"].items() if v_ > 0}
+            d2["autotune"] = tuned2
             configs[name] = d2
             print(f"[bench] {w2.name}: {r2['dt'] * 1e3:.3f} ms per step", file=sys.stderr,
                   flush=True)
@@ -831,6 +865,7 @@ def main():
         "step_algorithmic_GB": main_sum["step_algorithmic_GB"],
         "step_hbm_roofline_frac": main_sum["step_hbm_roofline_frac"],
         "plain": main_sum["plain"],
+        "option_ab_ms_per_step": main_sum["option_ab_ms_per_step"],
         "stages_ms": stages,
         "roofline": roof,
         "roofline_render_fwd": roof_fwd,

@@ -382,6 +382,7 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
         float acc[GRAD2D];
 #pragma unroll
         for (int i = 0; i < GRAD2D; ++i) acc[i] = 0.f;
+        float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f;
         bool act = false;
         // Branch-free per pixel: an entry a pixel does not blend gets zero
         // weight and zero gradients (selected, never multiplied, so an
@@ -409,16 +410,30 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
           const bool unc = ok && raw <= ALPHA_MAX;
           // unclamped: alpha = sigma G, so dL/dsigma = G dA = gp / sigma
           const float gp = unc ? al * dA : 0.f;
-          acc[5] += gp;
-          // moments of gp over dx, dy: the conic and mean gradients are
-          // linear in them (applied once per entry after the wave sum)
-          const float gpx = gp * dx, gpy = gp * dy;
-          acc[0] += gpx;
-          acc[1] += gpy;
-          acc[2] += gpx * dx;
-          acc[3] += gpx * dy;
-          acc[4] += gpy * dy;
+          // sums of gp weighted by the pixel's 8x8-block offsets (ix, iy) in
+          // block units (compile-time constants once unrolled)
+          const int ix = k % BX, iy = k / BX;
+          S0 += gp;
+          if (ix != 0) { Sx = fmaf((float)ix, gp, Sx); Sxx = fmaf((float)(ix * ix), gp, Sxx); }
+          if (iy != 0) { Sy = fmaf((float)iy, gp, Sy); Syy = fmaf((float)(iy * iy), gp, Syy); }
+          if (ix != 0 && iy != 0) Sxy = fmaf((float)(ix * iy), gp, Sxy);
+          (void)dx;
+          (void)dy;
           Tc[k] = ok ? Tb : Tc[k];
+        }
+        // moments of gp over dx, dy (the conic and mean gradients are linear
+        // in them, applied once per entry after the wave sum): pixel k sits
+        // 8 (ix, iy) from the lane's first pixel, so dx_k = dx_0 - 8 ix and
+        // sum gp dx = dx_0 S - 8 Sx, sum gp dx^2 = dx_0^2 S - 16 dx_0 Sx +
+        // 64 Sxx, and likewise for dy and dx dy
+        {
+          const float dx0 = a.x - fxp[0], dy0 = a.y - fyp[0];
+          acc[5] = S0;
+          acc[0] = fmaf(dx0, S0, -8.f * Sx);
+          acc[1] = fmaf(dy0, S0, -8.f * Sy);
+          acc[2] = fmaf(dx0, fmaf(dx0, S0, -16.f * Sx), 64.f * Sxx);
+          acc[3] = fmaf(dx0, acc[1], fmaf(-8.f * dy0, Sx, 64.f * Sxy));
+          acc[4] = fmaf(dy0, fmaf(dy0, S0, -16.f * Sy), 64.f * Syy);
         }
         if (__ballot(act) != 0ull) {
           static_assert(GRAD2D == 10, "ten splat gradients");
