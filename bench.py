@@ -342,14 +342,22 @@ def algorithmic(cnt, sc_np, V, H, W, sh_stride, fwd_only_views=0):
     par = 56 if rgb else 4 * (3 + 3 + 4 + 1 + 3 * sh_stride)
     npx = V * H * W
     byt = {
-        # parameters once per Gaussian, a key per pair, rect + record per visible pair
-        "project": par * sc_np.n + 4 * P + (48 + 8) * Pv,
-        "compact": 4 * P + 8 * Pv,
+        # key pass: the key path's parameters (means, log-scales, quaternion,
+        # opacity: 44 B) once per Gaussian, a depth key per pair
+        "project": 44 * sc_np.n + 4 * P,
+        # read the keys, write each pair's visible position, and per visible
+        # pair its key, its position and its pair id
+        "compact": 4 * P + 4 * P + 12 * Pv,
+        # record pass: every parameter once per Gaussian, the visible position
+        # per pair, rect + record per visible pair
+        "record": par * sc_np.n + 4 * P + (48 + 8) * Pv,
         "depth_sort": 4 * 24 * Pv,
         "binning": 2 * 12 * Pv + 4 * I,
         "render_fwd": 52 * cnt["E_fwd"] + 28 * npx,
         "render_bwd": 52 * cnt["E_bwd"] + 80 * cnt["E_bwd"] + 28 * npx,
-        "project_bwd": (40 + 32 + 4) * Pv + 2 * par * sc_np.n,
+        # parameters read and gradients written once per Gaussian, the visible
+        # position per pair, each visible pair's gradient row read and cleared
+        "project_bwd": 2 * par * sc_np.n + 4 * P + 80 * Pv,
     }
     ops = {
         "render_fwd": OPS_FWD_EXAMINED * cnt["examined"] + OPS_FWD_BLENDED * cnt["blended"],

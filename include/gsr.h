@@ -478,7 +478,7 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
  * them and writes the elapsed milliseconds of each stage of the most recent
  * calls into ms[0..n) (0 for stages not run), indexed by gsr_stage. */
 typedef enum gsr_stage {
-  GSR_STAGE_PROJECT = 0,     /* projection of every (view, Gaussian) pair */
+  GSR_STAGE_PROJECT = 0,     /* key path of every (view, Gaussian) pair */
   GSR_STAGE_COMPACT = 1,     /* ordered compaction of visible pairs */
   GSR_STAGE_DEPTH_SORT = 2,  /* depth digits of the (tile, depth) key sort */
   GSR_STAGE_BINNING = 3,     /* tile digit: counts, scans, scatter */
@@ -486,7 +486,8 @@ typedef enum gsr_stage {
   GSR_STAGE_ZERO = 5,        /* clearing of the backward accumulators */
   GSR_STAGE_RENDER_BWD = 6,  /* reverse compositing, splat gradients */
   GSR_STAGE_PROJECT_BWD = 7, /* chain rule to parameters and poses */
-  GSR_NUM_STAGES = 8
+  GSR_STAGE_RECORD = 8,      /* screen-space records of the visible pairs */
+  GSR_NUM_STAGES = 9
 } gsr_stage;
 gsr_status gsr_profile_enable(gsr_ctx* ctx, int enable);
 gsr_status gsr_profile_read(gsr_ctx* ctx, float* ms, int32_t n);

@@ -27,7 +27,7 @@ EXPORTED = ("gsr_create", "gsr_destroy", "gsr_plan", "gsr_state_bytes", "gsr_for
             "gsr_seed", "gsr_seed_noalloc", "gsr_adam")
 
 STAGES = ("project", "compact", "depth_sort", "binning", "render_fwd", "zero", "render_bwd",
-          "project_bwd")
+          "project_bwd", "record")
 
 
 class PlanDesc(C.Structure):

@@ -95,6 +95,7 @@ StateLayout state_layout(const gsr_plan_desc& p) {
   L.hdr = o; o = align256(o + STATE_HEADER_BYTES);
   L.zkey = o; o = align256(o + P * 4);
   L.vidx = o; o = align256(o + P * 4);
+  L.vpair = o; o = align256(o + P * 4);
   L.rect = o; o = align256(o + P * 8);
   L.rec = o; o = align256(o + P * 48);
   L.order = o; o = align256(o + P * 4);
@@ -114,6 +115,7 @@ StateDev state_ptrs(void* base, const gsr_plan_desc& p) {
   s.hdr = (StateHeader*)(b + L.hdr);
   s.zkey = (uint32_t*)(b + L.zkey);
   s.vidx = (uint32_t*)(b + L.vidx);
+  s.vpair = (uint32_t*)(b + L.vpair);
   s.rect = (uint2*)(b + L.rect);
   s.rec = (float4*)(b + L.rec);
   s.order = (uint32_t*)(b + L.order);
@@ -479,11 +481,17 @@ gsr_status gsr_forward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   hipError_t e;
   {
     StageMark m(c, GSR_STAGE_PROJECT, st);
-    if ((e = launch_project(t.pt, scd, cam, sd, c->blk_cnt, st)) != hipSuccess) return hip_fail(c, e, "project");
+    if ((e = launch_project_keys(t.pt, scd, cam, sd, c->blk_cnt, st)) != hipSuccess)
+      return hip_fail(c, e, "project");
   }
   {
     StageMark m(c, GSR_STAGE_COMPACT, st);
     if ((e = launch_compact(t.pt, sd, c->blk_cnt, c->blk_scan, c->ka, c->va, st)) != hipSuccess) return hip_fail(c, e, "compact");
+  }
+  {
+    StageMark m(c, GSR_STAGE_RECORD, st);
+    if ((e = launch_project_records(t.pt, scd, cam, sd, st)) != hipSuccess)
+      return hip_fail(c, e, "records");
   }
   {
     StageMark m(c, GSR_STAGE_DEPTH_SORT, st);
@@ -606,17 +614,32 @@ gsr_status gsr_debug_export(gsr_ctx* c, const void* state, int32_t n_views, gsr_
   for (auto& x : cps)
     if (x.bytes && (e = hipMemcpy(x.dst, x.src, x.bytes, hipMemcpyDeviceToHost)) != hipSuccess)
       return hip_fail(c, e, "debug copy");
+  // the sorted lists and the rects live at visible-list positions: report
+  // pair ids and per-pair rects
+  const size_t nvis = std::min<size_t>((size_t)h.vis_total, (size_t)c->plan.max_pairs);
+  std::vector<uint32_t> vpair(nvis);
+  if (nvis && (e = hipMemcpy(vpair.data(), sd.vpair, nvis * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(c, e, "debug vpair");
+  auto to_pair = [&](uint32_t* a, size_t n) {
+    for (size_t i = 0; i < n; ++i) a[i] = a[i] < nvis ? vpair[a[i]] : 0xFFFFFFFFu;
+  };
+  if (d->order) to_pair(d->order, std::min<size_t>(np, h.vis_total));
+  if (d->inst)
+    to_pair(d->inst, (size_t)std::min<unsigned long long>(
+                         std::min<unsigned long long>(h.inst_total, sd.cap),
+                         (unsigned long long)std::max<int64_t>(0, d->n_inst)));
   if (d->rects && np) {
-    std::vector<uint2> r(np);
-    std::vector<uint32_t> z(np);
-    if ((e = hipMemcpy(r.data(), sd.rect, np * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug rect");
-    if ((e = hipMemcpy(z.data(), sd.zkey, np * 4, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug zkey");
+    std::vector<uint2> r(std::max<size_t>(nvis, 1));
+    std::vector<uint32_t> vi(np);
+    if (nvis && (e = hipMemcpy(r.data(), sd.rect, nvis * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug rect");
+    if ((e = hipMemcpy(vi.data(), sd.vidx, np * 4, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug vidx");
     for (size_t i = 0; i < np; ++i) {
-      const bool vis = z[i] != CULLED;
-      d->rects[4 * i + 0] = vis ? (uint16_t)(r[i].x & 0xFFFF) : 0;
-      d->rects[4 * i + 1] = vis ? (uint16_t)(r[i].x >> 16) : 0;
-      d->rects[4 * i + 2] = vis ? (uint16_t)(r[i].y & 0xFFFF) : 0;
-      d->rects[4 * i + 3] = vis ? (uint16_t)(r[i].y >> 16) : 0;
+      const bool vis = vi[i] < nvis;
+      const uint2 q = vis ? r[vi[i]] : make_uint2(0u, 0u);
+      d->rects[4 * i + 0] = (uint16_t)(q.x & 0xFFFF);
+      d->rects[4 * i + 1] = (uint16_t)(q.x >> 16);
+      d->rects[4 * i + 2] = (uint16_t)(q.y & 0xFFFF);
+      d->rects[4 * i + 3] = (uint16_t)(q.y >> 16);
     }
   }
   if (d->vis_off)

@@ -97,7 +97,7 @@ static_assert(sizeof(StateHeader) <= STATE_HEADER_BYTES, "header");
 
 // Byte offsets of the arrays inside a saved-state buffer (all 256-aligned).
 struct StateLayout {
-  size_t hdr, zkey, vidx, rect, rec, order, ranges, torder, inst, tfinal, last, total;
+  size_t hdr, zkey, vidx, vpair, rect, rec, order, ranges, torder, inst, tfinal, last, total;
 };
 
 // Pointers into a saved-state buffer.
@@ -105,9 +105,11 @@ struct StateDev {
   StateHeader* hdr;
   uint32_t* zkey;     // [P]
   uint32_t* vidx;     // [P] position in the compacted visible list, CULLED if culled
-  uint2* rect;        // [P] packed (x0 | y0 << 16, x1 | y1 << 16)
-  float4* rec;        // [P][3]: (u, v, A', B'), (C', sigma, z, ex), (r, g, b, ey)
-  uint32_t* order;    // [P] pair ids in (view, depth, id) order
+  uint32_t* vpair;    // [Pv] pair of each visible-list position
+  uint2* rect;        // [Pv] by visible position: packed (x0 | y0 << 16, x1 | y1 << 16)
+  float4* rec;        // [Pv][3] by visible position: (u, v, A', B'), (C', sigma, z, ex),
+                      //   (r, g, b, ey)
+  uint32_t* order;    // [Pv] visible positions in (view, depth, id) order
   uint2* ranges;      // [V*T]
   uint32_t* torder;   // [V*T] tiles by decreasing list length (persistent render)
   uint32_t* inst;     // [cap]
@@ -146,8 +148,10 @@ StateLayout state_layout(const gsr_plan_desc& p);
 StateDev state_ptrs(void* base, const gsr_plan_desc& p);
 
 // ------------------------------------------------------------------ launches
-hipError_t launch_project(const ProjTab& t, const SceneDev& sc, const CamDev& cam,
-                          StateDev st, uint32_t* blk_cnt, hipStream_t s);
+hipError_t launch_project_keys(const ProjTab& t, const SceneDev& sc, const CamDev& cam,
+                               StateDev st, uint32_t* blk_cnt, hipStream_t s);
+hipError_t launch_project_records(const ProjTab& t, const SceneDev& sc, const CamDev& cam,
+                                  StateDev st, hipStream_t s);
 hipError_t launch_compact(const ProjTab& t, StateDev st, const uint32_t* blk_cnt,
                           uint32_t* blk_scan, uint32_t* kout, uint32_t* vout, hipStream_t s);
 hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,

@@ -173,7 +173,16 @@ __device__ __forceinline__ bool key_view(const float* m, const KeyGauss& g, cons
 // degree 0) is done once, instead of once per view.  Pair p of view v is
 // Gaussian p - pair_off[v] of the set, so the workgroup's 256 Gaussians are
 // the 256-pair block (blk_off[v] + its block index in the set) of each view.
-template <int SHD>
+//
+// Two passes.  Keys (RECORD = false): the FP32 key path of every pair, its
+// depth key (or CULLED) and the visible count of every 256-pair block, for
+// the ordered compaction that follows.  Records (RECORD = true, after the
+// compaction): for every visible pair, the tile rect (the key path again,
+// same code and inputs, so the same rect) and the FP64 screen-space record,
+// written at the pair's position in the compacted visible list, so that a
+// view's records are consecutive lines (written in full, read densely by
+// the binning and compositing).
+template <int SHD, bool RECORD>
 __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, CamDev cam,
                                                         StateDev st, uint32_t* blk_cnt) {
   const int b = xcd_remap(blockIdx.x, t.set_gblk[t.ns]);
@@ -201,7 +210,7 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
   double Sd[3][3];
   float sigf = 0.f, k2f = 0.f;
   float col[3] = {0.f, 0.f, 0.f};
-  {
+  if (RECORD) {
     cov3_fp64(ls, q, Sd);
     sigf = 1.f / (1.f + expf(-o));
     // half-extents of the alpha >= 1/255 ellipse use k2f, widened by a
@@ -221,12 +230,24 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
     const float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
     const float tc[3] = {vm[3], vm[7], vm[11]};
     const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
-    KeyResult kr;
-    const bool vis = key_view(m, kg, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX,
-                              t.TY, cam.z_near, kr);
-    if (valid) st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
-    if (vis) {
-      st.rect[pair] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
+    if (!RECORD) {
+      KeyResult kr;
+      const bool vis = key_view(m, kg, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH,
+                                t.TX, t.TY, cam.z_near, kr);
+      if (valid) st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
+      const int cnt = __syncthreads_count(vis);
+      if (threadIdx.x == 0) blk_cnt[t.blk_off[v] + lb] = (uint32_t)cnt;
+      continue;
+    }
+    const uint32_t row = valid ? st.vidx[pair] : CULLED;
+    if (row != CULLED) {
+      KeyResult kr;
+      // visible in the key pass, so visible here (the same pure function of
+      // the same inputs); an empty rect would only drop the pair
+      if (!key_view(m, kg, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX, t.TY,
+                    cam.z_near, kr))
+        kr.x0 = kr.x1 = kr.y0 = kr.y1 = 0u;
+      st.rect[row] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
       ScreenCov sc2 = screen_cov_fp64(Sd, Rc, tc, m, in.x, in.y, t.W, t.H);
       const double fx = in.x, fy = in.y;
       const double* p = sc2.p;
@@ -256,7 +277,7 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
       }
       const float exr = sqrtf(k2f * (float)a) * (1.f + 1e-4f) + 1e-2f;
       const float eyr = sqrtf(k2f * (float)c) * (1.f + 1e-4f) + 1e-2f;
-      float4* rp = st.rec + 3 * (long)pair;
+      float4* rp = st.rec + 3 * (long)row;
       // conic (A, B, C) = (c, -b, a)/det, stored pre-scaled so that the
       // exponent in base 2 is A' dx^2 + B' dx dy + C' dy^2:
       // A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2
@@ -266,8 +287,6 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
       rp[1] = make_float4((float)(-0.5 * h * a), sigf, (float)p[2], exr);
       rp[2] = make_float4(cv[0], cv[1], cv[2], eyr);
     }
-    const int cnt = __syncthreads_count(vis);
-    if (threadIdx.x == 0) blk_cnt[t.blk_off[v] + lb] = (uint32_t)cnt;
   }
 }
 
@@ -359,8 +378,10 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_compact(ProjTab t, StateDev st,
     if (key[k] != CULLED) {
       pos = blk_scan[b] + (uint32_t)__popcll(m[k] & ((1ull << lane) - 1ull));
       for (int i = 0; i < w; ++i) pos += wc[k][i];
+      // the sort carries the visible position; vpair maps it back to the pair
       kout[pos] = key[k];
-      vout[pos] = (uint32_t)pair[k];
+      vout[pos] = pos;
+      st.vpair[pos] = (uint32_t)pair[k];
     }
     // position of the pair in the compacted visible list (the row of its
     // screen-space gradient), CULLED for culled pairs
@@ -411,15 +432,26 @@ __global__ void k_pose_delta(const float* vin, const float* delta, float* vout, 
     for (int j = 0; j < 4; ++j) vout[12 * v + 4 * i + j] = (float)out[i][j];
 }
 
-hipError_t launch_project(const ProjTab& t, const SceneDev& sc, const CamDev& cam, StateDev st,
-                          uint32_t* blk_cnt, hipStream_t s) {
+hipError_t launch_project_keys(const ProjTab& t, const SceneDev& sc, const CamDev& cam,
+                               StateDev st, uint32_t* blk_cnt, hipStream_t s) {
   const int nb = t.set_gblk[t.ns];
   if (nb == 0) return hipSuccess;
+  // the key path does not read colours: one instantiation for every degree
+  hipLaunchKernelGGL((k_project<0, false>), dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc,
+                     cam, st, blk_cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_records(const ProjTab& t, const SceneDev& sc, const CamDev& cam,
+                                  StateDev st, hipStream_t s) {
+  const int nb = t.set_gblk[t.ns];
+  if (nb == 0) return hipSuccess;
+  const dim3 g(xcd_grid(nb)), b(PROJ_BLOCK);
   switch (sc.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_project<0>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
-    case 1: hipLaunchKernelGGL(k_project<1>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
-    case 2: hipLaunchKernelGGL(k_project<2>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
-    default: hipLaunchKernelGGL(k_project<3>, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st, blk_cnt); break;
+    case 0: hipLaunchKernelGGL((k_project<0, true>), g, b, 0, s, t, sc, cam, st, nullptr); break;
+    case 1: hipLaunchKernelGGL((k_project<1, true>), g, b, 0, s, t, sc, cam, st, nullptr); break;
+    case 2: hipLaunchKernelGGL((k_project<2, true>), g, b, 0, s, t, sc, cam, st, nullptr); break;
+    default: hipLaunchKernelGGL((k_project<3, true>), g, b, 0, s, t, sc, cam, st, nullptr); break;
   }
   return hipGetLastError();
 }

@@ -363,7 +363,7 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
         s1[lane + 64 * r] = r1;
         s2[lane + 64 * r] = r2;
         // the entry's screen-space gradient row: its visible-list position
-        sp[lane + 64 * r] = st.vidx[pr];
+        sp[lane + 64 * r] = pr;
         mr[r] = m;
       }
     }
