@@ -105,14 +105,14 @@ typedef struct gsr_plan_desc {
   int32_t tile_h;
   int32_t chunk;         /* depth-sorted pairs per binning chunk, at most 256
                             (0 = automatic) */
-  int32_t fwd_batch;     /* list entries staged per thread per round in the
+  int32_t fwd_batch;     /* list entries staged per lane per round in the
                             forward compositing: 1 or 2 (0 = 1) */
   int32_t bwd_batch;     /* list entries staged per lane per round in the
                             backward compositing: 1, 2 or 4 (0 = 2) */
   int32_t persistent;    /* 1: compositing kernels run a grid of resident
-                            workgroups that take tiles from a queue ordered by
-                            decreasing list length; 0: one workgroup (forward)
-                            or wave (backward) per tile */
+                            workgroups whose waves take tiles from a queue
+                            ordered by decreasing list length; 0: one wave per
+                            tile */
   int32_t reserved;
 } gsr_plan_desc;
 

@@ -1,10 +1,13 @@
 // Per-tile compositing, forward and backward.
 //
-// Forward: one workgroup per (view, tile), one thread per pixel.  The tile's
-// sorted instance list is walked in batches of NT entries: each thread
-// gathers one 48-byte record into LDS, then every thread walks the batch
-// (all lanes read the same LDS word, a broadcast).  The whole tile stops
-// once every pixel has terminated.
+// Forward: one wave per (view, tile), PPL = TW*TH/64 pixels per lane (one per
+// 8x8 block of the tile), TPW tiles per workgroup with a private LDS slice
+// each (no workgroup barrier).  The tile's sorted instance list is walked in
+// rounds of B entries: each lane gathers its entries' 48-byte records into
+// the slice and tests which of the tile's 8x8 blocks each can reach; then
+// the wave walks the round in list order, every lane reading the entry once
+// (an LDS broadcast) for all of its pixels in the blocks the entry reaches.
+// The tile stops once every pixel has terminated.
 //
 // Backward: one wave per (view, tile), PPL = TW*TH/64 pixels per lane, TPW
 // tiles per workgroup with a private LDS slice each (no workgroup barrier).
@@ -48,7 +51,9 @@ __device__ __forceinline__ float exp2_fast(float p) { return __builtin_amdgcn_ex
 __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Whether the splat's alpha >= 1/255 region can reach a pixel centre of the
-// box [x0, x1] x [y0, y1].  The region is the ellipse
+// box [x0, x1] x [y0, y1], in two parts: row_extent gives the region's x
+// extent [xl, xr] within the pixel-centre rows y0..y1 (false: the rows miss
+// it), cols_reached tests that extent against the columns.  The region is the ellipse
 // a dx^2 + b dx dy + c dy^2 <= t (a = -A', b = -B', c = -C', dx = x - u,
 // dy = y - v); taking t so that its y half-extent equals the record's
 // conservative ey (which carries a margin) gives an ellipse containing the
@@ -59,8 +64,8 @@ __device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcp
 // the FP32 arithmetic.  Square roots and reciprocals are the hardware
 // approximations (about 1 ulp, no correctly-rounded expansion): their error
 // is orders of magnitude inside that margin.  NaN inputs give true.
-__device__ __forceinline__ bool reaches(const float4& r0, float Cs, float ex, float ey, float x0,
-                                        float x1, float y0, float y1) {
+__device__ __forceinline__ bool row_extent(const float4& r0, float Cs, float ey, float y0, float y1,
+                                           float& xl, float& xr) {
   const float a = -r0.z, b = -r0.w, c = -Cs;
   const float lo = fmaxf(y0 - r0.y, -ey), hi = fminf(y1 - r0.y, ey);
   if (lo > hi) return false;
@@ -70,172 +75,193 @@ __device__ __forceinline__ bool reaches(const float4& r0, float Cs, float ex, fl
   const float wr = sd * __builtin_amdgcn_sqrtf(fmaxf((ey - yr) * (ey + yr), 0.f));
   const float wl = sd * __builtin_amdgcn_sqrtf(fmaxf((ey - yl) * (ey + yl), 0.f));
   const float h = 0.5f * __builtin_amdgcn_rcpf(a);
-  const float xr = r0.x + (wr - b * yr) * h, xl = r0.x - (wl + b * yl) * h;
+  xr = r0.x + (wr - b * yr) * h;
+  xl = r0.x - (wl + b * yl) * h;
+  return true;
+}
+__device__ __forceinline__ bool cols_reached(float xl, float xr, float ex, float x0, float x1) {
   const float m = 0.05f + 1e-3f * ex;
   return !(xr + m < x0 || xl - m > x1);
 }
+__device__ __forceinline__ bool reaches(const float4& r0, float Cs, float ex, float ey, float x0,
+                                        float x1, float y0, float y1) {
+  float xl, xr;
+  return row_extent(r0, Cs, ey, y0, y1, xl, xr) && cols_reached(xl, xr, ex, x0, x1);
+}
 
-// One tile of the forward: FB * TW * TH list entries are staged per round
-// (FB per thread).
-template <int TW, int TH, int FB>
+// One tile of the forward on one wave.  Lane l shades pixel (l % 8, l / 8)
+// of each of the tile's PPL 8x8 blocks; B list entries are staged per round
+// in the wave's LDS slice, with a mask per entry of the blocks it can reach.
+template <int TW, int TH, int B>
 __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, const CamDev& cam,
                                          const StateDev& st, float* color, float* depth,
                                          float* alpha, int32_t* n_eval, float4* s0, float4* s1,
-                                         float4* s2, uint32_t* smask) {
-  constexpr int NT = TW * TH, NS = FB * NT;
+                                         float4* s2) {
+  constexpr int PPL = TW * TH / 64, BX = TW / 8, BY = TH / 8, R = B / 64;
+  static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 blocks");
+  static_assert(PPL <= 32, "one mask bit per block");
   const int T = TX * TY;
   const int v = g / T, tl = g - v * T;
   const int ty = tl / TX, tx = tl - ty * TX;
-  const int tid = threadIdx.x;
-  // wave w shades the 8x8 block (w % BX, w / BX) of the tile (BX blocks per
-  // tile row), whose reach box is tighter around round footprints than a
-  // strip of whole tile rows
-  constexpr int BX = TW / 8;
-  static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 blocks");
-  const int px = tx * TW + ((tid >> 6) % BX) * 8 + (tid & 7);
-  const int py = ty * TH + ((tid >> 6) / BX) * 8 + ((tid >> 3) & 7);
-  const bool inside = px < W && py < H;
+  const int lane = threadIdx.x & 63;
   uint2 rg = st.ranges[g];
   if (st.hdr->overflow) rg = make_uint2(0u, 0u);
-  const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
-  float Tc = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, dz = 0.f;
-  uint32_t last = 0, stopn = 0;
-  bool done = !inside;
+  // pixel k of the lane: block (k % BX, k / BX); its centre is exact in FP32
+  const float fx0 = (float)(tx * TW + (lane & 7)) + 0.5f;
+  const float fy0 = (float)(ty * TH + (lane >> 3)) + 0.5f;
+  // stopn: 1 + the position of the entry at which the pixel stopped, 0 while
+  // it runs (a pixel outside the image starts stopped)
+  float Tc[PPL], c0[PPL], c1[PPL], c2[PPL], dz[PPL];
+  uint32_t last[PPL], stopn[PPL];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int px = tx * TW + 8 * (k % BX) + (lane & 7);
+    const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
+    stopn[k] = (px < W && py < H) ? 0u : ~0u;
+    Tc[k] = 1.f;
+    c0[k] = c1[k] = c2[k] = dz[k] = 0.f;
+    last[k] = 0u;
+  }
   // pixel-centre corner of the tile
-  constexpr int NWV = NT / 64;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const float x0c = (float)(tx * TW) + 0.5f;
   const float y0c = (float)(ty * TH) + 0.5f;
-  for (uint32_t base = rg.x; base < rg.y; base += NS) {
-    if (__syncthreads_count(!done) == 0) break;
+  bool live = true;
+  for (uint32_t base = rg.x; live && base < rg.y; base += B) {
+    // bit k of mr[r]: the entry this lane staged in round r can reach alpha
+    // >= 1/255 in block k (the extent within a block row is shared by the
+    // blocks of that row)
+    uint32_t mr[R];
 #pragma unroll
-    for (int k = 0; k < FB; ++k) {
-      const uint32_t idx = base + tid + k * NT;
+    for (int r = 0; r < R; ++r) {
+      const uint32_t idx = base + (uint32_t)(lane + 64 * r);
+      mr[r] = 0u;
       if (idx < rg.y) {
-        const float4* r = st.rec + 3 * (size_t)st.inst[idx];
-        const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-        // bit w: the entry can reach a pixel of wave w's block
-        uint32_t m = 0;
+        const float4* rp = st.rec + 3 * (size_t)st.inst[idx];
+        const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
+        uint32_t m = 0u;
 #pragma unroll
-        for (int w = 0; w < NWV; ++w)
-          m |= (uint32_t)reaches(r0, r1.x, r1.w, r2.w, x0c + (float)((w % BX) * 8),
-                                 x0c + (float)((w % BX) * 8 + 7), y0c + (float)((w / BX) * 8),
-                                 y0c + (float)((w / BX) * 8 + 7))
-               << w;
-        s0[tid + k * NT] = r0;
-        s1[tid + k * NT] = r1;
-        s2[tid + k * NT] = r2;
-        smask[tid + k * NT] = m;
+        for (int by = 0; by < BY; ++by) {
+          float xl, xr;
+          if (row_extent(r0, r1.x, r2.w, y0c + (float)(8 * by), y0c + (float)(8 * by + 7), xl, xr)) {
+#pragma unroll
+            for (int bx = 0; bx < BX; ++bx)
+              m |= (uint32_t)cols_reached(xl, xr, r1.w, x0c + (float)(8 * bx),
+                                          x0c + (float)(8 * bx + 7))
+                   << (by * BX + bx);
+          }
+        }
+        s0[lane + 64 * r] = r0;
+        s1[lane + 64 * r] = r1;
+        s2[lane + 64 * r] = r2;
+        mr[r] = m;
       }
     }
-    __syncthreads();
-    const int n = (int)min((uint32_t)NS, rg.y - base);
-    // Branch-free per pixel: every lane evaluates every entry and a finished
-    // or skipped pixel takes a zero weight (adding an exact zero leaves the
-    // sums unchanged), so the loop carries no divergent control flow; a wave
-    // leaves the batch once all its pixels have finished.
-    // The wave walks only the entries that can reach alpha >= 1/255 in its
-    // rows: 64 entries at a time, the set bits of a ballot over their reach
-    // masks, in list order.
-    bool live = true;
-    for (int jb = 0; jb < n && live; jb += 64) {
-      const uint32_t mv = jb + lane < n ? smask[jb + lane] : 0u;
-      unsigned long long rel = __ballot((mv >> wv) & 1u);
-      // two entries per step: their exponentials and LDS reads overlap; the
-      // second is blended after the first (its weight uses the first's T)
+    __builtin_amdgcn_wave_barrier();
+    // In list order over the staged entries that reach a block of the tile
+    // (set bits of a ballot per staging round).  Branch-free per pixel: a
+    // finished or skipped pixel takes a zero weight (adding an exact zero
+    // leaves the sums unchanged); a block the entry cannot reach is not
+    // evaluated at all (a uniform branch on the entry's mask).
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      unsigned long long rel = __ballot(mr[r] != 0u);
       while (rel) {
-        if (__ballot(!done) == 0ull) {
+        uint32_t run = stopn[0];
+#pragma unroll
+        for (int k = 1; k < PPL; ++k) run = min(run, stopn[k]);
+        if (__ballot(run == 0u) == 0ull) {
           live = false;
           break;
         }
-        const int j0 = jb + (int)__builtin_ctzll(rel);
+        const int jj = (int)__builtin_ctzll(rel);
         rel &= rel - 1ull;
-        const bool two = rel != 0ull;
-        const int j1 = two ? jb + (int)__builtin_ctzll(rel) : j0;
-        rel = two ? rel & (rel - 1ull) : rel;
-        const float4 a0 = s0[j0], b0 = s1[j0], a1 = s0[j1], b1 = s1[j1];
-        float dx0, dy0, dx1, dy1;
-        const float p0 = splat_power(a0, b0, fx, fy, dx0, dy0);
-        const float p1 = splat_power(a1, b1, fx, fy, dx1, dy1);
-        const float al0 = fminf(ALPHA_MAX, b0.y * exp2_fast(p0));
-        const float al1 = fminf(ALPHA_MAX, b1.y * exp2_fast(p1));
-        const float4 c0v = s2[j0], c1v = s2[j1];
-        {
-          const bool use = !done && !(p0 > 0.f || al0 < ALPHA_MIN);
-          const float Tn = Tc * (1.f - al0);
+        const int j = 64 * r + jj;
+        const uint32_t mj = (uint32_t)__builtin_amdgcn_readlane((int)mr[r], jj);
+        // the entry's 1-based position, copied to a vector register once
+        // for the per-pixel selects
+        uint32_t pos1;
+        asm volatile("v_mov_b32 %0, %1" : "=v"(pos1) : "s"(base - rg.x + (uint32_t)j + 1u));
+        const float4 a = s0[j], b = s1[j], c = s2[j];
+        auto blend = [&](int k) {
+          float dx, dy;
+          const float p = splat_power(a, b, fx0 + (float)(8 * (k % BX)), fy0 + (float)(8 * (k / BX)),
+                                      dx, dy);
+          const float al = fminf(ALPHA_MAX, b.y * exp2_fast(p));
+          const bool use = stopn[k] == 0u && !(p > 0.f || al < ALPHA_MIN);
+          // T (1 - alpha) with one rounding
+          const float Tn = fmaf(-al, Tc[k], Tc[k]);
           const bool stop = use && Tn < T_MIN;
           const bool ok = use && !stop;
-          stopn = stop ? base - rg.x + (uint32_t)j0 + 1u : stopn;
-          done = done || stop;
-          const float wgt = ok ? al0 * Tc : 0.f;
-          c0 += c0v.x * wgt;
-          c1 += c0v.y * wgt;
-          c2 += c0v.z * wgt;
-          dz += b0.z * wgt;
-          Tc = ok ? Tn : Tc;
-          last = ok ? base - rg.x + (uint32_t)j0 + 1u : last;
-        }
-        {
-          const bool use = two && !done && !(p1 > 0.f || al1 < ALPHA_MIN);
-          const float Tn = Tc * (1.f - al1);
-          const bool stop = use && Tn < T_MIN;
-          const bool ok = use && !stop;
-          stopn = stop ? base - rg.x + (uint32_t)j1 + 1u : stopn;
-          done = done || stop;
-          const float wgt = ok ? al1 * Tc : 0.f;
-          c0 += c1v.x * wgt;
-          c1 += c1v.y * wgt;
-          c2 += c1v.z * wgt;
-          dz += b1.z * wgt;
-          Tc = ok ? Tn : Tc;
-          last = ok ? base - rg.x + (uint32_t)j1 + 1u : last;
-        }
+          stopn[k] = stop ? pos1 : stopn[k];
+          const float wgt = ok ? al * Tc[k] : 0.f;
+          c0[k] += c.x * wgt;
+          c1[k] += c.y * wgt;
+          c2[k] += c.z * wgt;
+          dz[k] += b.z * wgt;
+          Tc[k] = ok ? Tn : Tc[k];
+          last[k] = ok ? pos1 : last[k];
+        };
+#pragma unroll
+        for (int k = 0; k < PPL; ++k)
+          if ((mj >> k) & 1u) blend(k);
       }
+      if (!live) break;
     }
+    // the next round's staging overwrites the slice: every lane has read it
+    __builtin_amdgcn_wave_barrier();
   }
-  if (inside) {
-    const size_t HW = (size_t)W * H, p = (size_t)py * W + px;
-    color[(3 * (size_t)v + 0) * HW + p] = c0 + Tc * cam.bg0;
-    color[(3 * (size_t)v + 1) * HW + p] = c1 + Tc * cam.bg1;
-    color[(3 * (size_t)v + 2) * HW + p] = c2 + Tc * cam.bg2;
-    depth[v * HW + p] = dz;
-    alpha[v * HW + p] = 1.f - Tc;
-    st.tfinal[v * HW + p] = Tc;
-    st.last[v * HW + p] = last;
-    // entries examined: up to and including the stopping one, else the list
-    if (n_eval) n_eval[v * HW + p] = (int)(stopn ? stopn : rg.y - rg.x);
+  const size_t HW = (size_t)W * H;
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    const int px = tx * TW + 8 * (k % BX) + (lane & 7);
+    const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
+    if (px < W && py < H) {
+      const size_t p = (size_t)py * W + px;
+      color[(3 * (size_t)v + 0) * HW + p] = c0[k] + Tc[k] * cam.bg0;
+      color[(3 * (size_t)v + 1) * HW + p] = c1[k] + Tc[k] * cam.bg1;
+      color[(3 * (size_t)v + 2) * HW + p] = c2[k] + Tc[k] * cam.bg2;
+      depth[v * HW + p] = dz[k];
+      alpha[v * HW + p] = 1.f - Tc[k];
+      st.tfinal[v * HW + p] = Tc[k];
+      st.last[v * HW + p] = last[k];
+      // entries examined: up to and including the stopping one, else the list
+      if (n_eval) n_eval[v * HW + p] = (int)(stopn[k] ? stopn[k] : rg.y - rg.x);
+    }
   }
 }
 
-// Grid form: one workgroup per (view, tile), XCD-aware order.  Persistent
-// form: a grid sized to the resident workgroups, each taking tiles from the
-// forward's length-ordered queue (longest lists first) until it is empty.
-template <int TW, int TH, int FB, bool PERSIST>
-__global__ __launch_bounds__(TW* TH) void k_render_fwd(int ntiles, int W, int H, int TX, int TY,
-                                                       CamDev cam, StateDev st,
-                                                       unsigned int* next, float* color,
-                                                       float* depth, float* alpha,
-                                                       int32_t* n_eval) {
-  constexpr int NS = FB * TW * TH;
-  __shared__ float4 s0[NS], s1[NS], s2[NS];
-  __shared__ uint32_t smask[NS];
-  __shared__ int s_tile;
+// TPW waves per workgroup, each with a private LDS slice and no workgroup
+// barrier.  Grid form: wave w of workgroup b takes tile b TPW + w (XCD-aware
+// order).  Persistent form: a grid sized to the resident waves, each wave
+// taking tiles from the length-ordered queue (longest lists first) until it
+// is empty.
+template <int TW, int TH, int FB, int TPW, bool PERSIST>
+__global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int H, int TX, int TY,
+                                                         CamDev cam, StateDev st,
+                                                         unsigned int* next, float* color,
+                                                         float* depth, float* alpha,
+                                                         int32_t* n_eval) {
+  constexpr int B = 64 * FB;
+  __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (!PERSIST) {
-    const int g = xcd_remap(blockIdx.x, ntiles);
-    if (g < 0) return;
-    fwd_tile<TW, TH, FB>(g, W, H, TX, TY, cam, st, color, depth, alpha, n_eval, s0, s1, s2,
-                         smask);
+    const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
+    if (blk < 0) return;
+    const int g = blk * TPW + wv;
+    if (g >= ntiles) return;
+    fwd_tile<TW, TH, B>(g, W, H, TX, TY, cam, st, color, depth, alpha, n_eval, L0[wv], L1[wv],
+                        L2[wv]);
     return;
   }
   for (;;) {
-    // the barrier also ends every read of the previous tile's staged entries
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(next, 1u);
-    __syncthreads();
-    const int q = s_tile;
-    __syncthreads();
-    if (q >= ntiles) return;
-    fwd_tile<TW, TH, FB>((int)st.torder[q], W, H, TX, TY, cam, st, color, depth, alpha, n_eval,
-                         s0, s1, s2, smask);
+    uint32_t q = 0;
+    if ((threadIdx.x & 63) == 0) q = atomicAdd(next, 1u);
+    q = (uint32_t)__builtin_amdgcn_readfirstlane((int)q);
+    if (q >= (uint32_t)ntiles) return;
+    fwd_tile<TW, TH, B>((int)st.torder[q], W, H, TX, TY, cam, st, color, depth, alpha, n_eval,
+                        L0[wv], L1[wv], L2[wv]);
+    // the next tile's staging overwrites this wave's LDS slice
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -580,19 +606,23 @@ static int resident_blocks(const void* kernel, int threads) {
   return std::max(1, cus) * std::max(1, per);
 }
 
+constexpr int FWD_TPW = 4;  // tiles (waves) per workgroup
+
 template <int TW, int TH, int FB>
 static void fwd_fb(int nv, int W, int H, int TX, int TY, bool persist, const CamDev& cam,
                    StateDev st, unsigned int* sched, float* color, float* depth, float* alpha,
                    int32_t* n_eval, hipStream_t s) {
   const int ntiles = nv * TX * TY;
+  const int need = (ntiles + FWD_TPW - 1) / FWD_TPW;
   if (persist) {
-    const auto k = k_render_fwd<TW, TH, FB, true>;
-    const int grid = std::min(ntiles, resident_blocks((const void*)k, TW * TH));
-    hipLaunchKernelGGL(k, dim3(std::max(1, grid)), dim3(TW * TH), 0, s, ntiles, W, H, TX, TY, cam,
-                       st, sched, color, depth, alpha, n_eval);
+    const auto k = k_render_fwd<TW, TH, FB, FWD_TPW, true>;
+    const int grid = std::min(need, resident_blocks((const void*)k, 64 * FWD_TPW));
+    hipLaunchKernelGGL(k, dim3(std::max(1, grid)), dim3(64 * FWD_TPW), 0, s, ntiles, W, H, TX, TY,
+                       cam, st, sched, color, depth, alpha, n_eval);
   } else {
-    hipLaunchKernelGGL((k_render_fwd<TW, TH, FB, false>), dim3(xcd_grid(ntiles)), dim3(TW * TH),
-                       0, s, ntiles, W, H, TX, TY, cam, st, sched, color, depth, alpha, n_eval);
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, FB, FWD_TPW, false>), dim3(xcd_grid(need)),
+                       dim3(64 * FWD_TPW), 0, s, ntiles, W, H, TX, TY, cam, st, sched, color,
+                       depth, alpha, n_eval);
   }
 }
 
