@@ -327,7 +327,8 @@ def work_counts(np, rast, sc, vw, V, H, W, tile):
         return pad.reshape(V, TY, tile[1], TX, tile[0]).max(axis=(2, 4))
 
     out = dict(pairs=P, visible_pairs=int(counts["visible_pairs"]),
-               instances=int(counts["instances"]), examined=int(n_eval.sum()),
+               instances=int(counts["instances"]), row_entries=int(counts["row_entries"]),
+               examined=int(n_eval.sum()),
                walked=int(last.sum()), blended=int(dbg["n_blend"].astype(np.int64).sum()),
                E_fwd=int(tile_max(n_eval).sum()), E_bwd=int(tile_max(last).sum()))
     del state, c, d, a, ne
@@ -337,7 +338,7 @@ def work_counts(np, rast, sc, vw, V, H, W, tile):
 def algorithmic(cnt, sc_np, V, H, W, sh_stride, fwd_only_views=0):
     """Algorithmic bytes per stage (the minimum each stage must move, from
     the measured counts) and operations of the compositing kernels."""
-    P, Pv, I = cnt["pairs"], cnt["visible_pairs"], cnt["instances"]
+    P, Pv = cnt["pairs"], cnt["visible_pairs"]
     rgb = sc_np.sh_degree == 0
     par = 56 if rgb else 4 * (3 + 3 + 4 + 1 + 3 * sh_stride)
     npx = V * H * W
@@ -352,7 +353,10 @@ def algorithmic(cnt, sc_np, V, H, W, sh_stride, fwd_only_views=0):
         # per pair, rect + record per visible pair
         "record": par * sc_np.n + 4 * P + (48 + 8) * Pv,
         "depth_sort": 4 * 24 * Pv,
-        "binning": 2 * 12 * Pv + 4 * I,
+        # rects and depth order read by the counting and scatter passes, the
+        # (pair, tile row) entries written; the tile lists are filtered from
+        # them by the compositing kernels
+        "binning": 2 * 12 * Pv + 8 * cnt["row_entries"],
         "render_fwd": 52 * cnt["E_fwd"] + 28 * npx,
         "render_bwd": 52 * cnt["E_bwd"] + 80 * cnt["E_bwd"] + 28 * npx,
         # parameters read and gradients written once per Gaussian, the visible
@@ -519,7 +523,7 @@ def summary(res):
                 evals_per_s=round((cnt["examined"] + cnt["walked"]) / dt, 1),
                 evals={"forward": cnt["examined"], "backward": cnt["walked"],
                        "blended": cnt["blended"]},
-                counts={k: cnt[k] for k in ("pairs", "visible_pairs", "instances")},
+                counts={k: cnt[k] for k in ("pairs", "visible_pairs", "instances", "row_entries")},
                 step_algorithmic_GB=round(res["step_bytes"] / 1e9, 3),
                 step_hbm_roofline_frac=round(res["step_bytes"] / (dt * HBM_PEAK_GBS * 1e9), 4),
                 tile=f"{res['tile'][0]}x{res['tile'][1]}", options=res["opts"],

@@ -56,12 +56,12 @@
  * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
  * stream).  gsr_forward and gsr_backward only enqueue work: they do not
  * allocate, free, synchronise or copy to the host, so they may be captured
- * in a HIP graph.  Work-dependent sizes (visible pairs, tile instances) stay
+ * in a HIP graph.  Work-dependent sizes (visible pairs, row entries) stay
  * on the device.
  *
  * Errors.  Every call returns a gsr_status and never aborts; the context's
  * last error message gives details.  One context is used by one host
- * thread at a time.  A forward whose tile instances exceed the planned
+ * thread at a time.  A forward whose binning entries exceed the planned
  * capacity sets a device flag, renders nothing useful, and gsr_poll then
  * reports GSR_E_OVERFLOW with the needed capacity.
  */
@@ -97,7 +97,12 @@ typedef struct gsr_ctx gsr_ctx;
 /* Capacities.  All workspace is sized from these at gsr_plan time. */
 typedef struct gsr_plan_desc {
   int64_t max_pairs;     /* >= sum over views of the size of the view's set */
-  int64_t max_instances; /* >= (Gaussian, tile) copies per forward call */
+  int64_t max_instances; /* >= (Gaussian, tile row) entries per forward call:
+                            the binning stores each visible pair once per
+                            tile row its rect spans, and every tile's list
+                            is that row's list filtered by column, so a
+                            bound on the (Gaussian, tile) copies is also
+                            enough */
   int32_t max_views;     /* 1..GSR_MAX_VIEWS */
   int32_t width;         /* image size every call of this plan uses */
   int32_t height;
@@ -173,9 +178,11 @@ typedef struct gsr_grads {
 
 typedef struct gsr_counts {
   int64_t visible_pairs; /* pairs that survived culling, summed over views */
-  int64_t instances;     /* (Gaussian, tile) copies of the last forward */
+  int64_t instances;     /* (Gaussian, tile) copies of the last forward (the
+                            tile lists' total length; never stored) */
+  int64_t row_entries;   /* (Gaussian, tile row) entries of the last forward */
   int64_t capacity;      /* max_instances of the plan */
-  int32_t overflow;      /* 1 if instances > capacity */
+  int32_t overflow;      /* 1 if row_entries > capacity */
   int32_t n_views;
 } gsr_counts;
 
@@ -207,11 +214,13 @@ gsr_status gsr_backward(gsr_ctx* ctx, const gsr_scene* scene, const gsr_views* v
                         const gsr_grad_images* grad_in, const gsr_grads* out, void* stream);
 
 /* Synchronise `stream` and read the device counters of the forward that
- * wrote `state`.  Returns GSR_E_OVERFLOW if its instances exceeded the plan. */
+ * wrote `state`.  Returns GSR_E_OVERFLOW if its row entries exceeded the
+ * plan (re-plan with max_instances >= row_entries). */
 gsr_status gsr_poll(gsr_ctx* ctx, const void* state, gsr_counts* out, void* stream);
 
-/* Test/debug export of a forward's binning (synchronises `stream`).  Host
- * buffers, each may be NULL:
+/* Test/debug export of a forward's binning (synchronises `stream`; the tile
+ * lists and the blend counts are formed by debug kernels in temporary device
+ * buffers).  Host buffers, each may be NULL:
  *   zkeys   uint32 [P]  FP32 bits of camera depth per pair, 0xFFFFFFFF = culled
  *   rects   uint16 [P,4] tile rect x0,y0,x1,y1 (zeros when culled)
  *   order   uint32 [P]  pair ids of each view's visible pairs in (depth, id)
@@ -460,13 +469,13 @@ gsr_status gsr_seed_noalloc(const float* depth, const float* color, const float*
 
 /* Time forward+backward of the given call for each candidate plan and
  * report the fastest in `best`, by coordinate search: every tile shape
- * (binning chunk automatic, one entry per thread in the forward, two per
- * lane in the backward, grid launch), then for the fastest plan so far each
+ * (binning chunk automatic, one entry per lane in the forward, two per lane
+ * in the backward, grid launch), then for the fastest plan so far each
  * binning chunk of 64, 128 and 256 pairs, the forward's 1 or 2 entries per
- * thread, the backward's 1, 2 or 4 entries per lane, and the grid or
+ * lane, the backward's 1, 2 or 4 entries per lane, and the grid or
  * persistent tile queue.  `best` holds tile_w, tile_h, chunk, fwd_batch,
  * bwd_batch and persistent; other fields are copied from `base` (the
- * instance capacity raised if a candidate overflowed).  Synchronises;
+ * entry capacity raised if a candidate overflowed).  Synchronises;
  * allocates its own temporary contexts and buffers. */
 gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* scene,
                         const gsr_views* views, const gsr_settings* settings,

@@ -72,7 +72,8 @@ class Grads(C.Structure):
 
 
 class Counts(C.Structure):
-    _fields_ = [("visible_pairs", C.c_int64), ("instances", C.c_int64), ("capacity", C.c_int64),
+    _fields_ = [("visible_pairs", C.c_int64), ("instances", C.c_int64),
+                ("row_entries", C.c_int64), ("capacity", C.c_int64),
                 ("overflow", C.c_int32), ("n_views", C.c_int32)]
 
 

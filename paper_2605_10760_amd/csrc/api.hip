@@ -99,9 +99,9 @@ StateLayout state_layout(const gsr_plan_desc& p) {
   L.rect = o; o = align256(o + P * 8);
   L.rec = o; o = align256(o + P * 48);
   L.order = o; o = align256(o + P * 4);
-  L.ranges = o; o = align256(o + V * (size_t)TX * TY * 8);
+  L.row_rg = o; o = align256(o + V * (size_t)TY * 8);
+  L.rows = o; o = align256(o + (size_t)p.max_instances * 8);
   L.torder = o; o = align256(o + V * (size_t)TX * TY * 4);
-  L.inst = o; o = align256(o + (size_t)p.max_instances * 4);
   L.tfinal = o; o = align256(o + px * 4);
   L.last = o; o = align256(o + px * 4);
   L.total = o;
@@ -119,9 +119,9 @@ StateDev state_ptrs(void* base, const gsr_plan_desc& p) {
   s.rect = (uint2*)(b + L.rect);
   s.rec = (float4*)(b + L.rec);
   s.order = (uint32_t*)(b + L.order);
-  s.ranges = (uint2*)(b + L.ranges);
+  s.row_rg = (uint2*)(b + L.row_rg);
+  s.rows = (uint2*)(b + L.rows);
   s.torder = (uint32_t*)(b + L.torder);
-  s.inst = (uint32_t*)(b + L.inst);
   s.tfinal = (float*)(b + L.tfinal);
   s.last = (uint32_t*)(b + L.last);
   s.cap = (unsigned long long)p.max_instances;
@@ -404,14 +404,7 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   const size_t o_hist = o; o = align256(o + c->max_sblocks * RADIX * 4);
   const size_t o_cnt = o; o = align256(o + c->max_chunks * (size_t)c->TY * 4);
   const size_t o_rt = o; o = align256(o + V * (size_t)c->TY * 4);
-  const size_t o_rr = o; o = align256(o + V * (size_t)c->TY * 8);
-  const size_t o_rf = o; o = align256(o + 4);
-  const size_t o_rows = o; o = align256(o + (size_t)p->max_instances * 8);
-  const size_t o_tc = o; o = align256(o + V * (size_t)c->T * 4);
-  const size_t seg_cap = (size_t)p->max_instances / SEG + V * (size_t)c->TY + 1;
-  const size_t o_so = o; o = align256(o + (V * (size_t)c->TY + 1) * 4);
-  const size_t o_sr = o; o = align256(o + seg_cap * 4);
-  const size_t o_sc = o; o = align256(o + seg_cap * (size_t)c->TX * 4);
+  const size_t o_ap = o; o = align256(o + (c->max_chunks / RC_SUB + 1) * 4);
   const size_t o_g2 = o; o = align256(o + P * GRAD2D * 4);
   const size_t o_sch = o; o = align256(o + SCHED_WORDS * 4);
   void* ws = nullptr;
@@ -432,18 +425,7 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   c->hist = (uint32_t*)(b + o_hist);
   c->bw.counts = (uint32_t*)(b + o_cnt);
   c->bw.row_tot = (uint32_t*)(b + o_rt);
-  c->bw.row_rg = (uint2*)(b + o_rr);
-  c->bw.row_flag = (unsigned int*)(b + o_rf);
-  c->bw.rows = (uint2*)(b + o_rows);
-  c->bw.row_cap = (unsigned long long)p->max_instances;
-  c->bw.tile_cnt = (uint32_t*)(b + o_tc);
-  c->bw.seg_off = (uint32_t*)(b + o_so);
-  c->bw.seg_row = (uint32_t*)(b + o_sr);
-  c->bw.seg_cnt = (uint32_t*)(b + o_sc);
-  c->bw.seg_cap = seg_cap;
-  // per-segment kernels loop over the device-side segment count; a few
-  // workgroups per CU (256 CUs) keep every CU busy
-  c->bw.seg_grid = (int)std::min<size_t>(2048, 8 * ((seg_cap + 7) / 8));
+  c->bw.area_part = (uint32_t*)(b + o_ap);
   c->grad2d = (float*)(b + o_g2);
   c->sched = (unsigned int*)(b + o_sch);
   c->rc.fwd_batch = p->fwd_batch == 2 ? 2 : 1;
@@ -505,7 +487,7 @@ gsr_status gsr_forward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   {
     StageMark m(c, GSR_STAGE_RENDER_FWD, st);
     if (c->rc.persistent &&
-        (e = launch_tile_order(vw->n_views * c->T, sd, c->sched, st)) != hipSuccess)
+        (e = launch_tile_order(vw->n_views, c->TX, c->TY, sd, c->sched, st)) != hipSuccess)
       return hip_fail(c, e, "tile order");
     if ((e = launch_render_fwd(vw->n_views, c->plan.width, c->plan.height, c->plan.tile_w,
                                c->plan.tile_h, c->TX, c->TY, c->rc, cam, sd, c->sched,
@@ -566,12 +548,13 @@ gsr_status gsr_poll(gsr_ctx* c, const void* state, gsr_counts* out, void* stream
   if (e != hipSuccess) return hip_fail(c, e, "poll");
   out->visible_pairs = h.vis_total;
   out->instances = (int64_t)h.inst_total;
+  out->row_entries = (int64_t)h.row_total;
   out->capacity = c->plan.max_instances;
   out->overflow = (int32_t)h.overflow;
   out->n_views = 0;
   if (h.overflow)
-    return fail(c, GSR_E_OVERFLOW, "forward needed %llu instances, plan holds %lld",
-                (unsigned long long)h.inst_total, (long long)c->plan.max_instances);
+    return fail(c, GSR_E_OVERFLOW, "forward needed %llu (pair, tile row) entries, plan holds %lld",
+                (unsigned long long)h.row_total, (long long)c->plan.max_instances);
   return GSR_OK;
 }
 
@@ -592,22 +575,61 @@ gsr_status gsr_debug_export(gsr_ctx* c, const void* state, int32_t n_views, gsr_
   std::vector<Cp> cps;
   if (d->zkeys) cps.push_back({d->zkeys, sd.zkey, np * 4});
   if (d->order) cps.push_back({d->order, sd.order, std::min<size_t>(np, h.vis_total) * 4});
-  if (d->ranges) cps.push_back({d->ranges, sd.ranges, (size_t)n_views * c->T * 8});
-  if (d->inst) {
-    const size_t ni = (size_t)std::min<unsigned long long>(
-        std::min<unsigned long long>(h.inst_total, sd.cap), (unsigned long long)std::max<int64_t>(0, d->n_inst));
-    cps.push_back({d->inst, sd.inst, ni * 4});
-  }
-  if (d->n_blend) {
-    // blended entries per pixel, counted by a debug kernel into a temporary
-    int32_t* tmp = nullptr;
-    if ((e = hipMalloc(&tmp, std::max<size_t>(px, 1) * 4)) != hipSuccess) return hip_fail(c, e, "debug alloc");
-    e = launch_count_blend(n_views, c->plan.width, c->plan.height, c->plan.tile_w, c->plan.tile_h,
-                           c->TX, c->TY, sd, tmp, (hipStream_t)stream);
-    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
-    if (e == hipSuccess) e = hipMemcpy(d->n_blend, tmp, px * 4, hipMemcpyDeviceToHost);
-    (void)hipFree(tmp);
-    if (e != hipSuccess) return hip_fail(c, e, "debug blend count");
+  // The tile lists are never stored by the forward: debug kernels filter
+  // them from the row lists into temporary buffers (counts, host scan,
+  // write), for the export and for the blend counter.
+  size_t n_inst_out = 0;
+  if (d->ranges || d->inst || d->n_blend) {
+    const size_t nt = (size_t)n_views * c->T;
+    hipStream_t hs = (hipStream_t)stream;
+    uint32_t* tcnt = nullptr;
+    uint2* trg = nullptr;
+    uint32_t* tinst = nullptr;
+    std::vector<uint32_t> cnt(nt);
+    std::vector<uint2> rg(nt);
+    size_t total = 0;
+    auto release = [&]() {
+      if (tcnt) (void)hipFree(tcnt);
+      if (trg) (void)hipFree(trg);
+      if (tinst) (void)hipFree(tinst);
+    };
+    e = hipMalloc(&tcnt, std::max<size_t>(nt, 1) * 4);
+    if (e == hipSuccess) e = hipMalloc(&trg, std::max<size_t>(nt, 1) * 8);
+    if (e == hipSuccess) e = launch_tile_lists(n_views, c->TX, c->TY, sd, tcnt, nullptr, nullptr, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e == hipSuccess) e = hipMemcpy(cnt.data(), tcnt, nt * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) {
+      for (size_t t = 0; t < nt; ++t) {
+        rg[t] = cnt[t] ? make_uint2((uint32_t)total, (uint32_t)(total + cnt[t])) : make_uint2(0u, 0u);
+        total += cnt[t];
+      }
+      e = hipMemcpy(trg, rg.data(), nt * 8, hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess) e = hipMalloc(&tinst, std::max<size_t>(total, 1) * 4);
+    if (e == hipSuccess) e = launch_tile_lists(n_views, c->TX, c->TY, sd, tcnt, trg, tinst, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e == hipSuccess && d->ranges)
+      for (size_t t = 0; t < nt; ++t) {
+        d->ranges[2 * t] = rg[t].x;
+        d->ranges[2 * t + 1] = rg[t].y;
+      }
+    if (e == hipSuccess && d->inst) {
+      n_inst_out = std::min<size_t>(total, (size_t)std::max<int64_t>(0, d->n_inst));
+      if (n_inst_out) e = hipMemcpy(d->inst, tinst, n_inst_out * 4, hipMemcpyDeviceToHost);
+    }
+    if (e == hipSuccess && d->n_blend) {
+      // blended entries per pixel, counted by a debug kernel into a temporary
+      int32_t* tmp = nullptr;
+      e = hipMalloc(&tmp, std::max<size_t>(px, 1) * 4);
+      if (e == hipSuccess)
+        e = launch_count_blend(n_views, c->plan.width, c->plan.height, c->plan.tile_w,
+                               c->plan.tile_h, c->TX, c->TY, sd, trg, tinst, tmp, hs);
+      if (e == hipSuccess) e = hipStreamSynchronize(hs);
+      if (e == hipSuccess) e = hipMemcpy(d->n_blend, tmp, px * 4, hipMemcpyDeviceToHost);
+      if (tmp) (void)hipFree(tmp);
+    }
+    release();
+    if (e != hipSuccess) return hip_fail(c, e, "debug tile lists");
   }
   if (d->t_final) cps.push_back({d->t_final, sd.tfinal, px * 4});
   if (d->last) cps.push_back({d->last, sd.last, px * 4});
@@ -624,10 +646,7 @@ gsr_status gsr_debug_export(gsr_ctx* c, const void* state, int32_t n_views, gsr_
     for (size_t i = 0; i < n; ++i) a[i] = a[i] < nvis ? vpair[a[i]] : 0xFFFFFFFFu;
   };
   if (d->order) to_pair(d->order, std::min<size_t>(np, h.vis_total));
-  if (d->inst)
-    to_pair(d->inst, (size_t)std::min<unsigned long long>(
-                         std::min<unsigned long long>(h.inst_total, sd.cap),
-                         (unsigned long long)std::max<int64_t>(0, d->n_inst)));
+  if (d->inst) to_pair(d->inst, n_inst_out);
   if (d->rects && np) {
     std::vector<uint2> r(std::max<size_t>(nvis, 1));
     std::vector<uint32_t> vi(np);
@@ -1027,7 +1046,8 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
       gsr_counts cnt;
       gsr_status ps = gsr_poll(ctx, state, &cnt, st);
       if (ps == GSR_E_OVERFLOW) {
-        p.max_instances = std::min<int64_t>(0xFFFFFFFEL, cnt.instances + cnt.instances / 8 + 1024);
+        p.max_instances =
+            std::min<int64_t>(0xFFFFFFFEL, cnt.row_entries + cnt.row_entries / 8 + 1024);
         continue;
       }
       if (ps != GSR_OK) break;

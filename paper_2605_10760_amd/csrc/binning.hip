@@ -1,26 +1,18 @@
 // Tile binning: the last (most significant) digit of the (tile, depth) key
-// sort, done as a stable two-level counting sort - rows, then tiles - that
-// writes each tile's list in (depth, pair id) order without ever forming the
-// 64-bit keys.
+// sort, done as a stable counting sort on tile rows; the per-tile lists are
+// the row lists filtered by column, which the compositing kernels do as they
+// walk (a tile reads only the prefix of its row list that it needs).
 //
 // Input: each view's visible pairs in (depth, id) order and their tile
-// rectangles.
-//   row level  : the depth-ordered pairs are cut into chunks; per chunk the
-//                number of pairs spanning each tile row (1D difference array
-//                in LDS), an exclusive scan down each row's chunks, a scan
-//                over all (view, row) buckets, and a scatter where one wave
-//                per chunk takes its pairs 64 at a time and appends
-//                (pair id, x0, x1) to every row the rect spans, ranked inside
-//                each row by a wave ballot (lane order = depth order).
-//   Both scatters hold their chunk / segment in registers and walk it
-//   bucket by bucket, so each bucket's stores are issued back to back.
-//   tile level : each row list (still in depth order) is cut into segments
-//                of SEG entries; per segment the number of entries covering
-//                each tile of the row, an exclusive scan down each tile's
-//                segments, a scan over all tiles (the tile ranges), and a
-//                scatter where one wave per segment holds the segment in
-//                registers and, column by column, ranks the entries covering
-//                the column by a wave ballot per 64 entries.
+// rectangles.  The depth-ordered pairs are cut into chunks; per chunk the
+// number of pairs spanning each tile row (1D difference array in LDS), an
+// exclusive scan down each row's chunks, a scan over all (view, row) buckets
+// (the row ranges), and a scatter where one wave per chunk holds its pairs in
+// registers, 64 per step, and appends (visible position, x0 | x1 << 16) to
+// every row the rect spans, ranked inside each row by a wave ballot (lane
+// order = depth order), row by row so each row's stores are issued back to
+// back.  The counting pass also sums the (pair, tile) copies the rects stand
+// for (reported, never stored).
 #include <algorithm>
 
 #include "common.h"
@@ -45,9 +37,10 @@ __device__ __forceinline__ void unpack_rect(uint2 r, int& x0, int& y0, int& x1, 
 // Per chunk: pairs spanning each row (rows[y] for y < TY).  A workgroup
 // takes RC_SUB chunks: their rects are loaded together, counted into one 1D
 // difference array per chunk in LDS, and wave k scans chunk k's array.
-constexpr int RC_SUB = 4;
-__global__ __launch_bounds__(256) void k_row_count(BinTab t, StateDev st, uint32_t* counts) {
+__global__ __launch_bounds__(256) void k_row_count(BinTab t, StateDev st, uint32_t* counts,
+                                                   uint32_t* area_part) {
   __shared__ int dif[RC_SUB][MAX_ROWS + 1];
+  __shared__ uint32_t wsum[4];
   const int nc = t.cblk_off[t.nv];
   const int g = xcd_remap(blockIdx.x, (nc + RC_SUB - 1) / RC_SUB);
   if (g < 0) return;
@@ -68,6 +61,7 @@ __global__ __launch_bounds__(256) void k_row_count(BinTab t, StateDev st, uint32
   }
   for (int i = threadIdx.x; i < RC_SUB * (MAX_ROWS + 1); i += 256) (&dif[0][0])[i] = 0;
   __syncthreads();
+  uint32_t area = 0;
 #pragma unroll
   for (int k = 0; k < RC_SUB; ++k) {
     if (lo[k] + (int)threadIdx.x < hi[k]) {
@@ -75,9 +69,16 @@ __global__ __launch_bounds__(256) void k_row_count(BinTab t, StateDev st, uint32
       unpack_rect(rc[k], x0, y0, x1, y1);
       atomicAdd(&dif[k][y0], 1);
       atomicSub(&dif[k][y1], 1);
+      area += (uint32_t)((x1 - x0) * (y1 - y0));
     }
   }
+  // (pair, tile) copies of the workgroup's pairs (at most 1024 x 512 x 512),
+  // one partial per workgroup: the row range scan adds them up
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) area += (uint32_t)__shfl_xor((int)area, d, 64);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = area;
   __syncthreads();
+  if (threadIdx.x == 0) area_part[g] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
   // wave k: inclusive scan of chunk k's difference array, 64 rows at a time
   const int k = threadIdx.x >> 6;
   const int b = g * RC_SUB + k;
@@ -151,15 +152,15 @@ __global__ __launch_bounds__(CS_COLS* CS_SEGS) void k_colscan(BinTab t, const St
 // Exclusive scan of n bucket totals into [first, last+1) ranges ((0, 0)
 // when empty), over ceil(n / RS_TILE) workgroups: workgroup b scans tile b
 // after summing every total before it; the last workgroup writes the grand
-// total into *total (if given) and the capacity flag into *flag (set when
-// the total exceeds cap).
+// total into *total and the capacity flag into *flag (set when the total
+// exceeds cap), and the sum of the np partials in part into *part_total.
 constexpr int RS_TILE = 4096;  // 1024 threads x 4 totals
 __global__ __launch_bounds__(1024) void k_range_scan(int n, const uint32_t* cnt, uint2* ranges,
                                                     unsigned long long cap,
                                                     unsigned long long* total,
-                                                    unsigned int* flag,
-                                                    const unsigned int* prior_flag,
-                                                    const unsigned long long* prior_total) {
+                                                    unsigned int* flag, int np,
+                                                    const uint32_t* part,
+                                                    unsigned long long* part_total) {
   __shared__ unsigned long long sh[17];
   const int base = (int)blockIdx.x * RS_TILE;
   const unsigned long long carry = wg_sum_before<1024>(cnt, base, sh);
@@ -182,24 +183,18 @@ __global__ __launch_bounds__(1024) void k_range_scan(int n, const uint32_t* cnt,
     }
     pre += x[k];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-    unsigned long long all = carry + tot;
-    // an earlier level that overflowed leaves this level's counts empty: keep
-    // the flag and report the earlier level's total as a lower bound
-    const bool prior = prior_flag && *prior_flag;
-    if (prior && prior_total && *prior_total > all) all = *prior_total;
-    if (total) *total = all;
-    *flag = (prior || all > cap) ? 1u : 0u;
+  if (blockIdx.x == gridDim.x - 1) {
+    unsigned long long ps = 0;
+    for (int i = threadIdx.x; i < np; i += 1024) ps += part[i];
+    unsigned long long pall;
+    (void)wg_excl_scan<1024>(ps, sh, &pall);
+    if (threadIdx.x == 0) {
+      const unsigned long long all = carry + tot;
+      *total = all;
+      *flag = all > cap ? 1u : 0u;
+      *part_total = pall;
+    }
   }
-}
-
-static void range_scan(int n, const uint32_t* cnt, uint2* ranges, unsigned long long cap,
-                       unsigned long long* total, unsigned int* flag,
-                       const unsigned int* prior_flag, const unsigned long long* prior_total,
-                       hipStream_t s) {
-  const int nb = std::max(1, (n + RS_TILE - 1) / RS_TILE);
-  hipLaunchKernelGGL(k_range_scan, dim3(nb), dim3(1024), 0, s, n, cnt, ranges, cap, total, flag,
-                     prior_flag, prior_total);
 }
 
 // Wave-wide minimum / maximum (every lane active), returned in every lane.
@@ -220,9 +215,7 @@ __device__ __forceinline__ int wave_max_i(int x) {
 // spans, a ballot per step gives the lanes spanning it, so lane l's slot in
 // that row is the row cursor plus the number of lower lanes in the mask.
 // The row cursors sit in the wave's row of LDS (no barriers: one wave).
-__global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, const uint32_t* counts,
-                                                     const uint2* row_rg, uint2* rows,
-                                                     const unsigned int* row_flag) {
+__global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, const uint32_t* counts) {
   constexpr int STEPS = MAX_CHUNK / 64;
   __shared__ uint32_t curs[4][MAX_ROWS];
   const int nc = t.cblk_off[t.nv];
@@ -231,7 +224,7 @@ __global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, cons
   if (b < 0 || b >= nc) return;
   int v, lo, hi;
   chunk_range(t, st.hdr, b, v, lo, hi);
-  if (lo >= hi || *row_flag) return;
+  if (lo >= hi || st.hdr->overflow) return;
   const int lane = threadIdx.x & 63, TY = t.TY;
   const int nsteps = (hi - lo + 63) / 64;
   // the chunk's pairs and rects, every load issued before the first use
@@ -260,7 +253,7 @@ __global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, cons
   ymax = __builtin_amdgcn_readfirstlane(wave_max_i(ymax));
   uint32_t* cw = curs[wave];
   for (int y = ymin + lane; y < ymax; y += 64)
-    cw[y] = row_rg[(size_t)v * TY + y].x + counts[(size_t)b * TY + y];
+    cw[y] = st.row_rg[(size_t)v * TY + y].x + counts[(size_t)b * TY + y];
   __builtin_amdgcn_wave_barrier();
   // row by row: a ballot per 64 pairs; the row's stores of the chunk are
   // issued back to back onto consecutive entries.  They stay inside the row's
@@ -277,7 +270,7 @@ __global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, cons
         if (cov) {
           const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
               (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          rows[c + rank] = make_uint2(pid[k], xs[k]);
+          st.rows[c + rank] = make_uint2(pid[k], xs[k]);
         }
         c += (uint32_t)__popcll(m);
       }
@@ -285,234 +278,22 @@ __global__ __launch_bounds__(256) void k_row_scatter(BinTab t, StateDev st, cons
   }
 }
 
-// Level 2 works on segments of SEG consecutive entries of a row list, so a
-// long row is spread over many workgroups; segment s of row r covers
-// entries [row_rg[r].x + (s - seg_off[r]) * SEG, ...) of that row.
-
-// One workgroup: segment offsets of the row lists (zero segments when the
-// row level overflowed).
-__global__ __launch_bounds__(1024) void k_seg_scan(int n, const uint2* row_rg, uint32_t* seg_off,
-                                                  const unsigned int* row_flag) {
-  __shared__ unsigned long long sh[17];
-  const bool off = *row_flag != 0u;
-  unsigned long long carry = 0;
-  for (int base = 0; base < n; base += 1024) {
-    const int r = base + (int)threadIdx.x;
-    uint32_t ns = 0;
-    if (r < n && !off) {
-      const uint2 rg = row_rg[r];
-      ns = (rg.y - rg.x + SEG - 1) / SEG;
-    }
-    unsigned long long tot;
-    const unsigned long long pre = wg_excl_scan<1024>(ns, sh, &tot) + carry;
-    if (r < n) seg_off[r] = (uint32_t)pre;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) seg_off[n] = (uint32_t)carry;
-}
-
-// One workgroup per row list: the row of each of its segments.
-__global__ __launch_bounds__(256) void k_seg_rows(const uint32_t* seg_off, uint32_t* seg_row) {
-  const int r = blockIdx.x;
-  const uint32_t s0 = seg_off[r], s1 = seg_off[r + 1];
-  for (uint32_t k = s0 + threadIdx.x; k < s1; k += 256) seg_row[k] = (uint32_t)r;
-}
-
-// Row r and entry range [lo, hi) of segment s.
-__device__ __forceinline__ void seg_range(const uint32_t* seg_off, const uint32_t* seg_row,
-                                          const uint2* row_rg, uint32_t s, int& r, uint32_t& lo,
-                                          uint32_t& hi) {
-  r = (int)seg_row[s];
-  const uint2 rg = row_rg[r];
-  lo = rg.x + (s - seg_off[r]) * (uint32_t)SEG;
-  hi = min(rg.y, lo + (uint32_t)SEG);
-}
-
-// Per segment: entries covering each tile of the row (1D difference array
-// over the columns).  Grid-stride over the device-side segment count.
-__global__ __launch_bounds__(256) void k_tile_count(int nrows, int TX, const uint32_t* seg_off,
-                                                    const uint32_t* seg_row, const uint2* row_rg,
-                                                    const uint2* rows, uint32_t* seg_cnt) {
-  __shared__ int dif[MAX_COLS + 1];
-  const uint32_t nseg = seg_off[nrows];
-  for (uint32_t s = (uint32_t)xcd_remap(blockIdx.x, gridDim.x); s < nseg; s += gridDim.x) {
-    int r;
-    uint32_t lo, hi;
-    seg_range(seg_off, seg_row, row_rg, s, r, lo, hi);
-    for (int i = threadIdx.x; i <= TX; i += 256) dif[i] = 0;
-    __syncthreads();
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256) {
-      const uint32_t xs = rows[i].y;
-      atomicAdd(&dif[xs & 0xFFFF], 1);
-      atomicSub(&dif[xs >> 16], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      int carry = 0;
-      for (int base = 0; base < TX; base += 64) {
-        const int x = base + (int)threadIdx.x;
-        const int d = x < TX ? dif[x] : 0;
-        const int inc = (int)wave_incl_scan((uint32_t)d) + carry;
-        if (x < TX) seg_cnt[(size_t)s * TX + x] = (uint32_t)inc;
-        carry = __shfl(inc, 63, 64);
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// One thread per (row, column): exclusive scan of the column's counts down
-// the row's segments (in place) and the tile's total.
-__global__ __launch_bounds__(256) void k_seg_colscan(int nrows, int TX, const uint32_t* seg_off,
-                                                     uint32_t* seg_cnt, uint32_t* tile_cnt) {
-  const int g = blockIdx.x * 256 + (int)threadIdx.x;
-  if (g >= nrows * TX) return;
-  const int r = g / TX, x = g - r * TX;
-  const uint32_t s0 = seg_off[r], s1 = seg_off[r + 1];
-  uint32_t* c = seg_cnt + (size_t)s0 * TX + x;
-  const int n = (int)(s1 - s0);
-  uint32_t run = 0;
-  int k = 0;
-  for (; k + 4 <= n; k += 4) {
-    uint32_t v[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = c[(size_t)(k + j) * TX];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      c[(size_t)(k + j) * TX] = run;
-      run += v[j];
-    }
-  }
-  for (; k < n; ++k) {
-    const uint32_t v = c[(size_t)k * TX];
-    c[(size_t)k * TX] = run;
-    run += v;
-  }
-  tile_cnt[g] = run;
-}
-
-// One wave per segment (grid-stride over the device-side segment count).
-// The segment's SEG entries are loaded into registers at once, 64 per step in
-// list order; the cursors of the columns it covers go to the wave's row of
-// LDS.  Column by column, a ballot per step gives the lanes whose entry
-// covers the column; lane l stores its pair at the column's cursor plus the
-// number of lower lanes in the mask, and the cursor advances by the mask's
-// count.  A column's stores of the whole segment are issued back to back and
-// land on consecutive words, so its cache lines are filled before the next
-// column starts (walking step-major instead interleaves every column's short
-// runs, and partly filled lines reach HBM about twice over).  The step loop
-// is unrolled so that the entries are addressed statically.
-constexpr int TS_WAVES = 4;
-constexpr int TS_STEPS = SEG / 64;
-// Lanes whose entry covers column x store their pair at c plus their rank
-// among the covering lanes; c advances by the number of covering lanes.
-__device__ __forceinline__ void scatter_step(int x, int x0, int span, uint32_t pid, uint32_t& c,
-                                             uint32_t* inst) {
-  const bool cov = (unsigned)(x - x0) < (unsigned)span;
-  const unsigned long long m = __ballot(cov);
-  if (cov) {
-    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    inst[c + rank] = pid;
-  }
-  c += (uint32_t)__popcll(m);
-}
-
-__global__ __launch_bounds__(64 * TS_WAVES) void k_tile_scatter(BinTab t, StateDev st,
-                                                                const uint32_t* seg_off,
-                                                                const uint32_t* seg_row,
-                                                                const uint32_t* seg_cnt,
-                                                                const uint2* row_rg,
-                                                                const uint2* rows) {
-  __shared__ uint32_t curs[TS_WAVES][MAX_COLS];
-  if (st.hdr->overflow) return;
-  const int nrows = t.nv * t.TY;
-  const uint32_t nseg = seg_off[nrows];
-  const int lane = threadIdx.x & 63, TX = t.TX;
-  const uint32_t nw = gridDim.x * TS_WAVES;
-  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  uint32_t* cw = curs[wave];
-  for (uint32_t s = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * TS_WAVES + wave; s < nseg;
-       s += nw) {
-    int r;
-    uint32_t lo, hi;
-    seg_range(seg_off, seg_row, row_rg, s, r, lo, hi);
-    const int nsteps = (int)((hi - lo + 63) / 64);
-    uint32_t pid[TS_STEPS];
-    int x0[TS_STEPS], span[TS_STEPS];
-    int xmin = TX, xmax = 0;
-    // unconditional loads (clamped into the segment) so that all of them are
-    // in flight together
-#pragma unroll
-    for (int k = 0; k < TS_STEPS; ++k) {
-      const uint32_t i = lo + (uint32_t)(k * 64 + lane);
-      const uint2 e = rows[min(i, hi - 1u)];
-      const bool valid = i < hi;
-      pid[k] = e.x;
-      x0[k] = (int)(e.y & 0xFFFF);
-      span[k] = valid ? (int)(e.y >> 16) - x0[k] : 0;
-      if (valid) {
-        xmin = min(xmin, x0[k]);
-        xmax = max(xmax, (int)(e.y >> 16));
-      }
-    }
-    xmin = __builtin_amdgcn_readfirstlane(wave_min_i(xmin));
-    xmax = __builtin_amdgcn_readfirstlane(wave_max_i(xmax));
-    // the cursors of the covered columns go to this wave's LDS row
-    for (int x = xmin + lane; x < xmax; x += 64)
-      cw[x] = st.ranges[(size_t)r * TX + x].x + seg_cnt[(size_t)s * TX + x];
-    __builtin_amdgcn_wave_barrier();
-    // Stores stay inside the tile's range: the column's cursor plus the
-    // covering entries of this segment end at the next segment's cursor
-    // (the counts used the same x0 <= x < x1 rule), and the ranges fit the
-    // capacity (checked above through the overflow flag).
-    if (nsteps == TS_STEPS) {
-#pragma unroll 1
-      for (int x = xmin; x < xmax; ++x) {
-        uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cw[x]);
-#pragma unroll
-        for (int k = 0; k < TS_STEPS; ++k) scatter_step(x, x0[k], span[k], pid[k], c, st.inst);
-      }
-    } else {
-#pragma unroll 1
-      for (int x = xmin; x < xmax; ++x) {
-        uint32_t c = (uint32_t)__builtin_amdgcn_readfirstlane((int)cw[x]);
-#pragma unroll
-        for (int k = 0; k < TS_STEPS; ++k)
-          if (k < nsteps) scatter_step(x, x0[k], span[k], pid[k], c, st.inst);
-      }
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
 hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStream_t s) {
   const int nc = t.cblk_off[t.nv];
   const int nrows = t.nv * t.TY;
-  // level 1: rows
+  const int nparts = (nc + RC_SUB - 1) / RC_SUB;
   if (nc > 0)
-    hipLaunchKernelGGL(k_row_count, dim3(xcd_grid((nc + RC_SUB - 1) / RC_SUB)), dim3(256), 0, s,
-                       t, st, w.counts);
+    hipLaunchKernelGGL(k_row_count, dim3(xcd_grid(nparts)), dim3(256), 0, s, t, st, w.counts,
+                       w.area_part);
   hipLaunchKernelGGL(k_colscan, dim3((nrows + CS_COLS - 1) / CS_COLS), dim3(CS_COLS * CS_SEGS),
                      0, s, t, st.hdr, t.TY, w.counts, w.row_tot);
-  range_scan(nrows, w.row_tot, w.row_rg, w.row_cap, &st.hdr->row_total, w.row_flag,
-             (const unsigned int*)nullptr, (const unsigned long long*)nullptr, s);
+  const int nb = std::max(1, (nrows + RS_TILE - 1) / RS_TILE);
+  hipLaunchKernelGGL(k_range_scan, dim3(nb), dim3(1024), 0, s, nrows, w.row_tot, st.row_rg,
+                     st.cap, &st.hdr->row_total, &st.hdr->overflow, nparts, w.area_part,
+                     &st.hdr->inst_total);
   if (nc > 0)
     hipLaunchKernelGGL(k_row_scatter, dim3(xcd_grid((nc + 3) / 4)), dim3(256), 0, s, t, st,
-                       w.counts, w.row_rg, w.rows, w.row_flag);
-  // level 2: tiles, per row segment
-  hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(1024), 0, s, nrows, w.row_rg, w.seg_off,
-                     w.row_flag);
-  if (nrows > 0)
-    hipLaunchKernelGGL(k_seg_rows, dim3(nrows), dim3(256), 0, s, w.seg_off, w.seg_row);
-  hipLaunchKernelGGL(k_tile_count, dim3(w.seg_grid), dim3(256), 0, s, nrows, t.TX, w.seg_off,
-                     w.seg_row, w.row_rg, w.rows, w.seg_cnt);
-  hipLaunchKernelGGL(k_seg_colscan, dim3((nrows * t.TX + 255) / 256), dim3(256), 0, s, nrows,
-                     t.TX, w.seg_off, w.seg_cnt, w.tile_cnt);
-  range_scan(t.nv * t.T, w.tile_cnt, st.ranges, st.cap, &st.hdr->inst_total, &st.hdr->overflow,
-             w.row_flag, &st.hdr->row_total, s);
-  hipLaunchKernelGGL(k_tile_scatter, dim3(w.seg_grid), dim3(64 * TS_WAVES), 0, s, t, st,
-                     w.seg_off, w.seg_row, w.seg_cnt, w.row_rg, w.rows);
+                       w.counts);
   return hipGetLastError();
 }
 

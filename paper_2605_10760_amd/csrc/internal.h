@@ -25,7 +25,7 @@ constexpr uint32_t CULLED = 0xFFFFFFFFu;
 constexpr int MAX_ROWS = 512;     // tile rows per view (binning LDS arrays)
 constexpr int MAX_COLS = 512;     // tile columns per view
 constexpr int MAX_CHUNK = 256;   // depth-sorted pairs per row-binning chunk
-constexpr int SEG = 1024;         // row-list entries per tile-binning segment
+constexpr int RC_SUB = 4;        // row-binning chunks per counting workgroup
 constexpr int SCHED_WORDS = 2 + 2 * 33;  // tile cursors + length-bucket counts (render.hip)
 constexpr int GSR_MAX_DEVICES = 64;  // devices with a looked-up library-held buffer
 constexpr long SEED_NOALLOC_MAX_POINTS = GSR_SEED_NOALLOC_MAX_POINTS;
@@ -86,8 +86,8 @@ struct CamDev {
 
 // Device header at the start of every saved-state buffer.
 struct StateHeader {
-  unsigned long long inst_total;  // sum of tile counts (may exceed capacity)
-  unsigned int overflow;
+  unsigned long long inst_total;  // (pair, tile) copies of the rects (reported only)
+  unsigned int overflow;          // the row entries exceeded the capacity
   unsigned int vis_total;
   unsigned long long row_total;   // (pair, tile row) entries of the binning
   unsigned int vis_off[MAXV + 1]; // visible-pair offsets per view (compacted order)
@@ -97,7 +97,7 @@ static_assert(sizeof(StateHeader) <= STATE_HEADER_BYTES, "header");
 
 // Byte offsets of the arrays inside a saved-state buffer (all 256-aligned).
 struct StateLayout {
-  size_t hdr, zkey, vidx, vpair, rect, rec, order, ranges, torder, inst, tfinal, last, total;
+  size_t hdr, zkey, vidx, vpair, rect, rec, order, row_rg, rows, torder, tfinal, last, total;
 };
 
 // Pointers into a saved-state buffer.
@@ -110,9 +110,10 @@ struct StateDev {
   float4* rec;        // [Pv][3] by visible position: (u, v, A', B'), (C', sigma, z, ex),
                       //   (r, g, b, ey)
   uint32_t* order;    // [Pv] visible positions in (view, depth, id) order
-  uint2* ranges;      // [V*T]
-  uint32_t* torder;   // [V*T] tiles by decreasing list length (persistent render)
-  uint32_t* inst;     // [cap]
+  uint2* row_rg;      // [V*TY] range of each (view, tile row) list in rows
+  uint2* rows;        // [cap] row lists: (visible position, x0 | x1 << 16) in
+                      //   (depth, id) order
+  uint32_t* torder;   // [V*T] tiles by decreasing row-list length (persistent render)
   float* tfinal;      // [V*H*W]
   uint32_t* last;     // [V*H*W]
   unsigned long long cap;
@@ -122,16 +123,7 @@ struct StateDev {
 struct BinWork {
   uint32_t* counts;     // [chunks][TY] per-chunk row counts -> exclusive bases
   uint32_t* row_tot;    // [V*TY] entries per (view, row)
-  uint2* row_rg;        // [V*TY] row list ranges
-  unsigned int* row_flag;
-  uint2* rows;          // [row_cap] (pair id, x0 | x1 << 16)
-  unsigned long long row_cap;
-  uint32_t* tile_cnt;   // [V*T]
-  uint32_t* seg_off;    // [V*TY+1] first level-2 segment of each row list
-  uint32_t* seg_row;    // [seg_cap] row of each segment
-  uint32_t* seg_cnt;    // [seg_cap][TX] per-segment tile counts -> exclusive bases
-  unsigned long long seg_cap;
-  int seg_grid;         // workgroups of the per-segment kernels (multiple of 8)
+  uint32_t* area_part;  // [chunks / RC_SUB + 1] (pair, tile) copies per counting workgroup
 };
 
 // Sim(3) corrections: Gaussian set offsets, and the set of every view.
@@ -157,16 +149,16 @@ hipError_t launch_compact(const ProjTab& t, StateDev st, const uint32_t* blk_cnt
 hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
                              uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s);
 hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStream_t s);
-// Compositing launch options (from the plan): list entries staged per
-// thread in the forward (1 or 2), per lane in the backward (1, 2 or 4), and
-// the persistent length-ordered tile queue instead of one workgroup/wave per
-// tile.
+// Compositing launch options (from the plan): list entries staged per lane
+// in the forward (1 or 2) and in the backward (1, 2 or 4), and the persistent
+// length-ordered tile queue instead of one wave per tile.
 struct RenderCfg {
   int fwd_batch;
   int bwd_batch;
   bool persistent;
 };
-hipError_t launch_tile_order(int ntiles, StateDev st, unsigned int* sched, hipStream_t s);
+hipError_t launch_tile_order(int nv, int TX, int TY, StateDev st, unsigned int* sched,
+                             hipStream_t s);
 hipError_t launch_render_fwd(int nv, int W, int H, int TW, int TH, int TX, int TY,
                              const RenderCfg& rc, const CamDev& cam, StateDev st,
                              unsigned int* sched, float* color, float* depth, float* alpha,
@@ -176,8 +168,14 @@ hipError_t launch_render_bwd(int nv, int W, int H, int TW, int TH, int TX, int T
                              const CamDev& cam, StateDev st, unsigned int* sched,
                              const float* g_color, const float* g_depth, const float* g_alpha,
                              float* grad2d, hipStream_t s);
+// Debug only: the per-tile lists filtered from the row lists, first as
+// counts per tile (tile_cnt [V*T]), then written at the tiles' offsets
+// (ranges [V*T], from the counts' exclusive scan) into inst.
+hipError_t launch_tile_lists(int nv, int TX, int TY, StateDev st, uint32_t* tile_cnt,
+                             const uint2* ranges, uint32_t* inst, hipStream_t s);
 hipError_t launch_count_blend(int nv, int W, int H, int TW, int TH, int TX, int TY, StateDev st,
-                              int32_t* n_blend, hipStream_t s);
+                              const uint2* ranges, const uint32_t* inst, int32_t* n_blend,
+                              hipStream_t s);
 hipError_t launch_zero_pose(float* d_pose, int nv, unsigned int* bwd_next, hipStream_t s);
 hipError_t launch_project_bwd(const SetTab& t, const SceneDev& sc, const CamDev& cam,
                               StateDev st, float* grad2d, const gsr_grads& g,

@@ -2,8 +2,8 @@
 //
 // Forward: one wave per (view, tile), PPL = TW*TH/64 pixels per lane (one per
 // 8x8 block of the tile), TPW tiles per workgroup with a private LDS slice
-// each (no workgroup barrier).  The tile's sorted instance list is walked in
-// rounds of B entries: each lane gathers its entries' 48-byte records into
+// each (no workgroup barrier).  The tile's list is walked in rounds of B
+// entries: each lane gathers its entries' 48-byte records into
 // the slice and tests which of the tile's 8x8 blocks each can reach; then
 // the wave walks the round in list order, every lane reading the entry once
 // (an LDS broadcast) for all of its pixels in the blocks the entry reaches.
@@ -11,11 +11,17 @@
 //
 // Backward: one wave per (view, tile), PPL = TW*TH/64 pixels per lane, TPW
 // tiles per workgroup with a private LDS slice each (no workgroup barrier).
-// Each tile's list is walked from the largest last-contributor position
-// down; every pixel recovers its transmittance by division
-// (T_j = T_{j+1} / (1 - alpha_j)) instead of storing per-pixel lists, the
-// ten splat gradients of an entry are summed over the wave with DPP row
-// operations, and ten lanes issue one global atomic each per (tile, entry).
+// Each tile's entries up to the largest last-contributor position are
+// filtered from its row list back to front; every pixel recovers its
+// transmittance by division (T_j = T_{j+1} / (1 - alpha_j)) instead of
+// storing per-pixel lists, the ten splat gradients of an entry are summed
+// over the wave with DPP row operations, and ten lanes issue one global
+// atomic each per (tile, entry).
+//
+// A tile's list (its entries in depth order) is its row list filtered by
+// column: both kernels scan the row list with a ballot per 64 entries and
+// keep the covering entries' visible positions in a ring in LDS, so only the
+// prefix of the row list a tile needs is ever read.
 #include <algorithm>
 
 #include "common.h"
@@ -89,14 +95,120 @@ __device__ __forceinline__ bool reaches(const float4& r0, float Cs, float ex, fl
   return row_extent(r0, Cs, ey, y0, y1, xl, xr) && cols_reached(xl, xr, ex, x0, x1);
 }
 
+// Ring of visible positions filtered from a row list (slots mod RING), in
+// the wave's LDS.  A round stages up to B entries; the ring is filled while
+// it holds fewer than B, two scan steps (128 row entries) at a time, so it
+// never holds more than B + 127.
+template <int B>
+struct RingSize {
+  static constexpr int value = B <= 128 ? 256 : 512;
+};
+
+// Whether tile column tx lies in the row entry's column span [x0, x1).
+__device__ __forceinline__ bool covers(uint32_t xs, uint32_t tx) {
+  return tx - (xs & 0xFFFFu) < (xs >> 16) - (xs & 0xFFFFu);
+}
+
+// Front to back: append the visible positions of the row entries at
+// [q, end) that cover column tx to the ring until it holds B or the list
+// ends; q advances past what was scanned.
+template <int B>
+__device__ __forceinline__ void fill_front(const uint2* rows, uint32_t& q, uint32_t end,
+                                           uint32_t tx, uint32_t* ring, uint32_t head,
+                                           uint32_t& tail) {
+  constexpr uint32_t RM = RingSize<B>::value - 1;
+  const int lane = threadIdx.x & 63;
+  while (tail - head < (uint32_t)B && q < end) {
+    uint2 e[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const uint32_t i = q + (uint32_t)(64 * k + lane);
+      e[k] = i < end ? rows[i] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const bool cov = covers(e[k].y, tx);
+      const unsigned long long m = __ballot(cov);
+      if (cov)
+        ring[(tail + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))) &
+             RM] = e[k].x;
+      tail += (uint32_t)__popcll(m);
+    }
+    q += 128u;
+  }
+}
+
+// Back to front: append the visible positions of the row entries at
+// [start, q) that cover column tx to the ring, in decreasing position, until
+// it holds B or the scan reaches start; q moves down past what was scanned.
+template <int B>
+__device__ __forceinline__ void fill_back(const uint2* rows, uint32_t& q, uint32_t start,
+                                          uint32_t tx, uint32_t* ring, uint32_t head,
+                                          uint32_t& tail) {
+  constexpr uint32_t RM = RingSize<B>::value - 1;
+  const int lane = threadIdx.x & 63;
+  const unsigned long long above = lane == 63 ? 0ull : (~0ull << (lane + 1));
+  while (tail - head < (uint32_t)B && q > start) {
+    uint2 e[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      // step k covers [q - 64 (k + 1), q - 64 k); lane l takes its entry l
+      const uint32_t back = (uint32_t)(64 * (k + 1) - lane);
+      e[k] = q - start >= back ? rows[q - back] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const bool cov = covers(e[k].y, tx);
+      const unsigned long long m = __ballot(cov);
+      // higher lanes (later entries) take the lower ring slots
+      if (cov) ring[(tail + (uint32_t)__popcll(m & above)) & RM] = e[k].x;
+      tail += (uint32_t)__popcll(m);
+    }
+    q = q - start > 128u ? q - 128u : start;
+  }
+}
+
+// The row position just after the n-th (1-based) entry of [q, end) that
+// covers column tx; end when there are fewer.
+__device__ __forceinline__ uint32_t nth_cover_end(const uint2* rows, uint32_t q, uint32_t end,
+                                                  uint32_t tx, uint32_t n) {
+  const int lane = threadIdx.x & 63;
+  uint32_t cnt = 0u;
+  while (q < end) {
+    uint32_t xs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = q + (uint32_t)(64 * k + lane);
+      xs[k] = i < end ? rows[i].y : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool cov = covers(xs[k], tx);
+      const unsigned long long m = __ballot(cov);
+      const uint32_t c = (uint32_t)__popcll(m);
+      if (cnt + c >= n) {
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const unsigned long long hit = __ballot(cov && rank == n - cnt - 1u);
+        return q + (uint32_t)(64 * k) + (uint32_t)__builtin_ctzll(hit) + 1u;
+      }
+      cnt += c;
+    }
+    q += 256u;
+  }
+  return end;
+}
+
 // One tile of the forward on one wave.  Lane l shades pixel (l % 8, l / 8)
-// of each of the tile's PPL 8x8 blocks; B list entries are staged per round
-// in the wave's LDS slice, with a mask per entry of the blocks it can reach.
+// of each of the tile's PPL 8x8 blocks.  The tile's list is its row list
+// filtered by column; B entries are staged per round in the wave's LDS
+// slice, with a mask per entry of the blocks it can reach.
 template <int TW, int TH, int B>
 __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, const CamDev& cam,
                                          const StateDev& st, float* color, float* depth,
                                          float* alpha, int32_t* n_eval, float4* s0, float4* s1,
-                                         float4* s2) {
+                                         float4* s2, uint32_t* ring) {
   constexpr int PPL = TW * TH / 64, BX = TW / 8, BY = TH / 8, R = B / 64;
   static_assert(TW % 8 == 0 && TH % 8 == 0, "tiles are made of 8x8 blocks");
   static_assert(PPL <= 32, "one mask bit per block");
@@ -104,8 +216,11 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
   const int v = g / T, tl = g - v * T;
   const int ty = tl / TX, tx = tl - ty * TX;
   const int lane = threadIdx.x & 63;
-  uint2 rg = st.ranges[g];
-  if (st.hdr->overflow) rg = make_uint2(0u, 0u);
+  uint2 rr = st.row_rg[(size_t)v * TY + ty];
+  if (st.hdr->overflow) rr = make_uint2(0u, 0u);
+  constexpr uint32_t RM = RingSize<B>::value - 1;
+  uint32_t q = rr.x, head = 0u, tail = 0u;  // next row entry to scan; ring cursors
+  uint32_t tbase = 0u;                      // tile entries staged before this round
   // pixel k of the lane: block (k % BX, k / BX); its centre is exact in FP32
   const float fx0 = (float)(tx * TW + (lane & 7)) + 0.5f;
   const float fy0 = (float)(ty * TH + (lane >> 3)) + 0.5f;
@@ -126,17 +241,20 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
   const float x0c = (float)(tx * TW) + 0.5f;
   const float y0c = (float)(ty * TH) + 0.5f;
   bool live = true;
-  for (uint32_t base = rg.x; live && base < rg.y; base += B) {
+  for (;;) {
+    fill_front<B>(st.rows, q, rr.y, (uint32_t)tx, ring, head, tail);
+    const uint32_t n = min((uint32_t)B, tail - head);
+    if (n == 0u) break;
     // bit k of mr[r]: the entry this lane staged in round r can reach alpha
     // >= 1/255 in block k (the extent within a block row is shared by the
     // blocks of that row)
     uint32_t mr[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint32_t idx = base + (uint32_t)(lane + 64 * r);
+      const uint32_t idx = (uint32_t)(lane + 64 * r);
       mr[r] = 0u;
-      if (idx < rg.y) {
-        const float4* rp = st.rec + 3 * (size_t)st.inst[idx];
+      if (idx < n) {
+        const float4* rp = st.rec + 3 * (size_t)ring[(head + idx) & RM];
         const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
         uint32_t m = 0u;
 #pragma unroll
@@ -180,7 +298,7 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
         // the entry's 1-based position, copied to a vector register once
         // for the per-pixel selects
         uint32_t pos1;
-        asm volatile("v_mov_b32 %0, %1" : "=v"(pos1) : "s"(base - rg.x + (uint32_t)j + 1u));
+        asm volatile("v_mov_b32 %0, %1" : "=v"(pos1) : "s"(tbase + (uint32_t)j + 1u));
         const float4 a = s0[j], b = s1[j], c = s2[j];
         auto blend = [&](int k) {
           float dx, dy;
@@ -207,6 +325,9 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
       }
       if (!live) break;
     }
+    if (!live) break;
+    head += n;
+    tbase += n;
     // the next round's staging overwrites the slice: every lane has read it
     __builtin_amdgcn_wave_barrier();
   }
@@ -224,8 +345,10 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
       alpha[v * HW + p] = 1.f - Tc[k];
       st.tfinal[v * HW + p] = Tc[k];
       st.last[v * HW + p] = last[k];
-      // entries examined: up to and including the stopping one, else the list
-      if (n_eval) n_eval[v * HW + p] = (int)(stopn[k] ? stopn[k] : rg.y - rg.x);
+      // entries examined: up to and including the stopping one, else the
+      // list (every inside pixel has stopped when the walk ends early, so
+      // tbase is the whole list whenever it is used)
+      if (n_eval) n_eval[v * HW + p] = (int)(stopn[k] ? stopn[k] : tbase);
     }
   }
 }
@@ -243,6 +366,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int 
                                                          int32_t* n_eval) {
   constexpr int B = 64 * FB;
   __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
+  __shared__ uint32_t LR[TPW][RingSize<B>::value];
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (!PERSIST) {
     const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
@@ -250,7 +374,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int 
     const int g = blk * TPW + wv;
     if (g >= ntiles) return;
     fwd_tile<TW, TH, B>(g, W, H, TX, TY, cam, st, color, depth, alpha, n_eval, L0[wv], L1[wv],
-                        L2[wv]);
+                        L2[wv], LR[wv]);
     return;
   }
   for (;;) {
@@ -259,7 +383,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int 
     q = (uint32_t)__builtin_amdgcn_readfirstlane((int)q);
     if (q >= (uint32_t)ntiles) return;
     fwd_tile<TW, TH, B>((int)st.torder[q], W, H, TX, TY, cam, st, color, depth, alpha, n_eval,
-                        L0[wv], L1[wv], L2[wv]);
+                        L0[wv], L1[wv], L2[wv], LR[wv]);
     // the next tile's staging overwrites this wave's LDS slice
     __builtin_amdgcn_wave_barrier();
   }
@@ -324,15 +448,16 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
                                          unsigned long long grad_mask, const CamDev& cam,
                                          const StateDev& st, const float* gcol, const float* gdep,
                                          const float* galp, float* grad2d, float4* s0, float4* s1,
-                                         float4* s2, uint32_t* sp) {
+                                         float4* s2, uint32_t* sp, uint32_t* ring) {
   constexpr int PPL = TW * TH / 64;
+  constexpr uint32_t RM = RingSize<B>::value - 1;
   const int T = TX * TY;
   const int v = g / T, tl = g - v * T;
   if (!((grad_mask >> v) & 1ull)) return;
   if (st.hdr->overflow) return;
-  const uint2 rg = st.ranges[g];
-  if (rg.x == rg.y) return;
   const int ty = tl / TX, tx = tl - ty * TX;
+  const uint2 rr = st.row_rg[(size_t)v * TY + ty];
+  if (rr.x == rr.y) return;
   const int lane = threadIdx.x & 63;
   const size_t HW = (size_t)W * H;
   // Per pixel: Q = sum over the entries behind the current one (and the
@@ -369,41 +494,60 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
   }
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) mylast = max(mylast, (uint32_t)__shfl_xor((int)mylast, d, 64));
-  const int maxlast = (int)mylast;
-  for (int end = maxlast; end > 0; end -= B) {
-    const int start = max(0, end - B);
-    uint32_t mr[B / 64];  // 1 if the entry this lane staged in round r reaches the tile
+  const uint32_t maxlast = mylast;
+  if (maxlast == 0u) return;
+  // The walk covers the tile's entries [0, maxlast): the row entries before
+  // the maxlast-th one covering this column, scanned back to front.
+  uint32_t qb = nth_cover_end(st.rows, rr.x, rr.y, (uint32_t)tx, maxlast);
+  uint32_t head = 0u, tail = 0u, top = maxlast;  // ring cursors; entries left to walk
+  for (;;) {
+    fill_back<B>(st.rows, qb, rr.x, (uint32_t)tx, ring, head, tail);
+    const uint32_t n = min((uint32_t)B, tail - head);
+    if (n == 0u) break;
+    uint32_t mr[B / 64];  // blocks the entry this lane staged in round r can reach
 #pragma unroll
     for (int r = 0; r < B / 64; ++r) {
-      const int i = start + lane + 64 * r;
+      const uint32_t idx = (uint32_t)(lane + 64 * r);
       mr[r] = 0u;
-      if (i < end) {
-        const uint32_t pr = st.inst[rg.x + i];
+      if (idx < n) {
+        const uint32_t pr = ring[(head + idx) & RM];
         const float4* rp = st.rec + 3 * (size_t)pr;
         const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
-        // whether the entry can reach a pixel of the tile at all
-        const float bx = (float)(tx * TW) + 0.5f, by = (float)(ty * TH) + 0.5f;
-        const uint32_t m =
-            (uint32_t)reaches(r0, r1.x, r1.w, r2.w, bx, bx + (float)(TW - 1), by, by + (float)(TH - 1));
-        s0[lane + 64 * r] = r0;
-        s1[lane + 64 * r] = r1;
-        s2[lane + 64 * r] = r2;
+        // bit k: the entry can reach alpha >= 1/255 in the tile's 8x8 block k
+        const float x0c = (float)(tx * TW) + 0.5f, y0c = (float)(ty * TH) + 0.5f;
+        uint32_t m = 0u;
+#pragma unroll
+        for (int by = 0; by < TH / 8; ++by) {
+          float xl, xr;
+          if (row_extent(r0, r1.x, r2.w, y0c + (float)(8 * by), y0c + (float)(8 * by + 7), xl, xr)) {
+#pragma unroll
+            for (int bx = 0; bx < BX; ++bx)
+              m |= (uint32_t)cols_reached(xl, xr, r1.w, x0c + (float)(8 * bx),
+                                          x0c + (float)(8 * bx + 7))
+                   << (by * BX + bx);
+          }
+        }
+        s0[idx] = r0;
+        s1[idx] = r1;
+        s2[idx] = r2;
         // the entry's screen-space gradient row: its visible-list position
-        sp[lane + 64 * r] = pr;
+        sp[idx] = pr;
         mr[r] = m;
       }
     }
     __builtin_amdgcn_wave_barrier();
-    // Back to front over the staged entries that can reach the tile (set
-    // bits of a ballot per staging round).
+    // The staged entries are in back-to-front order (entry j of the round
+    // is tile entry top - 1 - j); walk those that can reach a block of the
+    // tile (set bits of a ballot per staging round).
 #pragma unroll
-    for (int r = B / 64 - 1; r >= 0; --r) {
+    for (int r = 0; r < B / 64; ++r) {
       unsigned long long rel = __ballot(mr[r] != 0u);
       while (rel) {
-        const int jj = 63 - (int)__builtin_clzll(rel);
-        rel &= ~(1ull << jj);
+        const int jj = (int)__builtin_ctzll(rel);
+        rel &= rel - 1ull;
         const int j = 64 * r + jj;
-        const int pos = start + j;
+        const int pos = (int)top - 1 - j;
+        const uint32_t mj = (uint32_t)__builtin_amdgcn_readlane((int)mr[r], jj);
         const float4 a = s0[j], b = s1[j], c = s2[j];
         float acc[GRAD2D];
 #pragma unroll
@@ -413,9 +557,12 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
         // Branch-free per pixel: an entry a pixel does not blend gets zero
         // weight and zero gradients (selected, never multiplied, so an
         // infinite exp2 of a skipped entry cannot leak in); adding exact zeros
-        // leaves every sum unchanged.
+        // leaves every sum unchanged.  A block the entry cannot reach is not
+        // evaluated at all (a uniform branch on the entry's mask; none of its
+        // pixels would blend it).
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
+          if (!((mj >> k) & 1u)) continue;
           float dx, dy;
           const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
           const float G = exp2_fast(power);
@@ -480,6 +627,10 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
         }
       }
     }
+    head += n;
+    top -= n;
+    // the next round's staging overwrites the slice: every lane has read it
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -495,14 +646,15 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
                                                            const float* galp, float* grad2d) {
   __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
   __shared__ uint32_t LP[TPW][B];
-  const int wv = threadIdx.x >> 6;
+  __shared__ uint32_t LR[TPW][RingSize<B>::value];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (!PERSIST) {
     const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
     if (blk < 0) return;
     const int g = blk * TPW + wv;
     if (g >= ntiles) return;
     bwd_tile<TW, TH, B>(g, W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp, grad2d, L0[wv],
-                        L1[wv], L2[wv], LP[wv]);
+                        L1[wv], L2[wv], LP[wv], LR[wv]);
     return;
   }
   for (;;) {
@@ -511,7 +663,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
     q = (uint32_t)__builtin_amdgcn_readfirstlane((int)q);
     if (q >= (uint32_t)ntiles) return;
     bwd_tile<TW, TH, B>((int)st.torder[q], W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp,
-                        grad2d, L0[wv], L1[wv], L2[wv], LP[wv]);
+                        grad2d, L0[wv], L1[wv], L2[wv], LP[wv], LR[wv]);
     // the next tile's staging overwrites this wave's LDS slice: every lane
     // has finished reading it
     __builtin_amdgcn_wave_barrier();
@@ -528,16 +680,19 @@ __global__ __launch_bounds__(256) void k_zero_pose(float* d_pose, int nv, unsign
 }
 
 // ------------------------------------------------------ tile scheduling
-// The persistent forms take tiles in decreasing order of list length
-// (longest first, so that the last tiles to start are short ones): a bucket
-// sort by the position of the length's leading bit (bucket clz(len), empty
-// tiles last), per-workgroup bucket counts reserved with one global atomic
-// per bucket and workgroup.  Order within a bucket is arbitrary.
+// The persistent forms take tiles in decreasing order of their row list's
+// length (longest first, so that the last tiles to start are short ones; a
+// tile's list is a share of its row's): a bucket sort by the position of the
+// length's leading bit (bucket clz(len), empty rows last), per-workgroup
+// bucket counts reserved with one global atomic per bucket and workgroup.
+// Order within a bucket is arbitrary.
 // sched: [0] forward tile cursor, [1] backward tile cursor,
 // [2, 2 + NLB) bucket totals, [2 + NLB, 2 + 2 NLB) bucket fill cursors.
 constexpr int NLB = 33;
-__device__ __forceinline__ int len_bucket(uint2 r) {
-  const uint32_t n = r.y - r.x;
+__device__ __forceinline__ int len_bucket(const StateDev& st, int t, int TX, int TY) {
+  const int T = TX * TY, v = t / T, ty = (t - v * T) / TX;
+  const uint2 r = st.row_rg[(size_t)v * TY + ty];
+  const uint32_t n = st.hdr->overflow ? 0u : r.y - r.x;
   return n ? __clz((int)n) : 32;
 }
 
@@ -545,19 +700,19 @@ __global__ __launch_bounds__(64) void k_order_reset(unsigned int* sched) {
   for (int i = threadIdx.x; i < SCHED_WORDS; i += 64) sched[i] = 0u;
 }
 
-__global__ __launch_bounds__(1024) void k_len_hist(int ntiles, const uint2* ranges,
+__global__ __launch_bounds__(1024) void k_len_hist(int ntiles, int TX, int TY, StateDev st,
                                                    unsigned int* sched) {
   __shared__ unsigned int h[NLB];
   if (threadIdx.x < NLB) h[threadIdx.x] = 0u;
   __syncthreads();
   const int t = blockIdx.x * 1024 + (int)threadIdx.x;
-  if (t < ntiles) atomicAdd(&h[len_bucket(ranges[t])], 1u);
+  if (t < ntiles) atomicAdd(&h[len_bucket(st, t, TX, TY)], 1u);
   __syncthreads();
   if (threadIdx.x < NLB && h[threadIdx.x]) atomicAdd(&sched[2 + threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(1024) void k_len_scatter(int ntiles, const uint2* ranges,
-                                                      unsigned int* sched, uint32_t* torder) {
+__global__ __launch_bounds__(1024) void k_len_scatter(int ntiles, int TX, int TY, StateDev st,
+                                                      unsigned int* sched) {
   __shared__ unsigned int h[NLB], off[NLB], fill[NLB];
   if (threadIdx.x < NLB) {
     h[threadIdx.x] = 0u;
@@ -565,7 +720,7 @@ __global__ __launch_bounds__(1024) void k_len_scatter(int ntiles, const uint2* r
   }
   __syncthreads();
   const int t = blockIdx.x * 1024 + (int)threadIdx.x;
-  const int b = t < ntiles ? len_bucket(ranges[t]) : 0;
+  const int b = t < ntiles ? len_bucket(st, t, TX, TY) : 0;
   if (t < ntiles) atomicAdd(&h[b], 1u);
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -579,16 +734,17 @@ __global__ __launch_bounds__(1024) void k_len_scatter(int ntiles, const uint2* r
   if (threadIdx.x < NLB && h[threadIdx.x])
     off[threadIdx.x] += atomicAdd(&sched[2 + NLB + threadIdx.x], h[threadIdx.x]);
   __syncthreads();
-  if (t < ntiles) torder[off[b] + atomicAdd(&fill[b], 1u)] = (uint32_t)t;
+  if (t < ntiles) st.torder[off[b] + atomicAdd(&fill[b], 1u)] = (uint32_t)t;
 }
 
-hipError_t launch_tile_order(int ntiles, StateDev st, unsigned int* sched, hipStream_t s) {
+hipError_t launch_tile_order(int nv, int TX, int TY, StateDev st, unsigned int* sched,
+                             hipStream_t s) {
+  const int ntiles = nv * TX * TY;
   hipLaunchKernelGGL(k_order_reset, dim3(1), dim3(64), 0, s, sched);
   const int nb = (ntiles + 1023) / 1024;
   if (nb > 0) {
-    hipLaunchKernelGGL(k_len_hist, dim3(nb), dim3(1024), 0, s, ntiles, st.ranges, sched);
-    hipLaunchKernelGGL(k_len_scatter, dim3(nb), dim3(1024), 0, s, ntiles, st.ranges, sched,
-                       st.torder);
+    hipLaunchKernelGGL(k_len_hist, dim3(nb), dim3(1024), 0, s, ntiles, TX, TY, st, sched);
+    hipLaunchKernelGGL(k_len_scatter, dim3(nb), dim3(1024), 0, s, ntiles, TX, TY, st, sched);
   }
   return hipGetLastError();
 }
@@ -703,13 +859,57 @@ hipError_t launch_render_bwd(int nv, int W, int H, int TW, int TH, int TX, int T
                   g_alpha, grad2d, s);
 }
 
-// ------------------------------------------------------ debug counter
+// ------------------------------------------------------ debug kernels
+// The per-tile lists, filtered from the row lists (set-up and tests only):
+// one wave per tile scans its row list; WRITE = false counts the entries
+// covering the tile's column, WRITE = true writes their visible positions in
+// order at the tile's offset.
+template <bool WRITE>
+__global__ __launch_bounds__(256) void k_tile_lists(int ntiles, int TX, int TY, StateDev st,
+                                                    uint32_t* tile_cnt, const uint2* ranges,
+                                                    uint32_t* inst) {
+  const int g = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (g >= ntiles) return;
+  const int lane = threadIdx.x & 63;
+  const int T = TX * TY, v = g / T, tl = g - v * T, ty = tl / TX;
+  const uint32_t tx = (uint32_t)(tl - ty * TX);
+  uint2 rr = st.row_rg[(size_t)v * TY + ty];
+  if (st.hdr->overflow) rr = make_uint2(0u, 0u);
+  uint32_t c = WRITE ? ranges[g].x : 0u;
+  for (uint32_t q = rr.x; q < rr.y; q += 64u) {
+    const uint32_t i = q + (uint32_t)lane;
+    const uint2 e = i < rr.y ? st.rows[i] : make_uint2(0u, 0u);
+    const bool cov = covers(e.y, tx);
+    const unsigned long long m = __ballot(cov);
+    if (WRITE && cov)
+      inst[c + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = e.x;
+    c += (uint32_t)__popcll(m);
+  }
+  if (!WRITE && lane == 0) tile_cnt[g] = c;
+}
+
+hipError_t launch_tile_lists(int nv, int TX, int TY, StateDev st, uint32_t* tile_cnt,
+                             const uint2* ranges, uint32_t* inst, hipStream_t s) {
+  const int ntiles = nv * TX * TY;
+  if (ntiles > 0) {
+    if (inst)
+      hipLaunchKernelGGL(k_tile_lists<true>, dim3((ntiles + 3) / 4), dim3(256), 0, s, ntiles, TX,
+                         TY, st, tile_cnt, ranges, inst);
+    else
+      hipLaunchKernelGGL(k_tile_lists<false>, dim3((ntiles + 3) / 4), dim3(256), 0, s, ntiles,
+                         TX, TY, st, tile_cnt, ranges, inst);
+  }
+  return hipGetLastError();
+}
+
 // Entries blended per pixel (alpha >= 1/255 and before the stop): the
 // non-skipped entries before the pixel's last contributor, with the
 // forward's own skip arithmetic.  One workgroup per tile, one thread per
-// pixel, records read straight from the state (set-up and tests only).
+// pixel, the tile's list from k_tile_lists (set-up and tests only).
 __global__ __launch_bounds__(512) void k_count_blend(int ntiles, int W, int H, int TW, int TX,
-                                                     int TY, StateDev st, int32_t* n_blend) {
+                                                     int TY, StateDev st, const uint2* ranges,
+                                                     const uint32_t* inst, int32_t* n_blend) {
   const int g = blockIdx.x;
   if (g >= ntiles) return;
   const int T = TX * TY, v = g / T, tl = g - v * T;
@@ -718,12 +918,12 @@ __global__ __launch_bounds__(512) void k_count_blend(int ntiles, int W, int H, i
                                                         (int)threadIdx.x / TW;
   if (px >= W || py >= H) return;
   const size_t HW = (size_t)W * H, q = v * HW + (size_t)py * W + px;
-  const uint2 rg = st.ranges[g];
-  const uint32_t last = st.hdr->overflow ? 0u : st.last[q];
+  const uint2 rg = ranges[g];
+  const uint32_t last = st.hdr->overflow ? 0u : min(st.last[q], rg.y - rg.x);
   const float fx = (float)px + 0.5f, fy = (float)py + 0.5f;
   int cnt = 0;
   for (uint32_t i = 0; i < last; ++i) {
-    const float4* r = st.rec + 3 * (size_t)st.inst[rg.x + i];
+    const float4* r = st.rec + 3 * (size_t)inst[rg.x + i];
     const float4 a = r[0], b = r[1];
     float dx, dy;
     const float p = splat_power(a, b, fx, fy, dx, dy);
@@ -734,11 +934,12 @@ __global__ __launch_bounds__(512) void k_count_blend(int ntiles, int W, int H, i
 }
 
 hipError_t launch_count_blend(int nv, int W, int H, int TW, int TH, int TX, int TY, StateDev st,
-                              int32_t* n_blend, hipStream_t s) {
+                              const uint2* ranges, const uint32_t* inst, int32_t* n_blend,
+                              hipStream_t s) {
   const int ntiles = nv * TX * TY;
   if (ntiles > 0)
     hipLaunchKernelGGL(k_count_blend, dim3(ntiles), dim3(TW * TH), 0, s, ntiles, W, H, TW, TX, TY,
-                       st, n_blend);
+                       st, ranges, inst, n_blend);
   return hipGetLastError();
 }
 

@@ -106,7 +106,9 @@ class Rasterizer:
             raise L.GsrError(st, "gsr_create failed (no gfx950 device?)")
         self.ctx = h
         if max_instances is None:
-            max_instances = max(1 << 20, 24 * int(max_pairs))
+            # (pair, tile row) entries: a few per visible pair; fit_capacity
+            # and gsr_poll's overflow report give the measured need
+            max_instances = min(0xFFFFFFFE, max(1 << 20, 8 * int(max_pairs)))
         self.desc = L.PlanDesc(int(max_pairs), int(max_instances), int(max_views), int(width),
                                int(height), int(tile[0]), int(tile[1]), int(chunk),
                                int(fwd_batch), int(bwd_batch), int(bool(persistent)), 0)
@@ -221,16 +223,18 @@ class Rasterizer:
         st = self.lib.gsr_poll(self.ctx, C.c_void_p(state.data_ptr()), C.byref(c), _stream(stream))
         if st not in (L.GSR_OK, L.GSR_E_OVERFLOW) or (st == L.GSR_E_OVERFLOW and raise_on_overflow):
             self._check(st)
-        return dict(visible_pairs=c.visible_pairs, instances=c.instances, capacity=c.capacity,
-                    overflow=bool(c.overflow))
+        return dict(visible_pairs=c.visible_pairs, instances=c.instances,
+                    row_entries=c.row_entries, capacity=c.capacity, overflow=bool(c.overflow))
 
     def fit_capacity(self, scene: SceneTensors, views: ViewTensors, z_near=0.2, margin=1.25):
-        """Run one forward, and re-plan with more instance capacity if it
-        overflowed (synchronises; for set-up, not for captured steps)."""
+        """Run one forward, and re-plan the binning's entry capacity to the
+        measured need times `margin` if it overflowed or is more than four
+        times too large (synchronises; for set-up, not for captured steps)."""
         _, _, _, state = self.forward(scene, views, z_near=z_near)
         c = self.poll(state, raise_on_overflow=False)
-        if c["overflow"] or c["instances"] * margin > self.desc.max_instances * 4:
-            self.replan(max_instances=min(0xFFFFFFFE, max(1 << 20, int(c["instances"] * margin))))
+        if c["overflow"] or c["row_entries"] * margin * 4 < self.desc.max_instances:
+            self.replan(max_instances=min(0xFFFFFFFE,
+                                          max(1 << 20, int(c["row_entries"] * margin))))
         return c
 
     def profile(self, enable: bool = True):
@@ -274,15 +278,15 @@ def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = No
              max_instances: int | None = None, z_near=0.2, device: int | None = None,
              stream=None):
     """Native coordinate search (gsr_autotune) over the tile shape, binning
-    chunk, forward entries per thread, backward entries per lane and the
+    chunk, forward and backward entries per lane and the
     persistent tile queue for this call.  Returns a dict: tile (tile_w,
     tile_h), ms (its forward+backward time), chunk, fwd_batch, bwd_batch,
     persistent — the keyword arguments of Rasterizer besides the sizes."""
     lib = L.load()
     dev = torch.cuda.current_device() if device is None else int(device)
     P = pairs_of(scene, views) if max_pairs is None else int(max_pairs)
-    base = L.PlanDesc(P, int(max_instances or max(1 << 20, 24 * P)), views.n, views.width,
-                      views.height, 16, 16, 0, 1, 2, 0, 0)
+    base = L.PlanDesc(P, int(max_instances or min(0xFFFFFFFE, max(1 << 20, 8 * P))), views.n,
+                      views.width, views.height, 16, 16, 0, 1, 2, 0, 0)
     sc, keep1 = Rasterizer._scene(scene)
     vw, keep2 = Rasterizer._views(views)
     st = Rasterizer._settings(z_near)

@@ -139,7 +139,8 @@ def test_edge_cases_empty_and_ragged():
 
 
 def test_overflow_reported():
-    """A plan too small for the instances reports GSR_E_OVERFLOW via poll."""
+    """A plan too small for the binning's (pair, tile row) entries reports
+    GSR_E_OVERFLOW via poll; fit_capacity re-plans to the measured need."""
     announce("overflow")
     from paper_2605_10760_amd import Rasterizer
     scene, views = _scene_case("small-plain")
@@ -147,7 +148,7 @@ def test_overflow_reported():
     r = Rasterizer(views.width, views.height, scene.n, 1, max_instances=100)
     c, d, a, state = r.forward(st_, vt)
     cnt = r.poll(state, raise_on_overflow=False)
-    assert cnt["overflow"] and cnt["instances"] > 100
+    assert cnt["overflow"] and cnt["row_entries"] > 100 and cnt["instances"] >= cnt["row_entries"]
     from paper_2605_10760_amd import GsrError
     with pytest.raises(GsrError):
         r.poll(state)
