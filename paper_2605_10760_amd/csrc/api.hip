@@ -26,6 +26,7 @@ struct gsr_ctx {
   uint32_t* blk_scan = nullptr;  // their exclusive prefix
   uint32_t *ka = nullptr, *va = nullptr, *kb = nullptr, *vb = nullptr;
   uint32_t* hist = nullptr;
+  uint32_t* hoff = nullptr;
   BinWork bw{};
   float* grad2d = nullptr;
   unsigned int* sched = nullptr;  // tile cursors of the persistent compositing
@@ -402,6 +403,7 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   const size_t o_kb = o; o = align256(o + P * 4);
   const size_t o_vb = o; o = align256(o + P * 4);
   const size_t o_hist = o; o = align256(o + c->max_sblocks * RADIX * 4);
+  const size_t o_hoff = o; o = align256(o + c->max_sblocks * RADIX * 4);
   const size_t o_cnt = o; o = align256(o + c->max_chunks * (size_t)c->TY * 4);
   const size_t o_rt = o; o = align256(o + V * (size_t)c->TY * 4);
   const size_t o_ap = o; o = align256(o + (c->max_chunks / RC_SUB + 1) * 4);
@@ -423,6 +425,7 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   c->kb = (uint32_t*)(b + o_kb);
   c->vb = (uint32_t*)(b + o_vb);
   c->hist = (uint32_t*)(b + o_hist);
+  c->hoff = (uint32_t*)(b + o_hoff);
   c->bw.counts = (uint32_t*)(b + o_cnt);
   c->bw.row_tot = (uint32_t*)(b + o_rt);
   c->bw.area_part = (uint32_t*)(b + o_ap);
@@ -477,7 +480,7 @@ gsr_status gsr_forward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   }
   {
     StageMark m(c, GSR_STAGE_DEPTH_SORT, st);
-    if ((e = launch_depth_sort(t.stb, sd, c->ka, c->va, c->kb, c->vb, c->hist, st)) != hipSuccess)
+    if ((e = launch_depth_sort(t.stb, sd, c->ka, c->va, c->kb, c->vb, c->hist, c->hoff, st)) != hipSuccess)
       return hip_fail(c, e, "depth sort");
   }
   {

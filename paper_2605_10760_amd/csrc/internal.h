@@ -147,7 +147,8 @@ hipError_t launch_project_records(const ProjTab& t, const SceneDev& sc, const Ca
 hipError_t launch_compact(const ProjTab& t, StateDev st, const uint32_t* blk_cnt,
                           uint32_t* blk_scan, uint32_t* kout, uint32_t* vout, hipStream_t s);
 hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
-                             uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s);
+                             uint32_t* kb, uint32_t* vb, uint32_t* hist, uint32_t* off,
+                             hipStream_t s);
 hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStream_t s);
 // Compositing launch options (from the plan): list entries staged per lane
 // in the forward (1 or 2) and in the backward (1, 2 or 4), and the persistent

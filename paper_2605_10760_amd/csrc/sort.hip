@@ -8,11 +8,13 @@
 // binning kernels.  Each view's visible pairs form a contiguous segment, so
 // sorting segments independently equals sorting by (view, depth).
 //
-// A pass is three kernels: per-block digit histograms (LDS atomics), one
-// workgroup per view turning the [block][digit] counts into scatter bases
-// in (digit, block) order, and a scatter where each 256-key round is ranked
-// stably inside the block by wave64 ballots over the digit bits, the block
-// is reordered by digit in LDS and written out in runs.
+// A pass is three kernels: per-block digit histograms (LDS atomics, one per
+// wave when the wave's keys share a digit, as the high depth digits mostly
+// do), one workgroup per view turning the [block][digit] counts into
+// scatter bases in (digit, block) order (a separate array: the scatter also
+// reads its block's counts), and a scatter where each 256-key round is
+// ranked stably inside the block by wave64 ballots over the digit bits, the
+// block is reordered by digit in LDS and written out in runs.
 #include "common.h"
 
 namespace gsr {
@@ -37,50 +39,88 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(SortTab t, const St
   sort_block_range(t, hdr, b, v, lo, hi);
   cnt[threadIdx.x] = 0;
   __syncthreads();
+  uint32_t d[SORT_ITEMS];
 #pragma unroll
   for (int r = 0; r < SORT_ITEMS; ++r) {
     const int i = lo + r * SORT_THREADS + (int)threadIdx.x;
-    if (i < hi) atomicAdd(&cnt[(keys[i] >> SH) & (RADIX - 1)], 1u);
+    d[r] = i < hi ? (keys[i] >> SH) & (RADIX - 1) : RADIX;
+  }
+#pragma unroll
+  for (int r = 0; r < SORT_ITEMS; ++r) {
+    const bool valid = d[r] < (uint32_t)RADIX;
+    const unsigned long long act = __ballot(valid);
+    if (act == 0ull) continue;  // uniform
+    // the first valid lane's digit; a wave whose keys all share it adds them
+    // with one atomic
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d[r], (int)__builtin_ctzll(act));
+    if (__ballot(valid && d[r] == d0) == act) {
+      if (lane_id() == (int)__builtin_ctzll(act)) atomicAdd(&cnt[d0], (uint32_t)__popcll(act));
+    } else if (valid) {
+      atomicAdd(&cnt[d[r]], 1u);
+    }
   }
   __syncthreads();
   hist[(size_t)b * RADIX + threadIdx.x] = cnt[threadIdx.x];
 }
 
-// One workgroup per view; thread d owns digit d.
-__global__ __launch_bounds__(RADIX) void k_radix_scan(SortTab t, const StateHeader* hdr,
-                                                      uint32_t* hist) {
-  __shared__ unsigned long long sh[RADIX / 64 + 1];
+// One workgroup per view; thread (q, d) owns digit d over the q-th quarter
+// of the view's blocks (the walk down the blocks is 4x shorter).  Writes the
+// scatter base of every (block, digit) into off; the counts stay in hist.
+constexpr int SCAN_Q = 4;
+__global__ __launch_bounds__(RADIX* SCAN_Q) void k_radix_scan(SortTab t, const StateHeader* hdr,
+                                                             const uint32_t* hist,
+                                                             uint32_t* off) {
+  __shared__ unsigned long long sh[RADIX * SCAN_Q / 64 + 1];
+  __shared__ uint32_t part[SCAN_Q][RADIX];
+  __shared__ uint32_t dex[RADIX];
   const int v = blockIdx.x;
+  const int d = (int)threadIdx.x & (RADIX - 1), q = (int)threadIdx.x / RADIX;
   const int n = (int)(hdr->vis_off[v + 1] - hdr->vis_off[v]);
   const int nb = (n + SORT_TILE - 1) / SORT_TILE;
-  uint32_t* h = hist + (size_t)t.sblk_off[v] * RADIX + threadIdx.x;
+  const int b0 = nb * q / SCAN_Q, b1 = nb * (q + 1) / SCAN_Q;
+  const size_t base = (size_t)t.sblk_off[v] * RADIX + d;
+  const uint32_t* h = hist + base;
+  uint32_t* o = off + base;
   uint32_t tot = 0;
-  int b = 0;
-  for (; b + 8 <= nb; b += 8) {
+  int b = b0;
+  for (; b + 8 <= b1; b += 8) {
     uint32_t x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = h[(size_t)(b + k) * RADIX];
 #pragma unroll
     for (int k = 0; k < 8; ++k) tot += x[k];
   }
-  for (; b < nb; ++b) tot += h[(size_t)b * RADIX];
+  for (; b < b1; ++b) tot += h[(size_t)b * RADIX];
+  part[q][d] = tot;
+  __syncthreads();
+  uint32_t dtot = 0, before = 0;
+#pragma unroll
+  for (int k = 0; k < SCAN_Q; ++k) {
+    const uint32_t x = part[k][d];
+    dtot += x;
+    before += k < q ? x : 0u;
+  }
+  // exclusive scan of the digit totals over the digits: the q = 0 threads
+  // (the first RADIX of the workgroup) carry them, the others add zero
   unsigned long long all;
-  uint32_t run = hdr->vis_off[v] + (uint32_t)wg_excl_scan<RADIX>(tot, sh, &all);
-  b = 0;
-  for (; b + 8 <= nb; b += 8) {
+  const uint32_t ex = (uint32_t)wg_excl_scan<RADIX * SCAN_Q>(q == 0 ? dtot : 0u, sh, &all);
+  if (q == 0) dex[d] = ex;
+  __syncthreads();
+  uint32_t run = hdr->vis_off[v] + dex[d] + before;
+  b = b0;
+  for (; b + 8 <= b1; b += 8) {
     uint32_t x[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) x[k] = h[(size_t)(b + k) * RADIX];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      h[(size_t)(b + k) * RADIX] = run;
+      o[(size_t)(b + k) * RADIX] = run;
       run += x[k];
     }
   }
-  for (; b < nb; ++b) {
-    const uint32_t x = h[(size_t)b * RADIX];
-    h[(size_t)b * RADIX] = run;
-    run += x;
+  for (; b < b1; ++b) {
+    o[(size_t)b * RADIX] = run;
+    run += h[(size_t)b * RADIX];
   }
 }
 
@@ -94,8 +134,8 @@ __global__ __launch_bounds__(RADIX) void k_radix_scan(SortTab t, const StateHead
 // per key.
 template <int SH, bool KEYS_OUT>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
-    SortTab t, const StateHeader* hdr, const uint32_t* hist, const uint32_t* kin,
-    const uint32_t* vin, uint32_t* kout, uint32_t* vout) {
+    SortTab t, const StateHeader* hdr, const uint32_t* hist, const uint32_t* off,
+    const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout) {
   constexpr int NW = SORT_THREADS / 64;
   __shared__ uint32_t whist[NW][RADIX];
   __shared__ uint32_t cnt[RADIX];    // keys of each digit placed so far
@@ -110,27 +150,22 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
   if (lo >= hi) return;
   const int tid = threadIdx.x, w = tid >> 6, lane = lane_id();
   const int n = hi - lo;
-  // the block's digit counts, from the keys themselves (the histogram pass
-  // holds the global bases)
-  cnt[tid] = 0;
+  // the block's digit counts (from the histogram pass) and global bases
 #pragma unroll
   for (int i = 0; i < NW; ++i) whist[i][tid] = 0;
-  __syncthreads();
   uint32_t key[SORT_ITEMS], val[SORT_ITEMS];
 #pragma unroll
   for (int r = 0; r < SORT_ITEMS; ++r) {
     const int i = r * SORT_THREADS + tid;
     key[r] = i < n ? kin[lo + i] : 0u;
     val[r] = i < n ? vin[lo + i] : 0u;
-    if (i < n) atomicAdd(&cnt[(key[r] >> SH) & (RADIX - 1)], 1u);
   }
-  __syncthreads();
   {
     unsigned long long tot;
-    const uint32_t c = cnt[tid];
+    const uint32_t c = hist[(size_t)b * RADIX + tid];
     const uint32_t o = (uint32_t)wg_excl_scan<SORT_THREADS>(c, sh, &tot);
     loff[tid] = o;
-    goff[tid] = hist[(size_t)b * RADIX + tid];
+    goff[tid] = off[(size_t)b * RADIX + tid];
     cnt[tid] = 0;
   }
   __syncthreads();
@@ -181,26 +216,30 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
 }
 
 hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
-                             uint32_t* kb, uint32_t* vb, uint32_t* hist, hipStream_t s) {
+                             uint32_t* kb, uint32_t* vb, uint32_t* hist, uint32_t* off,
+                             hipStream_t s) {
   const int nb = t.sblk_off[t.nv];
   if (nb == 0) return hipSuccess;
-  const dim3 g(xcd_grid(nb)), blk(SORT_THREADS);
+  const dim3 g(xcd_grid(nb)), blk(SORT_THREADS), sg(t.nv), sb(RADIX * SCAN_Q);
   // pass 0: A -> B
   hipLaunchKernelGGL(k_radix_hist<0>, g, blk, 0, s, t, st.hdr, ka, hist);
-  hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
-  hipLaunchKernelGGL((k_radix_scatter<0, true>), g, blk, 0, s, t, st.hdr, hist, ka, va, kb, vb);
+  hipLaunchKernelGGL(k_radix_scan, sg, sb, 0, s, t, st.hdr, hist, off);
+  hipLaunchKernelGGL((k_radix_scatter<0, true>), g, blk, 0, s, t, st.hdr, hist, off, ka, va, kb,
+                     vb);
   // pass 1: B -> A
   hipLaunchKernelGGL(k_radix_hist<8>, g, blk, 0, s, t, st.hdr, kb, hist);
-  hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
-  hipLaunchKernelGGL((k_radix_scatter<8, true>), g, blk, 0, s, t, st.hdr, hist, kb, vb, ka, va);
+  hipLaunchKernelGGL(k_radix_scan, sg, sb, 0, s, t, st.hdr, hist, off);
+  hipLaunchKernelGGL((k_radix_scatter<8, true>), g, blk, 0, s, t, st.hdr, hist, off, kb, vb, ka,
+                     va);
   // pass 2: A -> B
   hipLaunchKernelGGL(k_radix_hist<16>, g, blk, 0, s, t, st.hdr, ka, hist);
-  hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
-  hipLaunchKernelGGL((k_radix_scatter<16, true>), g, blk, 0, s, t, st.hdr, hist, ka, va, kb, vb);
+  hipLaunchKernelGGL(k_radix_scan, sg, sb, 0, s, t, st.hdr, hist, off);
+  hipLaunchKernelGGL((k_radix_scatter<16, true>), g, blk, 0, s, t, st.hdr, hist, off, ka, va, kb,
+                     vb);
   // pass 3: B -> state order (values only)
   hipLaunchKernelGGL(k_radix_hist<24>, g, blk, 0, s, t, st.hdr, kb, hist);
-  hipLaunchKernelGGL(k_radix_scan, dim3(t.nv), dim3(RADIX), 0, s, t, st.hdr, hist);
-  hipLaunchKernelGGL((k_radix_scatter<24, false>), g, blk, 0, s, t, st.hdr, hist, kb, vb,
+  hipLaunchKernelGGL(k_radix_scan, sg, sb, 0, s, t, st.hdr, hist, off);
+  hipLaunchKernelGGL((k_radix_scatter<24, false>), g, blk, 0, s, t, st.hdr, hist, off, kb, vb,
                      (uint32_t*)nullptr, st.order);
   return hipGetLastError();
 }
