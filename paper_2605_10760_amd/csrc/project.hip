@@ -1,15 +1,17 @@
 // Projection of (view, Gaussian) pairs, visible-pair compaction and the
 // pose-delta update.
 //
-// One thread per Gaussian, looping over the views of its set.  Each pair
-// evaluates the key path in FP32 with no fused multiply-add and a fixed
+// Key pass: one thread per Gaussian, looping over the views of its set; each
+// pair evaluates the key path in FP32 with no fused multiply-add and a fixed
 // operation order (it decides culling, the tile rectangle and the depth key
-// and must match an FP32 re-evaluation bit for bit), then, for visible
-// pairs, the screen-space record in FP64 rounded once to FP32 (the 2D conic
-// of an elongated splat loses digits to cancellation in FP32).  The
-// parameters are read once per Gaussian (coalesced AoS rows); writes are one
-// 48-byte record, one 8-byte rect and one 4-byte key per pair, and one
-// visible count per 256-pair block for the ordered compaction that follows.
+// and must match an FP32 re-evaluation bit for bit) and writes a 4-byte key,
+// with one visible count per 256-pair block for the ordered compaction that
+// follows.  Record pass: for visible pairs, the rect again and the
+// screen-space record in FP64 rounded once to FP32 (the 2D conic of an
+// elongated splat loses digits to cancellation in FP32), one pair per lane
+// from a per-wave queue of the wave's visible pairs.  The parameters are
+// read once per Gaussian in each pass (coalesced AoS rows); the record pass
+// writes one 48-byte record and one 8-byte rect per visible pair.
 #include <algorithm>
 
 #include "common.h"
@@ -166,23 +168,15 @@ __device__ __forceinline__ bool key_view(const float* m, const KeyGauss& g, cons
   return true;
 }
 
-// One thread per Gaussian of a rendered set; it projects its Gaussian into
-// every view of the set in turn (views are uniform across the workgroup,
-// whose Gaussians all belong to one set).  The parameters are read once and
-// the view-independent work (3D covariance, opacity threshold, colour for
-// degree 0) is done once, instead of once per view.  Pair p of view v is
-// Gaussian p - pair_off[v] of the set, so the workgroup's 256 Gaussians are
-// the 256-pair block (blk_off[v] + its block index in the set) of each view.
-//
-// Two passes.  Keys (RECORD = false): the FP32 key path of every pair, its
-// depth key (or CULLED) and the visible count of every 256-pair block, for
-// the ordered compaction that follows.  Records (RECORD = true, after the
-// compaction): for every visible pair, the tile rect (the key path again,
-// same code and inputs, so the same rect) and the FP64 screen-space record,
-// written at the pair's position in the compacted visible list, so that a
-// view's records are consecutive lines (written in full, read densely by
-// the binning and compositing).
-template <int SHD, bool RECORD>
+// Key pass: one thread per Gaussian of a rendered set; it projects its
+// Gaussian into every view of the set in turn (views are uniform across the
+// workgroup, whose Gaussians all belong to one set).  The parameters are read
+// once and the view-independent part of the key path (3D covariance,
+// opacity threshold) is done once, instead of once per view.  Pair p of view
+// v is Gaussian p - pair_off[v] of the set, so the workgroup's 256 Gaussians
+// are the 256-pair block (blk_off[v] + its block index in the set) of each
+// view.  Writes the depth key (or CULLED) of every pair and the visible
+// count of every 256-pair block, for the ordered compaction that follows.
 __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, CamDev cam,
                                                         StateDev st, uint32_t* blk_cnt) {
   const int b = xcd_remap(blockIdx.x, t.set_gblk[t.ns]);
@@ -203,26 +197,6 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
   }
   KeyGauss kg = key_gauss(ls, q, o);
   kg.ok = kg.ok && valid;
-  // ---- view-independent part of the FP64 record.  Scales, rotation and
-  // opacity are formed in FP32 first: their rounding perturbs the parameters
-  // by ~1e-7 relative, while the products below, where elongated splats
-  // cancel, run in FP64.
-  double Sd[3][3];
-  float sigf = 0.f, k2f = 0.f;
-  float col[3] = {0.f, 0.f, 0.f};
-  if (RECORD) {
-    cov3_fp64(ls, q, Sd);
-    sigf = 1.f / (1.f + expf(-o));
-    // half-extents of the alpha >= 1/255 ellipse use k2f, widened by a
-    // margin far above FP32 rounding: every pixel outside that box has
-    // alpha < 1/255, so the compositing kernels may skip the splat there
-    // without changing any result
-    const float t255 = 255.f * sigf;
-    k2f = t255 > 1.f ? 2.f * logf(t255) : 0.f;
-    if (SHD == 0 && valid) {
-      col[0] = sc.colors[3 * gi]; col[1] = sc.colors[3 * gi + 1]; col[2] = sc.colors[3 * gi + 2];
-    }
-  }
   for (int vi = t.set_voff[s]; vi < t.set_voff[s + 1]; ++vi) {
     const int v = t.vset[vi];
     const int pair = t.pair_off[v] + local;
@@ -230,63 +204,183 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_project(ProjTab t, SceneDev sc, 
     const float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
     const float tc[3] = {vm[3], vm[7], vm[11]};
     const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
-    if (!RECORD) {
-      KeyResult kr;
-      const bool vis = key_view(m, kg, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH,
-                                t.TX, t.TY, cam.z_near, kr);
-      if (valid) st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
-      const int cnt = __syncthreads_count(vis);
-      if (threadIdx.x == 0) blk_cnt[t.blk_off[v] + lb] = (uint32_t)cnt;
-      continue;
-    }
-    const uint32_t row = valid ? st.vidx[pair] : CULLED;
-    if (row != CULLED) {
-      KeyResult kr;
-      // visible in the key pass, so visible here (the same pure function of
-      // the same inputs); an empty rect would only drop the pair
-      if (!key_view(m, kg, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX, t.TY,
-                    cam.z_near, kr))
-        kr.x0 = kr.x1 = kr.y0 = kr.y1 = 0u;
-      st.rect[row] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
-      ScreenCov sc2 = screen_cov_fp64(Sd, Rc, tc, m, in.x, in.y, t.W, t.H);
-      const double fx = in.x, fy = in.y;
-      const double* p = sc2.p;
-      const double rx = sc2.rx, ry = sc2.ry;
-      const double a = sc2.a, bb = sc2.b, c = sc2.c;
-      const double det = a * c - bb * bb;
-      const double u = fx * rx + (double)in.z, vv = fy * ry + (double)in.w;
-      float cv[3] = {col[0], col[1], col[2]};
-      if (SHD > 0) {
-        // camera centre o_cam = -Rc^T tc; direction d = (mu - o_cam)/|mu - o_cam|
-        const float ox = -(Rc[0] * tc[0] + Rc[3] * tc[1] + Rc[6] * tc[2]);
-        const float oy = -(Rc[1] * tc[0] + Rc[4] * tc[1] + Rc[7] * tc[2]);
-        const float oz = -(Rc[2] * tc[0] + Rc[5] * tc[1] + Rc[8] * tc[2]);
-        float dx = m[0] - ox, dy = m[1] - oy, dz = m[2] - oz;
-        const float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
-        dx *= inv; dy *= inv; dz *= inv;
-        constexpr int NB = (SHD + 1) * (SHD + 1);
-        float Y[16];
-        sh_eval<SHD>(dx, dy, dz, Y);
-        const float* k = sc.colors + (long)3 * sc.sh_stride * gi;
-        float r = 0.5f, g = 0.5f, bl = 0.5f;
+    KeyResult kr;
+    const bool vis = key_view(m, kg, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX,
+                              t.TY, cam.z_near, kr);
+    if (valid) st.zkey[pair] = vis ? __float_as_uint(kr.p2) : CULLED;
+    const int cnt = __syncthreads_count(vis);
+    if (threadIdx.x == 0) blk_cnt[t.blk_off[v] + lb] = (uint32_t)cnt;
+  }
+}
+
+// Record pass (after the compaction): for every visible pair, the tile rect
+// (the key path again, same code and inputs, so the same rect) and the FP64
+// screen-space record, written at the pair's position in the compacted
+// visible list, so that a view's records are consecutive lines (written in
+// full, read densely by the binning and compositing).
+//
+// One wave per 64 Gaussians of a set.  Each lane loads its Gaussian once and
+// puts the view-independent quantities (mean, FP32 key covariance and
+// threshold, FP64 covariance, opacity, threshold of the record extents,
+// degree-0 colour) in the wave's LDS slot.  The wave then walks the set's
+// views, appending its visible pairs (lane, view) to a queue in LDS, and
+// computes records 64 at a time from the queue, one pair per lane, so that
+// no lane idles on a culled pair.
+constexpr int RQ = 128;  // queue slots per wave (at most 63 + 64 held)
+struct RecSlot {
+  float m[3][64];
+  float S[6][64];      // FP32 key-path covariance
+  float k2[64];        // key-path 2 ln(255 sigma), negative: not renderable
+  double Sd[6][64];    // FP64 covariance (00, 01, 02, 11, 12, 22)
+  float sig[64], k2f[64];
+  float col[3][64];
+  uint32_t item[RQ], row[RQ];
+};
+
+template <int SHD>
+__device__ __forceinline__ void record_one(const ProjTab& t, const SceneDev& sc,
+                                           const CamDev& cam, const StateDev& st,
+                                           const RecSlot& L, long g0, uint32_t item,
+                                           uint32_t row) {
+  const int l = (int)(item & 63u), v = (int)(item >> 6);
+  const float m[3] = {L.m[0][l], L.m[1][l], L.m[2][l]};
+  KeyGauss kg;
+  kg.S00 = L.S[0][l]; kg.S01 = L.S[1][l]; kg.S02 = L.S[2][l];
+  kg.S11 = L.S[3][l]; kg.S12 = L.S[4][l]; kg.S22 = L.S[5][l];
+  kg.k2 = L.k2[l];
+  kg.ok = true;  // visible in the key pass
+  const float* vm = cam.viewmats + 12 * v;
+  const float Rc[9] = {vm[0], vm[1], vm[2], vm[4], vm[5], vm[6], vm[8], vm[9], vm[10]};
+  const float tc[3] = {vm[3], vm[7], vm[11]};
+  const float4 in = *reinterpret_cast<const float4*>(cam.intrinsics + 4 * v);
+  KeyResult kr;
+  // visible in the key pass, so visible here (the same pure function of the
+  // same inputs); an empty rect would only drop the pair
+  if (!key_view(m, kg, Rc, tc, in.x, in.y, in.z, in.w, t.W, t.H, t.TW, t.TH, t.TX, t.TY,
+                cam.z_near, kr))
+    kr.x0 = kr.x1 = kr.y0 = kr.y1 = 0u;
+  st.rect[row] = make_uint2(kr.x0 | (kr.y0 << 16), kr.x1 | (kr.y1 << 16));
+  double Sd[3][3];
+  Sd[0][0] = L.Sd[0][l]; Sd[0][1] = Sd[1][0] = L.Sd[1][l]; Sd[0][2] = Sd[2][0] = L.Sd[2][l];
+  Sd[1][1] = L.Sd[3][l]; Sd[1][2] = Sd[2][1] = L.Sd[4][l]; Sd[2][2] = L.Sd[5][l];
+  ScreenCov sc2 = screen_cov_fp64(Sd, Rc, tc, m, in.x, in.y, t.W, t.H);
+  const double fx = in.x, fy = in.y;
+  const double* p = sc2.p;
+  const double rx = sc2.rx, ry = sc2.ry;
+  const double a = sc2.a, bb = sc2.b, c = sc2.c;
+  const double det = a * c - bb * bb;
+  const double u = fx * rx + (double)in.z, vv = fy * ry + (double)in.w;
+  float cv[3] = {L.col[0][l], L.col[1][l], L.col[2][l]};
+  if (SHD > 0) {
+    // camera centre o_cam = -Rc^T tc; direction d = (mu - o_cam)/|mu - o_cam|
+    const float ox = -(Rc[0] * tc[0] + Rc[3] * tc[1] + Rc[6] * tc[2]);
+    const float oy = -(Rc[1] * tc[0] + Rc[4] * tc[1] + Rc[7] * tc[2]);
+    const float oz = -(Rc[2] * tc[0] + Rc[5] * tc[1] + Rc[8] * tc[2]);
+    float dx = m[0] - ox, dy = m[1] - oy, dz = m[2] - oz;
+    const float inv = 1.f / sqrtf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    constexpr int NB = (SHD + 1) * (SHD + 1);
+    float Y[16];
+    sh_eval<SHD>(dx, dy, dz, Y);
+    const float* k = sc.colors + (long)3 * sc.sh_stride * (g0 + l);
+    float r = 0.5f, g = 0.5f, bl = 0.5f;
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-          r += Y[i] * k[3 * i]; g += Y[i] * k[3 * i + 1]; bl += Y[i] * k[3 * i + 2];
-        }
-        cv[0] = fmaxf(r, 0.f); cv[1] = fmaxf(g, 0.f); cv[2] = fmaxf(bl, 0.f);
-      }
-      const float exr = sqrtf(k2f * (float)a) * (1.f + 1e-4f) + 1e-2f;
-      const float eyr = sqrtf(k2f * (float)c) * (1.f + 1e-4f) + 1e-2f;
-      float4* rp = st.rec + 3 * (long)row;
-      // conic (A, B, C) = (c, -b, a)/det, stored pre-scaled so that the
-      // exponent in base 2 is A' dx^2 + B' dx dy + C' dy^2:
-      // A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2
-      const double L2E = 1.4426950408889634;
-      const double h = L2E / det;
-      rp[0] = make_float4((float)u, (float)vv, (float)(-0.5 * h * c), (float)(h * bb));
-      rp[1] = make_float4((float)(-0.5 * h * a), sigf, (float)p[2], exr);
-      rp[2] = make_float4(cv[0], cv[1], cv[2], eyr);
+    for (int i = 0; i < NB; ++i) {
+      r += Y[i] * k[3 * i]; g += Y[i] * k[3 * i + 1]; bl += Y[i] * k[3 * i + 2];
     }
+    cv[0] = fmaxf(r, 0.f); cv[1] = fmaxf(g, 0.f); cv[2] = fmaxf(bl, 0.f);
+  }
+  const float k2f = L.k2f[l];
+  const float exr = sqrtf(k2f * (float)a) * (1.f + 1e-4f) + 1e-2f;
+  const float eyr = sqrtf(k2f * (float)c) * (1.f + 1e-4f) + 1e-2f;
+  float4* rp = st.rec + 3 * (long)row;
+  // conic (A, B, C) = (c, -b, a)/det, stored pre-scaled so that the exponent
+  // in base 2 is A' dx^2 + B' dx dy + C' dy^2:
+  // A' = -A log2(e)/2, B' = -B log2(e), C' = -C log2(e)/2
+  const double L2E = 1.4426950408889634;
+  const double h = L2E / det;
+  rp[0] = make_float4((float)u, (float)vv, (float)(-0.5 * h * c), (float)(h * bb));
+  rp[1] = make_float4((float)(-0.5 * h * a), L.sig[l], (float)p[2], exr);
+  rp[2] = make_float4(cv[0], cv[1], cv[2], eyr);
+}
+
+template <int SHD>
+__global__ __launch_bounds__(PROJ_BLOCK) void k_records(ProjTab t, SceneDev sc, CamDev cam,
+                                                        StateDev st) {
+  __shared__ RecSlot slots[PROJ_BLOCK / 64];
+  const int b = xcd_remap(blockIdx.x, t.set_gblk[t.ns]);
+  if (b < 0) return;
+  const int s = find_seg(t.set_gblk, t.ns, b);
+  const int lb = b - t.set_gblk[s];
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  RecSlot& L = slots[wv];
+  const int local = lb * PROJ_BLOCK + (int)threadIdx.x;
+  const bool valid = local < t.set_goff[s + 1] - t.set_goff[s];
+  const long gi = (long)t.set_goff[s] + (valid ? local : 0);
+  const long g0 = (long)t.set_goff[s] + lb * PROJ_BLOCK + 64 * wv;  // the wave's lane-0 Gaussian
+  {
+    float m[3] = {0.f, 0.f, 0.f}, ls[3] = {0.f, 0.f, 0.f}, q[4] = {1.f, 0.f, 0.f, 0.f}, o = 0.f;
+    if (valid) {
+      m[0] = sc.means[3 * gi]; m[1] = sc.means[3 * gi + 1]; m[2] = sc.means[3 * gi + 2];
+      ls[0] = sc.log_scales[3 * gi]; ls[1] = sc.log_scales[3 * gi + 1];
+      ls[2] = sc.log_scales[3 * gi + 2];
+      const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
+      q[0] = q4.x; q[1] = q4.y; q[2] = q4.z; q[3] = q4.w;
+      o = sc.opac[gi];
+    }
+    const KeyGauss kg = key_gauss(ls, q, o);
+    // ---- view-independent part of the FP64 record.  Scales, rotation and
+    // opacity are formed in FP32 first: their rounding perturbs the
+    // parameters by ~1e-7 relative, while the products, where elongated
+    // splats cancel, run in FP64.
+    double Sd[3][3];
+    cov3_fp64(ls, q, Sd);
+    const float sigf = 1.f / (1.f + expf(-o));
+    // half-extents of the alpha >= 1/255 ellipse use k2f, widened by a
+    // margin far above FP32 rounding: every pixel outside that box has
+    // alpha < 1/255, so the compositing kernels may skip the splat there
+    // without changing any result
+    const float t255 = 255.f * sigf;
+    L.m[0][lane] = m[0]; L.m[1][lane] = m[1]; L.m[2][lane] = m[2];
+    L.S[0][lane] = kg.S00; L.S[1][lane] = kg.S01; L.S[2][lane] = kg.S02;
+    L.S[3][lane] = kg.S11; L.S[4][lane] = kg.S12; L.S[5][lane] = kg.S22;
+    L.k2[lane] = kg.k2;
+    L.Sd[0][lane] = Sd[0][0]; L.Sd[1][lane] = Sd[0][1]; L.Sd[2][lane] = Sd[0][2];
+    L.Sd[3][lane] = Sd[1][1]; L.Sd[4][lane] = Sd[1][2]; L.Sd[5][lane] = Sd[2][2];
+    L.sig[lane] = sigf;
+    L.k2f[lane] = t255 > 1.f ? 2.f * logf(t255) : 0.f;
+    float col[3] = {0.f, 0.f, 0.f};
+    if (SHD == 0 && valid) {
+      col[0] = sc.colors[3 * gi]; col[1] = sc.colors[3 * gi + 1]; col[2] = sc.colors[3 * gi + 2];
+    }
+    L.col[0][lane] = col[0]; L.col[1][lane] = col[1]; L.col[2][lane] = col[2];
+  }
+  uint32_t head = 0u, tail = 0u;
+  for (int vi = t.set_voff[s]; vi < t.set_voff[s + 1]; ++vi) {
+    const int v = t.vset[vi];
+    const uint32_t row = valid ? st.vidx[t.pair_off[v] + local] : CULLED;
+    const bool vis = row != CULLED;
+    const unsigned long long mk = __ballot(vis);
+    if (vis) {
+      const uint32_t k = (tail + __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u))) &
+                         (RQ - 1);
+      L.item[k] = (uint32_t)lane | ((uint32_t)v << 6);
+      L.row[k] = row;
+    }
+    tail += (uint32_t)__popcll(mk);
+    __builtin_amdgcn_wave_barrier();
+    if (tail - head >= 64u) {
+      const uint32_t k = (head + (uint32_t)lane) & (RQ - 1);
+      record_one<SHD>(t, sc, cam, st, L, g0, L.item[k], L.row[k]);
+      head += 64u;
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  if ((uint32_t)lane < tail - head) {
+    const uint32_t k = (head + (uint32_t)lane) & (RQ - 1);
+    record_one<SHD>(t, sc, cam, st, L, g0, L.item[k], L.row[k]);
   }
 }
 
@@ -436,9 +530,9 @@ hipError_t launch_project_keys(const ProjTab& t, const SceneDev& sc, const CamDe
                                StateDev st, uint32_t* blk_cnt, hipStream_t s) {
   const int nb = t.set_gblk[t.ns];
   if (nb == 0) return hipSuccess;
-  // the key path does not read colours: one instantiation for every degree
-  hipLaunchKernelGGL((k_project<0, false>), dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc,
-                     cam, st, blk_cnt);
+  // the key path does not read colours: one kernel for every degree
+  hipLaunchKernelGGL(k_project, dim3(xcd_grid(nb)), dim3(PROJ_BLOCK), 0, s, t, sc, cam, st,
+                     blk_cnt);
   return hipGetLastError();
 }
 
@@ -448,10 +542,10 @@ hipError_t launch_project_records(const ProjTab& t, const SceneDev& sc, const Ca
   if (nb == 0) return hipSuccess;
   const dim3 g(xcd_grid(nb)), b(PROJ_BLOCK);
   switch (sc.sh_degree) {
-    case 0: hipLaunchKernelGGL((k_project<0, true>), g, b, 0, s, t, sc, cam, st, nullptr); break;
-    case 1: hipLaunchKernelGGL((k_project<1, true>), g, b, 0, s, t, sc, cam, st, nullptr); break;
-    case 2: hipLaunchKernelGGL((k_project<2, true>), g, b, 0, s, t, sc, cam, st, nullptr); break;
-    default: hipLaunchKernelGGL((k_project<3, true>), g, b, 0, s, t, sc, cam, st, nullptr); break;
+    case 0: hipLaunchKernelGGL(k_records<0>, g, b, 0, s, t, sc, cam, st); break;
+    case 1: hipLaunchKernelGGL(k_records<1>, g, b, 0, s, t, sc, cam, st); break;
+    case 2: hipLaunchKernelGGL(k_records<2>, g, b, 0, s, t, sc, cam, st); break;
+    default: hipLaunchKernelGGL(k_records<3>, g, b, 0, s, t, sc, cam, st); break;
   }
   return hipGetLastError();
 }
