@@ -150,7 +150,7 @@ def make_workload(name):
 def plan_options(tuned):
     """Rasterizer keyword arguments of an autotune result (or defaults)."""
     if tuned is None:
-        return dict(chunk=0, fwd_batch=1, bwd_batch=2, persistent=False)
+        return dict(chunk=0, fwd_batch=1, bwd_batch=1, persistent=False)
     return dict(chunk=tuned["chunk"], fwd_batch=tuned["fwd_batch"],
                 bwd_batch=tuned["bwd_batch"], persistent=tuned["persistent"])
 
@@ -483,7 +483,7 @@ def run_workload(torch, np, wl, args, steps, warmup, tuned=None, tile=(16, 16), 
     if ab_steps:
         # A/B of the compositing options on this workload: eager steps with
         # one option changed from the plan in use (same state buffer)
-        base = dict(fwd_batch=rast.desc.fwd_batch or 1, bwd_batch=rast.desc.bwd_batch or 2,
+        base = dict(fwd_batch=rast.desc.fwd_batch or 1, bwd_batch=rast.desc.bwd_batch or 1,
                     persistent=rast.desc.persistent)
         variants = [("plan", {})]
         variants.append(("persistent" if not base["persistent"] else "grid",

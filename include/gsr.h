@@ -113,7 +113,7 @@ typedef struct gsr_plan_desc {
   int32_t fwd_batch;     /* list entries staged per lane per round in the
                             forward compositing: 1 or 2 (0 = 1) */
   int32_t bwd_batch;     /* list entries staged per lane per round in the
-                            backward compositing: 1, 2 or 4 (0 = 2) */
+                            backward compositing: 1, 2 or 4 (0 = 1) */
   int32_t persistent;    /* 1: compositing kernels run a grid of resident
                             workgroups whose waves take tiles from a queue
                             ordered by decreasing list length; 0: one wave per
@@ -469,8 +469,8 @@ gsr_status gsr_seed_noalloc(const float* depth, const float* color, const float*
 
 /* Time forward+backward of the given call for each candidate plan and
  * report the fastest in `best`, by coordinate search: every tile shape
- * (binning chunk automatic, one entry per lane in the forward, two per lane
- * in the backward, grid launch), then for the fastest plan so far each
+ * (binning chunk automatic, one entry per lane in the forward and in the
+ * backward, grid launch), then for the fastest plan so far each
  * binning chunk of 64, 128 and 256 pairs, the forward's 1 or 2 entries per
  * lane, the backward's 1, 2 or 4 entries per lane, and the grid or
  * persistent tile queue.  `best` holds tile_w, tile_h, chunk, fwd_batch,

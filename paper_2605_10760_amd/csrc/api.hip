@@ -432,7 +432,7 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   c->grad2d = (float*)(b + o_g2);
   c->sched = (unsigned int*)(b + o_sch);
   c->rc.fwd_batch = p->fwd_batch == 2 ? 2 : 1;
-  c->rc.bwd_batch = p->bwd_batch == 0 ? 2 : p->bwd_batch;
+  c->rc.bwd_batch = p->bwd_batch == 0 ? 1 : p->bwd_batch;
   c->rc.persistent = p->persistent == 1;
   // The per-pair screen-space gradient rows start at zero and every
   // backward leaves them at zero (the projection backward clears what it
@@ -1017,7 +1017,7 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
       p.tile_h = tiles[ci][1];
       p.chunk = 0;
       p.fwd_batch = 1;
-      p.bwd_batch = 2;
+      p.bwd_batch = 1;
       p.persistent = 0;
     } else {
       if (result != GSR_OK) break;  // no tile shape ran

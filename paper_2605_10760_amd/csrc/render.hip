@@ -448,7 +448,7 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
                                          unsigned long long grad_mask, const CamDev& cam,
                                          const StateDev& st, const float* gcol, const float* gdep,
                                          const float* galp, float* grad2d, float4* s0, float4* s1,
-                                         float4* s2, uint32_t* sp, uint32_t* ring) {
+                                         float4* s2, uint32_t* sp, uint32_t* ring, float* red) {
   constexpr int PPL = TW * TH / 64;
   constexpr uint32_t RM = RingSize<B>::value - 1;
   const int T = TX * TY;
@@ -535,6 +535,8 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
         mr[r] = m;
       }
     }
+    // the round's wave sums start at zero (entries that reach no pixel keep it)
+    for (uint32_t i = (uint32_t)lane; i < n * GRAD2D; i += 64u) red[i] = 0.f;
     __builtin_amdgcn_wave_barrier();
     // The staged entries are in back-to-front order (entry j of the round
     // is tile entry top - 1 - j); walk those that can reach a block of the
@@ -612,18 +614,36 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
           static_assert(GRAD2D == 10, "ten splat gradients");
           const float tot = wave_sum10(acc, lane);
           const int idx = sum10_index(lane);
-          // d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy), etc.; the
-          // moment sums 0 and 1 sit in lanes 0 and 8
-          const float m0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 0));
-          const float m1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, tot), 8));
+          if (idx >= 0) red[GRAD2D * j + idx] = tot;
+        }
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // The round's wave sums to screen-space gradients, one (entry, value)
+    // per lane, and one atomic each (zero sums, of entries no pixel blended,
+    // are skipped): d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy),
+    // etc., with the moment sums in values 0 and 1; dL/dsigma = (sum of gp) /
+    // sigma, by the hardware reciprocal.
+    for (uint32_t i0 = 0; i0 < n * GRAD2D; i0 += 64u) {
+      const uint32_t i = i0 + (uint32_t)lane;
+      if (i < n * GRAD2D) {
+        const uint32_t j = i / GRAD2D, idx = i - j * GRAD2D;
+        const float tot = red[i];
+        if (tot != 0.f) {
+          const float4 a = s0[j];
           float out = tot;
-          out = idx == 0 ? LN2 * (2.f * a.z * m0 + a.w * m1) : out;
-          out = idx == 1 ? LN2 * (a.w * m0 + 2.f * b.x * m1) : out;
-          out = (idx == 2 || idx == 4) ? -0.5f * tot : out;
-          out = idx == 3 ? -tot : out;
-          // dL/dsigma = (sum of gp) / sigma, by the hardware reciprocal
-          out = idx == 5 ? tot * rcp_fast(b.y) : out;
-          if (idx >= 0 && out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
+          if (idx <= 1u) {
+            const float m0 = red[GRAD2D * j], m1 = red[GRAD2D * j + 1];
+            const float Bq = a.w, Cq = s1[j].x;
+            out = idx == 0u ? LN2 * (2.f * a.z * m0 + Bq * m1) : LN2 * (Bq * m0 + 2.f * Cq * m1);
+          } else if (idx == 2u || idx == 4u) {
+            out = -0.5f * tot;
+          } else if (idx == 3u) {
+            out = -tot;
+          } else if (idx == 5u) {
+            out = tot * rcp_fast(s1[j].y);
+          }
+          if (out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
         }
       }
     }
@@ -647,6 +667,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
   __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
   __shared__ uint32_t LP[TPW][B];
   __shared__ uint32_t LR[TPW][RingSize<B>::value];
+  __shared__ float LS[TPW][B * GRAD2D];
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (!PERSIST) {
     const int blk = xcd_remap(blockIdx.x, (ntiles + TPW - 1) / TPW);
@@ -654,7 +675,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
     const int g = blk * TPW + wv;
     if (g >= ntiles) return;
     bwd_tile<TW, TH, B>(g, W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp, grad2d, L0[wv],
-                        L1[wv], L2[wv], LP[wv], LR[wv]);
+                        L1[wv], L2[wv], LP[wv], LR[wv], LS[wv]);
     return;
   }
   for (;;) {
@@ -663,7 +684,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
     q = (uint32_t)__builtin_amdgcn_readfirstlane((int)q);
     if (q >= (uint32_t)ntiles) return;
     bwd_tile<TW, TH, B>((int)st.torder[q], W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp,
-                        grad2d, L0[wv], L1[wv], L2[wv], LP[wv], LR[wv]);
+                        grad2d, L0[wv], L1[wv], L2[wv], LP[wv], LR[wv], LS[wv]);
     // the next tile's staging overwrites this wave's LDS slice: every lane
     // has finished reading it
     __builtin_amdgcn_wave_barrier();

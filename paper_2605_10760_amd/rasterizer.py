@@ -97,7 +97,7 @@ class Rasterizer:
 
     def __init__(self, width: int, height: int, max_pairs: int, max_views: int = 1,
                  max_instances: int | None = None, tile=(16, 16), device: int | None = None,
-                 chunk: int = 0, fwd_batch: int = 1, bwd_batch: int = 2, persistent: bool = False):
+                 chunk: int = 0, fwd_batch: int = 1, bwd_batch: int = 1, persistent: bool = False):
         self.lib = L.load()
         self.device = torch.cuda.current_device() if device is None else int(device)
         h = C.c_void_p()
@@ -286,7 +286,7 @@ def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = No
     dev = torch.cuda.current_device() if device is None else int(device)
     P = pairs_of(scene, views) if max_pairs is None else int(max_pairs)
     base = L.PlanDesc(P, int(max_instances or min(0xFFFFFFFE, max(1 << 20, 8 * P))), views.n,
-                      views.width, views.height, 16, 16, 0, 1, 2, 0, 0)
+                      views.width, views.height, 16, 16, 0, 1, 1, 0, 0)
     sc, keep1 = Rasterizer._scene(scene)
     vw, keep2 = Rasterizer._views(views)
     st = Rasterizer._settings(z_near)
@@ -297,7 +297,7 @@ def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = No
     if status != L.GSR_OK:
         raise L.GsrError(status, "gsr_autotune failed")
     return dict(tile=(best.tile_w, best.tile_h), ms=float(ms.value), chunk=int(best.chunk),
-                fwd_batch=int(best.fwd_batch) or 1, bwd_batch=int(best.bwd_batch) or 2,
+                fwd_batch=int(best.fwd_batch) or 1, bwd_batch=int(best.bwd_batch) or 1,
                 persistent=bool(best.persistent))
 
 
