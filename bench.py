@@ -115,6 +115,8 @@ def parse():
                     help="skip gsr_autotune and use --tile with the default compositing options")
     ap.add_argument("--persistent", type=int, choices=(0, 1), default=None,
                     help="force the persistent tile queue off/on (after autotuning)")
+    ap.add_argument("--bwd-cols", type=int, choices=(1, 2), default=None,
+                    help="force the tiles per backward wave (after autotuning)")
     ap.add_argument("--no-graph", action="store_true", help="time the batched step eagerly")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -150,9 +152,10 @@ def make_workload(name):
 def plan_options(tuned):
     """Rasterizer keyword arguments of an autotune result (or defaults)."""
     if tuned is None:
-        return dict(chunk=0, fwd_batch=1, bwd_batch=1, persistent=False)
+        return dict(chunk=0, fwd_batch=1, bwd_batch=1, persistent=False, bwd_cols=1)
     return dict(chunk=tuned["chunk"], fwd_batch=tuned["fwd_batch"],
-                bwd_batch=tuned["bwd_batch"], persistent=tuned["persistent"])
+                bwd_batch=tuned["bwd_batch"], persistent=tuned["persistent"],
+                bwd_cols=tuned["bwd_cols"])
 
 
 class Step:
@@ -439,6 +442,8 @@ def run_workload(torch, np, wl, args, steps, warmup, tuned=None, tile=(16, 16), 
     opts = plan_options(tuned)
     if args.persistent is not None:
         opts["persistent"] = bool(args.persistent)
+    if getattr(args, "bwd_cols", None) is not None:
+        opts["bwd_cols"] = int(args.bwd_cols)
     rast = Rasterizer(W, H, P, V, tile=tile, **opts)
     rast.fit_capacity(sc, vw)
     cnt = work_counts(np, rast, sc, vw, V, H, W, tile)
@@ -484,7 +489,7 @@ def run_workload(torch, np, wl, args, steps, warmup, tuned=None, tile=(16, 16), 
         # A/B of the compositing options on this workload: eager steps with
         # one option changed from the plan in use (same state buffer)
         base = dict(fwd_batch=rast.desc.fwd_batch or 1, bwd_batch=rast.desc.bwd_batch or 1,
-                    persistent=rast.desc.persistent)
+                    persistent=rast.desc.persistent, bwd_cols=rast.desc.bwd_cols or 1)
         variants = [("plan", {})]
         variants.append(("persistent" if not base["persistent"] else "grid",
                          dict(persistent=1 - base["persistent"])))
@@ -492,6 +497,9 @@ def run_workload(torch, np, wl, args, steps, warmup, tuned=None, tile=(16, 16), 
         for bb in (1, 2, 4):
             if bb != base["bwd_batch"]:
                 variants.append((f"bwd_batch={bb}", dict(bwd_batch=bb)))
+        if rast.desc.tile_w <= 16 and 2 * rast.desc.tile_w * rast.desc.tile_h <= 512:
+            variants.append((f"bwd_cols={3 - base['bwd_cols']}",
+                             dict(bwd_cols=3 - base["bwd_cols"])))
         ab = {}
         for name, change in variants:
             rast.replan(**{**base, **change})
@@ -692,6 +700,12 @@ def measure_extras(torch, sc, vw, out_color, out_depth, tc, td, rast=None, reps=
     return res
 
 
+def tile_key(tile, opts):
+    """Tile shape as the counter summaries record it: WxH, with -bwd2 when
+    the backward takes two tiles of a tile row per wave."""
+    return f"{tile[0]}x{tile[1]}" + ("-bwd2" if int(opts.get("bwd_cols", 1)) == 2 else "")
+
+
 def roofline_of(res, kernel_stage, workload_name):
     """Roofline record of one compositing (VALU-bound) or HBM-bound stage:
     algorithmic rate over the measured average launch time, with the HBM
@@ -701,7 +715,7 @@ def roofline_of(res, kernel_stage, workload_name):
     if ms <= 0:
         return None
     kern = STAGE_KERNEL.get(kernel_stage, kernel_stage)
-    tile = f"{res['tile'][0]}x{res['tile'][1]}"
+    tile = tile_key(res["tile"], res["opts"])
     byt = res["bytes"].get(kernel_stage, 0)
     hbm = byt / (ms * 1e-3) / 1e9
     tr = recorded("traffic", kern, workload_name, tile)
@@ -870,6 +884,7 @@ def main():
                    "fwd_batch": int(res["opts"]["fwd_batch"]),
                    "bwd_batch": int(res["opts"]["bwd_batch"]),
                    "persistent": bool(res["opts"]["persistent"]),
+                   "bwd_cols": int(res["opts"].get("bwd_cols", 1)),
                    "autotuned": tuned is not None, "form": main_sum["form"]},
         "evals_per_s": main_sum["evals_per_s"],
         "evals": main_sum["evals"],

@@ -118,7 +118,10 @@ typedef struct gsr_plan_desc {
                             workgroups whose waves take tiles from a queue
                             ordered by decreasing list length; 0: one wave per
                             tile */
-  int32_t reserved;
+  int32_t bwd_cols;      /* tiles of a tile row per backward wave: 1 or 2
+                            (0 = 1); 2 needs tile_w <= 16 and
+                            2 tile_w tile_h <= 512, and its backward always
+                            runs one wave per pair of tiles (no queue) */
 } gsr_plan_desc;
 
 /* Gaussians, concatenated over sets; set s owns [set_offsets[s], set_offsets[s+1]). */
@@ -468,13 +471,14 @@ gsr_status gsr_seed_noalloc(const float* depth, const float* color, const float*
                             void* stream);
 
 /* Time forward+backward of the given call for each candidate plan and
- * report the fastest in `best`, by coordinate search: every tile shape
- * (binning chunk automatic, one entry per lane in the forward and in the
- * backward, grid launch), then for the fastest plan so far each
+ * report the fastest in `best`, by coordinate search: every tile shape with
+ * one and, where allowed, two tiles per backward wave (binning chunk
+ * automatic, one entry per lane in the forward and in the backward, grid
+ * launch), then for the fastest plan so far each
  * binning chunk of 64, 128 and 256 pairs, the forward's 1 or 2 entries per
  * lane, the backward's 1, 2 or 4 entries per lane, and the grid or
  * persistent tile queue.  `best` holds tile_w, tile_h, chunk, fwd_batch,
- * bwd_batch and persistent; other fields are copied from `base` (the
+ * bwd_batch, persistent and bwd_cols; other fields are copied from `base` (the
  * entry capacity raised if a candidate overflowed).  Synchronises;
  * allocates its own temporary contexts and buffers. */
 gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* scene,

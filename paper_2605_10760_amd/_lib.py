@@ -35,7 +35,7 @@ class PlanDesc(C.Structure):
                 ("max_views", C.c_int32), ("width", C.c_int32), ("height", C.c_int32),
                 ("tile_w", C.c_int32), ("tile_h", C.c_int32), ("chunk", C.c_int32),
                 ("fwd_batch", C.c_int32), ("bwd_batch", C.c_int32), ("persistent", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("bwd_cols", C.c_int32)]
 
 
 class Scene(C.Structure):

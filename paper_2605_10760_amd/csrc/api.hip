@@ -158,6 +158,10 @@ gsr_status check_plan(gsr_ctx* c, const gsr_plan_desc* p) {
     return fail(c, GSR_E_INVALID_ARG, "fwd_batch must be 0, 1 or 2");
   if (!(p->bwd_batch == 0 || p->bwd_batch == 1 || p->bwd_batch == 2 || p->bwd_batch == 4))
     return fail(c, GSR_E_INVALID_ARG, "bwd_batch must be 0, 1, 2 or 4");
+  if (!(p->bwd_cols == 0 || p->bwd_cols == 1 || p->bwd_cols == 2))
+    return fail(c, GSR_E_INVALID_ARG, "bwd_cols must be 0, 1 or 2");
+  if (p->bwd_cols == 2 && (p->tile_w > 16 || 2 * p->tile_w * p->tile_h > 512))
+    return fail(c, GSR_E_INVALID_ARG, "bwd_cols 2 needs tile_w <= 16 and 2 tile_w tile_h <= 512");
   if (p->persistent != 0 && p->persistent != 1)
     return fail(c, GSR_E_INVALID_ARG, "persistent must be 0 or 1");
   return GSR_OK;
@@ -434,6 +438,7 @@ gsr_status gsr_plan(gsr_ctx* c, const gsr_plan_desc* p) {
   c->rc.fwd_batch = p->fwd_batch == 2 ? 2 : 1;
   c->rc.bwd_batch = p->bwd_batch == 0 ? 1 : p->bwd_batch;
   c->rc.persistent = p->persistent == 1;
+  c->rc.bwd_cols = p->bwd_cols == 2 ? 2 : 1;
   // The per-pair screen-space gradient rows start at zero and every
   // backward leaves them at zero (the projection backward clears what it
   // reads), so no clearing pass is needed per call.
@@ -971,11 +976,14 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
                         float* best_ms, void* stream) {
   if (!base || !sc || !vw || !best || !best_ms) return GSR_E_INVALID_ARG;
   if (check_plan(nullptr, base) != GSR_OK) return GSR_E_INVALID_ARG;
-  // Coordinate search: every tile shape (other options at their defaults),
-  // then for the best plan so far the binning chunk (depth-sorted pairs per
-  // wave of the row binning), the forward's entries per thread, the
-  // backward's entries per lane, and the persistent tile queue.
-  static const int tiles[][2] = {{16, 16}, {16, 8}, {8, 16}, {8, 8}, {32, 8}, {32, 16}, {16, 32}};
+  // Coordinate search: every tile shape with one and (where allowed) two
+  // tiles per backward wave (other options at their defaults), then for the
+  // best plan so far the binning chunk (depth-sorted pairs per wave of the
+  // row binning), the forward's entries per lane, the backward's entries
+  // per lane, and the persistent tile queue.
+  static const int tiles[][3] = {{16, 16, 1}, {16, 16, 2}, {16, 8, 1}, {16, 8, 2}, {8, 16, 1},
+                                 {8, 16, 2},  {8, 8, 1},   {8, 8, 2},  {32, 8, 1}, {32, 16, 1},
+                                 {16, 32, 1}};
   static const int chunks[] = {64, 128, 256};
   static const int fbs[] = {1, 2};
   static const int bbs[] = {1, 2, 4};
@@ -1015,6 +1023,7 @@ gsr_status gsr_autotune(int device, const gsr_plan_desc* base, const gsr_scene* 
     if (ci < NT_) {
       p.tile_w = tiles[ci][0];
       p.tile_h = tiles[ci][1];
+      p.bwd_cols = tiles[ci][2];
       p.chunk = 0;
       p.fwd_batch = 1;
       p.bwd_batch = 1;

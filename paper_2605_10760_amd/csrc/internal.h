@@ -151,11 +151,13 @@ hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32
                              hipStream_t s);
 hipError_t launch_binning(const BinTab& t, StateDev st, const BinWork& w, hipStream_t s);
 // Compositing launch options (from the plan): list entries staged per lane
-// in the forward (1 or 2) and in the backward (1, 2 or 4), and the persistent
-// length-ordered tile queue instead of one wave per tile.
+// in the forward (1 or 2) and in the backward (1, 2 or 4), tiles of a tile
+// row per backward wave (1 or 2), and the persistent length-ordered tile
+// queue instead of one wave per tile.
 struct RenderCfg {
   int fwd_batch;
   int bwd_batch;
+  int bwd_cols;
   bool persistent;
 };
 hipError_t launch_tile_order(int nv, int TX, int TY, StateDev st, unsigned int* sched,

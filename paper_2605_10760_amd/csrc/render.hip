@@ -139,13 +139,14 @@ __device__ __forceinline__ void fill_front(const uint2* rows, uint32_t& q, uint3
   }
 }
 
-// Back to front: append the visible positions of the row entries at
-// [start, q) that cover column tx to the ring, in decreasing position, until
-// it holds B or the scan reaches start; q moves down past what was scanned.
-template <int B>
+// Back to front: append the visible positions (and, for CP > 1, the column
+// spans) of the row entries at [start, q) that cover one of the CP columns
+// tx0 .. tx0 + CP - 1 to the ring, in decreasing position, until it holds B
+// or the scan reaches start; q moves down past what was scanned.
+template <int B, int CP>
 __device__ __forceinline__ void fill_back(const uint2* rows, uint32_t& q, uint32_t start,
-                                          uint32_t tx, uint32_t* ring, uint32_t head,
-                                          uint32_t& tail) {
+                                          uint32_t tx0, uint32_t* ring, uint32_t* ringx,
+                                          uint32_t head, uint32_t& tail) {
   constexpr uint32_t RM = RingSize<B>::value - 1;
   const int lane = threadIdx.x & 63;
   const unsigned long long above = lane == 63 ? 0ull : (~0ull << (lane + 1));
@@ -159,14 +160,80 @@ __device__ __forceinline__ void fill_back(const uint2* rows, uint32_t& q, uint32
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-      const bool cov = covers(e[k].y, tx);
+      bool cov = false;
+#pragma unroll
+      for (int c = 0; c < CP; ++c) cov = cov || covers(e[k].y, tx0 + (uint32_t)c);
       const unsigned long long m = __ballot(cov);
       // higher lanes (later entries) take the lower ring slots
-      if (cov) ring[(tail + (uint32_t)__popcll(m & above)) & RM] = e[k].x;
+      if (cov) {
+        const uint32_t slot = (tail + (uint32_t)__popcll(m & above)) & RM;
+        ring[slot] = e[k].x;
+        if (CP > 1) ringx[slot] = e[k].y;
+      }
       tail += (uint32_t)__popcll(m);
     }
     q = q - start > 128u ? q - 128u : start;
   }
+}
+
+// For CP columns tx0 + c with n[c] entries each to walk: the row position
+// qb just after the last of the n[c]-th entries covering column tx0 + c
+// (start when every n[c] is 0), and top[c], the number of entries of
+// [start, qb) covering each column (n[c] for the column that ends last).
+template <int CP>
+__device__ __forceinline__ uint32_t cover_ends(const uint2* rows, uint32_t start, uint32_t end,
+                                               uint32_t tx0, const uint32_t* n, uint32_t* top) {
+  const int lane = threadIdx.x & 63;
+  uint32_t cnt[CP], qe[CP];
+  bool found[CP];
+  bool all = true;
+#pragma unroll
+  for (int c = 0; c < CP; ++c) {
+    cnt[c] = 0u;
+    qe[c] = start;
+    found[c] = n[c] == 0u;
+    all = all && found[c];
+    top[c] = 0u;
+  }
+  if (all) return start;
+  for (uint32_t q = start; q < end; q += 64u) {
+    const uint32_t i = q + (uint32_t)lane;
+    const uint32_t xs = i < end ? rows[i].y : 0u;
+    unsigned long long m[CP];
+#pragma unroll
+    for (int c = 0; c < CP; ++c) {
+      const bool cov = covers(xs, tx0 + (uint32_t)c);
+      m[c] = __ballot(cov);
+      const uint32_t pc = (uint32_t)__popcll(m[c]);
+      if (!found[c] && cnt[c] + pc >= n[c]) {
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m[c] >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m[c], 0u));
+        const unsigned long long hit = __ballot(cov && rank == n[c] - cnt[c] - 1u);
+        qe[c] = q + (uint32_t)__builtin_ctzll(hit) + 1u;
+        found[c] = true;
+      }
+    }
+    all = true;
+#pragma unroll
+    for (int c = 0; c < CP; ++c) all = all && found[c];
+    if (all) {
+      uint32_t qb = start;
+#pragma unroll
+      for (int c = 0; c < CP; ++c) qb = max(qb, qe[c]);
+      // qb lies in this step: the covering entries before it
+      const uint32_t in = qb - q;  // 1..64
+      const unsigned long long low = in >= 64u ? ~0ull : ((1ull << in) - 1ull);
+#pragma unroll
+      for (int c = 0; c < CP; ++c) top[c] = cnt[c] + (uint32_t)__popcll(m[c] & low);
+      return qb;
+    }
+#pragma unroll
+    for (int c = 0; c < CP; ++c) cnt[c] += (uint32_t)__popcll(m[c]);
+  }
+  // fewer covering entries than asked (not reached for a consistent state)
+#pragma unroll
+  for (int c = 0; c < CP; ++c) top[c] = cnt[c];
+  return end;
 }
 
 // The row position just after the n-th (1-based) entry of [q, end) that
@@ -440,22 +507,32 @@ __device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane) {
   return z;
 }
 
-// One tile of the backward on one wave.  Lane l shades pixel (l % 8, l / 8)
-// of each of the tile's PPL 8x8 blocks; a record staged in the wave's LDS
-// slice (B entries) is read once per lane and used for its PPL pixels.
-template <int TW, int TH, int B>
+// One tile, or CP adjacent tiles of a tile row, of the backward on one wave.
+// Lane l shades pixel (l % 8, l / 8) of each of the region's PPL 8x8 blocks;
+// a record staged in the wave's LDS slice (B entries) is read once per lane
+// and used for its PPL pixels.  With CP = 2 the wave walks the entries that
+// cover either tile (its row list filtered by two columns), and each entry
+// carries its position in each tile's own list, which the pixels of that
+// tile compare with their last contributor.
+template <int TW, int TH, int B, int CP>
 __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
                                          unsigned long long grad_mask, const CamDev& cam,
                                          const StateDev& st, const float* gcol, const float* gdep,
                                          const float* galp, float* grad2d, float4* s0, float4* s1,
-                                         float4* s2, uint32_t* sp, uint32_t* ring, float* red) {
-  constexpr int PPL = TW * TH / 64;
+                                         float4* s2, uint32_t* sp, uint32_t* ring, uint32_t* ringx,
+                                         float* red) {
+  constexpr int RW = CP * TW;           // region width
+  constexpr int PPL = RW * TH / 64;
+  constexpr int BX = RW / 8, HBX = TW / 8;  // blocks per region row, per tile row
+  constexpr int R = B / 64;
   constexpr uint32_t RM = RingSize<B>::value - 1;
-  const int T = TX * TY;
+  static_assert(PPL <= 32, "one mask bit per block");
+  const int TXR = (TX + CP - 1) / CP;   // regions per tile row
+  const int T = TXR * TY;
   const int v = g / T, tl = g - v * T;
   if (!((grad_mask >> v) & 1ull)) return;
   if (st.hdr->overflow) return;
-  const int ty = tl / TX, tx = tl - ty * TX;
+  const int ty = tl / TXR, tx0 = (tl - ty * TXR) * CP;
   const uint2 rr = st.row_rg[(size_t)v * TY + ty];
   if (rr.x == rr.y) return;
   const int lane = threadIdx.x & 63;
@@ -466,11 +543,12 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
   // alpha_j) with cg_j = c_j . dL/dC + z_j dL/dD, and Q += w_j cg_j.
   float fxp[PPL], fyp[PPL], Tc[PPL], g0[PPL], g1[PPL], g2[PPL], gd[PPL], Q[PPL];
   uint32_t lastp[PPL];
-  uint32_t mylast = 0;
-  constexpr int BX = TW / 8;
+  uint32_t mylast[CP];
+#pragma unroll
+  for (int c = 0; c < CP; ++c) mylast[c] = 0u;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
-    const int px = tx * TW + 8 * (k % BX) + (lane & 7);
+    const int px = tx0 * TW + 8 * (k % BX) + (lane & 7);
     const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
     fxp[k] = (float)px + 0.5f;
     fyp[k] = (float)py + 0.5f;
@@ -490,31 +568,65 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
       if (galp) ga = galp[v * HW + q];
     }
     Q[k] = Tc[k] * (cam.bg0 * g0[k] + cam.bg1 * g1[k] + cam.bg2 * g2[k]) - Tc[k] * ga;
-    mylast = max(mylast, lastp[k]);
+    mylast[(k % BX) / HBX] = max(mylast[(k % BX) / HBX], lastp[k]);
   }
+  uint32_t nwalk[CP], top[CP];
+  bool any = false;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) mylast = max(mylast, (uint32_t)__shfl_xor((int)mylast, d, 64));
-  const uint32_t maxlast = mylast;
-  if (maxlast == 0u) return;
-  // The walk covers the tile's entries [0, maxlast): the row entries before
-  // the maxlast-th one covering this column, scanned back to front.
-  uint32_t qb = nth_cover_end(st.rows, rr.x, rr.y, (uint32_t)tx, maxlast);
-  uint32_t head = 0u, tail = 0u, top = maxlast;  // ring cursors; entries left to walk
+  for (int c = 0; c < CP; ++c) {
+    uint32_t m = mylast[c];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+    nwalk[c] = m;
+    any = any || m != 0u;
+  }
+  if (!any) return;
+  // The walk covers each tile's entries [0, nwalk[c]): the row entries before
+  // the last of the nwalk[c]-th ones covering each column, back to front;
+  // top[c] counts the entries of that range covering column tx0 + c.
+  uint32_t qb;
+  if (CP == 1) {
+    qb = nth_cover_end(st.rows, rr.x, rr.y, (uint32_t)tx0, nwalk[0]);
+    top[0] = nwalk[0];
+  } else {
+    qb = cover_ends<CP>(st.rows, rr.x, rr.y, (uint32_t)tx0, nwalk, top);
+  }
+  uint32_t head = 0u, tail = 0u;  // ring cursors
   for (;;) {
-    fill_back<B>(st.rows, qb, rr.x, (uint32_t)tx, ring, head, tail);
+    fill_back<B, CP>(st.rows, qb, rr.x, (uint32_t)tx0, ring, ringx, head, tail);
     const uint32_t n = min((uint32_t)B, tail - head);
     if (n == 0u) break;
-    uint32_t mr[B / 64];  // blocks the entry this lane staged in round r can reach
+    uint32_t mr[R];        // blocks the entry this lane staged in round r can reach
+    uint32_t posr[CP][R];  // its position in each tile's list
+    uint32_t seen[CP];     // entries covering each column staged in earlier rounds
 #pragma unroll
-    for (int r = 0; r < B / 64; ++r) {
+    for (int c = 0; c < CP; ++c) seen[c] = 0u;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
       const uint32_t idx = (uint32_t)(lane + 64 * r);
+      const bool valid = idx < n;
+      const uint32_t slot = (head + idx) & RM;
+      const uint32_t xs = (CP > 1 && valid) ? ringx[slot] : 0u;
+      bool cov[CP];
+#pragma unroll
+      for (int c = 0; c < CP; ++c) {
+        cov[c] = valid && (CP == 1 || covers(xs, (uint32_t)(tx0 + c)));
+        const unsigned long long mc = __ballot(cov[c]);
+        // staged entries run back to front: the first one covering column c
+        // is its tile's entry top[c] - 1
+        posr[c][r] = top[c] - 1u - seen[c] -
+                     __builtin_amdgcn_mbcnt_hi((uint32_t)(mc >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)mc, 0u));
+        seen[c] += (uint32_t)__popcll(mc);
+      }
       mr[r] = 0u;
-      if (idx < n) {
-        const uint32_t pr = ring[(head + idx) & RM];
+      if (valid) {
+        const uint32_t pr = ring[slot];
         const float4* rp = st.rec + 3 * (size_t)pr;
         const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
-        // bit k: the entry can reach alpha >= 1/255 in the tile's 8x8 block k
-        const float x0c = (float)(tx * TW) + 0.5f, y0c = (float)(ty * TH) + 0.5f;
+        // bit k: the entry can reach alpha >= 1/255 in the region's 8x8 block
+        // k, within a tile whose list holds it
+        const float x0c = (float)(tx0 * TW) + 0.5f, y0c = (float)(ty * TH) + 0.5f;
         uint32_t m = 0u;
 #pragma unroll
         for (int by = 0; by < TH / 8; ++by) {
@@ -522,8 +634,8 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
           if (row_extent(r0, r1.x, r2.w, y0c + (float)(8 * by), y0c + (float)(8 * by + 7), xl, xr)) {
 #pragma unroll
             for (int bx = 0; bx < BX; ++bx)
-              m |= (uint32_t)cols_reached(xl, xr, r1.w, x0c + (float)(8 * bx),
-                                          x0c + (float)(8 * bx + 7))
+              m |= (uint32_t)(cov[bx / HBX] && cols_reached(xl, xr, r1.w, x0c + (float)(8 * bx),
+                                                            x0c + (float)(8 * bx + 7)))
                    << (by * BX + bx);
           }
         }
@@ -538,17 +650,18 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
     // the round's wave sums start at zero (entries that reach no pixel keep it)
     for (uint32_t i = (uint32_t)lane; i < n * GRAD2D; i += 64u) red[i] = 0.f;
     __builtin_amdgcn_wave_barrier();
-    // The staged entries are in back-to-front order (entry j of the round
-    // is tile entry top - 1 - j); walk those that can reach a block of the
-    // tile (set bits of a ballot per staging round).
+    // Walk the staged entries (back-to-front order) that can reach a block
+    // of the region (set bits of a ballot per staging round).
 #pragma unroll
-    for (int r = 0; r < B / 64; ++r) {
+    for (int r = 0; r < R; ++r) {
       unsigned long long rel = __ballot(mr[r] != 0u);
       while (rel) {
         const int jj = (int)__builtin_ctzll(rel);
         rel &= rel - 1ull;
         const int j = 64 * r + jj;
-        const int pos = (int)top - 1 - j;
+        int posc[CP];
+#pragma unroll
+        for (int c = 0; c < CP; ++c) posc[c] = __builtin_amdgcn_readlane((int)posr[c][r], jj);
         const uint32_t mj = (uint32_t)__builtin_amdgcn_readlane((int)mr[r], jj);
         const float4 a = s0[j], b = s1[j], c = s2[j];
         float acc[GRAD2D];
@@ -570,7 +683,7 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
           const float G = exp2_fast(power);
           const float raw = b.y * G;
           const float al = fminf(ALPHA_MAX, raw);
-          const bool ok = pos < (int)lastp[k] && !(power > 0.f || al < ALPHA_MIN);
+          const bool ok = posc[(k % BX) / HBX] < (int)lastp[k] && !(power > 0.f || al < ALPHA_MIN);
           act = act || ok;
           const float inv = rcp_fast(1.f - al);
           const float Tb = Tc[k] * inv;
@@ -648,25 +761,32 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
       }
     }
     head += n;
-    top -= n;
+#pragma unroll
+    for (int c = 0; c < CP; ++c) top[c] -= seen[c];
     // the next round's staging overwrites the slice: every lane has read it
     __builtin_amdgcn_wave_barrier();
   }
 }
 
 // TPW waves per workgroup, each with a private LDS slice and no workgroup
-// barrier.  Grid form: wave w of workgroup b takes tile b TPW + w (XCD-aware
-// order).  Persistent form: a grid sized to the resident waves, each wave
+// barrier.  Grid form: wave w of workgroup b takes region b TPW + w
+// (XCD-aware order; a region is CP adjacent tiles of a tile row).
+// Persistent form (CP = 1): a grid sized to the resident waves, each wave
 // taking tiles from the forward's length-ordered queue until it is empty.
-template <int TW, int TH, int B, int TPW, bool PERSIST>
-__global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, int H, int TX, int TY,
+// The two-tile form asks for four resident workgroups per CU: it fits in
+// 128 vector registers without spilling (four waves per SIMD instead of
+// three at its natural 133).
+template <int TW, int TH, int B, int TPW, bool PERSIST, int CP>
+__global__ __launch_bounds__(64 * TPW, CP == 2 ? 4 : 1) void k_render_bwd_w(int ntiles, int W, int H, int TX, int TY,
                                                            unsigned long long grad_mask, CamDev cam,
                                                            StateDev st, unsigned int* next,
                                                            const float* gcol, const float* gdep,
                                                            const float* galp, float* grad2d) {
+  static_assert(CP == 1 || !PERSIST, "the length-ordered queue holds single tiles");
   __shared__ float4 L0[TPW][B], L1[TPW][B], L2[TPW][B];
   __shared__ uint32_t LP[TPW][B];
   __shared__ uint32_t LR[TPW][RingSize<B>::value];
+  __shared__ uint32_t LX[TPW][CP > 1 ? RingSize<B>::value : 1];
   __shared__ float LS[TPW][B * GRAD2D];
   const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   if (!PERSIST) {
@@ -674,8 +794,8 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
     if (blk < 0) return;
     const int g = blk * TPW + wv;
     if (g >= ntiles) return;
-    bwd_tile<TW, TH, B>(g, W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp, grad2d, L0[wv],
-                        L1[wv], L2[wv], LP[wv], LR[wv], LS[wv]);
+    bwd_tile<TW, TH, B, CP>(g, W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp, grad2d,
+                            L0[wv], L1[wv], L2[wv], LP[wv], LR[wv], LX[wv], LS[wv]);
     return;
   }
   for (;;) {
@@ -683,8 +803,9 @@ __global__ __launch_bounds__(64 * TPW) void k_render_bwd_w(int ntiles, int W, in
     if ((threadIdx.x & 63) == 0) q = atomicAdd(next, 1u);
     q = (uint32_t)__builtin_amdgcn_readfirstlane((int)q);
     if (q >= (uint32_t)ntiles) return;
-    bwd_tile<TW, TH, B>((int)st.torder[q], W, H, TX, TY, grad_mask, cam, st, gcol, gdep, galp,
-                        grad2d, L0[wv], L1[wv], L2[wv], LP[wv], LR[wv], LS[wv]);
+    bwd_tile<TW, TH, B, CP>((int)st.torder[q], W, H, TX, TY, grad_mask, cam, st, gcol, gdep,
+                            galp, grad2d, L0[wv], L1[wv], L2[wv], LP[wv], LR[wv], LX[wv],
+                            LS[wv]);
     // the next tile's staging overwrites this wave's LDS slice: every lane
     // has finished reading it
     __builtin_amdgcn_wave_barrier();
@@ -819,18 +940,29 @@ static hipError_t fwd_t(int nv, int W, int H, int TX, int TY, const RenderCfg& r
 constexpr int BWD_TPW = 4;  // tiles (waves) per workgroup
 
 template <int TW, int TH, int B>
-static void bwd_b(int nv, int W, int H, int TX, int TY, bool persist, unsigned long long mask,
-                  const CamDev& cam, StateDev st, unsigned int* sched, const float* gc,
-                  const float* gd, const float* ga, float* grad2d, hipStream_t s) {
+static void bwd_b(int nv, int W, int H, int TX, int TY, bool persist, int cols,
+                  unsigned long long mask, const CamDev& cam, StateDev st, unsigned int* sched,
+                  const float* gc, const float* gd, const float* ga, float* grad2d,
+                  hipStream_t s) {
+  if constexpr (TW <= 16 && 2 * TW * TH <= 512) {
+    if (cols == 2) {
+      // two tiles of a tile row per wave (grid form only)
+      const int nreg = nv * TY * ((TX + 1) / 2);
+      hipLaunchKernelGGL((k_render_bwd_w<TW, TH, B, BWD_TPW, false, 2>),
+                         dim3(xcd_grid((nreg + BWD_TPW - 1) / BWD_TPW)), dim3(64 * BWD_TPW), 0,
+                         s, nreg, W, H, TX, TY, mask, cam, st, sched + 1, gc, gd, ga, grad2d);
+      return;
+    }
+  }
   const int ntiles = nv * TX * TY;
   if (persist) {
-    const auto k = k_render_bwd_w<TW, TH, B, BWD_TPW, true>;
+    const auto k = k_render_bwd_w<TW, TH, B, BWD_TPW, true, 1>;
     const int need = (ntiles + BWD_TPW - 1) / BWD_TPW;
     const int grid = std::min(need, resident_blocks((const void*)k, 64 * BWD_TPW));
     hipLaunchKernelGGL(k, dim3(std::max(1, grid)), dim3(64 * BWD_TPW), 0, s, ntiles, W, H, TX, TY,
                        mask, cam, st, sched + 1, gc, gd, ga, grad2d);
   } else {
-    hipLaunchKernelGGL((k_render_bwd_w<TW, TH, B, BWD_TPW, false>),
+    hipLaunchKernelGGL((k_render_bwd_w<TW, TH, B, BWD_TPW, false, 1>),
                        dim3(xcd_grid((ntiles + BWD_TPW - 1) / BWD_TPW)), dim3(64 * BWD_TPW), 0, s,
                        ntiles, W, H, TX, TY, mask, cam, st, sched + 1, gc, gd, ga, grad2d);
   }
@@ -842,13 +974,14 @@ static hipError_t bwd_t(int nv, int W, int H, int TX, int TY, const RenderCfg& r
                         unsigned int* sched, const float* gc, const float* gd, const float* ga,
                         float* grad2d, hipStream_t s) {
   if (rc.bwd_batch == 1)
-    bwd_b<TW, TH, 64>(nv, W, H, TX, TY, rc.persistent, mask, cam, st, sched, gc, gd, ga, grad2d, s);
+    bwd_b<TW, TH, 64>(nv, W, H, TX, TY, rc.persistent, rc.bwd_cols, mask, cam, st, sched, gc, gd,
+                      ga, grad2d, s);
   else if (rc.bwd_batch == 4)
-    bwd_b<TW, TH, 256>(nv, W, H, TX, TY, rc.persistent, mask, cam, st, sched, gc, gd, ga, grad2d,
-                       s);
+    bwd_b<TW, TH, 256>(nv, W, H, TX, TY, rc.persistent, rc.bwd_cols, mask, cam, st, sched, gc, gd,
+                       ga, grad2d, s);
   else
-    bwd_b<TW, TH, 128>(nv, W, H, TX, TY, rc.persistent, mask, cam, st, sched, gc, gd, ga, grad2d,
-                       s);
+    bwd_b<TW, TH, 128>(nv, W, H, TX, TY, rc.persistent, rc.bwd_cols, mask, cam, st, sched, gc, gd,
+                       ga, grad2d, s);
   return hipGetLastError();
 }
 

@@ -97,7 +97,8 @@ class Rasterizer:
 
     def __init__(self, width: int, height: int, max_pairs: int, max_views: int = 1,
                  max_instances: int | None = None, tile=(16, 16), device: int | None = None,
-                 chunk: int = 0, fwd_batch: int = 1, bwd_batch: int = 1, persistent: bool = False):
+                 chunk: int = 0, fwd_batch: int = 1, bwd_batch: int = 1, persistent: bool = False,
+                 bwd_cols: int = 1):
         self.lib = L.load()
         self.device = torch.cuda.current_device() if device is None else int(device)
         h = C.c_void_p()
@@ -111,7 +112,8 @@ class Rasterizer:
             max_instances = min(0xFFFFFFFE, max(1 << 20, 8 * int(max_pairs)))
         self.desc = L.PlanDesc(int(max_pairs), int(max_instances), int(max_views), int(width),
                                int(height), int(tile[0]), int(tile[1]), int(chunk),
-                               int(fwd_batch), int(bwd_batch), int(bool(persistent)), 0)
+                               int(fwd_batch), int(bwd_batch), int(bool(persistent)),
+                               int(bwd_cols))
         self._plan()
 
     def _plan(self):
@@ -278,15 +280,16 @@ def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = No
              max_instances: int | None = None, z_near=0.2, device: int | None = None,
              stream=None):
     """Native coordinate search (gsr_autotune) over the tile shape, binning
-    chunk, forward and backward entries per lane and the
-    persistent tile queue for this call.  Returns a dict: tile (tile_w,
-    tile_h), ms (its forward+backward time), chunk, fwd_batch, bwd_batch,
-    persistent — the keyword arguments of Rasterizer besides the sizes."""
+    chunk, forward and backward entries per lane, tiles per backward wave
+    and the persistent tile queue for this call.  Returns a dict: tile
+    (tile_w, tile_h), ms (its forward+backward time), chunk, fwd_batch,
+    bwd_batch, persistent, bwd_cols — the keyword arguments of Rasterizer
+    besides the sizes."""
     lib = L.load()
     dev = torch.cuda.current_device() if device is None else int(device)
     P = pairs_of(scene, views) if max_pairs is None else int(max_pairs)
     base = L.PlanDesc(P, int(max_instances or min(0xFFFFFFFE, max(1 << 20, 8 * P))), views.n,
-                      views.width, views.height, 16, 16, 0, 1, 1, 0, 0)
+                      views.width, views.height, 16, 16, 0, 1, 1, 0, 1)
     sc, keep1 = Rasterizer._scene(scene)
     vw, keep2 = Rasterizer._views(views)
     st = Rasterizer._settings(z_near)
@@ -298,7 +301,7 @@ def autotune(scene: SceneTensors, views: ViewTensors, max_pairs: int | None = No
         raise L.GsrError(status, "gsr_autotune failed")
     return dict(tile=(best.tile_w, best.tile_h), ms=float(ms.value), chunk=int(best.chunk),
                 fwd_batch=int(best.fwd_batch) or 1, bwd_batch=int(best.bwd_batch) or 1,
-                persistent=bool(best.persistent))
+                persistent=bool(best.persistent), bwd_cols=int(best.bwd_cols) or 1)
 
 
 def apply_pose_delta(viewmats: torch.Tensor, delta: torch.Tensor, out: torch.Tensor | None = None,

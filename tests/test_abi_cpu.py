@@ -48,11 +48,11 @@ def test_create_without_device_reports_device_error():
 def _desc(**kw):
     from paper_2605_10760_amd import _lib
     d = dict(max_pairs=1000, max_instances=10000, max_views=2, width=128, height=96,
-             tile_w=16, tile_h=16, chunk=0, fwd_batch=0, bwd_batch=0, persistent=0)
+             tile_w=16, tile_h=16, chunk=0, fwd_batch=0, bwd_batch=0, persistent=0, bwd_cols=0)
     d.update(kw)
     return _lib.PlanDesc(*[d[k] for k in ("max_pairs", "max_instances", "max_views", "width",
                                           "height", "tile_w", "tile_h", "chunk", "fwd_batch",
-                                          "bwd_batch", "persistent")])
+                                          "bwd_batch", "persistent", "bwd_cols")])
 
 
 def test_state_bytes_host_only_and_validation():
@@ -68,8 +68,12 @@ def test_state_bytes_host_only_and_validation():
     assert n.value % 256 == 0
     for bad in (dict(max_pairs=0), dict(max_views=65), dict(tile_w=12), dict(tile_w=32, tile_h=32),
                 dict(width=0), dict(max_instances=0), dict(chunk=-1), dict(fwd_batch=3),
-                dict(bwd_batch=3), dict(bwd_batch=8), dict(persistent=2)):
+                dict(bwd_batch=3), dict(bwd_batch=8), dict(persistent=2), dict(bwd_cols=3),
+                dict(bwd_cols=2, tile_w=32, tile_h=8), dict(bwd_cols=2, tile_w=16, tile_h=32)):
         assert lib.gsr_state_bytes(C.byref(_desc(**bad)), C.byref(n)) == _lib.GSR_E_INVALID_ARG, bad
+    for good in (dict(bwd_cols=2), dict(bwd_cols=2, tile_w=8, tile_h=16),
+                 dict(bwd_cols=1, tile_w=32, tile_h=16)):
+        assert lib.gsr_state_bytes(C.byref(_desc(**good)), C.byref(n)) == _lib.GSR_OK, good
     assert lib.gsr_state_bytes(None, C.byref(n)) == _lib.GSR_E_INVALID_ARG
 
 

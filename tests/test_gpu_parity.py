@@ -424,8 +424,10 @@ def test_profile_stages_and_autotune():
     np.testing.assert_array_equal(g2["color"], g["color"])
 
 
-# (entries per thread in the forward, per lane in the backward, persistent queue)
-RENDER_OPTS = [(2, 2, False), (1, 1, True), (2, 4, True), (1, 4, False)]
+# (entries per lane in the forward, per lane in the backward, persistent queue,
+# tiles per backward wave)
+RENDER_OPTS = [(2, 2, False, 1), (1, 1, True, 1), (2, 4, True, 1), (1, 4, False, 1),
+               (1, 2, True, 2)]
 
 
 @pytest.mark.parametrize("case", ["multi-agent-small", "sh3"])
@@ -434,11 +436,11 @@ def test_render_options(case, opts):
     """Every compositing batch size and the persistent tile queue: forward
     outputs bit-identical to the default launch (the per-pixel arithmetic
     and its order do not change), gradients against the oracle."""
-    fb, bb, pers = opts
-    announce(f"render options fb={fb} bb={bb} persistent={pers} {case}")
+    fb, bb, pers, cols = opts
+    announce(f"render options fb={fb} bb={bb} persistent={pers} cols={cols} {case}")
     scene, views = _scene_case(case)
     g0 = gpu_forward(scene, views)
-    g1 = gpu_forward(scene, views, fwd_batch=fb, bwd_batch=bb, persistent=pers)
+    g1 = gpu_forward(scene, views, fwd_batch=fb, bwd_batch=bb, persistent=pers, bwd_cols=cols)
     for key in ("color", "depth", "alpha", "n_eval"):
         np.testing.assert_array_equal(g0[key], g1[key], err_msg=key)
     for key in ("t_final", "last"):
@@ -456,6 +458,30 @@ def test_render_options(case, opts):
     for k_gpu, k_ref in GMAP.items():
         e_inf, e_2 = grad_rel_err(got2[k_gpu], ref[k_ref])
         assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+
+
+@pytest.mark.parametrize("case", ["tiny-0", "tiny-1", "multi-agent-small", "sh3"])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_backward_two_tiles_per_wave(case, tile):
+    """The backward on pairs of tiles of a tile row (each entry compared
+    with its position in each tile's own list; 70-pixel-wide views leave an
+    odd tile column at the row end): gradients against the oracle and
+    against the one-tile backward of the same forward."""
+    announce(f"backward two tiles per wave {case} {tile}")
+    scene, views = _scene_case(case)
+    g1 = gpu_forward(scene, views, tile=tile, export=False)
+    g2 = gpu_forward(scene, views, tile=tile, export=False, bwd_cols=2)
+    np.testing.assert_array_equal(g1["color"], g2["color"])
+    orc = _oracle_views(scene, views)
+    gc, gd, ga = _upstream(views, 11, orc)
+    a = _gpu_backward(g1, gc, gd, ga)
+    b = _gpu_backward(g2, gc, gd, ga)
+    ref = render_backward(scene, views, gc, gd, ga)
+    for k_gpu, k_ref in GMAP.items():
+        e_inf, e_2 = grad_rel_err(b[k_gpu], ref[k_ref])
+        assert e_inf <= GRAD_TOL and e_2 <= GRAD_TOL, (k_gpu, e_inf, e_2)
+        e_inf, _ = grad_rel_err(b[k_gpu], a[k_gpu])
+        assert e_inf <= RERUN_TOL, (k_gpu, e_inf)
 
 
 @pytest.mark.parametrize("case", ["small-plain", "multi-agent-small", "sh3"])
