@@ -39,13 +39,25 @@ constexpr float LN2 = 0.6931471805599453f;
 // G = 2^p with p = A' dx^2 + B' dx dy + C' dy^2.  The operation sequence is
 // spelled out (explicit fma, no other contraction) so the forward and the
 // backward take identical skip decisions.
-__device__ __forceinline__ float splat_power(const float4& a, const float4& b, float fx, float fy,
-                                             float& dx, float& dy) {
+// The terms that depend on the pixel row only (B' dy and C' dy^2) are formed
+// once per row of 8x8 blocks and shared by the blocks of that row; the
+// result is the same sequence of roundings as the one-call form.
+struct SplatRow {
+  float bdy, cdy2;
+};
+__device__ __forceinline__ SplatRow splat_row(const float4& a, const float4& b, float fy) {
 #pragma clang fp contract(off)
-  dx = a.x - fx;
-  dy = a.y - fy;
+  const float dy = a.y - fy;
+  return SplatRow{a.w * dy, (b.x * dy) * dy};
+}
+__device__ __forceinline__ float splat_power_row(const float4& a, const SplatRow& r, float fx) {
+#pragma clang fp contract(off)
+  const float dx = a.x - fx;
   // dx (A' dx + B' dy) + C' dy^2
-  return fmaf(dx, fmaf(a.z, dx, a.w * dy), (b.x * dy) * dy);
+  return fmaf(dx, fmaf(a.z, dx, r.bdy), r.cdy2);
+}
+__device__ __forceinline__ float splat_power(const float4& a, const float4& b, float fx, float fy) {
+  return splat_power_row(a, splat_row(a, b, fy), fx);
 }
 
 __device__ __forceinline__ float exp2_fast(float p) { return __builtin_amdgcn_exp2f(p); }
@@ -367,10 +379,8 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
         uint32_t pos1;
         asm volatile("v_mov_b32 %0, %1" : "=v"(pos1) : "s"(tbase + (uint32_t)j + 1u));
         const float4 a = s0[j], b = s1[j], c = s2[j];
-        auto blend = [&](int k) {
-          float dx, dy;
-          const float p = splat_power(a, b, fx0 + (float)(8 * (k % BX)), fy0 + (float)(8 * (k / BX)),
-                                      dx, dy);
+        auto blend = [&](int k, const SplatRow& rw) {
+          const float p = splat_power_row(a, rw, fx0 + (float)(8 * (k % BX)));
           const float al = fminf(ALPHA_MAX, b.y * exp2_fast(p));
           const bool use = stopn[k] == 0u && !(p > 0.f || al < ALPHA_MIN);
           // T (1 - alpha) with one rounding
@@ -387,8 +397,13 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
           last[k] = ok ? pos1 : last[k];
         };
 #pragma unroll
-        for (int k = 0; k < PPL; ++k)
-          if ((mj >> k) & 1u) blend(k);
+        for (int by = 0; by < BY; ++by) {
+          if (!((mj >> (by * BX)) & ((1u << BX) - 1u))) continue;
+          const SplatRow rw = splat_row(a, b, fy0 + (float)(8 * by));
+#pragma unroll
+          for (int bx = 0; bx < BX; ++bx)
+            if ((mj >> (by * BX + bx)) & 1u) blend(by * BX + bx, rw);
+        }
       }
       if (!live) break;
     }
@@ -461,8 +476,24 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int 
 // partner, so the number of values per lane halves as the partial sums
 // double (10 -> 5 -> 3 -> 2 -> 1 over lane bits 0..3, then bits 4 and 5 on
 // the single value).  Lane l < 16 ends with the total of value sum10_index(l)
-// (-1: no value); lanes 16..63 hold copies.  About 45 lane operations
-// instead of 70 for ten separate reductions.
+// (-1: no value); lanes 16..63 hold partial sums.  About 45 lane operations
+// instead of 70 for ten separate reductions, none through LDS.
+// z plus a zero register after swapping z's odd 16-lane rows (R = 16) or
+// its upper 32 lanes (R = 32) with the other register's even rows / lower
+// lanes: lane l of row 0 (and of row 2 for R = 16) gets z_l + z_{l+R}.  Both
+// registers are written by the swap, so it is spelled out with both as
+// in-out operands; the two wait states before it cover a vector write of
+// its operands just ahead of it.
+template <int R>
+__device__ __forceinline__ float row_swap_sum(float z) {
+  float o = 0.f;
+  if (R == 16)
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(z), "+v"(o));
+  else
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(z), "+v"(o));
+  return z + o;
+}
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
@@ -501,10 +532,13 @@ __device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane) {
   }
   // lane bit 3 (row_ror:8)
   float z = (b3 ? y[1] : y[0]) + dpp_mov<0x128>(b3 ? y[0] : y[1]);
-  // lane bits 4 and 5: the same value index in both partners
-  z += __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, z), 0x401F));
-  z += __shfl_xor(z, 32, 64);
-  return z;
+  // lane bits 4 and 5: the same value index in both partners, by the row
+  // swaps of the vector unit.  Swapping the odd 16-lane rows of z with the
+  // even rows of a zero register leaves z's even rows in z and z's odd rows,
+  // moved down one row, in the other register, so their sum holds the pair
+  // totals in rows 0 and 2; the 32-lane swap adds row 2 to row 0 the same
+  // way.
+  return row_swap_sum<32>(row_swap_sum<16>(z));
 }
 
 // One tile, or CP adjacent tiles of a tile row, of the backward on one wave.
@@ -570,6 +604,10 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
     Q[k] = Tc[k] * (cam.bg0 * g0[k] + cam.bg1 * g1[k] + cam.bg2 * g2[k]) - Tc[k] * ga;
     mylast[(k % BX) / HBX] = max(mylast[(k % BX) / HBX], lastp[k]);
   }
+  // the lane's pixel offset within an 8x8 block
+  const float lxf = (float)(lane & 7), lyf = (float)(lane >> 3);
+  // the region's first pixel centre
+  const float x0r = (float)(tx0 * TW) + 0.5f, y0r = (float)(ty * TH) + 0.5f;
   uint32_t nwalk[CP], top[CP];
   bool any = false;
 #pragma unroll
@@ -667,27 +705,37 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
         float acc[GRAD2D];
 #pragma unroll
         for (int i = 0; i < GRAD2D; ++i) acc[i] = 0.f;
-        float S0 = 0.f, Sx = 0.f, Sy = 0.f, Sxx = 0.f, Sxy = 0.f, Syy = 0.f;
+        // per-lane sums of gp weighted by the pixel's 8x8-block offsets
+        // (ix, iy): Sx8 and Sxx64 carry the factors 8 ix and 64 ix^2, Sy and
+        // Syy the factors iy and iy^2, Sxy64 the factor 64 ix iy (all
+        // compile-time constants once unrolled)
+        float S0 = 0.f, Sx8 = 0.f, Sy = 0.f, Sxx64 = 0.f, Sxy64 = 0.f, Syy = 0.f;
         bool act = false;
-        // Branch-free per pixel: an entry a pixel does not blend gets zero
-        // weight and zero gradients (selected, never multiplied, so an
-        // infinite exp2 of a skipped entry cannot leak in); adding exact zeros
-        // leaves every sum unchanged.  A block the entry cannot reach is not
+        // the exponent's row terms, once per row of blocks
+        SplatRow rws[TH / 8];
+#pragma unroll
+        for (int by = 0; by < TH / 8; ++by) rws[by] = splat_row(a, b, fyp[by * BX]);
+        // Branch-free per pixel: an entry a pixel does not blend gets a zero
+        // alpha (selected, never multiplied, so an infinite exp2 of a skipped
+        // entry cannot leak in), hence zero weight and gradients, and keeps
+        // its transmittance; adding exact zeros leaves every sum unchanged.  A block the entry cannot reach is not
         // evaluated at all (a uniform branch on the entry's mask; none of its
         // pixels would blend it).
 #pragma unroll
         for (int k = 0; k < PPL; ++k) {
           if (!((mj >> k) & 1u)) continue;
-          float dx, dy;
-          const float power = splat_power(a, b, fxp[k], fyp[k], dx, dy);
+          const float power = splat_power_row(a, rws[k / BX], fxp[k]);
           const float G = exp2_fast(power);
           const float raw = b.y * G;
           const float al = fminf(ALPHA_MAX, raw);
           const bool ok = posc[(k % BX) / HBX] < (int)lastp[k] && !(power > 0.f || al < ALPHA_MIN);
           act = act || ok;
-          const float inv = rcp_fast(1.f - al);
+          // the alpha the pixel blends: zero for an entry it does not blend,
+          // whose transmittance factor is then the reciprocal of 1, exactly 1
+          const float ab = ok ? al : 0.f;
+          const float inv = rcp_fast(1.f - ab);
           const float Tb = Tc[k] * inv;
-          const float wgt = ok ? al * Tb : 0.f;
+          const float wgt = ab * Tb;
           const float cg = c.x * g0[k] + c.y * g1[k] + c.z * g2[k] + b.z * gd[k];
           const float dA = Tb * cg - inv * Q[k];
           Q[k] += wgt * cg;
@@ -695,33 +743,32 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
           acc[7] += wgt * g1[k];
           acc[8] += wgt * g2[k];
           acc[9] += wgt * gd[k];
-          const bool unc = ok && raw <= ALPHA_MAX;
           // unclamped: alpha = sigma G, so dL/dsigma = G dA = gp / sigma
-          const float gp = unc ? al * dA : 0.f;
-          // sums of gp weighted by the pixel's 8x8-block offsets (ix, iy) in
-          // block units (compile-time constants once unrolled)
+          const float gp = raw <= ALPHA_MAX ? ab * dA : 0.f;
           const int ix = k % BX, iy = k / BX;
           S0 += gp;
-          if (ix != 0) { Sx = fmaf((float)ix, gp, Sx); Sxx = fmaf((float)(ix * ix), gp, Sxx); }
+          if (ix != 0) {
+            Sx8 = fmaf((float)(8 * ix), gp, Sx8);
+            Sxx64 = fmaf((float)(64 * ix * ix), gp, Sxx64);
+          }
           if (iy != 0) { Sy = fmaf((float)iy, gp, Sy); Syy = fmaf((float)(iy * iy), gp, Syy); }
-          if (ix != 0 && iy != 0) Sxy = fmaf((float)(ix * iy), gp, Sxy);
-          (void)dx;
-          (void)dy;
-          Tc[k] = ok ? Tb : Tc[k];
+          if (ix != 0 && iy != 0) Sxy64 = fmaf((float)(64 * ix * iy), gp, Sxy64);
+          Tc[k] = Tb;
         }
-        // moments of gp over dx, dy (the conic and mean gradients are linear
-        // in them, applied once per entry after the wave sum): pixel k sits
-        // 8 (ix, iy) from the lane's first pixel, so dx_k = dx_0 - 8 ix and
-        // sum gp dx = dx_0 S - 8 Sx, sum gp dx^2 = dx_0^2 S - 16 dx_0 Sx +
-        // 64 Sxx, and likewise for dy and dx dy
+        // moments of gp over the pixels' offsets (u, v) from the region's
+        // first pixel centre: pixel k of the lane sits at u = lx + 8 ix, v =
+        // ly + 8 iy.  Values 0..4 carry sum gp u, sum gp v, sum gp u^2, sum gp
+        // u v, sum gp v^2 and value 5 sum gp; the output pass turns them into
+        // moments over (dx, dy) = (DX - u, DY - v) with the entry's offset
+        // (DX, DY) once per entry.
         {
-          const float dx0 = a.x - fxp[0], dy0 = a.y - fyp[0];
+          const float Sy8 = 8.f * Sy;
           acc[5] = S0;
-          acc[0] = fmaf(dx0, S0, -8.f * Sx);
-          acc[1] = fmaf(dy0, S0, -8.f * Sy);
-          acc[2] = fmaf(dx0, fmaf(dx0, S0, -16.f * Sx), 64.f * Sxx);
-          acc[3] = fmaf(dx0, acc[1], fmaf(-8.f * dy0, Sx, 64.f * Sxy));
-          acc[4] = fmaf(dy0, fmaf(dy0, S0, -16.f * Sy), 64.f * Syy);
+          acc[0] = fmaf(lxf, S0, Sx8);
+          acc[1] = fmaf(lyf, S0, Sy8);
+          acc[2] = fmaf(lxf, acc[0] + Sx8, Sxx64);
+          acc[3] = fmaf(lxf, acc[1], fmaf(lyf, Sx8, Sxy64));
+          acc[4] = fmaf(lyf, acc[1] + Sy8, 64.f * Syy);
         }
         if (__ballot(act) != 0ull) {
           static_assert(GRAD2D == 10, "ten splat gradients");
@@ -733,31 +780,42 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
     }
     __builtin_amdgcn_wave_barrier();
     // The round's wave sums to screen-space gradients, one (entry, value)
-    // per lane, and one atomic each (zero sums, of entries no pixel blended,
-    // are skipped): d(power)/du = -(A dx + B dy) = ln2 (2A' dx + B' dy),
-    // etc., with the moment sums in values 0 and 1; dL/dsigma = (sum of gp) /
-    // sigma, by the hardware reciprocal.
+    // per lane, and one atomic each (zero results, as for entries no pixel
+    // blended, are skipped).  With (DX, DY) the entry's offset from the
+    // region's first pixel centre and T0, TU, TV, TUU, TUV, TVV the sums of
+    // gp, gp u, gp v, gp u^2, gp u v, gp v^2: sum gp dx = DX T0 - TU, sum gp
+    // dx^2 = DX (DX T0 - 2 TU) + TUU, sum gp dx dy = DX (DY T0 - TV) - DY TU +
+    // TUV, and likewise for dy; d(power)/du = -(A dx + B dy) = ln2 (2A' dx +
+    // B' dy), etc.; dL/dsigma = T0 / sigma, by the hardware reciprocal.
     for (uint32_t i0 = 0; i0 < n * GRAD2D; i0 += 64u) {
       const uint32_t i = i0 + (uint32_t)lane;
       if (i < n * GRAD2D) {
         const uint32_t j = i / GRAD2D, idx = i - j * GRAD2D;
         const float tot = red[i];
-        if (tot != 0.f) {
+        float out = tot;
+        if (idx <= 5u) {
           const float4 a = s0[j];
-          float out = tot;
-          if (idx <= 1u) {
-            const float m0 = red[GRAD2D * j], m1 = red[GRAD2D * j + 1];
-            const float Bq = a.w, Cq = s1[j].x;
-            out = idx == 0u ? LN2 * (2.f * a.z * m0 + Bq * m1) : LN2 * (Bq * m0 + 2.f * Cq * m1);
-          } else if (idx == 2u || idx == 4u) {
-            out = -0.5f * tot;
-          } else if (idx == 3u) {
-            out = -tot;
-          } else if (idx == 5u) {
+          const float T0 = red[GRAD2D * j + 5];
+          if (idx == 5u) {
             out = tot * rcp_fast(s1[j].y);
+          } else {
+            const float TU = red[GRAD2D * j], TV = red[GRAD2D * j + 1];
+            const float DX = a.x - x0r, DY = a.y - y0r;
+            const float m0 = fmaf(DX, T0, -TU), m1 = fmaf(DY, T0, -TV);
+            if (idx == 0u) {
+              out = LN2 * (2.f * a.z * m0 + a.w * m1);
+            } else if (idx == 1u) {
+              out = LN2 * (a.w * m0 + 2.f * s1[j].x * m1);
+            } else if (idx == 2u) {
+              out = -0.5f * fmaf(DX, fmaf(DX, T0, -2.f * TU), tot);
+            } else if (idx == 3u) {
+              out = -fmaf(DX, m1, fmaf(-DY, TU, tot));
+            } else {
+              out = -0.5f * fmaf(DY, fmaf(DY, T0, -2.f * TV), tot);
+            }
           }
-          if (out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
         }
+        if (out != 0.f) atomicAdd(grad2d + (size_t)GRAD2D * sp[j] + idx, out);
       }
     }
     head += n;
@@ -1079,8 +1137,7 @@ __global__ __launch_bounds__(512) void k_count_blend(int ntiles, int W, int H, i
   for (uint32_t i = 0; i < last; ++i) {
     const float4* r = st.rec + 3 * (size_t)inst[rg.x + i];
     const float4 a = r[0], b = r[1];
-    float dx, dy;
-    const float p = splat_power(a, b, fx, fy, dx, dy);
+    const float p = splat_power(a, b, fx, fy);
     const float al = fminf(ALPHA_MAX, b.y * exp2_fast(p));
     cnt += (p > 0.f || al < ALPHA_MIN) ? 0 : 1;
   }
