@@ -7,15 +7,17 @@
 // into chunks of ADAM_CHUNK elements, a workgroup takes one chunk (the
 // chunk -> array map travels in the kernel arguments), and every element is
 // read once (parameter, gradient, two moments) and written once (parameter,
-// two moments): HBM-bound, 28 B per element.  The step count lives on the
-// device and is advanced by the launch that follows, so a captured step
-// replays with the right bias corrections.
+// two moments): HBM-bound, 28 B per element.  The FP64 bias corrections are
+// formed once per workgroup.  The step count lives on the device and is
+// advanced by the launch that follows, so a captured step replays with the
+// right bias corrections.
 #include "common.h"
 
 namespace gsr {
 
 constexpr int ADAM_THREADS = 256;
-constexpr int ADAM_CHUNK = 4 * ADAM_THREADS;  // four elements per thread
+constexpr int ADAM_ROUNDS = 4;  // float4 rounds per thread
+constexpr int ADAM_CHUNK = 4 * ADAM_ROUNDS * ADAM_THREADS;
 
 struct AdamTab {
   int ng;
@@ -30,48 +32,60 @@ struct AdamTab {
   double b1d, b2d;            // the betas for the bias corrections
 };
 
+// The square root and the quotient by the hardware approximations (about
+// 1 ulp each), far inside the update's own rounding of m and v.
 __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, const AdamTab& t,
                                          float step_size, float inv_sqrt_bc2) {
   m = t.b1 * m + t.c1 * g;
   v = t.b2 * v + t.c2 * (g * g);
-  p -= step_size * (m / (sqrtf(v) * inv_sqrt_bc2 + t.eps));
+  p -= step_size * (m * __builtin_amdgcn_rcpf(__builtin_amdgcn_sqrtf(v) * inv_sqrt_bc2 + t.eps));
 }
 
 __global__ __launch_bounds__(ADAM_THREADS) void k_adam(AdamTab t, const int32_t* step) {
+  __shared__ float bc[2];
   const int b = xcd_remap(blockIdx.x, t.chunk_off[t.ng]);
   if (b < 0) return;
   const int a = find_seg(t.chunk_off, t.ng, b);
   const long long n = t.n[a];
-  const long long i0 = (long long)(b - t.chunk_off[a]) * ADAM_CHUNK + 4 * (long long)threadIdx.x;
-  // bias corrections of step t = *step + 1, in FP64 (1 - beta^t cancels)
-  const double tt = (double)(step[0] + 1);
-  const double bc1 = 1.0 - pow(t.b1d, tt), bc2 = 1.0 - pow(t.b2d, tt);
-  const float step_size = (float)((double)t.lr[a] / bc1);
-  const float inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+  // bias corrections of step t = *step + 1, in FP64 (1 - beta^t cancels),
+  // by one thread of the workgroup
+  if (threadIdx.x == 0) {
+    const double tt = (double)(step[0] + 1);
+    const double bc1 = 1.0 - pow(t.b1d, tt), bc2 = 1.0 - pow(t.b2d, tt);
+    bc[0] = (float)((double)t.lr[a] / bc1);
+    bc[1] = (float)(1.0 / sqrt(bc2));
+  }
+  __syncthreads();
+  const float step_size = bc[0], inv_sqrt_bc2 = bc[1];
   float* P = t.p[a];
   const float* G = t.g[a];
   float* M = t.m[a];
   float* V = t.v[a];
   const bool vec = ((((uintptr_t)P) | ((uintptr_t)G) | ((uintptr_t)M) | ((uintptr_t)V)) & 15) == 0;
-  if (vec && i0 + 4 <= n) {
-    float4 p = *reinterpret_cast<const float4*>(P + i0);
-    const float4 g = *reinterpret_cast<const float4*>(G + i0);
-    float4 m = *reinterpret_cast<const float4*>(M + i0);
-    float4 v = *reinterpret_cast<const float4*>(V + i0);
-    adam_one(p.x, g.x, m.x, v.x, t, step_size, inv_sqrt_bc2);
-    adam_one(p.y, g.y, m.y, v.y, t, step_size, inv_sqrt_bc2);
-    adam_one(p.z, g.z, m.z, v.z, t, step_size, inv_sqrt_bc2);
-    adam_one(p.w, g.w, m.w, v.w, t, step_size, inv_sqrt_bc2);
-    *reinterpret_cast<float4*>(P + i0) = p;
-    *reinterpret_cast<float4*>(M + i0) = m;
-    *reinterpret_cast<float4*>(V + i0) = v;
-  } else {
-    for (long long i = i0; i < i0 + 4 && i < n; ++i) {
-      float p = P[i], m = M[i], v = V[i];
-      adam_one(p, G[i], m, v, t, step_size, inv_sqrt_bc2);
-      P[i] = p;
-      M[i] = m;
-      V[i] = v;
+  const long long c0 = (long long)(b - t.chunk_off[a]) * ADAM_CHUNK;
+#pragma unroll
+  for (int r = 0; r < ADAM_ROUNDS; ++r) {
+    const long long i0 = c0 + (long long)r * (4 * ADAM_THREADS) + 4 * (long long)threadIdx.x;
+    if (vec && i0 + 4 <= n) {
+      float4 p = *reinterpret_cast<const float4*>(P + i0);
+      const float4 g = *reinterpret_cast<const float4*>(G + i0);
+      float4 m = *reinterpret_cast<const float4*>(M + i0);
+      float4 v = *reinterpret_cast<const float4*>(V + i0);
+      adam_one(p.x, g.x, m.x, v.x, t, step_size, inv_sqrt_bc2);
+      adam_one(p.y, g.y, m.y, v.y, t, step_size, inv_sqrt_bc2);
+      adam_one(p.z, g.z, m.z, v.z, t, step_size, inv_sqrt_bc2);
+      adam_one(p.w, g.w, m.w, v.w, t, step_size, inv_sqrt_bc2);
+      *reinterpret_cast<float4*>(P + i0) = p;
+      *reinterpret_cast<float4*>(M + i0) = m;
+      *reinterpret_cast<float4*>(V + i0) = v;
+    } else {
+      for (long long i = i0; i < i0 + 4 && i < n; ++i) {
+        float p = P[i], m = M[i], v = V[i];
+        adam_one(p, G[i], m, v, t, step_size, inv_sqrt_bc2);
+        P[i] = p;
+        M[i] = m;
+        V[i] = v;
+      }
     }
   }
 }
