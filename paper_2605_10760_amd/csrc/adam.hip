@@ -16,8 +16,7 @@
 namespace gsr {
 
 constexpr int ADAM_THREADS = 256;
-constexpr int ADAM_ROUNDS = 4;  // float4 rounds per thread
-constexpr int ADAM_CHUNK = 4 * ADAM_ROUNDS * ADAM_THREADS;
+constexpr int ADAM_CHUNK = 4 * ADAM_THREADS;  // one float4 per thread
 
 struct AdamTab {
   int ng;
@@ -47,6 +46,21 @@ __global__ __launch_bounds__(ADAM_THREADS) void k_adam(AdamTab t, const int32_t*
   if (b < 0) return;
   const int a = find_seg(t.chunk_off, t.ng, b);
   const long long n = t.n[a];
+  float* P = t.p[a];
+  const float* G = t.g[a];
+  float* M = t.m[a];
+  float* V = t.v[a];
+  const bool vec = ((((uintptr_t)P) | ((uintptr_t)G) | ((uintptr_t)M) | ((uintptr_t)V)) & 15) == 0;
+  const long long i0 = (long long)(b - t.chunk_off[a]) * ADAM_CHUNK + 4 * (long long)threadIdx.x;
+  const bool full = vec && i0 + 4 <= n;
+  // the element loads go out before the bias corrections are formed
+  float4 p = make_float4(0.f, 0.f, 0.f, 0.f), g = p, m = p, v = p;
+  if (full) {
+    p = *reinterpret_cast<const float4*>(P + i0);
+    g = *reinterpret_cast<const float4*>(G + i0);
+    m = *reinterpret_cast<const float4*>(M + i0);
+    v = *reinterpret_cast<const float4*>(V + i0);
+  }
   // bias corrections of step t = *step + 1, in FP64 (1 - beta^t cancels),
   // by one thread of the workgroup
   if (threadIdx.x == 0) {
@@ -57,35 +71,21 @@ __global__ __launch_bounds__(ADAM_THREADS) void k_adam(AdamTab t, const int32_t*
   }
   __syncthreads();
   const float step_size = bc[0], inv_sqrt_bc2 = bc[1];
-  float* P = t.p[a];
-  const float* G = t.g[a];
-  float* M = t.m[a];
-  float* V = t.v[a];
-  const bool vec = ((((uintptr_t)P) | ((uintptr_t)G) | ((uintptr_t)M) | ((uintptr_t)V)) & 15) == 0;
-  const long long c0 = (long long)(b - t.chunk_off[a]) * ADAM_CHUNK;
-#pragma unroll
-  for (int r = 0; r < ADAM_ROUNDS; ++r) {
-    const long long i0 = c0 + (long long)r * (4 * ADAM_THREADS) + 4 * (long long)threadIdx.x;
-    if (vec && i0 + 4 <= n) {
-      float4 p = *reinterpret_cast<const float4*>(P + i0);
-      const float4 g = *reinterpret_cast<const float4*>(G + i0);
-      float4 m = *reinterpret_cast<const float4*>(M + i0);
-      float4 v = *reinterpret_cast<const float4*>(V + i0);
-      adam_one(p.x, g.x, m.x, v.x, t, step_size, inv_sqrt_bc2);
-      adam_one(p.y, g.y, m.y, v.y, t, step_size, inv_sqrt_bc2);
-      adam_one(p.z, g.z, m.z, v.z, t, step_size, inv_sqrt_bc2);
-      adam_one(p.w, g.w, m.w, v.w, t, step_size, inv_sqrt_bc2);
-      *reinterpret_cast<float4*>(P + i0) = p;
-      *reinterpret_cast<float4*>(M + i0) = m;
-      *reinterpret_cast<float4*>(V + i0) = v;
-    } else {
-      for (long long i = i0; i < i0 + 4 && i < n; ++i) {
-        float p = P[i], m = M[i], v = V[i];
-        adam_one(p, G[i], m, v, t, step_size, inv_sqrt_bc2);
-        P[i] = p;
-        M[i] = m;
-        V[i] = v;
-      }
+  if (full) {
+    adam_one(p.x, g.x, m.x, v.x, t, step_size, inv_sqrt_bc2);
+    adam_one(p.y, g.y, m.y, v.y, t, step_size, inv_sqrt_bc2);
+    adam_one(p.z, g.z, m.z, v.z, t, step_size, inv_sqrt_bc2);
+    adam_one(p.w, g.w, m.w, v.w, t, step_size, inv_sqrt_bc2);
+    *reinterpret_cast<float4*>(P + i0) = p;
+    *reinterpret_cast<float4*>(M + i0) = m;
+    *reinterpret_cast<float4*>(V + i0) = v;
+  } else {
+    for (long long i = i0; i < i0 + 4 && i < n; ++i) {
+      float pp = P[i], mm = M[i], vv = V[i];
+      adam_one(pp, G[i], mm, vv, t, step_size, inv_sqrt_bc2);
+      P[i] = pp;
+      M[i] = mm;
+      V[i] = vv;
     }
   }
 }

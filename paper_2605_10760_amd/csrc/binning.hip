@@ -96,9 +96,10 @@ __global__ __launch_bounds__(256) void k_row_count(BinTab t, StateDev st, uint32
 
 // Exclusive prefix of a [chunk][cols] count matrix down each column over the
 // view's active chunks (in place), and the column totals.  A workgroup covers
-// 64 consecutive columns (lanes: coalesced rows) x 16 segments of the chunk
-// range (waves), so the dependent walk down a column is 16x shorter.
-constexpr int CS_COLS = 64, CS_SEGS = 16;
+// 16 consecutive columns (16 lanes: a 64-byte row piece) x 64 segments of the
+// chunk range (four per wave), so the walk down a column is 64x shorter and
+// there are few columns per workgroup (a view has one column per tile row).
+constexpr int CS_COLS = 16, CS_SEGS = 64;
 __global__ __launch_bounds__(CS_COLS* CS_SEGS) void k_colscan(BinTab t, const StateHeader* hdr,
                                                              int cols, uint32_t* counts,
                                                              uint32_t* totals) {

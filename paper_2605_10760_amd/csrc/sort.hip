@@ -10,7 +10,8 @@
 //
 // A pass is three kernels: per-block digit histograms (LDS atomics, one per
 // wave when the wave's keys share a digit, as the high depth digits mostly
-// do), one workgroup per view turning the [block][digit] counts into
+// do, else one per digit present in the wave for the top digit), one
+// workgroup per view turning the [block][digit] counts into
 // scatter bases in (digit, block) order (a separate array: the scatter also
 // reads its block's counts), and a scatter where each 256-key round is
 // ranked stably inside the block by wave64 ballots over the digit bits, the
@@ -55,6 +56,19 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_hist(SortTab t, const St
     const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)d[r], (int)__builtin_ctzll(act));
     if (__ballot(valid && d[r] == d0) == act) {
       if (lane_id() == (int)__builtin_ctzll(act)) atomicAdd(&cnt[d0], (uint32_t)__popcll(act));
+    } else if (SH >= 24) {
+      // the top digit takes few values: the lanes sharing a digit (found by
+      // a ballot per digit bit) add their count with one atomic from the
+      // lowest of them
+      unsigned long long peers = act;
+#pragma unroll
+      for (int bit = 0; bit < RADIX_BITS; ++bit) {
+        const bool on = (d[r] >> bit) & 1u;
+        const unsigned long long bb = __ballot(on);
+        peers &= on ? bb : ~bb;
+      }
+      const unsigned long long lt = (1ull << lane_id()) - 1ull;
+      if (valid && (peers & lt) == 0ull) atomicAdd(&cnt[d[r]], (uint32_t)__popcll(peers));
     } else if (valid) {
       atomicAdd(&cnt[d[r]], 1u);
     }

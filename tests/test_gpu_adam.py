@@ -10,7 +10,7 @@ from oracle.adam import adam_step
 
 pytestmark = pytest.mark.gpu
 
-# ragged against the kernel's 4096-element chunks and 1024-element rounds
+# ragged against the kernel's 1024-element chunks
 SIZES = (1, 5, 1023, 1025, 8195, 100_003)
 LRS = (1e-3, 5e-2, 2.5e-3, 1.6e-4, 3e-3, 1e-2)
 
