@@ -62,6 +62,25 @@ __device__ __forceinline__ void sh_eval_grad(float x, float y, float z, float* Y
   }
 }
 
+// Normalised quaternion, scales and rotation matrix of a Gaussian (identity
+// and unit scales for an invalid slot); returns the quaternion's norm.
+__device__ __forceinline__ float rot_scale(bool valid, const float* lsv, const float* q4v,
+                                           float* qh, float* sv, float (*R)[3]) {
+  float qn = 1.f;
+  qh[0] = 1.f; qh[1] = qh[2] = qh[3] = 0.f;
+  sv[0] = sv[1] = sv[2] = 1.f;
+  if (valid) {
+    for (int k = 0; k < 3; ++k) sv[k] = expf(lsv[k]);
+    qn = sqrtf(q4v[0] * q4v[0] + q4v[1] * q4v[1] + q4v[2] * q4v[2] + q4v[3] * q4v[3]);
+    for (int k = 0; k < 4; ++k) qh[k] = q4v[k] / qn;
+  }
+  const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
+  R[0][0] = 1.f - 2.f * (y * y + z * z); R[0][1] = 2.f * (x * y - w * z); R[0][2] = 2.f * (x * z + w * y);
+  R[1][0] = 2.f * (x * y + w * z); R[1][1] = 1.f - 2.f * (x * x + z * z); R[1][2] = 2.f * (y * z - w * x);
+  R[2][0] = 2.f * (x * z - w * y); R[2][1] = 2.f * (y * z + w * x); R[2][2] = 1.f - 2.f * (x * x + y * y);
+  return qn;
+}
+
 template <int SHD>
 __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamDev cam, StateDev st,
                                                      float* grad2d, gsr_grads out) {
@@ -75,37 +94,38 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
   const bool valid = local < nset;
   const long gi = (long)t.set_goff[s] + (valid ? local : 0);
 
-  float m[3] = {0.f, 0.f, 0.f}, sv[3] = {1.f, 1.f, 1.f}, qh[4] = {1.f, 0.f, 0.f, 0.f};
-  float qn = 1.f, R[3][3], M[3][3], S3[3][3];
-  float lsv[3] = {0.f, 0.f, 0.f}, q4v[4] = {1.f, 0.f, 0.f, 0.f};
-  if (valid) {
-    for (int k = 0; k < 3; ++k) {
-      m[k] = sc.means[3 * gi + k];
-      lsv[k] = sc.log_scales[3 * gi + k];
-      sv[k] = expf(lsv[k]);
-    }
-    const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
-    q4v[0] = q4.x; q4v[1] = q4.y; q4v[2] = q4.z; q4v[3] = q4.w;
-    qn = sqrtf(q4.x * q4.x + q4.y * q4.y + q4.z * q4.z + q4.w * q4.w);
-    qh[0] = q4.x / qn; qh[1] = q4.y / qn; qh[2] = q4.z / qn; qh[3] = q4.w / qn;
-  }
-  {
-    const float w = qh[0], x = qh[1], y = qh[2], z = qh[3];
-    R[0][0] = 1.f - 2.f * (y * y + z * z); R[0][1] = 2.f * (x * y - w * z); R[0][2] = 2.f * (x * z + w * y);
-    R[1][0] = 2.f * (x * y + w * z); R[1][1] = 1.f - 2.f * (x * x + z * z); R[1][2] = 2.f * (y * z - w * x);
-    R[2][0] = 2.f * (x * z - w * y); R[2][1] = 2.f * (y * z + w * x); R[2][2] = 1.f - 2.f * (x * x + y * y);
-  }
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sv[j];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) S3[i][j] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
-  // the forward's FP64 covariance (the conic is recomputed per view from it
-  // rather than read back from the screen-space record)
+  // Per-Gaussian quantities the view loop needs: the mean, the FP32 world
+  // covariance S3 (symmetric: six entries) and the forward's FP64 one (the
+  // conic is recomputed per view from it rather than read back from the
+  // screen-space record).  The rotation and scale factors are formed again
+  // after the loop, so they hold no registers during it.
+  float m[3] = {0.f, 0.f, 0.f};
+  float S3[6];  // 00 01 02 11 12 22
   double Sd[3][3];
-  cov3_fp64(lsv, q4v, Sd);
+  {
+    float lsv[3] = {0.f, 0.f, 0.f}, q4v[4] = {1.f, 0.f, 0.f, 0.f};
+    if (valid) {
+      for (int k = 0; k < 3; ++k) {
+        m[k] = sc.means[3 * gi + k];
+        lsv[k] = sc.log_scales[3 * gi + k];
+      }
+      const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
+      q4v[0] = q4.x; q4v[1] = q4.y; q4v[2] = q4.z; q4v[3] = q4.w;
+    }
+    float R[3][3], M[3][3], qh[4], sv[3];
+    const float qn = rot_scale(valid, lsv, q4v, qh, sv, R);
+    (void)qn;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sv[j];
+    int e = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = i; j < 3; ++j)
+        S3[e++] = M[i][0] * M[j][0] + M[i][1] * M[j][1] + M[i][2] * M[j][2];
+    cov3_fp64(lsv, q4v, Sd);
+  }
 
   float gm[3] = {0.f, 0.f, 0.f};
-  float GS3[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  float GS3[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric: 00 01 02 11 12 22
   float gsig = 0.f;
   float gk[NB][3];
   for (int i = 0; i < NB; ++i) gk[i][0] = gk[i][1] = gk[i][2] = 0.f;
@@ -146,10 +166,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
 
       float p[3];
       for (int i = 0; i < 3; ++i) p[i] = Rc[i][0] * m[0] + Rc[i][1] * m[1] + Rc[i][2] * m[2] + tc[i];
+      const float S3f[3][3] = {{S3[0], S3[1], S3[2]}, {S3[1], S3[3], S3[4]}, {S3[2], S3[4], S3[5]}};
       float Wm[3][3], V[3][3];
       for (int i = 0; i < 3; ++i)
         for (int k = 0; k < 3; ++k)
-          Wm[i][k] = Rc[i][0] * S3[0][k] + Rc[i][1] * S3[1][k] + Rc[i][2] * S3[2][k];
+          Wm[i][k] = Rc[i][0] * S3f[0][k] + Rc[i][1] * S3f[1][k] + Rc[i][2] * S3f[2][k];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
           V[i][j] = Wm[i][0] * Rc[j][0] + Wm[i][1] * Rc[j][1] + Wm[i][2] * Rc[j][2];
@@ -207,9 +228,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
           Y3[i][j] = GV[i][0] * Rc[0][j] + GV[i][1] * Rc[1][j] + GV[i][2] * Rc[2][j];
-      for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j)
-          GS3[i][j] += Rc[0][i] * Y3[0][j] + Rc[1][i] * Y3[1][j] + Rc[2][i] * Y3[2][j];
+      {
+        int e = 0;
+        for (int i = 0; i < 3; ++i)
+          for (int j = i; j < 3; ++j)
+            GS3[e++] += Rc[0][i] * Y3[0][j] + Rc[1][i] * Y3[1][j] + Rc[2][i] * Y3[2][j];
+      }
       gsig += gs;
       // pose: rho <- dL/dp (+ SH term below), phi <- p x dL/dp + covariance rotation
       pose[0] = gp[0]; pose[1] = gp[1]; pose[2] = gp[2];
@@ -272,10 +296,22 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
   }
   if (!valid) return;
   // covariance -> scales and rotation:  Sigma = M M^T, M = R diag(s)
+  float R[3][3], M[3][3], qh[4], sv[3];
+  float qn;
+  {
+    float lsv[3], q4v[4];
+    for (int k = 0; k < 3; ++k) lsv[k] = sc.log_scales[3 * gi + k];
+    const float4 q4 = *reinterpret_cast<const float4*>(sc.quats + 4 * gi);
+    q4v[0] = q4.x; q4v[1] = q4.y; q4v[2] = q4.z; q4v[3] = q4.w;
+    qn = rot_scale(true, lsv, q4v, qh, sv, R);
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[i][j] = R[i][j] * sv[j];
+  const float G3[3][3] = {{GS3[0], GS3[1], GS3[2]}, {GS3[1], GS3[3], GS3[4]}, {GS3[2], GS3[4], GS3[5]}};
   float GM[3][3];
   for (int i = 0; i < 3; ++i)
     for (int k = 0; k < 3; ++k)
-      GM[i][k] = 2.f * (GS3[i][0] * M[0][k] + GS3[i][1] * M[1][k] + GS3[i][2] * M[2][k]);
+      GM[i][k] = 2.f * (G3[i][0] * M[0][k] + G3[i][1] * M[1][k] + G3[i][2] * M[2][k]);
   float GR[3][3];
   for (int k = 0; k < 3; ++k) {
     const float gsk = GM[0][k] * R[0][k] + GM[1][k] * R[1][k] + GM[2][k] * R[2][k];

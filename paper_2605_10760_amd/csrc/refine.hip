@@ -105,9 +105,11 @@ hipError_t launch_l1_grad(int nv, int HW, const float* color, const float* depth
   const uintptr_t al = (uintptr_t)color | (uintptr_t)tcol | (uintptr_t)g_col |
                        (g_dep ? ((uintptr_t)depth | (uintptr_t)tdep | (uintptr_t)g_dep) : 0);
   const bool vec = HW % 4 == 0 && (al & 15) == 0;
-  // enough blocks to fill the chip, few enough per view for its atomics
+  // about one pixel group per thread across the batch (every load of the
+  // kernel in flight at once), at most a few hundred blocks per view for
+  // the exposure atomics
   const int per = vec ? HW / 4 : HW;
-  const int bpv = std::min((per + 255) / 256, std::max(64, 2048 / nv));
+  const int bpv = std::min((per + 255) / 256, std::max(64, 16384 / nv));
   if (vec)
     hipLaunchKernelGGL(k_l1_grad<true>, dim3(nv * bpv), dim3(256), 0, s, HW, bpv, color, depth,
                        tcol, tdep, expo, w_col, w_dep, g_col, g_dep, g_expo);
