@@ -577,9 +577,6 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
   // alpha_j) with cg_j = c_j . dL/dC + z_j dL/dD, and Q += w_j cg_j.
   float fxp[PPL], fyp[PPL], Tc[PPL], g0[PPL], g1[PPL], g2[PPL], gd[PPL], Q[PPL];
   uint32_t lastp[PPL];
-  uint32_t mylast[CP];
-#pragma unroll
-  for (int c = 0; c < CP; ++c) mylast[c] = 0u;
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int px = tx0 * TW + 8 * (k % BX) + (lane & 7);
@@ -602,7 +599,16 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
       if (galp) ga = galp[v * HW + q];
     }
     Q[k] = Tc[k] * (cam.bg0 * g0[k] + cam.bg1 * g1[k] + cam.bg2 * g2[k]) - Tc[k] * ga;
-    mylast[(k % BX) / HBX] = max(mylast[(k % BX) / HBX], lastp[k]);
+  }
+  // the largest last-contributor position over each block's pixels: an
+  // entry at or beyond it blends no pixel of the block
+  uint32_t blast[PPL];
+#pragma unroll
+  for (int k = 0; k < PPL; ++k) {
+    uint32_t m = lastp[k];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+    blast[k] = (uint32_t)__builtin_amdgcn_readfirstlane((int)m);
   }
   // the lane's pixel offset within an 8x8 block
   const float lxf = (float)(lane & 7), lyf = (float)(lane >> 3);
@@ -611,13 +617,11 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
   uint32_t nwalk[CP], top[CP];
   bool any = false;
 #pragma unroll
-  for (int c = 0; c < CP; ++c) {
-    uint32_t m = mylast[c];
+  for (int c = 0; c < CP; ++c) nwalk[c] = 0u;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
-    nwalk[c] = m;
-    any = any || m != 0u;
-  }
+  for (int k = 0; k < PPL; ++k) nwalk[(k % BX) / HBX] = max(nwalk[(k % BX) / HBX], blast[k]);
+#pragma unroll
+  for (int c = 0; c < CP; ++c) any = any || nwalk[c] != 0u;
   if (!any) return;
   // The walk covers each tile's entries [0, nwalk[c]): the row entries before
   // the last of the nwalk[c]-th ones covering each column, back to front;
@@ -663,7 +667,8 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
         const float4* rp = st.rec + 3 * (size_t)pr;
         const float4 r0 = rp[0], r1 = rp[1], r2 = rp[2];
         // bit k: the entry can reach alpha >= 1/255 in the region's 8x8 block
-        // k, within a tile whose list holds it
+        // k, within a tile whose list holds it, ahead of the block's last
+        // contributor
         const float x0c = (float)(tx0 * TW) + 0.5f, y0c = (float)(ty * TH) + 0.5f;
         uint32_t m = 0u;
 #pragma unroll
@@ -672,8 +677,9 @@ __device__ __forceinline__ void bwd_tile(int g, int W, int H, int TX, int TY,
           if (row_extent(r0, r1.x, r2.w, y0c + (float)(8 * by), y0c + (float)(8 * by + 7), xl, xr)) {
 #pragma unroll
             for (int bx = 0; bx < BX; ++bx)
-              m |= (uint32_t)(cov[bx / HBX] && cols_reached(xl, xr, r1.w, x0c + (float)(8 * bx),
-                                                            x0c + (float)(8 * bx + 7)))
+              m |= (uint32_t)(cov[bx / HBX] && posr[bx / HBX][r] < blast[by * BX + bx] &&
+                              cols_reached(xl, xr, r1.w, x0c + (float)(8 * bx),
+                                           x0c + (float)(8 * bx + 7)))
                    << (by * BX + bx);
           }
         }
