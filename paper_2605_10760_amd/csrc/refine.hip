@@ -106,10 +106,10 @@ hipError_t launch_l1_grad(int nv, int HW, const float* color, const float* depth
                        (g_dep ? ((uintptr_t)depth | (uintptr_t)tdep | (uintptr_t)g_dep) : 0);
   const bool vec = HW % 4 == 0 && (al & 15) == 0;
   // about one pixel group per thread across the batch (every load of the
-  // kernel in flight at once), at most a few hundred blocks per view for
-  // the exposure atomics
+  // kernel in flight at once); with exposure sums, fewer blocks per view
+  // (each adds to the view's two sums with one atomic apiece)
   const int per = vec ? HW / 4 : HW;
-  const int bpv = std::min((per + 255) / 256, std::max(64, 16384 / nv));
+  const int bpv = std::min((per + 255) / 256, std::max(64, (g_expo ? 2048 : 16384) / nv));
   if (vec)
     hipLaunchKernelGGL(k_l1_grad<true>, dim3(nv * bpv), dim3(256), 0, s, HW, bpv, color, depth,
                        tcol, tdep, expo, w_col, w_dep, g_col, g_dep, g_expo);

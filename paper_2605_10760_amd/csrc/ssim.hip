@@ -2,9 +2,12 @@
 // exposure-compensated render I~ = exp(a_v) I^ + b_v, and its gradient.
 //
 // Statistics under an 11 x 11 Gaussian window (sigma 1.5, zero outside the
-// image), per colour channel.  Two passes over 16 x 16 pixel tiles, each
+// image), per colour channel.  Two passes over 32 x 32 pixel tiles, each
 // staging the tile plus a 5-pixel halo in LDS and blurring separably
-// (horizontal into LDS, then vertical):
+// (horizontal into LDS, then vertical), every thread producing four
+// consecutive outputs of a row (horizontal) or a column (vertical) from 14
+// staged values held in registers, so each staged value is read from LDS
+// once per four outputs instead of once per tap:
 //   k_ssim_stats: the five moments of (x, y) -> S and the three gradient
 //     maps f1 = dS/dmx - 2 mx dS/dsxx - my dS/dsxy, f2 = dS/dsxx,
 //     f3 = dS/dsxy (12 B per pixel and channel to the workspace), and the sum
@@ -18,7 +21,12 @@
 
 namespace gsr {
 
-constexpr int SS_T = 16, SS_R = 5, SS_E = SS_T + 2 * SS_R;  // tile, radius, staged edge
+constexpr int SS_T = 32, SS_R = 5, SS_E = SS_T + 2 * SS_R;  // tile, radius, staged edge
+constexpr int SS_K = 2 * SS_R + 1;                           // taps
+constexpr int SS_P = 4;                                      // outputs per thread and pass
+constexpr int SS_L = SS_P + 2 * SS_R;                        // staged values they read
+constexpr int SS_RUNS = SS_T / SS_P;                         // runs of outputs per row
+static_assert(SS_T * SS_T == 256 * SS_P, "the vertical pass: SS_P outputs per thread");
 constexpr float SS_C1 = 0.01f * 0.01f, SS_C2 = 0.03f * 0.03f;
 
 struct SsimArgs {
@@ -36,11 +44,73 @@ __device__ __forceinline__ float block_sum_256(float x, float* red) {
   return t;
 }
 
+// Horizontal blur of NM staged maps (rows of SS_E values) into NM maps of
+// SS_E rows x SS_T columns: item (row r, run u) reads SS_L values of each map
+// and writes SS_P outputs.  PRODUCTS: the maps are (x, y) and the blurred
+// quantities are x, y, x^2, y^2, x y.
+template <int NM, bool PRODUCTS>
+__device__ __forceinline__ void ss_hblur(const SsimArgs& A, const float (*src)[SS_E][SS_E + 1],
+                                         float (*dst)[SS_E][SS_T + 1]) {
+  constexpr int NO = PRODUCTS ? 5 : NM;
+  for (int it = threadIdx.x; it < SS_E * SS_RUNS; it += 256) {
+    const int r = it / SS_RUNS, c0 = (it - r * SS_RUNS) * SS_P;
+    float acc[NO][SS_P];
+#pragma unroll
+    for (int k = 0; k < NO; ++k)
+#pragma unroll
+      for (int o = 0; o < SS_P; ++o) acc[k][o] = 0.f;
+    float val[NM][SS_L];
+#pragma unroll
+    for (int k = 0; k < NM; ++k)
+#pragma unroll
+      for (int t = 0; t < SS_L; ++t) val[k][t] = src[k][r][c0 + t];
+#pragma unroll
+    for (int t = 0; t < SS_L; ++t) {
+      float q[NO];
+      if constexpr (PRODUCTS) {
+        const float x = val[0][t], y = val[1][t];
+        q[0] = x; q[1] = y; q[2] = x * x; q[3] = y * y; q[4] = x * y;
+      } else {
+#pragma unroll
+        for (int k = 0; k < NO; ++k) q[k] = val[k % NM][t];
+      }
+#pragma unroll
+      for (int o = 0; o < SS_P; ++o) {
+        const int d = t - o;
+        if (d >= 0 && d < SS_K) {
+#pragma unroll
+          for (int k = 0; k < NO; ++k) acc[k][o] += A.w[d] * q[k];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NO; ++k)
+#pragma unroll
+      for (int o = 0; o < SS_P; ++o) dst[k][r][c0 + o] = acc[k][o];
+  }
+}
+
+// Vertical blur of map k of hm at column j, rows i0 .. i0 + SS_P - 1 of the
+// tile (staged rows i0 .. i0 + SS_L - 1).
+__device__ __forceinline__ void ss_vblur(const SsimArgs& A, const float (*m)[SS_T + 1], int i0,
+                                         int j, float (&out)[SS_P]) {
+  float val[SS_L];
+#pragma unroll
+  for (int t = 0; t < SS_L; ++t) val[t] = m[i0 + t][j];
+#pragma unroll
+  for (int o = 0; o < SS_P; ++o) {
+    float a = 0.f;
+#pragma unroll
+    for (int d = 0; d < SS_K; ++d) a += A.w[d] * val[o + d];
+    out[o] = a;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs A, const float* color,
                                                     const float* target, const float* expo,
                                                     float* f, float* ssim_part) {
-  __shared__ float sx[SS_E][SS_E + 1], sy[SS_E][SS_E + 1];
-  __shared__ float hm[5][SS_E][SS_T];
+  __shared__ float sxy[2][SS_E][SS_E + 1];
+  __shared__ float hm[5][SS_E][SS_T + 1];
   __shared__ float red[4];
   const int vc = blockIdx.y, v = vc / 3;
   const int ty = blockIdx.x / A.TX, tx = blockIdx.x - ty * A.TX;
@@ -54,49 +124,39 @@ __global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs A, const float* col
     const int gx = X0 + c, gy = Y0 + r;
     const bool in = gx >= 0 && gx < A.W && gy >= 0 && gy < A.H;
     const size_t q = (size_t)gy * A.W + gx;
-    sx[r][c] = in ? ea * ci[q] + eb : 0.f;
-    sy[r][c] = in ? ti[q] : 0.f;
+    sxy[0][r][c] = in ? ea * ci[q] + eb : 0.f;
+    sxy[1][r][c] = in ? ti[q] : 0.f;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < SS_E * SS_T; i += 256) {
-    const int r = i / SS_T, c = i - r * SS_T;
-    float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f, m4 = 0.f;
-#pragma unroll
-    for (int d = 0; d <= 2 * SS_R; ++d) {
-      const float x = sx[r][c + d], y = sy[r][c + d], w = A.w[d];
-      m0 += w * x;
-      m1 += w * y;
-      m2 += w * x * x;
-      m3 += w * y * y;
-      m4 += w * x * y;
-    }
-    hm[0][r][c] = m0; hm[1][r][c] = m1; hm[2][r][c] = m2; hm[3][r][c] = m3; hm[4][r][c] = m4;
-  }
+  ss_hblur<2, true>(A, sxy, hm);
   __syncthreads();
-  const int i = threadIdx.x / SS_T, j = threadIdx.x - i * SS_T;
-  float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  // thread: column j, rows i0 .. i0 + 3 of the tile
+  const int j = threadIdx.x % SS_T, i0 = (threadIdx.x / SS_T) * SS_P;
+  float m[5][SS_P];
 #pragma unroll
-  for (int d = 0; d <= 2 * SS_R; ++d) {
-#pragma unroll
-    for (int k = 0; k < 5; ++k) m[k] += A.w[d] * hm[k][i + d][j];
-  }
-  const int gx = tx * SS_T + j, gy = ty * SS_T + i;
+  for (int k = 0; k < 5; ++k) ss_vblur(A, hm[k], i0, j, m[k]);
+  const int gx = tx * SS_T + j;
+  const size_t all = (size_t)3 * A.nv * plane;
   float s = 0.f;
-  if (gx < A.W && gy < A.H) {
-    const float mx = m[0], my = m[1];
-    const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
-    const float a1 = 2.f * mx * my + SS_C1, a2 = 2.f * sxy + SS_C2;
-    const float b1 = mx * mx + my * my + SS_C1, b2 = sxx + syy + SS_C2;
-    const float ib = 1.f / (b1 * b2);
-    s = a1 * a2 * ib;
-    const float d_mx = 2.f * my * a2 * ib - 2.f * mx * s / b1;
-    const float d_sxx = -s / b2;
-    const float d_sxy = 2.f * a1 * ib;
-    const size_t q = (size_t)vc * plane + (size_t)gy * A.W + gx;
-    const size_t all = (size_t)3 * A.nv * plane;
-    f[q] = d_mx - 2.f * mx * d_sxx - my * d_sxy;
-    f[all + q] = d_sxx;
-    f[2 * all + q] = d_sxy;
+#pragma unroll
+  for (int o = 0; o < SS_P; ++o) {
+    const int gy = ty * SS_T + i0 + o;
+    if (gx < A.W && gy < A.H) {
+      const float mx = m[0][o], my = m[1][o];
+      const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
+      const float a1 = 2.f * mx * my + SS_C1, a2 = 2.f * sxy + SS_C2;
+      const float b1 = mx * mx + my * my + SS_C1, b2 = sxx + syy + SS_C2;
+      const float ib = 1.f / (b1 * b2);
+      const float so = a1 * a2 * ib;
+      const float d_mx = 2.f * my * a2 * ib - 2.f * mx * so / b1;
+      const float d_sxx = -so / b2;
+      const float d_sxy = 2.f * a1 * ib;
+      const size_t q = (size_t)vc * plane + (size_t)gy * A.W + gx;
+      f[q] = d_mx - 2.f * mx * d_sxx - my * d_sxy;
+      f[all + q] = d_sxx;
+      f[2 * all + q] = d_sxy;
+      s += so;
+    }
   }
   const float t = block_sum_256(s, red);
   if (threadIdx.x == 0) ssim_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
@@ -107,7 +167,7 @@ __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs A, const float* colo
                                                    const float* f, float* d_color,
                                                    float* e_part) {
   __shared__ float sf[3][SS_E][SS_E + 1];
-  __shared__ float hf[3][SS_E][SS_T];
+  __shared__ float hf[3][SS_E][SS_T + 1];
   __shared__ float red[4];
   const int vc = blockIdx.y, v = vc / 3;
   const int ty = blockIdx.x / A.TX, tx = blockIdx.x - ty * A.TX;
@@ -123,48 +183,36 @@ __global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs A, const float* colo
     for (int k = 0; k < 3; ++k) sf[k][r][c] = in ? fv[k * all + q] : 0.f;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < SS_E * SS_T; i += 256) {
-    const int r = i / SS_T, c = i - r * SS_T;
-    float h0 = 0.f, h1 = 0.f, h2 = 0.f;
-#pragma unroll
-    for (int d = 0; d <= 2 * SS_R; ++d) {
-      const float w = A.w[d];
-      h0 += w * sf[0][r][c + d];
-      h1 += w * sf[1][r][c + d];
-      h2 += w * sf[2][r][c + d];
-    }
-    hf[0][r][c] = h0; hf[1][r][c] = h1; hf[2][r][c] = h2;
-  }
+  ss_hblur<3, false>(A, sf, hf);
   __syncthreads();
-  const int i = threadIdx.x / SS_T, j = threadIdx.x - i * SS_T;
-  float b0 = 0.f, b1 = 0.f, b2 = 0.f;
+  const int j = threadIdx.x % SS_T, i0 = (threadIdx.x / SS_T) * SS_P;
+  float b[3][SS_P];
 #pragma unroll
-  for (int d = 0; d <= 2 * SS_R; ++d) {
-    const float w = A.w[d];
-    b0 += w * hf[0][i + d][j];
-    b1 += w * hf[1][i + d][j];
-    b2 += w * hf[2][i + d][j];
-  }
-  const int gx = tx * SS_T + j, gy = ty * SS_T + i;
+  for (int k = 0; k < 3; ++k) ss_vblur(A, hf[k], i0, j, b[k]);
+  const int gx = tx * SS_T + j;
   const float ea = expo ? expf(expo[2 * v]) : 1.f, eb = expo ? expo[2 * v + 1] : 0.f;
   float sa = 0.f, sb = 0.f;
-  if (gx < A.W && gy < A.H) {
-    const size_t q = (size_t)vc * plane + (size_t)gy * A.W + gx;
-    const float c = color[q];
-    const float x = ea * c + eb, y = target[q];
-    // loss = weight (1 - mean S): dL/dx~ = -weight/N (w*f1 + 2 x w*f2 + y w*f3)
-    const float g = -A.weight_over_n * (b0 + 2.f * x * b1 + y * b2);
-    d_color[q] += ea * g;
-    sa = g * c;
-    sb = g;
+#pragma unroll
+  for (int o = 0; o < SS_P; ++o) {
+    const int gy = ty * SS_T + i0 + o;
+    if (gx < A.W && gy < A.H) {
+      const size_t q = (size_t)vc * plane + (size_t)gy * A.W + gx;
+      const float c = color[q];
+      const float x = ea * c + eb, y = target[q];
+      // loss = weight (1 - mean S): dL/dx~ = -weight/N (w*f1 + 2 x w*f2 + y w*f3)
+      const float g = -A.weight_over_n * (b[0][o] + 2.f * x * b[1][o] + y * b[2][o]);
+      d_color[q] += ea * g;
+      sa += g * c;
+      sb += g;
+    }
   }
   if (!e_part) return;  // uniform
   const float ta = block_sum_256(sa, red);
   const float tb = block_sum_256(sb, red);
   if (threadIdx.x == 0) {
-    const size_t b = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-    e_part[2 * b] = ea * ta;
-    e_part[2 * b + 1] = tb;
+    const size_t bb = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    e_part[2 * bb] = ea * ta;
+    e_part[2 * bb + 1] = tb;
   }
 }
 
