@@ -316,7 +316,7 @@ gsr_status gsr_ssim_workspace_bytes(int32_t n_views, int32_t width, int32_t heig
  * SSIM to ssim_out (one device float) if not NULL.  color, target_color
  * [V,3,H,W] and exposure [V,2] (or NULL: a = b = 0) are device arrays;
  * workspace is a 256-byte aligned device buffer of at least
- * gsr_ssim_workspace_bytes bytes, overwritten.  Enqueues up to four kernels on
+ * gsr_ssim_workspace_bytes bytes, overwritten.  Enqueues up to three kernels on
  * `stream`, allocates nothing and does not synchronise (graph-capturable).
  * GSR_E_INVALID_ARG for null pointers, a misaligned workspace or sizes out of
  * range. */

@@ -2,31 +2,23 @@
 // exposure-compensated render I~ = exp(a_v) I^ + b_v, and its gradient.
 //
 // Statistics under an 11 x 11 Gaussian window (sigma 1.5, zero outside the
-// image), per colour channel.  Two passes over 32 x 32 pixel tiles, each
-// staging the tile plus a 5-pixel halo in LDS and blurring separably
-// (horizontal into LDS, then vertical), every thread producing four
-// consecutive outputs of a row (horizontal) or a column (vertical) from 14
-// staged values held in registers, so each staged value is read from LDS
-// once per four outputs instead of once per tap:
-//   k_ssim_stats: the five moments of (x, y) -> S and the three gradient
-//     maps f1 = dS/dmx - 2 mx dS/dsxx - my dS/dsxy, f2 = dS/dsxx,
-//     f3 = dS/dsxy (12 B per pixel and channel to the workspace), and the sum
-//     of S;
-//   k_ssim_grad: blurs of f1..f3 -> d mean(S)/dx = (w*f1 + 2 x w*f2 +
-//     y w*f3) / N, chained through the exposure into d_color (accumulated);
-//   k_ssim_reduce: per-block partial sums (S, and the exposure gradients)
-//     summed per view in a fixed order: no float atomics on a few hot
-//     addresses.
+// image), per colour channel, in one pass over 32 x 32 pixel tiles (k_ssim):
+// the five moments of (x, y) -> S and the gradient maps f1 = dS/dmx -
+// 2 mx dS/dsxx - my dS/dsxy, f2 = dS/dsxx, f3 = dS/dsxy on the tile plus a
+// 5-pixel halo, then blurs of f1..f3 -> d mean(S)/dx = (w*f1 + 2 x w*f2 +
+// y w*f3) / N at the tile's pixels, chained through the exposure into
+// d_color (accumulated); the maps never leave LDS.  k_ssim_reduce: per-block
+// partial sums (S, and the exposure gradients) summed per view in a fixed
+// order: no float atomics on a few hot addresses.
 #include "common.h"
 
 namespace gsr {
 
-constexpr int SS_T = 32, SS_R = 5, SS_E = SS_T + 2 * SS_R;  // tile, radius, staged edge
-constexpr int SS_K = 2 * SS_R + 1;                           // taps
-constexpr int SS_P = 4;                                      // outputs per thread and pass
-constexpr int SS_L = SS_P + 2 * SS_R;                        // staged values they read
-constexpr int SS_RUNS = SS_T / SS_P;                         // runs of outputs per row
-static_assert(SS_T * SS_T == 256 * SS_P, "the vertical pass: SS_P outputs per thread");
+constexpr int SS_T = 32, SS_R = 5;   // tile, window radius
+constexpr int SS_K = 2 * SS_R + 1;     // taps
+constexpr int SS_P = 4;                // outputs per thread and blur
+constexpr int SS_L = SS_P + 2 * SS_R;  // the values they read
+static_assert(SS_T * SS_T == 256 * SS_P, "the tile's blur: SS_P outputs per thread");
 constexpr float SS_C1 = 0.01f * 0.01f, SS_C2 = 0.03f * 0.03f;
 
 struct SsimArgs {
@@ -44,35 +36,49 @@ __device__ __forceinline__ float block_sum_256(float x, float* red) {
   return t;
 }
 
-// Horizontal blur of NM staged maps (rows of SS_E values) into NM maps of
-// SS_E rows x SS_T columns: item (row r, run u) reads SS_L values of each map
-// and writes SS_P outputs.  PRODUCTS: the maps are (x, y) and the blurred
-// quantities are x, y, x^2, y^2, x y.
-template <int NM, bool PRODUCTS>
-__device__ __forceinline__ void ss_hblur(const SsimArgs& A, const float (*src)[SS_E][SS_E + 1],
-                                         float (*dst)[SS_E][SS_T + 1]) {
-  constexpr int NO = PRODUCTS ? 5 : NM;
-  for (int it = threadIdx.x; it < SS_E * SS_RUNS; it += 256) {
-    const int r = it / SS_RUNS, c0 = (it - r * SS_RUNS) * SS_P;
+// One workgroup per 32 x 32 tile of one channel of one view, in LDS only:
+//  A  x~ = exp(a) I^ + b and the target, on the tile plus a 10-pixel halo
+//     (zero outside the image), SS_X x SS_X staged;
+//  B/C the five window moments on the SS_S x SS_S statistics region (the tile
+//     plus a 5-pixel halo, two spare rows and columns): horizontal blurs into
+//     LDS, then vertical blurs into registers, in two groups (x, y, xy; then
+//     xx, yy) so that one buffer of three maps serves both;
+//  D  S and the gradient maps f1..f3 of the region (zero outside the image)
+//     into the staging buffer, S summed over the tile;
+//  E/F the blurred maps at the tile's pixels, chained through the exposure
+//     into d_color.
+// Each thread blurs SS_P consecutive outputs of a row or column from SS_L
+// values held in registers.
+constexpr int SS_S = 44, SS_X = SS_S + 2 * SS_R;  // statistics region, staged edge
+constexpr int SS_SG = SS_S / SS_P;                // row groups of the region
+static_assert(SS_S >= SS_T + 2 * SS_R && SS_S % SS_P == 0, "statistics region");
+
+// Horizontal blur of rows [0, nrow) of NM maps (or of the products of (x, y)
+// when PROD > 0: PROD = 1 blurs x, y, xy; PROD = 2 blurs xx, yy) into NO maps
+// of nout columns (a multiple of SS_P).
+template <int NM, int NO, int PROD, int SW, int DW, int NROW>
+__device__ __forceinline__ void ss_hblur(const SsimArgs& A, const float (*src)[NROW][SW],
+                                         float (*dst)[NROW][DW], int nout) {
+  const int runs = nout / SS_P;
+  for (int it = threadIdx.x; it < NROW * runs; it += 256) {
+    const int r = it / runs, c0 = (it - r * runs) * SS_P;
     float acc[NO][SS_P];
 #pragma unroll
     for (int k = 0; k < NO; ++k)
 #pragma unroll
       for (int o = 0; o < SS_P; ++o) acc[k][o] = 0.f;
-    float val[NM][SS_L];
-#pragma unroll
-    for (int k = 0; k < NM; ++k)
-#pragma unroll
-      for (int t = 0; t < SS_L; ++t) val[k][t] = src[k][r][c0 + t];
 #pragma unroll
     for (int t = 0; t < SS_L; ++t) {
       float q[NO];
-      if constexpr (PRODUCTS) {
-        const float x = val[0][t], y = val[1][t];
-        q[0] = x; q[1] = y; q[2] = x * x; q[3] = y * y; q[4] = x * y;
+      if constexpr (PROD == 1) {
+        const float x = src[0][r][c0 + t], y = src[1][r][c0 + t];
+        q[0] = x; q[1] = y; q[2 % NO] = x * y;
+      } else if constexpr (PROD == 2) {
+        const float x = src[0][r][c0 + t], y = src[1][r][c0 + t];
+        q[0] = x * x; q[1 % NO] = y * y;
       } else {
 #pragma unroll
-        for (int k = 0; k < NO; ++k) q[k] = val[k % NM][t];
+        for (int k = 0; k < NO; ++k) q[k] = src[k % NM][r][c0 + t];
       }
 #pragma unroll
       for (int o = 0; o < SS_P; ++o) {
@@ -90,10 +96,11 @@ __device__ __forceinline__ void ss_hblur(const SsimArgs& A, const float (*src)[S
   }
 }
 
-// Vertical blur of map k of hm at column j, rows i0 .. i0 + SS_P - 1 of the
-// tile (staged rows i0 .. i0 + SS_L - 1).
-__device__ __forceinline__ void ss_vblur(const SsimArgs& A, const float (*m)[SS_T + 1], int i0,
-                                         int j, float (&out)[SS_P]) {
+// Vertical blur of one map at column j, output rows i0 .. i0 + SS_P - 1
+// (input rows i0 .. i0 + SS_L - 1).
+template <int DW, int NROW>
+__device__ __forceinline__ void ss_vblur(const SsimArgs& A, const float (*m)[DW], int i0, int j,
+                                         float (&out)[SS_P]) {
   float val[SS_L];
 #pragma unroll
   for (int t = 0; t < SS_L; ++t) val[t] = m[i0 + t][j];
@@ -106,111 +113,137 @@ __device__ __forceinline__ void ss_vblur(const SsimArgs& A, const float (*m)[SS_
   }
 }
 
-__global__ __launch_bounds__(256) void k_ssim_stats(SsimArgs A, const float* color,
-                                                    const float* target, const float* expo,
-                                                    float* f, float* ssim_part) {
-  __shared__ float sxy[2][SS_E][SS_E + 1];
-  __shared__ float hm[5][SS_E][SS_T + 1];
-  __shared__ float red[4];
+struct SsimSmem {
+  union {
+    float sxy[2][SS_X][SS_X + 1];  // A-B: x~ and the target
+    float f[3][SS_S][SS_S + 1];    // D-E: f1, f2, f3 on the statistics region
+  } u0;
+  union {
+    float hm[3][SS_X][SS_S + 1];   // B-C: horizontal moment blurs
+    float hf[3][SS_S][SS_T + 1];   // E-F: horizontal blurs of f1..f3
+  } u1;
+  float red[4];
+};
+
+constexpr int SS_ITEMS = SS_S * SS_SG;                     // vertical statistics items
+constexpr int SS_IPT = (SS_ITEMS + 255) / 256;              // per thread
+
+__global__ __launch_bounds__(256) void k_ssim(SsimArgs A, const float* color, const float* target,
+                                              const float* expo, float* d_color,
+                                              float* ssim_part, float* e_part) {
+  __shared__ SsimSmem sm;
   const int vc = blockIdx.y, v = vc / 3;
   const int ty = blockIdx.x / A.TX, tx = blockIdx.x - ty * A.TX;
-  const int X0 = tx * SS_T - SS_R, Y0 = ty * SS_T - SS_R;
+  // pixel of staged (0, 0) and of statistics-region (0, 0)
+  const int XS = tx * SS_T - 2 * SS_R, YS = ty * SS_T - 2 * SS_R;
+  const int XR = tx * SS_T - SS_R, YR = ty * SS_T - SS_R;
   const float ea = expo ? expf(expo[2 * v]) : 1.f, eb = expo ? expo[2 * v + 1] : 0.f;
   const size_t plane = (size_t)A.W * A.H;
   const float* ci = color + (size_t)vc * plane;
   const float* ti = target + (size_t)vc * plane;
-  for (int i = threadIdx.x; i < SS_E * SS_E; i += 256) {
-    const int r = i / SS_E, c = i - r * SS_E;
-    const int gx = X0 + c, gy = Y0 + r;
+  for (int i = threadIdx.x; i < SS_X * SS_X; i += 256) {
+    const int r = i / SS_X, c = i - r * SS_X;
+    const int gx = XS + c, gy = YS + r;
     const bool in = gx >= 0 && gx < A.W && gy >= 0 && gy < A.H;
     const size_t q = (size_t)gy * A.W + gx;
-    sxy[0][r][c] = in ? ea * ci[q] + eb : 0.f;
-    sxy[1][r][c] = in ? ti[q] : 0.f;
+    sm.u0.sxy[0][r][c] = in ? ea * ci[q] + eb : 0.f;
+    sm.u0.sxy[1][r][c] = in ? ti[q] : 0.f;
   }
   __syncthreads();
-  ss_hblur<2, true>(A, sxy, hm);
+  // moments of the statistics items: item = (column c, row group g)
+  float mom[SS_IPT][5][SS_P];
+  ss_hblur<2, 3, 1, SS_X + 1, SS_S + 1, SS_X>(A, sm.u0.sxy, sm.u1.hm, SS_S);
   __syncthreads();
-  // thread: column j, rows i0 .. i0 + 3 of the tile
-  const int j = threadIdx.x % SS_T, i0 = (threadIdx.x / SS_T) * SS_P;
-  float m[5][SS_P];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) ss_vblur(A, hm[k], i0, j, m[k]);
-  const int gx = tx * SS_T + j;
-  const size_t all = (size_t)3 * A.nv * plane;
-  float s = 0.f;
-#pragma unroll
-  for (int o = 0; o < SS_P; ++o) {
-    const int gy = ty * SS_T + i0 + o;
-    if (gx < A.W && gy < A.H) {
-      const float mx = m[0][o], my = m[1][o];
-      const float sxx = m[2][o] - mx * mx, syy = m[3][o] - my * my, sxy = m[4][o] - mx * my;
-      const float a1 = 2.f * mx * my + SS_C1, a2 = 2.f * sxy + SS_C2;
-      const float b1 = mx * mx + my * my + SS_C1, b2 = sxx + syy + SS_C2;
-      const float ib = 1.f / (b1 * b2);
-      const float so = a1 * a2 * ib;
-      const float d_mx = 2.f * my * a2 * ib - 2.f * mx * so / b1;
-      const float d_sxx = -so / b2;
-      const float d_sxy = 2.f * a1 * ib;
-      const size_t q = (size_t)vc * plane + (size_t)gy * A.W + gx;
-      f[q] = d_mx - 2.f * mx * d_sxx - my * d_sxy;
-      f[all + q] = d_sxx;
-      f[2 * all + q] = d_sxy;
-      s += so;
+  for (int u = 0; u < SS_IPT; ++u) {
+    const int it = (int)threadIdx.x + 256 * u;
+    if (it < SS_ITEMS) {
+      const int c = it % SS_S, g = it / SS_S;
+      ss_vblur<SS_S + 1, SS_X>(A, sm.u1.hm[0], g * SS_P, c, mom[u][0]);  // x
+      ss_vblur<SS_S + 1, SS_X>(A, sm.u1.hm[1], g * SS_P, c, mom[u][1]);  // y
+      ss_vblur<SS_S + 1, SS_X>(A, sm.u1.hm[2], g * SS_P, c, mom[u][4]);  // xy
     }
   }
-  const float t = block_sum_256(s, red);
-  if (threadIdx.x == 0) ssim_part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(256) void k_ssim_grad(SsimArgs A, const float* color,
-                                                   const float* target, const float* expo,
-                                                   const float* f, float* d_color,
-                                                   float* e_part) {
-  __shared__ float sf[3][SS_E][SS_E + 1];
-  __shared__ float hf[3][SS_E][SS_T + 1];
-  __shared__ float red[4];
-  const int vc = blockIdx.y, v = vc / 3;
-  const int ty = blockIdx.x / A.TX, tx = blockIdx.x - ty * A.TX;
-  const int X0 = tx * SS_T - SS_R, Y0 = ty * SS_T - SS_R;
-  const size_t plane = (size_t)A.W * A.H, all = (size_t)3 * A.nv * plane;
-  const float* fv = f + (size_t)vc * plane;
-  for (int i = threadIdx.x; i < SS_E * SS_E; i += 256) {
-    const int r = i / SS_E, c = i - r * SS_E;
-    const int gx = X0 + c, gy = Y0 + r;
-    const bool in = gx >= 0 && gx < A.W && gy >= 0 && gy < A.H;
-    const size_t q = (size_t)gy * A.W + gx;
+  __syncthreads();
+  ss_hblur<2, 2, 2, SS_X + 1, SS_S + 1, SS_X>(A, sm.u0.sxy, sm.u1.hm, SS_S);
+  __syncthreads();
 #pragma unroll
-    for (int k = 0; k < 3; ++k) sf[k][r][c] = in ? fv[k * all + q] : 0.f;
+  for (int u = 0; u < SS_IPT; ++u) {
+    const int it = (int)threadIdx.x + 256 * u;
+    if (it < SS_ITEMS) {
+      const int c = it % SS_S, g = it / SS_S;
+      ss_vblur<SS_S + 1, SS_X>(A, sm.u1.hm[0], g * SS_P, c, mom[u][2]);  // xx
+      ss_vblur<SS_S + 1, SS_X>(A, sm.u1.hm[1], g * SS_P, c, mom[u][3]);  // yy
+    }
+  }
+  __syncthreads();  // the staging buffer becomes the f maps
+  float s = 0.f;
+#pragma unroll
+  for (int u = 0; u < SS_IPT; ++u) {
+    const int it = (int)threadIdx.x + 256 * u;
+    if (it < SS_ITEMS) {
+      const int c = it % SS_S, g = it / SS_S;
+      const int gx = XR + c;
+#pragma unroll
+      for (int o = 0; o < SS_P; ++o) {
+        const int r = g * SS_P + o, gy = YR + r;
+        float f1 = 0.f, f2 = 0.f, f3 = 0.f;
+        if (gx >= 0 && gx < A.W && gy >= 0 && gy < A.H) {
+          const float mx = mom[u][0][o], my = mom[u][1][o];
+          const float sxx = mom[u][2][o] - mx * mx, syy = mom[u][3][o] - my * my;
+          const float sxy = mom[u][4][o] - mx * my;
+          const float a1 = 2.f * mx * my + SS_C1, a2 = 2.f * sxy + SS_C2;
+          const float b1 = mx * mx + my * my + SS_C1, b2 = sxx + syy + SS_C2;
+          // b1, b2 >= C1, C2 > 0: reciprocals by the hardware (about 1 ulp)
+          const float rb1 = __builtin_amdgcn_rcpf(b1), rb2 = __builtin_amdgcn_rcpf(b2);
+          const float ib = rb1 * rb2;
+          const float so = a1 * a2 * ib;
+          const float d_mx = 2.f * my * a2 * ib - 2.f * mx * so * rb1;
+          const float d_sxx = -so * rb2;
+          const float d_sxy = 2.f * a1 * ib;
+          f1 = d_mx - 2.f * mx * d_sxx - my * d_sxy;
+          f2 = d_sxx;
+          f3 = d_sxy;
+          // the tile's own pixels carry S
+          if (r >= SS_R && r < SS_R + SS_T && c >= SS_R && c < SS_R + SS_T) s += so;
+        }
+        sm.u0.f[0][r][c] = f1;
+        sm.u0.f[1][r][c] = f2;
+        sm.u0.f[2][r][c] = f3;
+      }
+    }
   }
   __syncthreads();
-  ss_hblur<3, false>(A, sf, hf);
+  ss_hblur<3, 3, 0, SS_S + 1, SS_T + 1, SS_S>(A, sm.u0.f, sm.u1.hf, SS_T);
   __syncthreads();
+  // thread: column j, rows i0 .. i0 + SS_P - 1 of the tile
   const int j = threadIdx.x % SS_T, i0 = (threadIdx.x / SS_T) * SS_P;
-  float b[3][SS_P];
+  float bl[3][SS_P];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) ss_vblur(A, hf[k], i0, j, b[k]);
+  for (int k = 0; k < 3; ++k) ss_vblur<SS_T + 1, SS_S>(A, sm.u1.hf[k], i0, j, bl[k]);
   const int gx = tx * SS_T + j;
-  const float ea = expo ? expf(expo[2 * v]) : 1.f, eb = expo ? expo[2 * v + 1] : 0.f;
   float sa = 0.f, sb = 0.f;
 #pragma unroll
   for (int o = 0; o < SS_P; ++o) {
     const int gy = ty * SS_T + i0 + o;
     if (gx < A.W && gy < A.H) {
-      const size_t q = (size_t)vc * plane + (size_t)gy * A.W + gx;
-      const float c = color[q];
-      const float x = ea * c + eb, y = target[q];
+      const size_t q = (size_t)gy * A.W + gx;
+      const float c = ci[q];
+      const float x = ea * c + eb, y = ti[q];
       // loss = weight (1 - mean S): dL/dx~ = -weight/N (w*f1 + 2 x w*f2 + y w*f3)
-      const float g = -A.weight_over_n * (b[0][o] + 2.f * x * b[1][o] + y * b[2][o]);
-      d_color[q] += ea * g;
+      const float g = -A.weight_over_n * (bl[0][o] + 2.f * x * bl[1][o] + y * bl[2][o]);
+      d_color[(size_t)vc * plane + q] += ea * g;
       sa += g * c;
       sb += g;
     }
   }
+  const size_t bb = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+  const float t = block_sum_256(s, sm.red);
+  if (threadIdx.x == 0) ssim_part[bb] = t;
   if (!e_part) return;  // uniform
-  const float ta = block_sum_256(sa, red);
-  const float tb = block_sum_256(sb, red);
+  const float ta = block_sum_256(sa, sm.red);
+  const float tb = block_sum_256(sb, sm.red);
   if (threadIdx.x == 0) {
-    const size_t bb = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
     e_part[2 * bb] = ea * ta;
     e_part[2 * bb + 1] = tb;
   }
@@ -259,8 +292,7 @@ static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 
 size_t ssim_workspace_bytes(int nv, int W, int H) {
   const size_t nb = (size_t)((W + SS_T - 1) / SS_T) * ((H + SS_T - 1) / SS_T) * 3 * nv;
-  return align_up(nb * 4) + align_up(nb * 8) + align_up((size_t)nv * 4) +
-         (size_t)3 * 3 * nv * (size_t)W * H * sizeof(float);
+  return align_up(nb * 4) + align_up(nb * 8) + align_up((size_t)nv * 4);
 }
 
 hipError_t launch_ssim(int nv, int W, int H, float weight, const float* color,
@@ -283,10 +315,8 @@ hipError_t launch_ssim(int nv, int W, int H, float weight, const float* color,
   float* s_part = (float*)w8;
   float* e_part = (float*)(w8 + align_up(nb * 4));
   float* s_view = (float*)(w8 + align_up(nb * 4) + align_up(nb * 8));
-  float* f = (float*)(w8 + align_up(nb * 4) + align_up(nb * 8) + align_up((size_t)nv * 4));
   const dim3 grid(nb_view, 3 * nv);
-  hipLaunchKernelGGL(k_ssim_stats, grid, dim3(256), 0, s, A, color, target, expo, f, s_part);
-  hipLaunchKernelGGL(k_ssim_grad, grid, dim3(256), 0, s, A, color, target, expo, f, d_color,
+  hipLaunchKernelGGL(k_ssim, grid, dim3(256), 0, s, A, color, target, expo, d_color, s_part,
                      d_expo ? e_part : (float*)nullptr);
   if (d_expo || ssim_out)
     hipLaunchKernelGGL(k_ssim_reduce, dim3(nv), dim3(256), 0, s, nb_view, s_part,
