@@ -63,17 +63,43 @@ STAGE_KERNEL = {"project": "k_project", "render_fwd": "k_render_fwd",
                 "render_bwd": "k_render_bwd_w", "project_bwd": "k_project_bwd"}
 
 
+def _code_only(text):
+    """C/C++ source without its comments and whitespace (string and character
+    literals kept as they are), so that editing a comment keeps the digest."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def source_digest():
-    """SHA-256 over the library's kernel sources and the ABI header: a
-    recorded counter figure holds only for the sources it was taken on."""
+    """SHA-256 over the code of the library's kernel sources and the ABI
+    header (comments and whitespace left out): a recorded counter figure
+    holds only for the code it was taken on."""
     import hashlib
     h = hashlib.sha256()
     for d in (os.path.join(ROOT, "paper_2605_10760_amd", "csrc"), os.path.join(ROOT, "include")):
         for f in sorted(os.listdir(d)):
             if f.endswith((".hip", ".h")):
                 h.update(f.encode())
-                with open(os.path.join(d, f), "rb") as fh:
-                    h.update(fh.read())
+                with open(os.path.join(d, f), encoding="utf-8") as fh:
+                    h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

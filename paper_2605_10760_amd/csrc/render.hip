@@ -9,14 +9,16 @@
 // (an LDS broadcast) for all of its pixels in the blocks the entry reaches.
 // The tile stops once every pixel has terminated.
 //
-// Backward: one wave per (view, tile), PPL = TW*TH/64 pixels per lane, TPW
-// tiles per workgroup with a private LDS slice each (no workgroup barrier).
-// Each tile's entries up to the largest last-contributor position are
-// filtered from its row list back to front; every pixel recovers its
+// Backward: one wave per (view, region), a region being one tile or two
+// adjacent tiles of a tile row, PPL = region pixels / 64 per lane, TPW
+// regions per workgroup with a private LDS slice each (no workgroup
+// barrier).  Each tile's entries up to the largest last-contributor position
+// are filtered from its row list back to front; every pixel recovers its
 // transmittance by division (T_j = T_{j+1} / (1 - alpha_j)) instead of
 // storing per-pixel lists, the ten splat gradients of an entry are summed
-// over the wave with DPP row operations, and ten lanes issue one global
-// atomic each per (tile, entry).
+// over the wave by a transposing butterfly (DPP row operations and row
+// swaps), and a dense pass per staging round turns the round's sums into
+// screen-space gradients with one global atomic per (entry, value).
 //
 // A tile's list (its entries in depth order) is its row list filtered by
 // column: both kernels scan the row list with a ballot per 64 entries and
