@@ -234,7 +234,9 @@ gsr_status gsr_poll(gsr_ctx* ctx, const void* state, gsr_counts* out, void* stre
  *   t_final float [V,H,W], last uint32 [V,H,W] (last blended list position + 1)
  *   n_blend int32 [V,H,W] list entries blended per pixel (counted by a debug
  *                       kernel with the forward's skip arithmetic)
- * P is the call's pair count (sum of set sizes over views); I from gsr_poll. */
+ * P is the call's pair count (sum of set sizes over views; order and inst
+ * map visible-list positions back to pair ids through the first n_pairs
+ * pairs, so n_pairs must be P for them); I from gsr_poll. */
 typedef struct gsr_debug {
   uint32_t* zkeys;
   uint16_t* rects;

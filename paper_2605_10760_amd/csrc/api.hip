@@ -96,7 +96,6 @@ StateLayout state_layout(const gsr_plan_desc& p) {
   L.hdr = o; o = align256(o + STATE_HEADER_BYTES);
   L.zkey = o; o = align256(o + P * 4);
   L.vidx = o; o = align256(o + P * 4);
-  L.vpair = o; o = align256(o + P * 4);
   L.rect = o; o = align256(o + P * 8);
   L.rec = o; o = align256(o + P * 48);
   L.order = o; o = align256(o + P * 4);
@@ -116,7 +115,6 @@ StateDev state_ptrs(void* base, const gsr_plan_desc& p) {
   s.hdr = (StateHeader*)(b + L.hdr);
   s.zkey = (uint32_t*)(b + L.zkey);
   s.vidx = (uint32_t*)(b + L.vidx);
-  s.vpair = (uint32_t*)(b + L.vpair);
   s.rect = (uint2*)(b + L.rect);
   s.rec = (float4*)(b + L.rec);
   s.order = (uint32_t*)(b + L.order);
@@ -476,7 +474,7 @@ gsr_status gsr_forward(gsr_ctx* c, const gsr_scene* sc, const gsr_views* vw,
   }
   {
     StageMark m(c, GSR_STAGE_COMPACT, st);
-    if ((e = launch_compact(t.pt, sd, c->blk_cnt, c->blk_scan, c->ka, c->va, st)) != hipSuccess) return hip_fail(c, e, "compact");
+    if ((e = launch_compact(t.pt, sd, c->blk_cnt, c->blk_scan, c->ka, st)) != hipSuccess) return hip_fail(c, e, "compact");
   }
   {
     StageMark m(c, GSR_STAGE_RECORD, st);
@@ -645,11 +643,15 @@ gsr_status gsr_debug_export(gsr_ctx* c, const void* state, int32_t n_views, gsr_
     if (x.bytes && (e = hipMemcpy(x.dst, x.src, x.bytes, hipMemcpyDeviceToHost)) != hipSuccess)
       return hip_fail(c, e, "debug copy");
   // the sorted lists and the rects live at visible-list positions: report
-  // pair ids and per-pair rects
+  // pair ids (the pair of each position, from the position of each pair)
+  // and per-pair rects
   const size_t nvis = std::min<size_t>((size_t)h.vis_total, (size_t)c->plan.max_pairs);
-  std::vector<uint32_t> vpair(nvis);
-  if (nvis && (e = hipMemcpy(vpair.data(), sd.vpair, nvis * 4, hipMemcpyDeviceToHost)) != hipSuccess)
-    return hip_fail(c, e, "debug vpair");
+  std::vector<uint32_t> vpair(nvis, 0xFFFFFFFFu);
+  std::vector<uint32_t> vi(np);
+  if (np && (e = hipMemcpy(vi.data(), sd.vidx, np * 4, hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(c, e, "debug vidx");
+  for (size_t i = 0; i < np; ++i)
+    if (vi[i] < nvis) vpair[vi[i]] = (uint32_t)i;
   auto to_pair = [&](uint32_t* a, size_t n) {
     for (size_t i = 0; i < n; ++i) a[i] = a[i] < nvis ? vpair[a[i]] : 0xFFFFFFFFu;
   };
@@ -657,9 +659,7 @@ gsr_status gsr_debug_export(gsr_ctx* c, const void* state, int32_t n_views, gsr_
   if (d->inst) to_pair(d->inst, n_inst_out);
   if (d->rects && np) {
     std::vector<uint2> r(std::max<size_t>(nvis, 1));
-    std::vector<uint32_t> vi(np);
     if (nvis && (e = hipMemcpy(r.data(), sd.rect, nvis * 8, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug rect");
-    if ((e = hipMemcpy(vi.data(), sd.vidx, np * 4, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(c, e, "debug vidx");
     for (size_t i = 0; i < np; ++i) {
       const bool vis = vi[i] < nvis;
       const uint2 q = vis ? r[vi[i]] : make_uint2(0u, 0u);

@@ -97,7 +97,7 @@ static_assert(sizeof(StateHeader) <= STATE_HEADER_BYTES, "header");
 
 // Byte offsets of the arrays inside a saved-state buffer (all 256-aligned).
 struct StateLayout {
-  size_t hdr, zkey, vidx, vpair, rect, rec, order, row_rg, rows, torder, tfinal, last, total;
+  size_t hdr, zkey, vidx, rect, rec, order, row_rg, rows, torder, tfinal, last, total;
 };
 
 // Pointers into a saved-state buffer.
@@ -105,7 +105,6 @@ struct StateDev {
   StateHeader* hdr;
   uint32_t* zkey;     // [P]
   uint32_t* vidx;     // [P] position in the compacted visible list, CULLED if culled
-  uint32_t* vpair;    // [Pv] pair of each visible-list position
   uint2* rect;        // [Pv] by visible position: packed (x0 | y0 << 16, x1 | y1 << 16)
   float4* rec;        // [Pv][3] by visible position: (u, v, A', B'), (C', sigma, z, ex),
                       //   (r, g, b, ey)
@@ -145,7 +144,7 @@ hipError_t launch_project_keys(const ProjTab& t, const SceneDev& sc, const CamDe
 hipError_t launch_project_records(const ProjTab& t, const SceneDev& sc, const CamDev& cam,
                                   StateDev st, hipStream_t s);
 hipError_t launch_compact(const ProjTab& t, StateDev st, const uint32_t* blk_cnt,
-                          uint32_t* blk_scan, uint32_t* kout, uint32_t* vout, hipStream_t s);
+                          uint32_t* blk_scan, uint32_t* kout, hipStream_t s);
 hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32_t* va,
                              uint32_t* kb, uint32_t* vb, uint32_t* hist, uint32_t* off,
                              hipStream_t s);

@@ -434,7 +434,7 @@ __global__ __launch_bounds__(1024) void k_scan_blocks(ProjTab t, const uint32_t*
 constexpr int CP_SUB = 4;
 __global__ __launch_bounds__(PROJ_BLOCK) void k_compact(ProjTab t, StateDev st,
                                                         const uint32_t* blk_scan,
-                                                        uint32_t* kout, uint32_t* vout) {
+                                                        uint32_t* kout) {
   const int nb = t.blk_off[t.nv];
   const int g = xcd_remap(blockIdx.x, (nb + CP_SUB - 1) / CP_SUB);
   if (g < 0) return;
@@ -472,10 +472,9 @@ __global__ __launch_bounds__(PROJ_BLOCK) void k_compact(ProjTab t, StateDev st,
     if (key[k] != CULLED) {
       pos = blk_scan[b] + (uint32_t)__popcll(m[k] & ((1ull << lane) - 1ull));
       for (int i = 0; i < w; ++i) pos += wc[k][i];
-      // the sort carries the visible position; vpair maps it back to the pair
+      // the sort carries the visible position (its first pass takes each
+      // key's index as its value)
       kout[pos] = key[k];
-      vout[pos] = pos;
-      st.vpair[pos] = (uint32_t)pair[k];
     }
     // position of the pair in the compacted visible list (the row of its
     // screen-space gradient), CULLED for culled pairs
@@ -551,13 +550,13 @@ hipError_t launch_project_records(const ProjTab& t, const SceneDev& sc, const Ca
 }
 
 hipError_t launch_compact(const ProjTab& t, StateDev st, const uint32_t* blk_cnt,
-                          uint32_t* blk_scan, uint32_t* kout, uint32_t* vout, hipStream_t s) {
+                          uint32_t* blk_scan, uint32_t* kout, hipStream_t s) {
   hipLaunchKernelGGL(k_scan_blocks, dim3(std::max(1, (t.blk_off[t.nv] + SB_TILE - 1) / SB_TILE)),
                      dim3(1024), 0, s, t, blk_cnt, blk_scan, st.hdr);
   const int nb = t.blk_off[t.nv];
   if (nb > 0)
     hipLaunchKernelGGL(k_compact, dim3(xcd_grid((nb + CP_SUB - 1) / CP_SUB)), dim3(PROJ_BLOCK), 0,
-                       s, t, st, blk_scan, kout, vout);
+                       s, t, st, blk_scan, kout);
   return hipGetLastError();
 }
 

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(RADIX* SCAN_Q) void k_radix_scan(SortTab t, const S
 // slot by slot: a digit's run of the block (about 8 keys) is stored by
 // consecutive lanes to consecutive addresses instead of one scattered store
 // per key.
-template <int SH, bool KEYS_OUT>
+template <int SH, bool KEYS_OUT, bool VAL_INDEX = false>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
     SortTab t, const StateHeader* hdr, const uint32_t* hist, const uint32_t* off,
     const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout) {
@@ -172,7 +172,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(
   for (int r = 0; r < SORT_ITEMS; ++r) {
     const int i = r * SORT_THREADS + tid;
     key[r] = i < n ? kin[lo + i] : 0u;
-    val[r] = i < n ? vin[lo + i] : 0u;
+    // the first pass's values are the keys' own positions
+    val[r] = i < n ? (VAL_INDEX ? (uint32_t)(lo + i) : vin[lo + i]) : 0u;
   }
   {
     unsigned long long tot;
@@ -238,8 +239,8 @@ hipError_t launch_depth_sort(const SortTab& t, StateDev st, uint32_t* ka, uint32
   // pass 0: A -> B
   hipLaunchKernelGGL(k_radix_hist<0>, g, blk, 0, s, t, st.hdr, ka, hist);
   hipLaunchKernelGGL(k_radix_scan, sg, sb, 0, s, t, st.hdr, hist, off);
-  hipLaunchKernelGGL((k_radix_scatter<0, true>), g, blk, 0, s, t, st.hdr, hist, off, ka, va, kb,
-                     vb);
+  hipLaunchKernelGGL((k_radix_scatter<0, true, true>), g, blk, 0, s, t, st.hdr, hist, off, ka,
+                     (const uint32_t*)nullptr, kb, vb);
   // pass 1: B -> A
   hipLaunchKernelGGL(k_radix_hist<8>, g, blk, 0, s, t, st.hdr, kb, hist);
   hipLaunchKernelGGL(k_radix_scan, sg, sb, 0, s, t, st.hdr, hist, off);

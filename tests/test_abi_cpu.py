@@ -60,10 +60,9 @@ def test_state_bytes_host_only_and_validation():
     lib = _lib.load()
     n = C.c_size_t()
     assert lib.gsr_state_bytes(C.byref(_desc()), C.byref(n)) == _lib.GSR_OK
-    # header + per pair (depth key, visible position, pair of each position, rect, record,
-    # order) + row ranges (2 views x 6 rows) + row entries (8 B each) + tile order + 2
-    # per-pixel planes
-    assert n.value >= (512 + 1000 * (4 + 4 + 4 + 8 + 48 + 4) + 2 * 6 * 8 + 10000 * 8
+    # header + per pair (depth key, visible position, rect, record, order) + row ranges
+    # (2 views x 6 rows) + row entries (8 B each) + tile order + 2 per-pixel planes
+    assert n.value >= (512 + 1000 * (4 + 4 + 8 + 48 + 4) + 2 * 6 * 8 + 10000 * 8
                        + 2 * 48 * 4 + 2 * 2 * 128 * 96 * 4)
     assert n.value % 256 == 0
     for bad in (dict(max_pairs=0), dict(max_views=65), dict(tile_w=12), dict(tile_w=32, tile_h=32),
