@@ -375,13 +375,16 @@ def algorithmic(cnt, sc_np, V, H, W, sh_stride, fwd_only_views=0):
         # key pass: the key path's parameters (means, log-scales, quaternion,
         # opacity: 44 B) once per Gaussian, a depth key per pair
         "project": 44 * sc_np.n + 4 * P,
-        # read the keys, write each pair's visible position, and per visible
-        # pair its key, its position and its pair id
-        "compact": 4 * P + 4 * P + 12 * Pv,
+        # read the keys, write each pair's visible position and each visible
+        # pair's key
+        "compact": 4 * P + 4 * P + 4 * Pv,
         # record pass: every parameter once per Gaussian, the visible position
         # per pair, rect + record per visible pair
         "record": par * sc_np.n + 4 * P + (48 + 8) * Pv,
-        "depth_sort": 4 * 24 * Pv,
+        # four 8-bit passes over the visible keys: the histogram reads the
+        # keys, the scatter reads keys (and values, from the second pass on)
+        # and writes values (and keys, except in the last pass)
+        "depth_sort": (4 + 4 + 8) * Pv + 2 * (4 + 8 + 8) * Pv + (4 + 8 + 4) * Pv,
         # rects and depth order read by the counting and scatter passes, the
         # (pair, tile row) entries written; the tile lists are filtered from
         # them by the compositing kernels
