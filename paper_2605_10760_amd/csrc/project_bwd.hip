@@ -4,7 +4,8 @@
 // One thread per Gaussian; it loops over the grad-needing views of its set
 // (uniform across the workgroup, whose Gaussians all belong to one set),
 // recomputes the projection in FP32, accumulates the parameter gradients in
-// registers and writes them once (no atomics, so summing over views is
+// registers (the colour sums of SH degrees above 0 in its own LDS column)
+// and writes them once (no atomics, so summing over views is
 // deterministic).  Each view's 6-DoF pose gradient is reduced over the
 // workgroup (DPP wave sums, then LDS) into one atomic per component.
 #include "common.h"
@@ -127,8 +128,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
   float gm[3] = {0.f, 0.f, 0.f};
   float GS3[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // symmetric: 00 01 02 11 12 22
   float gsig = 0.f;
-  float gk[NB][3];
-  for (int i = 0; i < NB; ++i) gk[i][0] = gk[i][1] = gk[i][2] = 0.f;
+  // colour gradients: in registers for degree 0; for higher degrees (up to
+  // 48 per Gaussian) in the thread's own LDS column (stride 257 words: the
+  // lanes of a wave hit distinct banks), out of the registers during the
+  // view loop
+  float gk0[3] = {0.f, 0.f, 0.f};
+  __shared__ float gkl[SHD > 0 ? 3 * NB : 1][257];
+  if (SHD > 0)
+    for (int j = 0; j < 3 * NB; ++j) gkl[j][threadIdx.x] = 0.f;
 
   int parity = 0;
   for (int vi = t.set_voff[s]; vi < t.set_voff[s + 1]; ++vi, parity ^= 1) {
@@ -250,7 +257,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
       pose[5] += 2.f * (VG[0][1] - VG[1][0]);
       // colour
       if (SHD == 0) {
-        gk[0][0] += gc[0]; gk[0][1] += gc[1]; gk[0][2] += gc[2];
+        gk0[0] += gc[0]; gk0[1] += gc[1]; gk0[2] += gc[2];
       } else {
         const float ox = -(Rc[0][0] * tc[0] + Rc[1][0] * tc[1] + Rc[2][0] * tc[2]);
         const float oy = -(Rc[0][1] * tc[0] + Rc[1][1] * tc[1] + Rc[2][1] * tc[2]);
@@ -262,16 +269,24 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
         float Y[16], dY[16][3];
         sh_eval_grad<SHD>(d[0], d[1], d[2], Y, dY);
         const float* kk = sc.colors + (long)3 * sc.sh_stride * gi;
+        // the colour and its Jacobian with respect to the direction,
+        // Jr[c][k] = sum_i k_ic dY_i/dd_k, in one pass over the coefficients
+        // (each coefficient and basis derivative is used once, so neither
+        // stays live past it)
         float raw[3] = {0.5f, 0.5f, 0.5f};
+        float Jr[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
         for (int i = 0; i < NB; ++i)
-          for (int c = 0; c < 3; ++c) raw[c] += Y[i] * kk[3 * i + c];
+          for (int c = 0; c < 3; ++c) {
+            const float kc = kk[3 * i + c];
+            raw[c] += Y[i] * kc;
+            Jr[c][0] += kc * dY[i][0]; Jr[c][1] += kc * dY[i][1]; Jr[c][2] += kc * dY[i][2];
+          }
         for (int c = 0; c < 3; ++c) gc[c] = raw[c] > 0.f ? gc[c] : 0.f;
-        float gdir[3] = {0.f, 0.f, 0.f};
-        for (int i = 0; i < NB; ++i) {
-          const float e = gc[0] * kk[3 * i] + gc[1] * kk[3 * i + 1] + gc[2] * kk[3 * i + 2];
-          gdir[0] += e * dY[i][0]; gdir[1] += e * dY[i][1]; gdir[2] += e * dY[i][2];
-          gk[i][0] += Y[i] * gc[0]; gk[i][1] += Y[i] * gc[1]; gk[i][2] += Y[i] * gc[2];
-        }
+        // d L/d d = Jr^T gc
+        float gdir[3];
+        for (int k = 0; k < 3; ++k) gdir[k] = gc[0] * Jr[0][k] + gc[1] * Jr[1][k] + gc[2] * Jr[2][k];
+        for (int i = 0; i < NB; ++i)
+          for (int c = 0; c < 3; ++c) gkl[3 * i + c][threadIdx.x] += Y[i] * gc[c];
         const float dd = d[0] * gdir[0] + d[1] * gdir[1] + d[2] * gdir[2];
         float gmd[3];
         for (int k = 0; k < 3; ++k) {
@@ -339,11 +354,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(SetTab t, SceneDev sc, CamD
   const float ro = 1.f / (1.f + eo);
   out.d_opacity_logits[gi] = gsig * (eo * ro * ro);
   if (SHD == 0) {
-    for (int c = 0; c < 3; ++c) out.d_colors[3 * gi + c] = gk[0][c];
+    for (int c = 0; c < 3; ++c) out.d_colors[3 * gi + c] = gk0[c];
   } else {
     float* dk = out.d_colors + (long)3 * sc.sh_stride * gi;
     for (int i = 0; i < NB; ++i)
-      for (int c = 0; c < 3; ++c) dk[3 * i + c] = gk[i][c];
+      for (int c = 0; c < 3; ++c) dk[3 * i + c] = gkl[3 * i + c][threadIdx.x];
     for (int i = 3 * NB; i < 3 * sc.sh_stride; ++i) dk[i] = 0.f;
   }
 }
