@@ -30,12 +30,16 @@ def _scene_case(name):
     if name == "multi-agent-small":
         wl = multi_agent(scale=0.002, keyframes=3, width=160, height=120)
         return wl.scene, wl.views
-    if name == "sh3":
-        return tiny_scene(5, n=80, width=96, height=64, sh_degree=3, pose_noise=0.2)
+    if name.startswith("sh"):
+        # SH degrees 1..3 (each its own kernel instantiation), rows of
+        # exactly (degree + 1)^2 coefficients
+        deg = int(name[2:])
+        seed = {1: 11, 2: 12, 3: 5}[deg]
+        return tiny_scene(seed, n=80, width=96, height=64, sh_degree=deg, pose_noise=0.2)
     raise KeyError(name)
 
 
-CASES = ["small-plain", "tiny-0", "tiny-1", "tiny-2", "multi-agent-small", "sh3"]
+CASES = ["small-plain", "tiny-0", "tiny-1", "tiny-2", "multi-agent-small", "sh1", "sh2", "sh3"]
 
 
 @pytest.mark.parametrize("case", CASES)
