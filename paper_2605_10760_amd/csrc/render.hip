@@ -480,15 +480,17 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int 
 // the single value).  Lane l < 16 ends with the total of value sum10_index(l)
 // (-1: no value); lanes 16..63 hold partial sums.  About 45 lane operations
 // instead of 70 for ten separate reductions, none through LDS.
-// z plus a zero register after swapping z's odd 16-lane rows (R = 16) or
-// its upper 32 lanes (R = 32) with the other register's even rows / lower
-// lanes: lane l of row 0 (and of row 2 for R = 16) gets z_l + z_{l+R}.  Both
-// registers are written by the swap, so it is spelled out with both as
-// in-out operands; the two wait states before it cover a vector write of
-// its operands just ahead of it.
+// z plus a second register after swapping z's odd 16-lane rows (R = 16) or
+// its upper 32 lanes (R = 32) with that register's even rows / lower lanes:
+// lane l of row 0 (and of row 2 for R = 16) gets z_l + z_{l+R}, whatever the
+// second register held (its values reach only rows 1 and 3, or lanes 32..63,
+// of the sum), so a value that is dead at this point serves and no register
+// is cleared for it.  Both registers are written by the swap, so it is
+// spelled out with both as in-out operands; the two wait states before it
+// cover a vector write of its operands just ahead of it.
 template <int R>
-__device__ __forceinline__ float row_swap_sum(float z) {
-  float o = 0.f;
+__device__ __forceinline__ float row_swap_sum(float z, float spare) {
+  float o = spare;
   if (R == 16)
     asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(z), "+v"(o));
   else
@@ -496,10 +498,12 @@ __device__ __forceinline__ float row_swap_sum(float z) {
   return z + o;
 }
 
+// A DPP lane move; a lane whose source lane lies outside its row reads 0
+// (bound control set, so no zeroed register is needed for the old value).
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
-                                                               0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL,
+                                                            0xF, 0xF, true));
 }
 __host__ __device__ constexpr int sum10_index(int l) {
   const int b0 = l & 1, b1 = (l >> 1) & 1, b2 = (l >> 2) & 1, b3 = (l >> 3) & 1;
@@ -540,7 +544,11 @@ __device__ __forceinline__ float wave_sum10(const float (&v)[10], int lane) {
   // moved down one row, in the other register, so their sum holds the pair
   // totals in rows 0 and 2; the 32-lane swap adds row 2 to row 0 the same
   // way.
-  return row_swap_sum<32>(row_swap_sum<16>(z));
+  // y is dead once z is formed: its registers take the swaps' second
+  // operands (the first reaches rows 1 and 3 of the first sum and through
+  // them lanes 16..31 of the result, the second lanes 32..63; lanes 0..15,
+  // which hold the totals, depend on neither)
+  return row_swap_sum<32>(row_swap_sum<16>(z, y[1]), y[0]);
 }
 
 // One tile, or CP adjacent tiles of a tile row, of the backward on one wave.
