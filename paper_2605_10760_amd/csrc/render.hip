@@ -285,7 +285,7 @@ __device__ __forceinline__ uint32_t nth_cover_end(const uint2* rows, uint32_t q,
 // of each of the tile's PPL 8x8 blocks.  The tile's list is its row list
 // filtered by column; B entries are staged per round in the wave's LDS
 // slice, with a mask per entry of the blocks it can reach.
-template <int TW, int TH, int B>
+template <int TW, int TH, int B, bool NEVAL>
 __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, const CamDev& cam,
                                          const StateDev& st, float* color, float* depth,
                                          float* alpha, int32_t* n_eval, float4* s0, float4* s1,
@@ -305,15 +305,19 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
   // pixel k of the lane: block (k % BX, k / BX); its centre is exact in FP32
   const float fx0 = (float)(tx * TW + (lane & 7)) + 0.5f;
   const float fy0 = (float)(ty * TH + (lane >> 3)) + 0.5f;
-  // stopn: 1 + the position of the entry at which the pixel stopped, 0 while
-  // it runs (a pixel outside the image starts stopped)
-  float Tc[PPL], c0[PPL], c1[PPL], c2[PPL], dz[PPL];
-  uint32_t last[PPL], stopn[PPL];
+  // thr: the pixel's alpha threshold, 1/255 while it runs; once it has
+  // stopped (and from the start for a pixel outside the image) a value no
+  // alpha reaches (alpha <= 0.99, and the clamp maps a NaN product to 0.99),
+  // so a stopped pixel needs no test of its own: 2, or, when the entry
+  // counts are wanted, 2 + the 1-based position of the entry at which it
+  // stopped (exact below 2^24 entries)
+  float Tc[PPL], c0[PPL], c1[PPL], c2[PPL], dz[PPL], thr[PPL];
+  uint32_t last[PPL];
 #pragma unroll
   for (int k = 0; k < PPL; ++k) {
     const int px = tx * TW + 8 * (k % BX) + (lane & 7);
     const int py = ty * TH + 8 * (k / BX) + (lane >> 3);
-    stopn[k] = (px < W && py < H) ? 0u : ~0u;
+    thr[k] = (px < W && py < H) ? ALPHA_MIN : 2.f;
     Tc[k] = 1.f;
     c0[k] = c1[k] = c2[k] = dz[k] = 0.f;
     last[k] = 0u;
@@ -365,10 +369,10 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
     for (int r = 0; r < R; ++r) {
       unsigned long long rel = __ballot(mr[r] != 0u);
       while (rel) {
-        uint32_t run = stopn[0];
+        float run = thr[0];
 #pragma unroll
-        for (int k = 1; k < PPL; ++k) run = min(run, stopn[k]);
-        if (__ballot(run == 0u) == 0ull) {
+        for (int k = 1; k < PPL; ++k) run = fminf(run, thr[k]);
+        if (__ballot(run < 1.f) == 0ull) {
           live = false;
           break;
         }
@@ -380,16 +384,17 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
         // for the per-pixel selects
         uint32_t pos1;
         asm volatile("v_mov_b32 %0, %1" : "=v"(pos1) : "s"(tbase + (uint32_t)j + 1u));
+        const float stopv = NEVAL ? 2.f + (float)(tbase + (uint32_t)j + 1u) : 2.f;
         const float4 a = s0[j], b = s1[j], c = s2[j];
         auto blend = [&](int k, const SplatRow& rw) {
           const float p = splat_power_row(a, rw, fx0 + (float)(8 * (k % BX)));
           const float al = fminf(ALPHA_MAX, b.y * exp2_fast(p));
-          const bool use = stopn[k] == 0u && !(p > 0.f || al < ALPHA_MIN);
+          const bool use = !(p > 0.f || al < thr[k]);
           // T (1 - alpha) with one rounding
           const float Tn = fmaf(-al, Tc[k], Tc[k]);
           const bool stop = use && Tn < T_MIN;
           const bool ok = use && !stop;
-          stopn[k] = stop ? pos1 : stopn[k];
+          thr[k] = stop ? stopv : thr[k];
           const float wgt = ok ? al * Tc[k] : 0.f;
           c0[k] += c.x * wgt;
           c1[k] += c.y * wgt;
@@ -432,7 +437,8 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
       // entries examined: up to and including the stopping one, else the
       // list (every inside pixel has stopped when the walk ends early, so
       // tbase is the whole list whenever it is used)
-      if (n_eval) n_eval[v * HW + p] = (int)(stopn[k] ? stopn[k] : tbase);
+      if (NEVAL)
+        n_eval[v * HW + p] = (int)(thr[k] >= 2.f ? (uint32_t)(thr[k] - 2.f) : tbase);
     }
   }
 }
@@ -442,7 +448,7 @@ __device__ __forceinline__ void fwd_tile(int g, int W, int H, int TX, int TY, co
 // order).  Persistent form: a grid sized to the resident waves, each wave
 // taking tiles from the length-ordered queue (longest lists first) until it
 // is empty.
-template <int TW, int TH, int FB, int TPW, bool PERSIST>
+template <int TW, int TH, int FB, int TPW, bool PERSIST, bool NEVAL>
 __global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int H, int TX, int TY,
                                                          CamDev cam, StateDev st,
                                                          unsigned int* next, float* color,
@@ -457,7 +463,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int 
     if (blk < 0) return;
     const int g = blk * TPW + wv;
     if (g >= ntiles) return;
-    fwd_tile<TW, TH, B>(g, W, H, TX, TY, cam, st, color, depth, alpha, n_eval, L0[wv], L1[wv],
+    fwd_tile<TW, TH, B, NEVAL>(g, W, H, TX, TY, cam, st, color, depth, alpha, n_eval, L0[wv], L1[wv],
                         L2[wv], LR[wv]);
     return;
   }
@@ -466,7 +472,7 @@ __global__ __launch_bounds__(64 * TPW) void k_render_fwd(int ntiles, int W, int 
     if ((threadIdx.x & 63) == 0) q = atomicAdd(next, 1u);
     q = (uint32_t)__builtin_amdgcn_readfirstlane((int)q);
     if (q >= (uint32_t)ntiles) return;
-    fwd_tile<TW, TH, B>((int)st.torder[q], W, H, TX, TY, cam, st, color, depth, alpha, n_eval,
+    fwd_tile<TW, TH, B, NEVAL>((int)st.torder[q], W, H, TX, TY, cam, st, color, depth, alpha, n_eval,
                         L0[wv], L1[wv], L2[wv], LR[wv]);
     // the next tile's staging overwrites this wave's LDS slice
     __builtin_amdgcn_wave_barrier();
@@ -983,22 +989,35 @@ static int resident_blocks(const void* kernel, int threads) {
 // its longest tile ended: 0.72 -> 0.70 ms forward, 1.46 -> 1.39 ms backward)
 constexpr int FWD_TPW = 1;
 
-template <int TW, int TH, int FB>
-static void fwd_fb(int nv, int W, int H, int TX, int TY, bool persist, const CamDev& cam,
-                   StateDev st, unsigned int* sched, float* color, float* depth, float* alpha,
-                   int32_t* n_eval, hipStream_t s) {
+template <int TW, int TH, int FB, bool NEVAL>
+static void fwd_fbn(int nv, int W, int H, int TX, int TY, bool persist, const CamDev& cam,
+                    StateDev st, unsigned int* sched, float* color, float* depth, float* alpha,
+                    int32_t* n_eval, hipStream_t s) {
   const int ntiles = nv * TX * TY;
   const int need = (ntiles + FWD_TPW - 1) / FWD_TPW;
   if (persist) {
-    const auto k = k_render_fwd<TW, TH, FB, FWD_TPW, true>;
+    const auto k = k_render_fwd<TW, TH, FB, FWD_TPW, true, NEVAL>;
     const int grid = std::min(need, resident_blocks((const void*)k, 64 * FWD_TPW));
     hipLaunchKernelGGL(k, dim3(std::max(1, grid)), dim3(64 * FWD_TPW), 0, s, ntiles, W, H, TX, TY,
                        cam, st, sched, color, depth, alpha, n_eval);
   } else {
-    hipLaunchKernelGGL((k_render_fwd<TW, TH, FB, FWD_TPW, false>), dim3(xcd_grid(need)),
+    hipLaunchKernelGGL((k_render_fwd<TW, TH, FB, FWD_TPW, false, NEVAL>), dim3(xcd_grid(need)),
                        dim3(64 * FWD_TPW), 0, s, ntiles, W, H, TX, TY, cam, st, sched, color,
                        depth, alpha, n_eval);
   }
+}
+
+// the per-pixel entry counts (a debug output) only in their own instantiation
+template <int TW, int TH, int FB>
+static void fwd_fb(int nv, int W, int H, int TX, int TY, bool persist, const CamDev& cam,
+                   StateDev st, unsigned int* sched, float* color, float* depth, float* alpha,
+                   int32_t* n_eval, hipStream_t s) {
+  if (n_eval)
+    fwd_fbn<TW, TH, FB, true>(nv, W, H, TX, TY, persist, cam, st, sched, color, depth, alpha,
+                              n_eval, s);
+  else
+    fwd_fbn<TW, TH, FB, false>(nv, W, H, TX, TY, persist, cam, st, sched, color, depth, alpha,
+                               n_eval, s);
 }
 
 template <int TW, int TH>

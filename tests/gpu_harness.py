@@ -54,6 +54,12 @@ def gpu_forward(scene, views, tile=(16, 16), z_near=0.2, bg=(0.0, 0.0, 0.0), exp
     else:
         P = int(sum(scene.set_offsets[s + 1] - scene.set_offsets[s] for s in views.view_set))
     c, d, a, state, ne = rast.forward(st_, vt, z_near=z_near, bg=bg, n_eval=True)
+    # the same forward without the per-pixel entry counts runs its own kernel
+    # instantiation (the one the training step uses): bit-identical images
+    c2, d2, a2, st2 = rast.forward(st_, vt, z_near=z_near, bg=bg)
+    for x, y, name in ((c, c2, "color"), (d, d2, "depth"), (a, a2, "alpha")):
+        assert torch.equal(x, y), f"forward without entry counts differs in {name}"
+    del c2, d2, a2, st2
     counts = rast.poll(state)
     out = dict(color=c.cpu().numpy(), depth=d.cpu().numpy(), alpha=a.cpu().numpy(),
                n_eval=ne.cpu().numpy(), counts=counts, state=state, rast=rast, scene_t=st_,
